@@ -1,0 +1,232 @@
+"""ctypes front-end of the plain CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and
+the CPU-baseline leg of the benchmark, never by the product path.  It shares
+no code with the GPU library; see ``oracle.c`` for what each function computes
+and which part of the paper it follows.
+
+Array conventions (numpy, C-contiguous):
+  packed codes/masks  uint64 [n, 200]
+  shares              uint16 [n, 2 (code, mask), 3 (component), 12800]
+  per-party outputs   [3, rows, n]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+L = 12800
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+DOM_SHARE_DB, DOM_SHARE_QUERY = 1, 2
+N_GATES = 94
+
+
+def build_lib() -> str:
+    subprocess.check_call(
+        ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", _LIB, os.path.join(_HERE, "oracle.c")]
+    )
+    return _LIB
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build_lib()
+        _lib = ctypes.CDLL(_LIB)
+        _lib.orc_test_bit_extract.restype = ctypes.c_long
+        _lib.orc_test_compare_one.restype = ctypes.c_int
+        _lib.orc_prf_u16.restype = ctypes.c_uint16
+        _lib.orc_prf_u64.restype = ctypes.c_uint64
+        _lib.orc_threads.restype = ctypes.c_int
+        _lib.orc_compare.restype = ctypes.c_int
+    return _lib
+
+
+def threads() -> int:
+    return lib().orc_threads()
+
+
+def chacha_block(key: bytes, rounds: int, words12_15) -> np.ndarray:
+    out = np.zeros(16, dtype=np.uint32)
+    inp = np.asarray(words12_15, dtype=np.uint32)
+    lib().orc_chacha_block(ctypes.c_char_p(bytes(key)), ctypes.c_int(rounds), _p(inp), _p(out))
+    return out
+
+
+def prf_block(key: bytes, stream: int, pos: int) -> np.ndarray:
+    out = np.zeros(16, dtype=np.uint32)
+    lib().orc_prf_block(ctypes.c_char_p(bytes(key)), ctypes.c_uint64(stream), ctypes.c_uint64(pos), _p(out))
+    return out
+
+
+def _rot(rot):
+    return np.ascontiguousarray(np.asarray(rot, dtype=np.int32))
+
+
+def plain(qc, qm, rot, dc, dm):
+    """O1: (hd, ml, match) [rows, n] and dup [nq] for packed inputs."""
+    nq, n, r = qc.shape[0], dc.shape[0], len(rot)
+    rows = nq * r
+    hd = np.zeros((rows, n), dtype=np.int32)
+    ml = np.zeros((rows, n), dtype=np.int32)
+    match = np.zeros((rows, n), dtype=np.uint8)
+    dup = np.zeros(nq, dtype=np.uint8)
+    rr = _rot(rot)
+    lib().orc_plain(_p(np.ascontiguousarray(qc)), _p(np.ascontiguousarray(qm)), ctypes.c_int(nq), _p(rr),
+                    ctypes.c_int(r), _p(np.ascontiguousarray(dc)), _p(np.ascontiguousarray(dm)), ctypes.c_long(n),
+                    _p(hd), _p(ml), _p(match), _p(dup))
+    return hd, ml, match, dup
+
+
+def encode(code, mask):
+    xc = np.zeros(L, dtype=np.uint16)
+    xm = np.zeros(L, dtype=np.uint16)
+    lib().orc_encode(_p(np.ascontiguousarray(code)), _p(np.ascontiguousarray(mask)), _p(xc), _p(xm))
+    return xc, xm
+
+
+def share(dealer_key: bytes, dom: int, codes, masks, first_id: int):
+    n = codes.shape[0]
+    out = np.zeros((n, 2, 3, L), dtype=np.uint16)
+    lib().orc_share(ctypes.c_char_p(bytes(dealer_key)), ctypes.c_int(dom), _p(np.ascontiguousarray(codes)),
+                    _p(np.ascontiguousarray(masks)), ctypes.c_long(n), ctypes.c_uint64(first_id), _p(out))
+    return out
+
+
+def local_dot(p: int, qsh, rot, dsh):
+    nq, n, r = qsh.shape[0], dsh.shape[0], len(rot)
+    oc = np.zeros((nq * r, n), dtype=np.uint16)
+    om = np.zeros((nq * r, n), dtype=np.uint16)
+    lib().orc_local_dot(ctypes.c_int(p), _p(np.ascontiguousarray(qsh)), ctypes.c_int(nq), _p(_rot(rot)),
+                        ctypes.c_int(r), _p(np.ascontiguousarray(dsh)), ctypes.c_long(n), _p(oc), _p(om))
+    return oc, om
+
+
+def reshare(keys: bytes, z_code, z_mask, nq, rot, qid_base, first_entry):
+    """z_*: [3, rows, n] additive shares -> [3, rows, n] re-randomised components."""
+    _, rows, n = z_code.shape
+    oc = np.zeros_like(z_code)
+    om = np.zeros_like(z_mask)
+    lib().orc_reshare(ctypes.c_char_p(bytes(keys)), _p(np.ascontiguousarray(z_code)),
+                      _p(np.ascontiguousarray(z_mask)), ctypes.c_int(nq), _p(_rot(rot)), ctypes.c_int(len(rot)),
+                      ctypes.c_long(n), ctypes.c_uint64(qid_base), ctypes.c_uint64(first_entry), _p(oc), _p(om))
+    return oc, om
+
+
+def compare(keys: bytes, d_comp, x_comp, nq, rot, qid_base, first_entry, want_aux=False):
+    """Components of the match bits [3, rows, nw] (u64) from components of the
+    code dot and ml [3, rows, n].  With want_aux also returns lifted-ml and y
+    components [3, rows, n] (u32) and counts (AND gates, bits sent by 0,1,2)."""
+    _, rows, n = d_comp.shape
+    nw = (n + 63) // 64
+    match = np.zeros((3, rows, nw), dtype=np.uint64)
+    ml = np.zeros((3, rows, n), dtype=np.uint32) if want_aux else None
+    y = np.zeros((3, rows, n), dtype=np.uint32) if want_aux else None
+    counts = np.zeros(4, dtype=np.int64)
+    rc = lib().orc_compare(ctypes.c_char_p(bytes(keys)), _p(np.ascontiguousarray(d_comp)),
+                           _p(np.ascontiguousarray(x_comp)), ctypes.c_int(nq), _p(_rot(rot)),
+                           ctypes.c_int(len(rot)), ctypes.c_long(n), ctypes.c_uint64(qid_base),
+                           ctypes.c_uint64(first_entry), _p(match), _p(ml), _p(y), _p(counts))
+    if rc != 0:
+        raise ValueError("first_entry must be a multiple of 64")
+    if want_aux:
+        return match, ml, y, counts
+    return match
+
+
+def or_tree(keys: bytes, match, nq, r, qid_base):
+    """match [3, nq*r, nw] -> dup components [3, nq] (0/1) and the number of
+    word-wide AND gates."""
+    _, rows, nw = match.shape
+    dup = np.zeros((3, nq), dtype=np.uint8)
+    cnt = ctypes.c_long(0)
+    lib().orc_or_tree(ctypes.c_char_p(bytes(keys)), _p(np.ascontiguousarray(match)), ctypes.c_int(nq),
+                      ctypes.c_int(r), ctypes.c_long(nw), ctypes.c_uint64(qid_base), _p(dup), ctypes.byref(cnt))
+    return dup, cnt.value
+
+
+def open_add(comps, bits: int):
+    """Reconstruct arithmetic components [3, ...] mod 2^bits."""
+    s = comps.astype(np.uint64).sum(axis=0)
+    return (s & np.uint64((1 << bits) - 1)).astype(np.uint32 if bits > 16 else np.uint16)
+
+
+def open_xor(comps):
+    return comps[0] ^ comps[1] ^ comps[2]
+
+
+# ---- sub-protocol hooks on explicit or seeded randomness (for pinning) ----
+def t_bit_extract(k, m, x0, x1, x2, seed):
+    bits = np.zeros(m + 1, dtype=np.uint8)
+    comp = np.zeros(3 * (m + 1), dtype=np.uint8)
+    depth = np.zeros(m + 1, dtype=np.int32)
+    ands = lib().orc_test_bit_extract(ctypes.c_int(k), ctypes.c_int(m), ctypes.c_uint32(x0), ctypes.c_uint32(x1),
+                                      ctypes.c_uint32(x2), ctypes.c_uint64(seed), _p(bits), _p(comp), _p(depth))
+    return bits, comp.reshape(m + 1, 3), ands, depth
+
+
+def t_and(x, y, f):
+    x, y, f = (np.asarray(v, dtype=np.uint8) for v in (x, y, f))
+    z = np.zeros(3, dtype=np.uint8)
+    lib().orc_test_and(_p(x), _p(y), _p(f), _p(z))
+    return z
+
+
+def t_fa(a, b, c, f):
+    a, b, c, f = (np.asarray(v, dtype=np.uint8) for v in (a, b, c, f))
+    s = np.zeros(3, dtype=np.uint8)
+    o = np.zeros(3, dtype=np.uint8)
+    lib().orc_test_fa(_p(a), _p(b), _p(c), _p(f), _p(s), _p(o))
+    return s, o
+
+
+def t_bit_inject(x, k, c0, c2, w0, w1):
+    x = np.asarray(x, dtype=np.uint8)
+    out = np.zeros(3, dtype=np.uint32)
+    bits = np.zeros(3, dtype=np.int64)
+    lib().orc_test_bit_inject(_p(x), ctypes.c_int(k), ctypes.c_uint32(c0), ctypes.c_uint32(c2),
+                              ctypes.c_uint32(w0), ctypes.c_uint32(w1), _p(out), _p(bits))
+    return out, bits
+
+
+def t_compare_one(d, x, seed):
+    d = np.asarray(d, dtype=np.uint16)
+    x = np.asarray(x, dtype=np.uint16)
+    mlo = ctypes.c_uint32(0)
+    yo = ctypes.c_uint32(0)
+    counts = np.zeros(4, dtype=np.int64)
+    depth = ctypes.c_int(0)
+    m = lib().orc_test_compare_one(_p(d), _p(x), ctypes.c_uint64(seed), ctypes.byref(mlo), ctypes.byref(yo),
+                                   _p(counts), ctypes.byref(depth))
+    return m, mlo.value, yo.value, counts, depth.value
+
+
+def protocol(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_base=0, first_entry=0):
+    """The whole shared protocol on the CPU: share, per-party local dots,
+    reshare, compare, OR-tree.  Returns a dict of every intermediate."""
+    nq, r = qc.shape[0], len(rot)
+    qsh = share(dealer_key, DOM_SHARE_QUERY, qc, qm, qid_base)
+    dsh = share(dealer_key, DOM_SHARE_DB, dc, dm, first_entry)
+    zc, zm = [], []
+    for p in range(3):
+        c, m = local_dot(p, qsh, rot, dsh)
+        zc.append(c)
+        zm.append(m)
+    zc = np.stack(zc)
+    zm = np.stack(zm)
+    rc, rm = reshare(keys, zc, zm, nq, rot, qid_base, first_entry)
+    match, ml, y, counts = compare(keys, rc, rm, nq, rot, qid_base, first_entry, want_aux=True)
+    dup, or_words = or_tree(keys, match, nq, r, qid_base)
+    return dict(qsh=qsh, dsh=dsh, z_code=zc, z_mask=zm, rep_code=rc, rep_mask=rm, match=match,
+                ml_lift=ml, y=y, counts=counts, dup=dup, or_words=or_words)

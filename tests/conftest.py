@@ -1,0 +1,23 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: longer CPU-side checks")
+
+
+@pytest.fixture(scope="session")
+def keys():
+    """Dealer key and the three party keys used across the tests."""
+    import hashlib
+
+    dealer = hashlib.sha256(b"dealer").digest()
+    party = b"".join(hashlib.sha256(b"party%d" % i).digest() for i in range(3))
+    return dealer, party
