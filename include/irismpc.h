@@ -1,0 +1,205 @@
+/*
+ * irismpc.h -- C ABI of the MI355X (gfx950) library for the secret-shared
+ * masked Hamming-distance uniqueness check of arxiv 2405.04463
+ * ("Large-Scale MPC: Scaling Private Iris Code Uniqueness Checks to Millions
+ * of Users"), protocol of Alg. 3 (codes and masks shared) in 3-party
+ * replicated sharing over Z_2^16 with the MPCLift threshold comparison.
+ *
+ * All three parties are simulated on one GPU.  Party p (0-based; the paper's
+ * parties are 1..3) holds components (x_p, x_{p-1 mod 3}) of every replicated
+ * sharing (App. C) and key_p, key_{p-1} of the correlated randomness (App. D).
+ * Calls that need an exchange between parties (reshare, compare_threshold,
+ * or_tree, open) take all three parties' buffers; what party p sends to
+ * party p+1 passes through caller-visible device memory.
+ *
+ * Conventions
+ *   - Every large buffer is caller-owned DEVICE memory on the context's
+ *     device; pointers are plain addresses, sizes are element counts.
+ *   - Work is enqueued on the caller's stream and is asynchronous, except
+ *     where a call says it synchronises.
+ *   - Argument errors are reported before anything is enqueued; the library
+ *     never throws across this boundary.  A failed launch returns
+ *     IMC_EDEVICE; a fault inside a kernel surfaces at the caller's next
+ *     synchronisation.
+ *   - A context is used by one host thread at a time.  Calls that share a
+ *     context's internal scratch (dot_shares, open with check) must not
+ *     overlap on different streams.
+ *   - Identifiers: query qi of a call has id ids->query_id_base + qi (< 2^48),
+ *     result row qi*r + ri is that query at rotation ids->rot[ri]; result
+ *     column j is database entry ids->first_entry_id + j.  Every random value
+ *     the protocol draws is addressed by (query id, rotation, entry id, gate),
+ *     never by batch position, so results do not depend on batching.
+ *
+ * Code layout: 12,800 bits, bit i in u64 word i>>6 at bit i&63, with
+ * i = ((row*200 + col)*2 + f)*2 + j (16 rows x 200 columns x 4 bits).  A
+ * rotation by s moves column col to col + s (mod 200) within each row.
+ */
+#ifndef IRISMPC_H
+#define IRISMPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int imc_status;
+#define IMC_OK 0
+#define IMC_EINVAL (-1)        /* null/misaligned pointer, bad party, rotation or id */
+#define IMC_ESHAPE (-2)        /* sizes inconsistent (ld < n, capacity exceeded, rows > max_rows) */
+#define IMC_ENOMEM (-3)        /* the context could not allocate its own scratch */
+#define IMC_EDEVICE (-4)       /* a HIP call or launch failed */
+#define IMC_ECORRUPT (-5)      /* open with check: the two holders of a component disagree */
+#define IMC_EUNSUPPORTED (-6)  /* a parameter outside what this build implements */
+
+#define IMC_CODE_BITS 12800
+#define IMC_CODE_WORDS 200
+#define IMC_MAX_ROT 32         /* rotations per query in one call */
+#define IMC_ENTRY_BYTES 102400 /* one party's database bytes per entry */
+
+/* Stream handle: a hipStream_t (NULL = the default stream). */
+typedef struct ihipStream_t* imc_stream;
+
+typedef struct imc_ctx imc_ctx;
+
+typedef struct imc_params {
+  uint32_t code_bits;          /* l; must be 12800 (Sec. 3) */
+  uint32_t thr_a;              /* threshold a with b = 2^16, 1 - 2*MATCH_RATIO = a/b (Sec. 5);
+                                  must be 16384 (MATCH_RATIO = 3/8) */
+  uint32_t max_rows;           /* largest q*r any dot_shares call uses (sizes internal scratch) */
+  uint32_t flags;              /* reserved, must be 0 */
+  uint8_t dealer_key[32];      /* key of the input dealer's sharing PRF */
+  uint8_t party_key[3][32];    /* key_p of party p; the paper's seed_{p+1} (App. D) */
+} imc_params;
+
+typedef struct imc_ids {
+  uint64_t query_id_base;      /* id of the call's query 0 */
+  uint64_t first_entry_id;     /* entry id of result column 0; multiple of 64 */
+  int32_t r;                   /* rotations per query, 1..32 */
+  int8_t rot[IMC_MAX_ROT];     /* rotation offsets, each in [-15, 15] */
+} imc_ids;
+
+/* Create a context on HIP device `device`.  Copies the keys, allocates the
+ * internal scratch (rotated query operands for params->max_rows rows, about
+ * 102,400 B per row, and a few counters).  Errors: IMC_EINVAL (null),
+ * IMC_EUNSUPPORTED (code_bits, thr_a, flags), IMC_ENOMEM, IMC_EDEVICE. */
+imc_status imc_create(const imc_params* params, int device, imc_ctx** out);
+
+/* Release the context and its scratch (synchronises the device).  NULL is a no-op. */
+void imc_destroy(imc_ctx* ctx);
+
+/* Static text for a status code. */
+const char* imc_strerror(imc_status s);
+
+/* Bytes of one party's database region for `capacity` entries (entries are
+ * stored in blocks of 32; see imc_share_db). */
+size_t imc_db_bytes(size_t capacity);
+/* Bytes of one party's query operand / raw query shares for q queries. */
+size_t imc_query_op_bytes(size_t q);
+size_t imc_query_raw_bytes(size_t q);
+/* Bytes of the OR-tree workspace for q queries with r rotations and nw words per row. */
+size_t imc_or_tree_ws_bytes(size_t q, size_t r, size_t nw);
+
+/* Enrolment (Sec. 4.3, "the orb secret shares each bit"; App. C sharing).
+ * codes, masks: device u64 [n][200] packed bits of entries first_entry_id ..
+ * first_entry_id + n - 1.  Each bit becomes the masked bit c' = m - 2 (c AND m)
+ * in Z_2^16 (Sec. 4.1.1) and each mask bit m in Z_2^16; the dealer splits
+ * x = x_0 + x_1 + x_2 with x_0, x_1 from its PRF; party p's region db[p]
+ * receives (x_p, x_{p-1}) of code and mask for every entry.
+ * db[p]: device region of imc_db_bytes(db_capacity) bytes (alignment 256).
+ * Layout: entry e lives in block e/32 at slot e%32; a block is
+ * [plane 4][k-chunk 1600][slot 32][16 B] with planes (code lo, code hi,
+ * mask lo, mask hi) of the balanced byte limbs v = lo + 256 hi (lo, hi signed
+ * bytes), k < 12800 holding x_p and k >= 12800 holding x_{p-1}.
+ * Errors: IMC_EINVAL (null, unaligned), IMC_ESHAPE (first+n > capacity). */
+imc_status imc_share_db(imc_ctx* ctx, const uint64_t* codes, const uint64_t* masks, size_t n,
+                        uint64_t first_entry_id, void* const db[3], size_t db_capacity,
+                        imc_stream stream);
+
+/* Query sharing (same dealer sharing, its own PRF domain, keyed by query id).
+ * qop[p]: party p's dot-product operand, device i8 [q][plane 4][25600] with
+ * k < 12800 holding x_p + x_{p-1} and k >= 12800 holding x_p (the
+ * preprocessed share of App. C on the query side), balanced byte limbs.
+ * qraw[p] (optional, may be NULL): device u16 [q][vec 2][comp 2][12800],
+ * vec 0 code / 1 mask, comp 0 = x_p, comp 1 = x_{p-1}; imc_append_db copies
+ * it into a database region. */
+imc_status imc_share_query(imc_ctx* ctx, const uint64_t* codes, const uint64_t* masks, size_t q,
+                           uint64_t query_id_base, void* const qop[3], void* const qraw[3],
+                           imc_stream stream);
+
+/* Party-local dot products (Alg. 3, the two inner products; App. C):
+ * for every row (query qi at rotation rot[ri]) and entry e,
+ *   code_dot = sum_k (x_p + x_{p-1})_k y_{p,k} + (x_p)_k y_{p-1,k}  mod 2^16
+ * over the rotated code shares x and entry shares y, and mask_dot likewise:
+ * party p's additive share of <c', C'_e> and of ml before re-randomisation.
+ * Rotating shares rotates the secret (sharing is elementwise, Sec. 3).
+ * qop: party p's operand from imc_share_query; db: party p's region;
+ * code_dot, mask_dot: device u16 [q*ids->r][ld], ld >= n.
+ * Errors: IMC_EINVAL (party, rotation, first_entry_id % 64), IMC_ESHAPE
+ * (q*r > max_rows, ld < n, first+n > capacity). */
+imc_status imc_dot_shares(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_ids* ids,
+                          const void* db, size_t db_capacity, size_t n, uint16_t* code_dot,
+                          uint16_t* mask_dot, size_t ld, imc_stream stream);
+
+/* Resharing of the dot products (App. C: add a zero share, send to the next
+ * party).  add_code[p], add_mask[p]: party p's additive shares, u16
+ * [rows][ld].  Party p adds F(key_p) - F(key_{p-1}) (ChaCha12 at (query id,
+ * rotation, entry)) and sends the result to party p+1: msg[p] is device u16
+ * [2][rows][ld] (code, mask).  rep_code[p], rep_mask[p]: device u16
+ * [2][rows][ld]: plane 0 = own re-randomised share, plane 1 = the one
+ * received from party p-1.  rows must equal q * ids->r for some q. */
+imc_status imc_reshare(imc_ctx* ctx, const uint16_t* const add_code[3], const uint16_t* const add_mask[3],
+                       size_t rows, size_t n, size_t ld, const imc_ids* ids, uint16_t* const msg[3],
+                       uint16_t* const rep_code[3], uint16_t* const rep_mask[3], imc_stream stream);
+
+/* Threshold comparison, MPCLift variant (Alg. 3 lines lift/MSB; Sec. 5.1,
+ * Sec. 5.2; App. D Lift, BitExtract, BitInject, 3OT, ConstLift):
+ *   [ml'] = Lift([ml]_{2^16}) to Z_2^32, y = 2^14 [ml'] - ConstLift([dot], 2^16),
+ *   [match] = MSB(y)   (match <=> hd/ml < 3/8 <=> 4 dot > ml).
+ * rep_code[p], rep_mask[p]: as produced by imc_reshare ([2][rows][ld]).
+ * match[p]: device u64 [2][rows][mw_ld] (mw_ld >= ceil(n/64)): plane 0 = party
+ * p's own component, plane 1 = component p-1; bit o of word w is column
+ * 64w + o; bits at columns >= n are public zeros.  All 3 x 94 AND gates per
+ * comparison and both BitInjects run; one GPU lane evaluates 64 comparisons
+ * bit-sliced.  ids->first_entry_id must be a multiple of 64. */
+imc_status imc_compare_threshold(imc_ctx* ctx, const uint16_t* const rep_code[3],
+                                 const uint16_t* const rep_mask[3], size_t rows, size_t n, size_t ld,
+                                 const imc_ids* ids, uint64_t* const match[3], size_t mw_ld,
+                                 imc_stream stream);
+
+/* OR-tree (Sec. 4.2; Alg. 3 return): dup[q] = OR over rotations and entries
+ * of the shared match bits, as a binary tree of x OR y = x ^ y ^ (x AND y):
+ * words 2i, 2i+1 of each level pair up (rotation-major order, a public zero
+ * word appended to odd levels), then six in-word levels fold 64 bits to 1.
+ * match[p]: [2][q*r][mw_ld] from imc_compare_threshold; nw = words per row.
+ * ws: device workspace of imc_or_tree_ws_bytes(q, r, nw) bytes.
+ * dup[p]: device u8 [2][q] (0/1), own component then component p-1. */
+imc_status imc_or_tree(imc_ctx* ctx, const uint64_t* const match[3], size_t q, size_t nw, size_t mw_ld,
+                       const imc_ids* ids, void* ws, size_t ws_bytes, uint8_t* const dup[3],
+                       imc_stream stream);
+
+#define IMC_OPEN_U8_XOR 0      /* bits stored one per byte, reconstructed by XOR */
+#define IMC_OPEN_U64_XOR 1     /* bit-sliced words, XOR */
+#define IMC_OPEN_U16_ADD 2     /* Z_2^16 values, sum */
+#define IMC_OPEN_U32_ADD 3     /* Z_2^32 values, sum */
+
+/* Opening: each party sends its own component to the party that lacks it;
+ * out = x_0 op x_1 op x_2.  rep[p]: device [2][count] elements of the kind's
+ * type (plane 0 own component, plane 1 component p-1); out: device [count].
+ * check != 0 additionally compares every component's two holders and
+ * SYNCHRONISES the stream; a disagreement returns IMC_ECORRUPT (out is still
+ * written). */
+imc_status imc_open(imc_ctx* ctx, int kind, const void* const rep[3], size_t count, void* out, int check,
+                    imc_stream stream);
+
+/* Append: copy query qi's raw shares (qraw[p] from imc_share_query) into
+ * database slot entry_id of every party's region (Sec. 1: a unique query is
+ * enrolled).  Errors: IMC_ESHAPE (entry_id >= capacity). */
+imc_status imc_append_db(imc_ctx* ctx, const void* const qraw[3], size_t qi, void* const db[3],
+                         size_t db_capacity, uint64_t entry_id, imc_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IRISMPC_H */

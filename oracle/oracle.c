@@ -63,20 +63,32 @@
 #define DOM_OR 5u
 
 /* Circuit layout of one comparison (gate numbers index the PRF tape). */
-#define LIFT_M 17            /* Lift extracts bits {17,16} */
-#define LIFT_G0 0            /* gates 0..32 */
-#define MSB_M 31             /* MSB of the 32-bit comparison ring */
-#define MSB_G0 33            /* gates 33..93 */
-#define N_GATES 94
+#define LIFT_M 17            /* Lift extracts bits {17,16}: 33 AND gates */
+#define LIFT_W0 0            /* tape words 0..33 */
+#define MSB_M 31             /* MSB of the 32-bit comparison ring: 61 AND gates */
+#define MSB_W0 40            /* tape words 40..101 */
+#define N_GATE_WORDS 102
 #define INJ_A_K 15           /* bit 17 is injected into Z_2^15 */
 #define INJ_B_K 16           /* bit 16 is injected into Z_2^16 */
-#define TAPE_C_A 96          /* key_0: c0 planes; key_2: c2 planes (inject A) */
-#define TAPE_C_B 111         /*   ... inject B */
-#define TAPE_W0_A 128        /* key_2: OT pad w0 (inject A) */
-#define TAPE_W0_B 143
-#define TAPE_W1_A 160        /* key_2: OT pad w1 (inject A) */
-#define TAPE_W1_B 175
-#define TAPE_WORDS 192       /* 24 ChaCha blocks per key per 64-entry group */
+/* Per 64-entry group each key has a tape of u64 words (8 per ChaCha block).
+ * AND gates of a BitExtract with word base w0: the FA-layer gate of bit i
+ * uses word w0 + 2i, the ripple gate producing the carry into bit i+1 uses
+ * word w0 + 2i + 1 (so word w0 + 1 is unused).
+ *   words   0..33   Lift (w0 = 0)                          blocks 0..4
+ *   words  40..101  MSB  (w0 = 40)                         blocks 5..12
+ *   BitInject values, bit j of a k-bit value in word base + j:
+ *     key_0: c0 of inject A at 104, of inject B at 120     blocks 13..16
+ *     key_2: c2, w0, w1 of inject A at 104, 120, 136;
+ *            c2, w0, w1 of inject B at 152, 168, 184      blocks 13..24 */
+#define TAPE_C0_A 104
+#define TAPE_C0_B 120
+#define TAPE_C2_A 104
+#define TAPE_W0_A 120
+#define TAPE_W1_A 136
+#define TAPE_C2_B 152
+#define TAPE_W0_B 168
+#define TAPE_W1_B 184
+#define TAPE_WORDS 200       /* 25 ChaCha blocks per key per 64-entry group */
 #define TAPE_BLOCKS_PER_GROUP 32
 
 /* ------------------------------------------------------------------ */
@@ -324,7 +336,7 @@ typedef struct { uint8_t c[3]; int depth; } bsh;   /* depth: AND rounds behind t
 /* Randomness of one comparison: one bit per key per AND gate, and the
  * BitInject values (c0 from key_0; c2, w0, w1 from key_2). */
 typedef struct {
-  uint8_t g[N_GATES][3];
+  uint8_t g[N_GATE_WORDS][3];   /* indexed by tape word */
   uint32_t c0[2], c2[2], w0[2], w1[2];   /* [0] = inject A (Z_2^15), [1] = inject B (Z_2^16) */
 } crand;
 
@@ -364,9 +376,10 @@ static bsh full_adder(bsh a, bsh b, bsh c, const uint8_t* f, bsh* carry, ccount*
  * beyond bit m).  ShareSplit: bit i of component j becomes the trivial
  * sharing InpLocal(x_j[i], j) (component j set, others zero).  FA layer on
  * bits 0..m (carry of bit m unused), then BinAdd((c[m-1..0], 0), s[m..0]).
- * Gates: FA layer g0+i (i < m), ripple carry into bit i+1 g0+m+i-1
- * (1 <= i < m).  Returns r[0..m]. */
-static void bit_extract(const uint32_t x[3], int m, int g0, int d0, const crand* rnd, bsh* r, ccount* cnt) {
+ * Randomness: the FA-layer gate of bit i (i < m) uses tape word w0 + 2i, the
+ * ripple gate producing the carry into bit i+1 (1 <= i < m) word w0 + 2i + 1.
+ * Returns r[0..m]. */
+static void bit_extract(const uint32_t x[3], int m, int w0, int d0, const crand* rnd, bsh* r, ccount* cnt) {
   bsh s[33], c[33];
   for (int i = 0; i < 33; ++i) s[i] = c[i] = bsh_zero();
   for (int i = 0; i <= m; ++i) {
@@ -375,7 +388,7 @@ static void bit_extract(const uint32_t x[3], int m, int g0, int d0, const crand*
     a.c[0] = (uint8_t)((x[0] >> i) & 1u);   /* InpLocal(x_1[i], party 1) */
     b.c[1] = (uint8_t)((x[1] >> i) & 1u);   /* InpLocal(x_2[i], party 2) */
     cc.c[2] = (uint8_t)((x[2] >> i) & 1u);  /* InpLocal(x_3[i], party 3) */
-    s[i] = full_adder(a, b, cc, rnd->g[g0 + i], i < m ? &c[i] : NULL, cnt);
+    s[i] = full_adder(a, b, cc, rnd->g[w0 + 2 * i], i < m ? &c[i] : NULL, cnt);
   }
   /* BinAdd: A[0] = 0 (public), A[i] = c[i-1]; B[i] = s[i]. */
   bsh carry = bsh_zero();   /* carry into bit 1 is A[0] AND B[0] = 0 (public) */
@@ -385,7 +398,7 @@ static void bit_extract(const uint32_t x[3], int m, int g0, int d0, const crand*
     r[i] = bxor(bxor(A, B), carry);
     if (i < m) {
       bsh t1 = bxor(A, carry), t2 = bxor(B, carry);
-      carry = bxor(band(t1, t2, rnd->g[g0 + m + i - 1], cnt), carry);
+      carry = bxor(band(t1, t2, rnd->g[w0 + 2 * i + 1], cnt), carry);
     }
   }
 }
@@ -425,7 +438,7 @@ static bsh compare_one(const uint16_t d[3], const uint16_t x[3], const crand* rn
   /* Lift [App. D]: InpLocal each component into Z_2^32 and add. */
   uint32_t S[3] = {x[0], x[1], x[2]};
   bsh r[33];
-  bit_extract(S, LIFT_M, LIFT_G0, 0, rnd, r, cnt);
+  bit_extract(S, LIFT_M, LIFT_W0, 0, rnd, r, cnt);
   bsh a = r[17], b = r[16];
   int d_inj = (a.depth > b.depth ? a.depth : b.depth) + 2;   /* 3OT round + c1 forwarding round */
   uint32_t A[3], B[3];
@@ -441,7 +454,7 @@ static bsh compare_one(const uint16_t d[3], const uint16_t x[3], const crand* rn
     if (ml_lift) ml_lift[p] = ml[p];
     if (y_out) y_out[p] = y[p];
   }
-  bit_extract(y, MSB_M, MSB_G0, d_inj, rnd, r, cnt);
+  bit_extract(y, MSB_M, MSB_W0, d_inj, rnd, r, cnt);
   return r[31];
 }
 
@@ -450,15 +463,16 @@ static bsh compare_one(const uint16_t d[3], const uint16_t x[3], const crand* rn
  * a word belongs to the comparison at offset o in the group.  A k-bit value
  * takes its bit j from word (base + j). */
 static void gather_rand(const uint64_t tape[3][TAPE_WORDS], int o, crand* rnd) {
-  for (int g = 0; g < N_GATES; ++g)
-    for (int k = 0; k < 3; ++k) rnd->g[g][k] = (uint8_t)((tape[k][g] >> o) & 1u);
+  for (int w = 0; w < N_GATE_WORDS; ++w)
+    for (int k = 0; k < 3; ++k) rnd->g[w][k] = (uint8_t)((tape[k][w] >> o) & 1u);
   const int kk[2] = {INJ_A_K, INJ_B_K};
-  const int bc[2] = {TAPE_C_A, TAPE_C_B}, bw0[2] = {TAPE_W0_A, TAPE_W0_B}, bw1[2] = {TAPE_W1_A, TAPE_W1_B};
+  const int bc0[2] = {TAPE_C0_A, TAPE_C0_B}, bc2[2] = {TAPE_C2_A, TAPE_C2_B};
+  const int bw0[2] = {TAPE_W0_A, TAPE_W0_B}, bw1[2] = {TAPE_W1_A, TAPE_W1_B};
   for (int v = 0; v < 2; ++v) {
     uint32_t c0 = 0, c2 = 0, w0 = 0, w1 = 0;
     for (int j = 0; j < kk[v]; ++j) {
-      c0 |= (uint32_t)((tape[0][bc[v] + j] >> o) & 1u) << j;
-      c2 |= (uint32_t)((tape[2][bc[v] + j] >> o) & 1u) << j;
+      c0 |= (uint32_t)((tape[0][bc0[v] + j] >> o) & 1u) << j;
+      c2 |= (uint32_t)((tape[2][bc2[v] + j] >> o) & 1u) << j;
       w0 |= (uint32_t)((tape[2][bw0[v] + j] >> o) & 1u) << j;
       w1 |= (uint32_t)((tape[2][bw1[v] + j] >> o) & 1u) << j;
     }
@@ -605,8 +619,8 @@ static uint64_t sm64(uint64_t* s) {
 }
 
 static void random_crand(uint64_t* s, crand* rnd) {
-  for (int g = 0; g < N_GATES; ++g)
-    for (int k = 0; k < 3; ++k) rnd->g[g][k] = (uint8_t)(sm64(s) & 1u);
+  for (int w = 0; w < N_GATE_WORDS; ++w)
+    for (int k = 0; k < 3; ++k) rnd->g[w][k] = (uint8_t)(sm64(s) & 1u);
   for (int v = 0; v < 2; ++v) {
     rnd->c0[v] = (uint32_t)sm64(s); rnd->c2[v] = (uint32_t)sm64(s);
     rnd->w0[v] = (uint32_t)sm64(s); rnd->w1[v] = (uint32_t)sm64(s);

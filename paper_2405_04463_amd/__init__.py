@@ -1,0 +1,238 @@
+"""Python binding of libirismpc.so (the C ABI in include/irismpc.h).
+
+Argument marshalling only: every step of the protocol runs in the library's
+HIP kernels.  Device buffers are passed as torch CUDA tensors (used for their
+memory and streams) or raw integer addresses.  The library must have been
+built (``python -m paper_2405_04463_amd.build``); if it is missing this
+module raises at first use instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libirismpc.so")
+
+IMC_OK, IMC_EINVAL, IMC_ESHAPE, IMC_ENOMEM, IMC_EDEVICE, IMC_ECORRUPT, IMC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+OPEN_U8_XOR, OPEN_U64_XOR, OPEN_U16_ADD, OPEN_U32_ADD = 0, 1, 2, 3
+CODE_BITS, CODE_WORDS, MAX_ROT, ENTRY_BYTES = 12800, 200, 32, 102400
+
+EXPORTS = [
+    "imc_create", "imc_destroy", "imc_strerror", "imc_db_bytes", "imc_query_op_bytes", "imc_query_raw_bytes",
+    "imc_or_tree_ws_bytes", "imc_share_db", "imc_share_query", "imc_dot_shares", "imc_reshare",
+    "imc_compare_threshold", "imc_or_tree", "imc_open", "imc_append_db",
+]
+
+
+class IMCError(RuntimeError):
+    def __init__(self, status: int, call: str):
+        self.status = status
+        super().__init__(f"{call}: {status} ({_strerror(status)})")
+
+
+class imc_params(ctypes.Structure):
+    _fields_ = [
+        ("code_bits", ctypes.c_uint32),
+        ("thr_a", ctypes.c_uint32),
+        ("max_rows", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("dealer_key", ctypes.c_uint8 * 32),
+        ("party_key", (ctypes.c_uint8 * 32) * 3),
+    ]
+
+
+class imc_ids(ctypes.Structure):
+    _fields_ = [
+        ("query_id_base", ctypes.c_uint64),
+        ("first_entry_id", ctypes.c_uint64),
+        ("r", ctypes.c_int32),
+        ("rot", ctypes.c_int8 * MAX_ROT),
+    ]
+
+
+_VP = ctypes.c_void_p
+_P3 = _VP * 3
+_lib = None
+
+
+def lib():
+    """Load libirismpc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2405_04463_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        sz = ctypes.c_size_t
+        st = ctypes.c_int
+        L.imc_create.argtypes = [ctypes.POINTER(imc_params), ctypes.c_int, ctypes.POINTER(_VP)]
+        L.imc_destroy.argtypes = [_VP]
+        L.imc_destroy.restype = None
+        L.imc_strerror.argtypes = [st]
+        L.imc_strerror.restype = ctypes.c_char_p
+        for f in ("imc_db_bytes", "imc_query_op_bytes", "imc_query_raw_bytes"):
+            getattr(L, f).argtypes = [sz]
+            getattr(L, f).restype = sz
+        L.imc_or_tree_ws_bytes.argtypes = [sz, sz, sz]
+        L.imc_or_tree_ws_bytes.restype = sz
+        L.imc_share_db.argtypes = [_VP, _VP, _VP, sz, ctypes.c_uint64, _P3, sz, _VP]
+        L.imc_share_query.argtypes = [_VP, _VP, _VP, sz, ctypes.c_uint64, _P3, _VP, _VP]
+        L.imc_dot_shares.argtypes = [_VP, ctypes.c_int, _VP, sz, ctypes.POINTER(imc_ids), _VP, sz, sz, _VP, _VP, sz, _VP]
+        L.imc_reshare.argtypes = [_VP, _P3, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _P3, _P3, _P3, _VP]
+        L.imc_compare_threshold.argtypes = [_VP, _P3, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _P3, sz, _VP]
+        L.imc_or_tree.argtypes = [_VP, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, sz, _P3, _VP]
+        L.imc_open.argtypes = [_VP, ctypes.c_int, _P3, sz, _VP, ctypes.c_int, _VP]
+        L.imc_append_db.argtypes = [_VP, _P3, sz, _P3, sz, ctypes.c_uint64, _VP]
+        for f in EXPORTS:
+            if f not in ("imc_destroy", "imc_strerror") and not f.endswith("_bytes"):
+                getattr(L, f).restype = st
+        _lib = L
+    return _lib
+
+
+def _strerror(s: int) -> str:
+    try:
+        return lib().imc_strerror(s).decode()
+    except Exception:  # noqa: BLE001 - message only
+        return "?"
+
+
+def _check(status: int, call: str) -> int:
+    if status != IMC_OK:
+        raise IMCError(status, call)
+    return status
+
+
+def addr(t) -> int:
+    """Device address of a tensor (or an int address passed through)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _p3(ts):
+    return _P3(*[addr(t) for t in ts])
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def make_ids(query_id_base: int, rot, first_entry_id: int = 0) -> imc_ids:
+    ids = imc_ids()
+    ids.query_id_base = query_id_base
+    ids.first_entry_id = first_entry_id
+    ids.r = len(rot)
+    for i, s in enumerate(rot):
+        ids.rot[i] = int(s)
+    return ids
+
+
+# ---- sizes -------------------------------------------------------------
+def db_bytes(capacity: int) -> int:
+    return lib().imc_db_bytes(capacity)
+
+
+def query_op_bytes(q: int) -> int:
+    return lib().imc_query_op_bytes(q)
+
+
+def query_raw_bytes(q: int) -> int:
+    return lib().imc_query_raw_bytes(q)
+
+
+def or_tree_ws_bytes(q: int, r: int, nw: int) -> int:
+    return lib().imc_or_tree_ws_bytes(q, r, nw)
+
+
+@dataclass
+class Keys:
+    dealer: bytes
+    party: bytes   # 3 x 32 bytes
+
+
+class Context:
+    """An imc_ctx on one device; methods mirror the C calls one to one."""
+
+    def __init__(self, keys: Keys, max_rows: int, device: int = 0):
+        p = imc_params()
+        p.code_bits = CODE_BITS
+        p.thr_a = 16384
+        p.max_rows = max_rows
+        p.flags = 0
+        assert len(keys.dealer) == 32 and len(keys.party) == 96
+        for i in range(32):
+            p.dealer_key[i] = keys.dealer[i]
+        for k in range(3):
+            for i in range(32):
+                p.party_key[k][i] = keys.party[32 * k + i]
+        h = _VP()
+        _check(lib().imc_create(ctypes.byref(p), device, ctypes.byref(h)), "imc_create")
+        self._h = h
+        self.device = device
+        self.max_rows = max_rows
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().imc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    # -- imc_share_db
+    def share_db(self, codes, masks, n, first_entry_id, db3, capacity, stream=None):
+        return _check(lib().imc_share_db(self._h, addr(codes), addr(masks), n, first_entry_id, _p3(db3), capacity,
+                                         _stream(stream)), "imc_share_db")
+
+    # -- imc_share_query
+    def share_query(self, codes, masks, q, query_id_base, qop3, qraw3=None, stream=None):
+        raw = _p3(qraw3) if qraw3 is not None else None
+        return _check(lib().imc_share_query(self._h, addr(codes), addr(masks), q, query_id_base, _p3(qop3),
+                                            ctypes.cast(raw, _VP) if raw is not None else None, _stream(stream)),
+                      "imc_share_query")
+
+    # -- imc_dot_shares
+    def dot_shares(self, party, qop, q, ids: imc_ids, db, capacity, n, code_dot, mask_dot, ld, stream=None):
+        return _check(lib().imc_dot_shares(self._h, party, addr(qop), q, ctypes.byref(ids), addr(db), capacity, n,
+                                           addr(code_dot), addr(mask_dot), ld, _stream(stream)), "imc_dot_shares")
+
+    # -- imc_reshare
+    def reshare(self, add_code3, add_mask3, rows, n, ld, ids: imc_ids, msg3, rep_code3, rep_mask3, stream=None):
+        return _check(lib().imc_reshare(self._h, _p3(add_code3), _p3(add_mask3), rows, n, ld, ctypes.byref(ids),
+                                        _p3(msg3), _p3(rep_code3), _p3(rep_mask3), _stream(stream)), "imc_reshare")
+
+    # -- imc_compare_threshold
+    def compare_threshold(self, rep_code3, rep_mask3, rows, n, ld, ids: imc_ids, match3, mw_ld, stream=None):
+        return _check(lib().imc_compare_threshold(self._h, _p3(rep_code3), _p3(rep_mask3), rows, n, ld,
+                                                  ctypes.byref(ids), _p3(match3), mw_ld, _stream(stream)),
+                      "imc_compare_threshold")
+
+    # -- imc_or_tree
+    def or_tree(self, match3, q, nw, mw_ld, ids: imc_ids, ws, ws_bytes, dup3, stream=None):
+        return _check(lib().imc_or_tree(self._h, _p3(match3), q, nw, mw_ld, ctypes.byref(ids), addr(ws), ws_bytes,
+                                        _p3(dup3), _stream(stream)), "imc_or_tree")
+
+    # -- imc_open (returns the status: IMC_ECORRUPT is reported, not raised)
+    def open(self, kind, rep3, count, out, check=0, stream=None):
+        s = lib().imc_open(self._h, kind, _p3(rep3), count, addr(out), int(check), _stream(stream))
+        if s not in (IMC_OK, IMC_ECORRUPT):
+            raise IMCError(s, "imc_open")
+        return s
+
+    # -- imc_append_db
+    def append_db(self, qraw3, qi, db3, capacity, entry_id, stream=None):
+        return _check(lib().imc_append_db(self._h, _p3(qraw3), qi, _p3(db3), capacity, entry_id, _stream(stream)),
+                      "imc_append_db")

@@ -1,0 +1,271 @@
+// api.cpp -- the C ABI (include/irismpc.h): argument checks, the context and
+// its scratch, and dispatch to the kernels.  Every argument error is found
+// here, before anything is enqueued.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "../../include/irismpc.h"
+#include "device.h"
+#include "launch.h"
+
+struct imc_ctx {
+  int device;
+  imc::Key dealer;
+  imc::Keys3 party;
+  uint32_t max_rows;
+  int8_t* rot_op;                 // rotated query operand, max_rows (rounded to 32) rows
+  size_t rot_op_bytes;
+  unsigned long long* bad;        // open-check counter
+};
+
+namespace {
+
+imc::Key load_key(const uint8_t* b) {
+  imc::Key k;
+  for (int i = 0; i < 8; ++i)
+    k.w[i] = uint32_t(b[4 * i]) | (uint32_t(b[4 * i + 1]) << 8) | (uint32_t(b[4 * i + 2]) << 16) |
+             (uint32_t(b[4 * i + 3]) << 24);
+  return k;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+imc_status dev_status(hipError_t e) { return e == hipSuccess ? IMC_OK : IMC_EDEVICE; }
+
+// Make the context's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) return;
+    ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (ok && hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+imc_status check_ids(const imc_ids* ids) {
+  if (!ids) return IMC_EINVAL;
+  if (ids->r < 1 || ids->r > IMC_MAX_ROT) return IMC_EINVAL;
+  for (int i = 0; i < ids->r; ++i)
+    if (ids->rot[i] < -15 || ids->rot[i] > 15) return IMC_EINVAL;
+  if (ids->first_entry_id % 64) return IMC_EINVAL;
+  if (ids->query_id_base >= (1ull << 48)) return IMC_EINVAL;
+  return IMC_OK;
+}
+
+size_t blocks_for(size_t capacity) { return (capacity + 31) / 32; }
+
+}  // namespace
+
+extern "C" {
+
+const char* imc_strerror(imc_status s) {
+  switch (s) {
+    case IMC_OK: return "ok";
+    case IMC_EINVAL: return "invalid argument";
+    case IMC_ESHAPE: return "inconsistent sizes";
+    case IMC_ENOMEM: return "out of device memory";
+    case IMC_EDEVICE: return "HIP error";
+    case IMC_ECORRUPT: return "components of a sharing disagree";
+    case IMC_EUNSUPPORTED: return "unsupported parameter";
+    default: return "unknown status";
+  }
+}
+
+size_t imc_db_bytes(size_t capacity) { return blocks_for(capacity) * imc::kBlockBytes; }
+size_t imc_query_op_bytes(size_t q) { return q * imc::kQopRowBytes; }
+size_t imc_query_raw_bytes(size_t q) { return q * 2 * 2 * imc::kCodeBits * sizeof(uint16_t); }
+size_t imc_or_tree_ws_bytes(size_t q, size_t r, size_t nw) { return imc::or_tree_ws_bytes(q, r, nw); }
+
+imc_status imc_create(const imc_params* p, int device, imc_ctx** out) {
+  if (!p || !out) return IMC_EINVAL;
+  *out = nullptr;
+  if (p->code_bits != IMC_CODE_BITS || p->thr_a != 16384u || p->flags != 0) return IMC_EUNSUPPORTED;
+  if (p->max_rows == 0) return IMC_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess) return IMC_EDEVICE;
+  if (device < 0 || device >= ndev) return IMC_EINVAL;
+  DeviceGuard g(device);
+  if (!g.ok) return IMC_EDEVICE;
+  imc_ctx* c = new (std::nothrow) imc_ctx();
+  if (!c) return IMC_ENOMEM;
+  c->device = device;
+  c->dealer = load_key(p->dealer_key);
+  for (int k = 0; k < 3; ++k) c->party.k[k] = load_key(p->party_key[k]);
+  c->max_rows = p->max_rows;
+  c->rot_op_bytes = blocks_for(p->max_rows) * imc::kBlockBytes;
+  if (hipMalloc(reinterpret_cast<void**>(&c->rot_op), c->rot_op_bytes) != hipSuccess) {
+    delete c;
+    return IMC_ENOMEM;
+  }
+  if (hipMalloc(reinterpret_cast<void**>(&c->bad), sizeof(unsigned long long)) != hipSuccess) {
+    (void)hipFree(c->rot_op);
+    delete c;
+    return IMC_ENOMEM;
+  }
+  *out = c;
+  return IMC_OK;
+}
+
+void imc_destroy(imc_ctx* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(c->rot_op);
+  (void)hipFree(c->bad);
+  delete c;
+}
+
+imc_status imc_share_db(imc_ctx* c, const uint64_t* codes, const uint64_t* masks, size_t n, uint64_t first,
+                        void* const db[3], size_t capacity, imc_stream stream) {
+  if (!c || !db) return IMC_EINVAL;
+  if (n && (!codes || !masks)) return IMC_EINVAL;
+  for (int p = 0; p < 3; ++p)
+    if (!db[p] || !aligned(db[p], 256)) return IMC_EINVAL;
+  if (!aligned(codes, 8) || !aligned(masks, 8)) return IMC_EINVAL;
+  if (first > capacity || n > capacity - first) return IMC_ESHAPE;
+  if (first + n > (1ull << 48)) return IMC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  uint8_t* d[3] = {static_cast<uint8_t*>(db[0]), static_cast<uint8_t*>(db[1]), static_cast<uint8_t*>(db[2])};
+  return dev_status(imc::launch_share_db(c->dealer, codes, masks, n, first, d, hipStream_t(stream)));
+}
+
+imc_status imc_share_query(imc_ctx* c, const uint64_t* codes, const uint64_t* masks, size_t q, uint64_t qid_base,
+                           void* const qop[3], void* const qraw[3], imc_stream stream) {
+  if (!c || !qop) return IMC_EINVAL;
+  if (q && (!codes || !masks)) return IMC_EINVAL;
+  if (!aligned(codes, 8) || !aligned(masks, 8)) return IMC_EINVAL;
+  for (int p = 0; p < 3; ++p) {
+    if (!qop[p] || !aligned(qop[p], 16)) return IMC_EINVAL;
+    if (qraw && (!qraw[p] || !aligned(qraw[p], 16))) return IMC_EINVAL;
+  }
+  if (qid_base + q > (1ull << 48)) return IMC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  int8_t* op[3] = {static_cast<int8_t*>(qop[0]), static_cast<int8_t*>(qop[1]), static_cast<int8_t*>(qop[2])};
+  uint16_t* raw[3] = {nullptr, nullptr, nullptr};
+  if (qraw)
+    for (int p = 0; p < 3; ++p) raw[p] = static_cast<uint16_t*>(qraw[p]);
+  return dev_status(imc::launch_share_query(c->dealer, codes, masks, q, qid_base, op, qraw ? raw : nullptr,
+                                            hipStream_t(stream)));
+}
+
+imc_status imc_dot_shares(imc_ctx* c, int party, const void* qop, size_t q, const imc_ids* ids, const void* db,
+                          size_t capacity, size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
+                          imc_stream stream) {
+  if (!c || party < 0 || party > 2) return IMC_EINVAL;
+  imc_status st = check_ids(ids);
+  if (st != IMC_OK) return st;
+  const size_t rows = q * size_t(ids->r);
+  if (rows == 0 || n == 0) return IMC_OK;
+  if (!qop || !db || !code_dot || !mask_dot) return IMC_EINVAL;
+  if (!aligned(qop, 16) || !aligned(db, 256) || !aligned(code_dot, 2) || !aligned(mask_dot, 2)) return IMC_EINVAL;
+  if (rows > c->max_rows) return IMC_ESHAPE;
+  if (ld < n) return IMC_ESHAPE;
+  if (ids->first_entry_id > capacity || n > capacity - ids->first_entry_id) return IMC_ESHAPE;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  const uint32_t rows_pad = uint32_t(blocks_for(rows) * 32);
+  hipError_t e = imc::launch_expand(static_cast<const int8_t*>(qop), uint32_t(q), uint32_t(ids->r), ids->rot,
+                                    c->rot_op, rows_pad, hipStream_t(stream));
+  if (e != hipSuccess) return IMC_EDEVICE;
+  e = imc::launch_dot(c->rot_op, uint32_t(rows), rows_pad / 32, static_cast<const int8_t*>(db), ids->first_entry_id,
+                      n, code_dot, mask_dot, ld, hipStream_t(stream));
+  return dev_status(e);
+}
+
+imc_status imc_reshare(imc_ctx* c, const uint16_t* const add_code[3], const uint16_t* const add_mask[3], size_t rows,
+                       size_t n, size_t ld, const imc_ids* ids, uint16_t* const msg[3], uint16_t* const rep_code[3],
+                       uint16_t* const rep_mask[3], imc_stream stream) {
+  if (!c || !add_code || !add_mask || !msg || !rep_code || !rep_mask) return IMC_EINVAL;
+  imc_status st = check_ids(ids);
+  if (st != IMC_OK) return st;
+  if (rows % size_t(ids->r)) return IMC_ESHAPE;
+  if (ld < n) return IMC_ESHAPE;
+  if (rows == 0 || n == 0) return IMC_OK;
+  for (int p = 0; p < 3; ++p)
+    if (!add_code[p] || !add_mask[p] || !msg[p] || !rep_code[p] || !rep_mask[p]) return IMC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  return dev_status(
+      imc::launch_reshare(c->party, add_code, add_mask, rows, n, ld, *ids, msg, rep_code, rep_mask, hipStream_t(stream)));
+}
+
+imc_status imc_compare_threshold(imc_ctx* c, const uint16_t* const rep_code[3], const uint16_t* const rep_mask[3],
+                                 size_t rows, size_t n, size_t ld, const imc_ids* ids, uint64_t* const match[3],
+                                 size_t mw_ld, imc_stream stream) {
+  if (!c || !rep_code || !rep_mask || !match) return IMC_EINVAL;
+  imc_status st = check_ids(ids);
+  if (st != IMC_OK) return st;
+  if (rows % size_t(ids->r)) return IMC_ESHAPE;
+  if (ld < n || mw_ld < (n + 63) / 64) return IMC_ESHAPE;
+  if (rows == 0 || n == 0) return IMC_OK;
+  for (int p = 0; p < 3; ++p) {
+    if (!rep_code[p] || !rep_mask[p] || !match[p]) return IMC_EINVAL;
+    if (!aligned(rep_code[p], 2) || !aligned(rep_mask[p], 2) || !aligned(match[p], 8)) return IMC_EINVAL;
+  }
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  return dev_status(imc::launch_compare(c->party, rep_code, rep_mask, rows, n, ld, *ids, match, mw_ld,
+                                        hipStream_t(stream)));
+}
+
+imc_status imc_or_tree(imc_ctx* c, const uint64_t* const match[3], size_t q, size_t nw, size_t mw_ld,
+                       const imc_ids* ids, void* ws, size_t ws_bytes, uint8_t* const dup[3], imc_stream stream) {
+  if (!c || !match || !dup) return IMC_EINVAL;
+  imc_status st = check_ids(ids);
+  if (st != IMC_OK) return st;
+  if (q == 0) return IMC_OK;
+  if (nw == 0 || mw_ld < nw) return IMC_ESHAPE;
+  if (ws_bytes < imc::or_tree_ws_bytes(q, size_t(ids->r), nw)) return IMC_ESHAPE;
+  const size_t len0 = size_t(ids->r) * nw;
+  if (len0 > 1 && (!ws || !aligned(ws, 8))) return IMC_EINVAL;
+  for (int p = 0; p < 3; ++p)
+    if (!match[p] || !dup[p] || !aligned(match[p], 8)) return IMC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  return dev_status(imc::launch_or_tree(c->party, match, q, nw, mw_ld, *ids, ws, dup, hipStream_t(stream)));
+}
+
+imc_status imc_open(imc_ctx* c, int kind, const void* const rep[3], size_t count, void* out, int check,
+                    imc_stream stream) {
+  if (!c || !rep || kind < IMC_OPEN_U8_XOR || kind > IMC_OPEN_U32_ADD) return IMC_EINVAL;
+  if (count == 0) return IMC_OK;
+  static const size_t width[4] = {1, 8, 2, 4};
+  if (!out || !aligned(out, width[kind])) return IMC_EINVAL;
+  for (int p = 0; p < 3; ++p)
+    if (!rep[p] || !aligned(rep[p], width[kind])) return IMC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  hipStream_t s = hipStream_t(stream);
+  if (imc::launch_open(kind, rep, count, out, check, c->bad, s) != hipSuccess) return IMC_EDEVICE;
+  if (!check) return IMC_OK;
+  unsigned long long bad = 0;
+  if (hipMemcpyAsync(&bad, c->bad, sizeof bad, hipMemcpyDeviceToHost, s) != hipSuccess) return IMC_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return IMC_EDEVICE;
+  return bad ? IMC_ECORRUPT : IMC_OK;
+}
+
+imc_status imc_append_db(imc_ctx* c, const void* const qraw[3], size_t qi, void* const db[3], size_t capacity,
+                         uint64_t entry_id, imc_stream stream) {
+  if (!c || !qraw || !db) return IMC_EINVAL;
+  for (int p = 0; p < 3; ++p) {
+    if (!qraw[p] || !db[p] || !aligned(db[p], 256) || !aligned(qraw[p], 2)) return IMC_EINVAL;
+  }
+  if (entry_id >= capacity) return IMC_ESHAPE;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  const uint16_t* raw[3] = {static_cast<const uint16_t*>(qraw[0]), static_cast<const uint16_t*>(qraw[1]),
+                            static_cast<const uint16_t*>(qraw[2])};
+  uint8_t* d[3] = {static_cast<uint8_t*>(db[0]), static_cast<uint8_t*>(db[1]), static_cast<uint8_t*>(db[2])};
+  return dev_status(imc::launch_append(raw, qi, d, entry_id, hipStream_t(stream)));
+}
+
+}  // extern "C"

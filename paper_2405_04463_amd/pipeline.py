@@ -1,0 +1,128 @@
+"""Buffers and the call sequence of one uniqueness check (Alg. 3) on one GPU.
+
+Allocation and sequencing only; all arithmetic is in the library's kernels:
+  share_db / share_query -> dot_shares (each party) -> reshare ->
+  compare_threshold -> or_tree -> open
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import (OPEN_U8_XOR, OPEN_U16_ADD, OPEN_U64_XOR, Context, db_bytes, make_ids, or_tree_ws_bytes,
+               query_op_bytes, query_raw_bytes)
+
+ROW_BYTES = 102400
+
+
+def _dev(device):
+    return torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+
+
+class SharedDB:
+    """The three parties' database regions (one device buffer each)."""
+
+    def __init__(self, ctx: Context, capacity: int, device=0):
+        self.ctx = ctx
+        self.capacity = capacity
+        self.n = 0
+        nb = db_bytes(capacity)
+        self.regions = [torch.empty(nb, dtype=torch.uint8, device=_dev(device)) for _ in range(3)]
+
+    def enroll(self, codes, masks, first: int | None = None, stream=None):
+        """Share packed device codes/masks [n, 200] (uint64 as int64) into slots first.."""
+        n = codes.shape[0]
+        first = self.n if first is None else first
+        self.ctx.share_db(codes, masks, n, first, self.regions, self.capacity, stream)
+        self.n = max(self.n, first + n)
+        return first
+
+    def append(self, qs: "SharedQueries", qi: int, stream=None) -> int:
+        e = self.n
+        self.ctx.append_db(qs.raw, qi, self.regions, self.capacity, e, stream)
+        self.n += 1
+        return e
+
+
+class SharedQueries:
+    """Shares of q queries: each party's dot operand and raw shares."""
+
+    def __init__(self, ctx: Context, codes, masks, query_id_base: int, device=0, keep_raw: bool = True, stream=None):
+        self.q = codes.shape[0]
+        self.qid_base = query_id_base
+        d = _dev(device)
+        self.op = [torch.empty(max(1, query_op_bytes(self.q)), dtype=torch.uint8, device=d) for _ in range(3)]
+        self.raw = ([torch.empty(max(1, query_raw_bytes(self.q)) // 2, dtype=torch.int16, device=d) for _ in range(3)]
+                    if keep_raw else None)
+        ctx.share_query(codes, masks, self.q, query_id_base, self.op, self.raw, stream)
+
+
+@dataclass
+class CheckBuffers:
+    rows: int
+    n: int
+    ld: int
+    nw: int
+    dot_code: list
+    dot_mask: list
+    msg: list
+    rep_code: list
+    rep_mask: list
+    match: list
+    dup: list
+    ws: torch.Tensor
+
+
+def alloc_check(q: int, r: int, n: int, device=0) -> CheckBuffers:
+    d = _dev(device)
+    rows = q * r
+    ld = ((n + 63) // 64) * 64
+    nw = ld // 64
+    u16 = lambda *s: torch.empty(*s, dtype=torch.int16, device=d)  # noqa: E731
+    return CheckBuffers(
+        rows=rows, n=n, ld=ld, nw=nw,
+        dot_code=[u16(rows, ld) for _ in range(3)],
+        dot_mask=[u16(rows, ld) for _ in range(3)],
+        msg=[u16(2, rows, ld) for _ in range(3)],
+        rep_code=[u16(2, rows, ld) for _ in range(3)],
+        rep_mask=[u16(2, rows, ld) for _ in range(3)],
+        match=[torch.empty(2, rows, nw, dtype=torch.int64, device=d) for _ in range(3)],
+        dup=[torch.empty(2, q, dtype=torch.uint8, device=d) for _ in range(3)],
+        ws=torch.empty(max(8, or_tree_ws_bytes(q, r, nw)), dtype=torch.uint8, device=d),
+    )
+
+
+def run_check(ctx: Context, qs: SharedQueries, rot, db: SharedDB, first_entry: int, n: int, buf: CheckBuffers,
+              or_tree: bool = True, stream=None):
+    """Alg. 3 for queries qs at rotations rot against entries first_entry..+n."""
+    ids = make_ids(qs.qid_base, rot, first_entry)
+    for p in range(3):
+        ctx.dot_shares(p, qs.op[p], qs.q, ids, db.regions[p], db.capacity, n, buf.dot_code[p], buf.dot_mask[p],
+                       buf.ld, stream)
+    ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, n, buf.ld, ids, buf.msg, buf.rep_code, buf.rep_mask, stream)
+    ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, n, buf.ld, ids, buf.match, buf.nw, stream)
+    if or_tree:
+        nw = (n + 63) // 64
+        ctx.or_tree(buf.match, qs.q, nw, buf.nw, ids, buf.ws, buf.ws.numel(), buf.dup, stream)
+    return ids
+
+
+def open_dup(ctx: Context, buf: CheckBuffers, q: int, check: int = 1, stream=None):
+    out = torch.empty(q, dtype=torch.uint8, device=buf.dup[0].device)
+    s = ctx.open(OPEN_U8_XOR, buf.dup, q, out, check, stream)
+    return out, s
+
+
+def open_match(ctx: Context, buf: CheckBuffers, check: int = 1, stream=None):
+    out = torch.empty(buf.rows, buf.nw, dtype=torch.int64, device=buf.match[0].device)
+    s = ctx.open(OPEN_U64_XOR, buf.match, buf.rows * buf.nw, out, check, stream)
+    return out, s
+
+
+def open_dots(ctx: Context, buf: CheckBuffers, check: int = 1, stream=None):
+    outc = torch.empty(buf.rows, buf.ld, dtype=torch.int16, device=buf.rep_code[0].device)
+    outm = torch.empty_like(outc)
+    s1 = ctx.open(OPEN_U16_ADD, buf.rep_code, buf.rows * buf.ld, outc, check, stream)
+    s2 = ctx.open(OPEN_U16_ADD, buf.rep_mask, buf.rows * buf.ld, outm, check, stream)
+    return outc, outm, (s1, s2)
