@@ -58,6 +58,12 @@ typedef int imc_status;
 #define IMC_MAX_ROT 32         /* rotations per query in one call */
 #define IMC_ENTRY_BYTES 102400 /* one party's database bytes per entry */
 
+/* Tile configurations of the dot-product kernel (imc_params.flags bits 0-3). */
+#define IMC_DOT_TILES_256x128_W8 0   /* 256 rows x 128 entries, 8 waves of 64 x 64 (default) */
+#define IMC_DOT_TILES_256x128_W4 1   /* 256 x 128, 4 waves of 128 x 64 */
+#define IMC_DOT_TILES_128x128_W4 2   /* 128 x 128, 4 waves of 64 x 64 */
+#define IMC_DOT_TILES_MAX 2
+
 /* Stream handle: a hipStream_t (NULL = the default stream). */
 typedef struct ihipStream_t* imc_stream;
 
@@ -68,7 +74,8 @@ typedef struct imc_params {
   uint32_t thr_a;              /* threshold a with b = 2^16, 1 - 2*MATCH_RATIO = a/b (Sec. 5);
                                   must be 16384 (MATCH_RATIO = 3/8) */
   uint32_t max_rows;           /* largest q*r any dot_shares call uses (sizes internal scratch) */
-  uint32_t flags;              /* reserved, must be 0 */
+  uint32_t flags;              /* bits 0-3: dot-product tile configuration (IMC_DOT_TILES_*);
+                                  other bits reserved, must be 0 */
   uint8_t dealer_key[32];      /* key of the input dealer's sharing PRF */
   uint8_t party_key[3][32];    /* key_p of party p; the paper's seed_{p+1} (App. D) */
 } imc_params;

@@ -163,12 +163,12 @@ class Keys:
 class Context:
     """An imc_ctx on one device; methods mirror the C calls one to one."""
 
-    def __init__(self, keys: Keys, max_rows: int, device: int = 0):
+    def __init__(self, keys: Keys, max_rows: int, device: int = 0, dot_tiles: int = 0):
         p = imc_params()
         p.code_bits = CODE_BITS
         p.thr_a = 16384
         p.max_rows = max_rows
-        p.flags = 0
+        p.flags = dot_tiles
         assert len(keys.dealer) == 32 and len(keys.party) == 96
         for i in range(32):
             p.dealer_key[i] = keys.dealer[i]

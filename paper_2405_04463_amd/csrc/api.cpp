@@ -16,6 +16,7 @@ struct imc_ctx {
   imc::Key dealer;
   imc::Keys3 party;
   uint32_t max_rows;
+  int dot_variant;                // dot kernel tile configuration (params->flags & 0xF)
   int8_t* rot_op;                 // rotated query operand, max_rows (rounded to 32) rows
   size_t rot_op_bytes;
   unsigned long long* bad;        // open-check counter
@@ -86,7 +87,8 @@ size_t imc_or_tree_ws_bytes(size_t q, size_t r, size_t nw) { return imc::or_tree
 imc_status imc_create(const imc_params* p, int device, imc_ctx** out) {
   if (!p || !out) return IMC_EINVAL;
   *out = nullptr;
-  if (p->code_bits != IMC_CODE_BITS || p->thr_a != 16384u || p->flags != 0) return IMC_EUNSUPPORTED;
+  if (p->code_bits != IMC_CODE_BITS || p->thr_a != 16384u) return IMC_EUNSUPPORTED;
+  if ((p->flags & ~0xFu) != 0 || (p->flags & 0xFu) > IMC_DOT_TILES_MAX) return IMC_EUNSUPPORTED;
   if (p->max_rows == 0) return IMC_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess) return IMC_EDEVICE;
@@ -99,6 +101,7 @@ imc_status imc_create(const imc_params* p, int device, imc_ctx** out) {
   c->dealer = load_key(p->dealer_key);
   for (int k = 0; k < 3; ++k) c->party.k[k] = load_key(p->party_key[k]);
   c->max_rows = p->max_rows;
+  c->dot_variant = int(p->flags & 0xFu);
   c->rot_op_bytes = blocks_for(p->max_rows) * imc::kBlockBytes;
   if (hipMalloc(reinterpret_cast<void**>(&c->rot_op), c->rot_op_bytes) != hipSuccess) {
     delete c;
@@ -177,7 +180,7 @@ imc_status imc_dot_shares(imc_ctx* c, int party, const void* qop, size_t q, cons
                                     c->rot_op, rows_pad, hipStream_t(stream));
   if (e != hipSuccess) return IMC_EDEVICE;
   e = imc::launch_dot(c->rot_op, uint32_t(rows), rows_pad / 32, static_cast<const int8_t*>(db), ids->first_entry_id,
-                      n, code_dot, mask_dot, ld, hipStream_t(stream));
+                      n, code_dot, mask_dot, ld, hipStream_t(stream), c->dot_variant);
   return dev_status(e);
 }
 

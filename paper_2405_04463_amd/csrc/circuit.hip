@@ -312,6 +312,32 @@ struct ReshareArgs {
   int8_t rot[IMC_MAX_ROT_DEV];
 };
 
+__device__ __forceinline__ void ld16(const uint16_t* p, int nval, bool vec, uint16_t v[16]) {
+  if (vec && nval == 16) {
+    const uint4 a = reinterpret_cast<const uint4*>(p)[0], b = reinterpret_cast<const uint4*>(p)[1];
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = uint16_t((j & 1) ? (w[j >> 1] >> 16) : (w[j >> 1] & 0xFFFF));
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = j < nval ? p[j] : 0;
+  }
+}
+
+__device__ __forceinline__ void st16(uint16_t* p, int nval, bool vec, const uint16_t v[16]) {
+  if (vec && nval == 16) {
+    uint32_t w[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) w[j] = uint32_t(v[2 * j]) | (uint32_t(v[2 * j + 1]) << 16);
+    reinterpret_cast<uint4*>(p)[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    reinterpret_cast<uint4*>(p)[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (j < nval) p[j] = v[j];
+  }
+}
+
 __global__ void __launch_bounds__(256) reshare_kernel(ReshareArgs a) {
   const uint64_t nc = (a.n + 15) / 16;
   const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -321,34 +347,38 @@ __global__ void __launch_bounds__(256) reshare_kernel(ReshareArgs a) {
   const int rot = a.rot[row % uint64_t(a.r)];
   const uint64_t stream = row_stream(kDomReshare, qid, rot);
   const uint64_t e0 = a.first_entry + 16 * c;
-  uint32_t F[3][16];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) chacha12(a.keys.k[k], stream, e0 >> 4, F[k]);
   const uint64_t col0 = 16 * c;
   const int nval = int(min<uint64_t>(16, a.n - col0));
   const uint64_t off = row * a.ld + col0;
+  const bool vec = (a.ld % 8) == 0;
+  uint16_t zc[3][16], zm[3][16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    if (j >= nval) continue;
-    uint16_t zc[3], zm[3];
+  for (int p = 0; p < 3; ++p) {
+    ld16(a.add_code[p] + off, nval, vec, zc[p]);
+    ld16(a.add_mask[p] + off, nval, vec, zm[p]);
+  }
+  uint32_t F[3][16];
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      const int pm = (p + 2) % 3;
-      const uint16_t ac = uint16_t((F[p][j] & 0xFFFFu) - (F[pm][j] & 0xFFFFu));
-      const uint16_t am = uint16_t((F[p][j] >> 16) - (F[pm][j] >> 16));
-      zc[p] = uint16_t(a.add_code[p][off + j] + ac);
-      zm[p] = uint16_t(a.add_mask[p][off + j] + am);
+  for (int k = 0; k < 3; ++k) chacha12(a.keys.k[k], stream, e0 >> 4, F[k]);
+  uint16_t oc[3][16], om[3][16];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const int pm = (p + 2) % 3;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      oc[p][j] = uint16_t(zc[p][j] + uint16_t((F[p][j] & 0xFFFFu) - (F[pm][j] & 0xFFFFu)));
+      om[p][j] = uint16_t(zm[p][j] + uint16_t((F[p][j] >> 16) - (F[pm][j] >> 16)));
     }
+  }
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      const int pm = (p + 2) % 3;
-      a.msg[p][off + j] = zc[p];
-      a.msg[p][a.plane + off + j] = zm[p];
-      a.rep_code[p][off + j] = zc[p];
-      a.rep_code[p][a.plane + off + j] = zc[pm];   // received from party p-1
-      a.rep_mask[p][off + j] = zm[p];
-      a.rep_mask[p][a.plane + off + j] = zm[pm];
-    }
+  for (int p = 0; p < 3; ++p) {
+    const int pm = (p + 2) % 3;
+    st16(a.msg[p] + off, nval, vec, oc[p]);              // party p -> party p+1
+    st16(a.msg[p] + a.plane + off, nval, vec, om[p]);
+    st16(a.rep_code[p] + off, nval, vec, oc[p]);
+    st16(a.rep_code[p] + a.plane + off, nval, vec, oc[pm]);   // received from party p-1
+    st16(a.rep_mask[p] + off, nval, vec, om[p]);
+    st16(a.rep_mask[p] + a.plane + off, nval, vec, om[pm]);
   }
 }
 

@@ -58,10 +58,14 @@ __global__ void __launch_bounds__(256) expand_kernel(const int8_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// dot kernel: workgroup tile 128 rows x 128 entries, 4 waves of 64 x 64 (2x2
-// MFMA 32x32x32 blocks).  Operand fragments are 1 KB contiguous in the tiled
-// layout (lanes 0..31: chunk 2ks, lanes 32..63: chunk 2ks+1), loaded straight
-// into registers.  blockIdx.z = 0 code, 1 mask.
+// dot kernel.  Workgroup tile BM rows x BN entries, WAVES_M x WAVES_N waves of
+// (32 WM) x (32 WN) outputs (WM x WN MFMA 32x32x32 blocks, two accumulators
+// each).  Per K-step (32 bytes of k per plane) the workgroup stages its
+// operand slices in LDS once -- A: BM/32 row-blocks, B: BN/32 entry-blocks,
+// each 2 planes x 2 k-chunks x 32 slots x 16 B, i.e. exactly the tiled HBM
+// layout -- so fragment reads are 1 KB contiguous per wave.  Two LDS stages and
+// two register sets keep the global loads two steps ahead.  blockIdx.z = 0
+// code, 1 mask.
 // ---------------------------------------------------------------------------
 struct DotArgs {
   const int8_t* a;       // rotated query operand, tiled, rows_pad rows
@@ -76,87 +80,131 @@ struct DotArgs {
   uint32_t mt, nt;       // tiles along rows / columns
 };
 
-__device__ __forceinline__ v4i ldfrag(const int8_t* base, int ks, int lane) {
-  return *reinterpret_cast<const v4i*>(base + size_t(2 * ks + (lane >> 5)) * 512 + (lane & 31) * 16);
-}
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+struct DotCfg {
+  static constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N;
+  static constexpr int kThreads = 64 * WAVES_M * WAVES_N;
+  static constexpr int kABlk = kBM / 32, kBBlk = kBN / 32;
+  static constexpr int kChunksPerStep = (kABlk + kBBlk) * 2 * 2 * 32;   // 16-byte chunks
+  static constexpr int kPerThread = kChunksPerStep / kThreads;
+  static constexpr int kStageBytes = kChunksPerStep * 16;
+  static_assert(kChunksPerStep % kThreads == 0, "chunks must divide evenly");
+};
 
-__global__ void __launch_bounds__(256) dot_kernel(DotArgs args) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) dot_kernel(DotArgs args) {
+  using C = DotCfg<WM, WN, WAVES_M, WAVES_N>;
+  extern __shared__ __align__(16) int8_t lds[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
   const int vec = blockIdx.z;
   // XCD-aware order: workgroup i runs on XCD i % 8; the workgroups one XCD
-  // holds at a time share database tiles (all row tiles of a column tile).
+  // holds at a time are all row tiles of a few column tiles, so each database
+  // slice is fetched from HBM once and served to them from that XCD's L2.
   const uint32_t i = blockIdx.x;
   const uint32_t xcd = i & 7, s = i >> 3;
   const uint32_t u = s % args.mt, tg = s / args.mt;
   const uint32_t t = tg * 8 + xcd;
   if (t >= args.nt) return;
 
-  const int8_t* abase[2];
-  const int8_t* bbase[2];
+  // Global source of each 16-byte chunk this thread stages per K-step.
+  // Chunk c: block (A row-blocks first, then B entry-blocks), plane, k-chunk, slot.
+  const int8_t* src[C::kPerThread];
 #pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    uint32_t rb = u * 4 + wm * 2 + x;
-    rb = rb < args.a_blocks ? rb : args.a_blocks - 1;
-    abase[x] = args.a + size_t(rb) * kBlockBytes + size_t(2 * vec) * kPlaneBlockBytes;
-    uint64_t cb = uint64_t(t) * 4 + wn * 2 + x;
-    cb = cb < args.b_blocks ? cb : args.b_blocks - 1;
-    bbase[x] = args.b + size_t(args.b_block0 + cb) * kBlockBytes + size_t(2 * vec) * kPlaneBlockBytes;
+  for (int j = 0; j < C::kPerThread; ++j) {
+    const int c = tid + j * C::kThreads;
+    const int blk = c >> 7, rem = c & 127;
+    const int plane = rem >> 6, kcl = (rem >> 5) & 1, slot = rem & 31;
+    const int8_t* base;
+    if (blk < C::kABlk) {
+      uint32_t rb = u * C::kABlk + blk;
+      rb = rb < args.a_blocks ? rb : args.a_blocks - 1;
+      base = args.a + size_t(rb) * kBlockBytes;
+    } else {
+      uint64_t cb = uint64_t(t) * C::kBBlk + (blk - C::kABlk);
+      cb = cb < args.b_blocks ? cb : args.b_blocks - 1;
+      base = args.b + size_t(args.b_block0 + cb) * kBlockBytes;
+    }
+    src[j] = base + size_t(2 * vec + plane) * kPlaneBlockBytes + size_t(kcl) * 512 + slot * 16;
   }
 
-  v16i acc0[2][2], acc1[2][2];
+  v16i acc0[WM][WN], acc1[WM][WN];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < WM; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < WN; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) { acc0[x][y][e] = 0; acc1[x][y][e] = 0; }
 
-  v4i alo[2], ahi[2], blo[2], bhi[2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    alo[x] = ldfrag(abase[x], 0, lane);
-    ahi[x] = ldfrag(abase[x] + kPlaneBlockBytes, 0, lane);
-    blo[x] = ldfrag(bbase[x], 0, lane);
-    bhi[x] = ldfrag(bbase[x] + kPlaneBlockBytes, 0, lane);
-  }
   constexpr int kSteps = kChunks / 2;   // 800 steps of 32 bytes of k
-  for (int ks = 0; ks < kSteps; ++ks) {
-    v4i nalo[2], nahi[2], nblo[2], nbhi[2];
-    const int kn = ks + 1 < kSteps ? ks + 1 : ks;
-#pragma unroll
-    for (int x = 0; x < 2; ++x) {
-      nalo[x] = ldfrag(abase[x], kn, lane);
-      nahi[x] = ldfrag(abase[x] + kPlaneBlockBytes, kn, lane);
-      nblo[x] = ldfrag(bbase[x], kn, lane);
-      nbhi[x] = ldfrag(bbase[x] + kPlaneBlockBytes, kn, lane);
-    }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo[x], blo[y], acc0[x][y], 0, 0, 0);
-        acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo[x], bhi[y], acc1[x][y], 0, 0, 0);
-        acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ahi[x], blo[y], acc1[x][y], 0, 0, 0);
-      }
-#pragma unroll
-    for (int x = 0; x < 2; ++x) { alo[x] = nalo[x]; ahi[x] = nahi[x]; blo[x] = nblo[x]; bhi[x] = nbhi[x]; }
+  v4i r0[C::kPerThread], r1[C::kPerThread];
+
+#define IMC_GLOAD(R, KS)                                                              \
+  _Pragma("unroll") for (int j = 0; j < C::kPerThread; ++j)                           \
+      R[j] = *reinterpret_cast<const v4i*>(src[j] + size_t(2 * (KS)) * 512);
+#define IMC_LSTORE(R, STAGE)                                                          \
+  _Pragma("unroll") for (int j = 0; j < C::kPerThread; ++j)                           \
+      *reinterpret_cast<v4i*>(lds + (STAGE) * C::kStageBytes + (tid + j * C::kThreads) * 16) = R[j];
+#define IMC_COMPUTE(STAGE)                                                            \
+  {                                                                                   \
+    const int8_t* st = lds + (STAGE) * C::kStageBytes;                                \
+    v4i alo[WM], ahi[WM], blo[WN], bhi[WN];                                           \
+    _Pragma("unroll") for (int x = 0; x < WM; ++x) {                                  \
+      const int8_t* p = st + (wm * WM + x) * 2048 + lane * 16;                        \
+      alo[x] = *reinterpret_cast<const v4i*>(p);                                      \
+      ahi[x] = *reinterpret_cast<const v4i*>(p + 1024);                               \
+    }                                                                                 \
+    _Pragma("unroll") for (int y = 0; y < WN; ++y) {                                  \
+      const int8_t* p = st + (C::kABlk + wn * WN + y) * 2048 + lane * 16;             \
+      blo[y] = *reinterpret_cast<const v4i*>(p);                                      \
+      bhi[y] = *reinterpret_cast<const v4i*>(p + 1024);                               \
+    }                                                                                 \
+    _Pragma("unroll") for (int x = 0; x < WM; ++x)                                    \
+    _Pragma("unroll") for (int y = 0; y < WN; ++y) {                                  \
+      acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo[x], blo[y], acc0[x][y], 0, 0, 0); \
+      acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo[x], bhi[y], acc1[x][y], 0, 0, 0); \
+      acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ahi[x], blo[y], acc1[x][y], 0, 0, 0); \
+    }                                                                                 \
   }
+
+  // prologue: step 0 staged, step 1 in registers
+  IMC_GLOAD(r0, 0)
+  IMC_GLOAD(r1, 1)
+  IMC_LSTORE(r0, 0)
+  __syncthreads();
+  // The last iterations re-load the final step (indices clamped) instead of
+  // branching, so the staging registers stay in VGPRs.
+  for (int ks = 0; ks < kSteps; ks += 2) {
+    // even step ks: stage 0 holds ks, r1 holds ks+1
+    IMC_GLOAD(r0, min(ks + 2, kSteps - 1))
+    IMC_COMPUTE(0)
+    IMC_LSTORE(r1, 1)
+    __syncthreads();
+    // odd step ks+1: stage 1 holds ks+1, r0 holds ks+2
+    IMC_GLOAD(r1, min(ks + 3, kSteps - 1))
+    IMC_COMPUTE(1)
+    IMC_LSTORE(r0, 0)
+    __syncthreads();
+  }
+#undef IMC_GLOAD
+#undef IMC_LSTORE
+#undef IMC_COMPUTE
 
   // Epilogue: 32x32 block, lane l holds column l%32, register e holds row
   // 8*(e/4) + 4*(l/32) + e%4.
   uint16_t* out = args.out[vec];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < WM; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      uint64_t col = uint64_t(t) * 128 + wn * 64 + y * 32 + (lane & 31);
+    for (int y = 0; y < WN; ++y) {
+      const uint64_t col = uint64_t(t) * C::kBN + (wn * WN + y) * 32 + (lane & 31);
       if (col >= args.n) continue;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        uint32_t row = u * 128 + wm * 64 + x * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        const uint32_t row = u * C::kBM + (wm * WM + x) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         if (row < args.rows) {
-          uint32_t z = uint32_t(acc0[x][y][e]) + (uint32_t(acc1[x][y][e]) << 8);
+          const uint32_t z = uint32_t(acc0[x][y][e]) + (uint32_t(acc1[x][y][e]) << 8);
           out[uint64_t(row) * args.ld + col] = uint16_t(z);
         }
       }
@@ -172,8 +220,24 @@ hipError_t launch_expand(const int8_t* qop, uint32_t q, uint32_t r, const int8_t
   return hipGetLastError();
 }
 
+template <int WM, int WN, int WAVES_M, int WAVES_N>
+static hipError_t launch_dot_cfg(DotArgs d, uint32_t rows, uint64_t n, hipStream_t s) {
+  using C = DotCfg<WM, WN, WAVES_M, WAVES_N>;
+  d.mt = (rows + C::kBM - 1) / C::kBM;
+  d.nt = uint32_t((n + C::kBN - 1) / C::kBN);
+  const uint32_t ntg = (d.nt + 7) / 8;
+  const dim3 grid(ntg * 8 * d.mt, 1, 2);
+  const size_t lds = 2 * size_t(C::kStageBytes);
+  auto kern = dot_kernel<WM, WN, WAVES_M, WAVES_N>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, grid, dim3(C::kThreads), lds, s, d);
+  return hipGetLastError();
+}
+
 hipError_t launch_dot(const int8_t* a, uint32_t rows, uint32_t a_blocks, const int8_t* b, uint64_t first_entry,
-                      uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld, hipStream_t s) {
+                      uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld, hipStream_t s, int variant) {
   if (rows == 0 || n == 0) return hipSuccess;
   DotArgs d;
   d.a = a;
@@ -186,12 +250,11 @@ hipError_t launch_dot(const int8_t* a, uint32_t rows, uint32_t a_blocks, const i
   d.b_block0 = first_entry / 32;
   d.b_blocks = (n + 31) / 32;
   d.n = n;
-  d.mt = (rows + 127) / 128;
-  d.nt = uint32_t((n + 127) / 128);
-  uint32_t ntg = (d.nt + 7) / 8;
-  dim3 grid(ntg * 8 * d.mt, 1, 2);
-  hipLaunchKernelGGL(dot_kernel, grid, dim3(256), 0, s, d);
-  return hipGetLastError();
+  switch (variant) {
+    case 1: return launch_dot_cfg<4, 2, 2, 2>(d, rows, n, s);    // 256 x 128, 4 waves of 128 x 64
+    case 2: return launch_dot_cfg<2, 2, 2, 2>(d, rows, n, s);    // 128 x 128, 4 waves of 64 x 64
+    default: return launch_dot_cfg<2, 2, 4, 2>(d, rows, n, s);   // 256 x 128, 8 waves of 64 x 64
+  }
 }
 
 }  // namespace imc

@@ -112,15 +112,17 @@ def _setup(imc, ctx, seed, n, q, first=0, cap=None):
     return dc, dm, qc, qm, db, qs
 
 
+@pytest.mark.parametrize("tiles", [0, 2])
 @pytest.mark.parametrize("q,rot,n,first", [
-    (5, list(range(-15, 16)), 300, 64),   # 155 rows: 2 row tiles; 3 column tiles, ragged
+    (9, list(range(-15, 16)), 300, 64),   # 279 rows: 2 row tiles of 256, ragged; 3 column tiles, ragged
     (1, [0], 1, 0),                        # a single comparison
     (2, [-3, 7], 129, 0),                  # one past a column tile
 ])
-def test_dot_shares_matches_oracle(ctx, imc, keys, q, rot, n, first):
+def test_dot_shares_matches_oracle(imc, keys, q, rot, n, first, tiles):
     from paper_2405_04463_amd.pipeline import alloc_check
 
-    dealer, _ = keys
+    dealer, party = keys
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=512, dot_tiles=tiles)
     dc, dm, qc, qm, db, qs = _setup(imc, ctx, 33 + n, n, q, first)
     qsh = orc.share(dealer, orc.DOM_SHARE_QUERY, qc, qm, 100)
     dsh = orc.share(dealer, orc.DOM_SHARE_DB, dc, dm, first)
@@ -133,6 +135,7 @@ def test_dot_shares_matches_oracle(ctx, imc, keys, q, rot, n, first):
         rc, rm = orc.local_dot(p, qsh, rot, dsh)
         assert np.array_equal(u16(buf.dot_code[p])[:, :n], rc), f"party {p} code"
         assert np.array_equal(u16(buf.dot_mask[p])[:, :n], rm), f"party {p} mask"
+    ctx.close()
 
 
 def test_full_protocol_matches_oracle(ctx, imc, keys):
