@@ -59,10 +59,11 @@ typedef int imc_status;
 #define IMC_ENTRY_BYTES 102400 /* one party's database bytes per entry */
 
 /* Tile configurations of the dot-product kernel (imc_params.flags bits 0-3). */
-#define IMC_DOT_TILES_256x128_W8 0   /* 256 rows x 128 entries, 8 waves of 64 x 64 (default) */
+#define IMC_DOT_TILES_256x128_W8 0   /* 256 rows x 128 entries, 8 waves of 64 x 64, loads 4 K-steps ahead (default) */
 #define IMC_DOT_TILES_256x128_W4 1   /* 256 x 128, 4 waves of 128 x 64 */
 #define IMC_DOT_TILES_128x128_W4 2   /* 128 x 128, 4 waves of 64 x 64 */
-#define IMC_DOT_TILES_MAX 2
+#define IMC_DOT_TILES_256x128_W8_P2 3  /* as 0 with loads two K-steps ahead instead of four */
+#define IMC_DOT_TILES_MAX 3
 
 /* Stream handle: a hipStream_t (NULL = the default stream). */
 typedef struct ihipStream_t* imc_stream;

@@ -91,7 +91,7 @@ struct DotCfg {
   static_assert(kChunksPerStep % kThreads == 0, "chunks must divide evenly");
 };
 
-template <int WM, int WN, int WAVES_M, int WAVES_N>
+template <int WM, int WN, int WAVES_M, int WAVES_N, int NSETS>
 __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) dot_kernel(DotArgs args) {
   using C = DotCfg<WM, WN, WAVES_M, WAVES_N>;
   extern __shared__ __align__(16) int8_t lds[];
@@ -138,54 +138,57 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) dot_kernel(DotArgs arg
       for (int e = 0; e < 16; ++e) { acc0[x][y][e] = 0; acc1[x][y][e] = 0; }
 
   constexpr int kSteps = kChunks / 2;   // 800 steps of 32 bytes of k
-  v4i r0[C::kPerThread], r1[C::kPerThread];
-
+  static_assert(kSteps % NSETS == 0, "the K loop is unrolled by NSETS");
+  v4i rs[NSETS][C::kPerThread];
 #define IMC_GLOAD(R, KS)                                                              \
-  _Pragma("unroll") for (int j = 0; j < C::kPerThread; ++j)                           \
-      R[j] = *reinterpret_cast<const v4i*>(src[j] + size_t(2 * (KS)) * 512);
+  _Pragma("unroll") for (int c_ = 0; c_ < C::kPerThread; ++c_)                        \
+      R[c_] = *reinterpret_cast<const v4i*>(src[c_] + size_t(2 * (KS)) * 512);
 #define IMC_LSTORE(R, STAGE)                                                          \
-  _Pragma("unroll") for (int j = 0; j < C::kPerThread; ++j)                           \
-      *reinterpret_cast<v4i*>(lds + (STAGE) * C::kStageBytes + (tid + j * C::kThreads) * 16) = R[j];
+  _Pragma("unroll") for (int c_ = 0; c_ < C::kPerThread; ++c_)                        \
+      *reinterpret_cast<v4i*>(lds + (STAGE) * C::kStageBytes + (tid + c_ * C::kThreads) * 16) = R[c_];
 #define IMC_COMPUTE(STAGE)                                                            \
   {                                                                                   \
-    const int8_t* st = lds + (STAGE) * C::kStageBytes;                                \
-    v4i alo[WM], ahi[WM], blo[WN], bhi[WN];                                           \
-    _Pragma("unroll") for (int x = 0; x < WM; ++x) {                                  \
-      const int8_t* p = st + (wm * WM + x) * 2048 + lane * 16;                        \
-      alo[x] = *reinterpret_cast<const v4i*>(p);                                      \
-      ahi[x] = *reinterpret_cast<const v4i*>(p + 1024);                               \
+    const int8_t* st_ = lds + (STAGE) * C::kStageBytes;                               \
+    v4i alo_[WM], ahi_[WM], blo_[WN], bhi_[WN];                                       \
+    _Pragma("unroll") for (int x_ = 0; x_ < WM; ++x_) {                               \
+      const int8_t* p_ = st_ + (wm * WM + x_) * 2048 + lane * 16;                     \
+      alo_[x_] = *reinterpret_cast<const v4i*>(p_);                                   \
+      ahi_[x_] = *reinterpret_cast<const v4i*>(p_ + 1024);                            \
     }                                                                                 \
-    _Pragma("unroll") for (int y = 0; y < WN; ++y) {                                  \
-      const int8_t* p = st + (C::kABlk + wn * WN + y) * 2048 + lane * 16;             \
-      blo[y] = *reinterpret_cast<const v4i*>(p);                                      \
-      bhi[y] = *reinterpret_cast<const v4i*>(p + 1024);                               \
+    _Pragma("unroll") for (int y_ = 0; y_ < WN; ++y_) {                               \
+      const int8_t* p_ = st_ + (C::kABlk + wn * WN + y_) * 2048 + lane * 16;          \
+      blo_[y_] = *reinterpret_cast<const v4i*>(p_);                                   \
+      bhi_[y_] = *reinterpret_cast<const v4i*>(p_ + 1024);                            \
     }                                                                                 \
-    _Pragma("unroll") for (int x = 0; x < WM; ++x)                                    \
-    _Pragma("unroll") for (int y = 0; y < WN; ++y) {                                  \
-      acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo[x], blo[y], acc0[x][y], 0, 0, 0); \
-      acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo[x], bhi[y], acc1[x][y], 0, 0, 0); \
-      acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ahi[x], blo[y], acc1[x][y], 0, 0, 0); \
+    _Pragma("unroll") for (int x_ = 0; x_ < WM; ++x_)                                 \
+    _Pragma("unroll") for (int y_ = 0; y_ < WN; ++y_) {                               \
+      acc0[x_][y_] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo_[x_], blo_[y_], acc0[x_][y_], 0, 0, 0); \
+      acc1[x_][y_] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo_[x_], bhi_[y_], acc1[x_][y_], 0, 0, 0); \
+      acc1[x_][y_] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ahi_[x_], blo_[y_], acc1[x_][y_], 0, 0, 0); \
     }                                                                                 \
   }
 
-  // prologue: step 0 staged, step 1 in registers
-  IMC_GLOAD(r0, 0)
-  IMC_GLOAD(r1, 1)
-  IMC_LSTORE(r0, 0)
-  __syncthreads();
-  // The last iterations re-load the final step (indices clamped) instead of
-  // branching, so the staging registers stay in VGPRs.
-  for (int ks = 0; ks < kSteps; ks += 2) {
-    // even step ks: stage 0 holds ks, r1 holds ks+1
-    IMC_GLOAD(r0, min(ks + 2, kSteps - 1))
-    IMC_COMPUTE(0)
-    IMC_LSTORE(r1, 1)
-    __syncthreads();
-    // odd step ks+1: stage 1 holds ks+1, r0 holds ks+2
-    IMC_GLOAD(r1, min(ks + 3, kSteps - 1))
-    IMC_COMPUTE(1)
+  // Global loads run NSETS steps ahead of the LDS write (register sets), the
+  // LDS write one step ahead of the MFMAs (two stages).  Step j (j >= 1) lives
+  // in register set (j - 1) % NSETS.  Indices past the last step are clamped
+  // (redundant reloads instead of branches keep the sets in VGPRs).
+  {
+    v4i r0[C::kPerThread];
+    IMC_GLOAD(r0, 0)
     IMC_LSTORE(r0, 0)
-    __syncthreads();
+  }
+#pragma unroll
+  for (int set = 0; set < NSETS; ++set) { IMC_GLOAD(rs[set], set + 1) }
+  __syncthreads();
+  for (int k0 = 0; k0 < kSteps; k0 += NSETS) {
+#pragma unroll
+    for (int u = 0; u < NSETS; ++u) {
+      const int k = k0 + u;
+      IMC_COMPUTE(u & 1)
+      IMC_LSTORE(rs[u], (u + 1) & 1)             // step k + 1
+      __syncthreads();
+      IMC_GLOAD(rs[u], min(k + 1 + NSETS, kSteps - 1))
+    }
   }
 #undef IMC_GLOAD
 #undef IMC_LSTORE
@@ -220,7 +223,7 @@ hipError_t launch_expand(const int8_t* qop, uint32_t q, uint32_t r, const int8_t
   return hipGetLastError();
 }
 
-template <int WM, int WN, int WAVES_M, int WAVES_N>
+template <int WM, int WN, int WAVES_M, int WAVES_N, int NSETS>
 static hipError_t launch_dot_cfg(DotArgs d, uint32_t rows, uint64_t n, hipStream_t s) {
   using C = DotCfg<WM, WN, WAVES_M, WAVES_N>;
   d.mt = (rows + C::kBM - 1) / C::kBM;
@@ -228,7 +231,7 @@ static hipError_t launch_dot_cfg(DotArgs d, uint32_t rows, uint64_t n, hipStream
   const uint32_t ntg = (d.nt + 7) / 8;
   const dim3 grid(ntg * 8 * d.mt, 1, 2);
   const size_t lds = 2 * size_t(C::kStageBytes);
-  auto kern = dot_kernel<WM, WN, WAVES_M, WAVES_N>;
+  auto kern = dot_kernel<WM, WN, WAVES_M, WAVES_N, NSETS>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (e != hipSuccess) return e;
@@ -251,9 +254,10 @@ hipError_t launch_dot(const int8_t* a, uint32_t rows, uint32_t a_blocks, const i
   d.b_blocks = (n + 31) / 32;
   d.n = n;
   switch (variant) {
-    case 1: return launch_dot_cfg<4, 2, 2, 2>(d, rows, n, s);    // 256 x 128, 4 waves of 128 x 64
-    case 2: return launch_dot_cfg<2, 2, 2, 2>(d, rows, n, s);    // 128 x 128, 4 waves of 64 x 64
-    default: return launch_dot_cfg<2, 2, 4, 2>(d, rows, n, s);   // 256 x 128, 8 waves of 64 x 64
+    case 1: return launch_dot_cfg<4, 2, 2, 2, 2>(d, rows, n, s);    // 256 x 128, 4 waves of 128 x 64
+    case 2: return launch_dot_cfg<2, 2, 2, 2, 2>(d, rows, n, s);    // 128 x 128, 4 waves of 64 x 64
+    case 3: return launch_dot_cfg<2, 2, 4, 2, 2>(d, rows, n, s);    // 256 x 128, 8 waves, 2-step prefetch
+    default: return launch_dot_cfg<2, 2, 4, 2, 4>(d, rows, n, s);   // 256 x 128, 8 waves, 4-step prefetch
   }
 }
 
