@@ -199,8 +199,8 @@ def run_party(args):
     w = wl.party_local(n_db=args.n_db, n_q=args.n_q)
     dealer, party = keys()
     ctx = imc.Context(imc.Keys(dealer, party), max_rows=w.rows, dot_tiles=args.dot_tiles)
-    db = SharedDB(ctx, w.n_db)
-    log(f"enrolling {w.n_db} entries ({3 * imc.db_bytes(w.n_db) / 1e9:.1f} GB for 3 parties)")
+    db = SharedDB(ctx, w.n_db, parties=(0,))
+    log(f"enrolling {w.n_db} entries ({imc.db_bytes(w.n_db) / 1e9:.1f} GB, party 0's region)")
     enroll_db(ctx, db, w.seed, w.n_db)
     qc, qm = wl.make_queries(w)
     qs = SharedQueries(ctx, torch.from_numpy(qc.view(np.int64)).cuda(), torch.from_numpy(qm.view(np.int64)).cuda(), 0)

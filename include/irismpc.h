@@ -58,12 +58,19 @@ typedef int imc_status;
 #define IMC_MAX_ROT 32         /* rotations per query in one call */
 #define IMC_ENTRY_BYTES 102400 /* one party's database bytes per entry */
 
-/* Tile configurations of the dot-product kernel (imc_params.flags bits 0-3). */
-#define IMC_DOT_TILES_256x128_W8 0   /* 256 rows x 128 entries, 8 waves of 64 x 64, loads 4 K-steps ahead (default) */
-#define IMC_DOT_TILES_256x128_W4 1   /* 256 x 128, 4 waves of 128 x 64 */
-#define IMC_DOT_TILES_128x128_W4 2   /* 128 x 128, 4 waves of 64 x 64 */
-#define IMC_DOT_TILES_256x128_W8_P2 3  /* as 0 with loads two K-steps ahead instead of four */
-#define IMC_DOT_TILES_MAX 3
+/* Dot-product kernel configurations (imc_params.flags bits 0-3).  All give
+ * identical results; they differ in tiling and in how rotations are formed. */
+#define IMC_DOT_TILES_AUTO 0             /* ROTATION when r >= 24, else EXPANDED_256x128 */
+#define IMC_DOT_TILES_EXPANDED_256x128 1 /* rotated rows expanded into scratch; 256 x 128 tiles,
+                                            8 waves of 64 x 64, loads 4 K-steps ahead */
+#define IMC_DOT_TILES_EXPANDED_128x128 2 /* as 1 with 128 x 128 tiles, 4 waves */
+#define IMC_DOT_TILES_EXPANDED_P2 3      /* as 1 with loads 2 K-steps ahead */
+#define IMC_DOT_TILES_ROTATION 4         /* 256 x 128 tiles; each tile's queries staged unrotated in
+                                            LDS per 800-byte segment, rotations read in place
+                                            (used when r >= 24, else as AUTO) */
+#define IMC_DOT_TILES_MAX 4
+#define IMC_DOT_PERSISTENT 0x10          /* bit 4: expanded tilings run a persistent grid (one
+                                            workgroup per CU walking its XCD's tile sequence) */
 
 /* Stream handle: a hipStream_t (NULL = the default stream). */
 typedef struct ihipStream_t* imc_stream;
@@ -76,10 +83,18 @@ typedef struct imc_params {
                                   must be 16384 (MATCH_RATIO = 3/8) */
   uint32_t max_rows;           /* largest q*r any dot_shares call uses (sizes internal scratch) */
   uint32_t flags;              /* bits 0-3: dot-product tile configuration (IMC_DOT_TILES_*);
-                                  other bits reserved, must be 0 */
+                                  bit 4: IMC_DOT_PERSISTENT; other bits reserved, must be 0 */
   uint8_t dealer_key[32];      /* key of the input dealer's sharing PRF */
   uint8_t party_key[3][32];    /* key_p of party p; the paper's seed_{p+1} (App. D) */
 } imc_params;
+
+/* One result row of a batched dot product: which query operand row to use,
+ * at which rotation.  Rows of several uneven batches (different query counts
+ * and rotation counts) go through one launch with a table of these. */
+typedef struct imc_row {
+  uint32_t query_index;        /* row of the query operand (< q; otherwise the row is zero) */
+  int32_t rot;                 /* rotation offset in [-15, 15] */
+} imc_row;
 
 typedef struct imc_ids {
   uint64_t query_id_base;      /* id of the call's query 0 */
@@ -115,7 +130,8 @@ size_t imc_or_tree_ws_bytes(size_t q, size_t r, size_t nw);
  * in Z_2^16 (Sec. 4.1.1) and each mask bit m in Z_2^16; the dealer splits
  * x = x_0 + x_1 + x_2 with x_0, x_1 from its PRF; party p's region db[p]
  * receives (x_p, x_{p-1}) of code and mask for every entry.
- * db[p]: device region of imc_db_bytes(db_capacity) bytes (alignment 256).
+ * db[p]: device region of imc_db_bytes(db_capacity) bytes (alignment 256), or
+ * NULL for a party whose region is not held on this device (at least one set).
  * Layout: entry e lives in block e/32 at slot e%32; a block is
  * [plane 4][k-chunk 1600][slot 32][16 B] with planes (code lo, code hi,
  * mask lo, mask hi) of the balanced byte limbs v = lo + 256 hi (lo, hi signed
@@ -149,6 +165,22 @@ imc_status imc_share_query(imc_ctx* ctx, const uint64_t* codes, const uint64_t* 
 imc_status imc_dot_shares(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_ids* ids,
                           const void* db, size_t db_capacity, size_t n, uint16_t* code_dot,
                           uint16_t* mask_dot, size_t ld, imc_stream stream);
+
+/* Batched party-local dot products (the same arithmetic as imc_dot_shares)
+ * for an arbitrary list of (query, rotation) rows: rows[i] (DEVICE array of
+ * nrows imc_row) selects query operand row rows[i].query_index of qop (q
+ * rows) at rotation rows[i].rot; output row i of code_dot / mask_dot holds its
+ * products with entries first_entry_id .. first_entry_id + n - 1.  Used to
+ * run many small uneven batches as one launch over one pass of the database.
+ * The rows' rotated operands are expanded into context scratch (nrows <=
+ * max_rows).  Errors as imc_dot_shares; first_entry_id % 64 != 0 -> EINVAL. */
+imc_status imc_dot_shares_rows(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_row* rows,
+                               size_t nrows, const void* db, size_t db_capacity, uint64_t first_entry_id,
+                               size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld, imc_stream stream);
+
+/* Select the dot-product configuration of an existing context (same values as
+ * imc_params.flags bits 0-4).  Errors: IMC_EUNSUPPORTED. */
+imc_status imc_set_dot_tiles(imc_ctx* ctx, uint32_t flags);
 
 /* Resharing of the dot products (App. C: add a zero share, send to the next
  * party).  add_code[p], add_mask[p]: party p's additive shares, u16
@@ -203,7 +235,8 @@ imc_status imc_open(imc_ctx* ctx, int kind, const void* const rep[3], size_t cou
 
 /* Append: copy query qi's raw shares (qraw[p] from imc_share_query) into
  * database slot entry_id of every party's region (Sec. 1: a unique query is
- * enrolled).  Errors: IMC_ESHAPE (entry_id >= capacity). */
+ * enrolled); a NULL db[p] skips that party.  Errors: IMC_EINVAL (no region,
+ * or a held region without its qraw), IMC_ESHAPE (entry_id >= capacity). */
 imc_status imc_append_db(imc_ctx* ctx, const void* const qraw[3], size_t qi, void* const db[3],
                          size_t db_capacity, uint64_t entry_id, imc_stream stream);
 

@@ -22,8 +22,13 @@ CODE_BITS, CODE_WORDS, MAX_ROT, ENTRY_BYTES = 12800, 200, 32, 102400
 EXPORTS = [
     "imc_create", "imc_destroy", "imc_strerror", "imc_db_bytes", "imc_query_op_bytes", "imc_query_raw_bytes",
     "imc_or_tree_ws_bytes", "imc_share_db", "imc_share_query", "imc_dot_shares", "imc_reshare",
-    "imc_compare_threshold", "imc_or_tree", "imc_open", "imc_append_db",
+    "imc_compare_threshold", "imc_or_tree", "imc_open", "imc_append_db", "imc_dot_shares_rows",
+    "imc_set_dot_tiles",
 ]
+
+DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_P2, DOT_TILES_ROTATION = (
+    0, 1, 2, 3, 4)
+DOT_PERSISTENT = 0x10
 
 
 class IMCError(RuntimeError):
@@ -41,6 +46,10 @@ class imc_params(ctypes.Structure):
         ("dealer_key", ctypes.c_uint8 * 32),
         ("party_key", (ctypes.c_uint8 * 32) * 3),
     ]
+
+
+class imc_row(ctypes.Structure):
+    _fields_ = [("query_index", ctypes.c_uint32), ("rot", ctypes.c_int32)]
 
 
 class imc_ids(ctypes.Structure):
@@ -84,6 +93,9 @@ def lib():
         L.imc_or_tree.argtypes = [_VP, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, sz, _P3, _VP]
         L.imc_open.argtypes = [_VP, ctypes.c_int, _P3, sz, _VP, ctypes.c_int, _VP]
         L.imc_append_db.argtypes = [_VP, _P3, sz, _P3, sz, ctypes.c_uint64, _VP]
+        L.imc_dot_shares_rows.argtypes = [_VP, ctypes.c_int, _VP, sz, _VP, sz, _VP, sz, ctypes.c_uint64, sz, _VP, _VP,
+                                          sz, _VP]
+        L.imc_set_dot_tiles.argtypes = [_VP, ctypes.c_uint32]
         for f in EXPORTS:
             if f not in ("imc_destroy", "imc_strerror") and not f.endswith("_bytes"):
                 getattr(L, f).restype = st
@@ -114,7 +126,7 @@ def addr(t) -> int:
 
 
 def _p3(ts):
-    return _P3(*[addr(t) for t in ts])
+    return _P3(*[addr(t) for t in ts])   # None -> NULL
 
 
 def _stream(stream) -> int | None:
@@ -208,6 +220,17 @@ class Context:
     def dot_shares(self, party, qop, q, ids: imc_ids, db, capacity, n, code_dot, mask_dot, ld, stream=None):
         return _check(lib().imc_dot_shares(self._h, party, addr(qop), q, ctypes.byref(ids), addr(db), capacity, n,
                                            addr(code_dot), addr(mask_dot), ld, _stream(stream)), "imc_dot_shares")
+
+    # -- imc_dot_shares_rows (rows: device int32 tensor [nrows, 2] = (query_index, rot))
+    def dot_shares_rows(self, party, qop, q, rows, nrows, db, capacity, first_entry_id, n, code_dot, mask_dot, ld,
+                        stream=None):
+        return _check(lib().imc_dot_shares_rows(self._h, party, addr(qop), q, addr(rows), nrows, addr(db), capacity,
+                                                first_entry_id, n, addr(code_dot), addr(mask_dot), ld,
+                                                _stream(stream)), "imc_dot_shares_rows")
+
+    # -- imc_set_dot_tiles
+    def set_dot_tiles(self, flags: int):
+        return _check(lib().imc_set_dot_tiles(self._h, flags), "imc_set_dot_tiles")
 
     # -- imc_reshare
     def reshare(self, add_code3, add_mask3, rows, n, ld, ids: imc_ids, msg3, rep_code3, rep_mask3, stream=None):

@@ -88,7 +88,7 @@ imc_status imc_create(const imc_params* p, int device, imc_ctx** out) {
   if (!p || !out) return IMC_EINVAL;
   *out = nullptr;
   if (p->code_bits != IMC_CODE_BITS || p->thr_a != 16384u) return IMC_EUNSUPPORTED;
-  if ((p->flags & ~0xFu) != 0 || (p->flags & 0xFu) > IMC_DOT_TILES_MAX) return IMC_EUNSUPPORTED;
+  if ((p->flags & ~0x1Fu) != 0 || (p->flags & 0xFu) > IMC_DOT_TILES_MAX) return IMC_EUNSUPPORTED;
   if (p->max_rows == 0) return IMC_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess) return IMC_EDEVICE;
@@ -101,7 +101,7 @@ imc_status imc_create(const imc_params* p, int device, imc_ctx** out) {
   c->dealer = load_key(p->dealer_key);
   for (int k = 0; k < 3; ++k) c->party.k[k] = load_key(p->party_key[k]);
   c->max_rows = p->max_rows;
-  c->dot_variant = int(p->flags & 0xFu);
+  c->dot_variant = int(p->flags & 0x1Fu);
   c->rot_op_bytes = blocks_for(p->max_rows) * imc::kBlockBytes;
   if (hipMalloc(reinterpret_cast<void**>(&c->rot_op), c->rot_op_bytes) != hipSuccess) {
     delete c;
@@ -129,8 +129,12 @@ imc_status imc_share_db(imc_ctx* c, const uint64_t* codes, const uint64_t* masks
                         void* const db[3], size_t capacity, imc_stream stream) {
   if (!c || !db) return IMC_EINVAL;
   if (n && (!codes || !masks)) return IMC_EINVAL;
-  for (int p = 0; p < 3; ++p)
-    if (!db[p] || !aligned(db[p], 256)) return IMC_EINVAL;
+  int held = 0;
+  for (int p = 0; p < 3; ++p) {
+    if (db[p] && !aligned(db[p], 256)) return IMC_EINVAL;
+    held += db[p] != nullptr;
+  }
+  if (!held) return IMC_EINVAL;
   if (!aligned(codes, 8) || !aligned(masks, 8)) return IMC_EINVAL;
   if (first > capacity || n > capacity - first) return IMC_ESHAPE;
   if (first + n > (1ull << 48)) return IMC_EINVAL;
@@ -175,13 +179,54 @@ imc_status imc_dot_shares(imc_ctx* c, int party, const void* qop, size_t q, cons
   if (ids->first_entry_id > capacity || n > capacity - ids->first_entry_id) return IMC_ESHAPE;
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;
+  const int v = c->dot_variant;
+  const int tiles = v & 0xF;
+  if ((tiles == IMC_DOT_TILES_AUTO || tiles == IMC_DOT_TILES_ROTATION) && imc::rot_dot_applies(uint32_t(ids->r))) {
+    // rotations read straight from the unrotated operand staged in LDS
+    return dev_status(imc::launch_rot_dot(static_cast<const int8_t*>(qop), uint32_t(q), uint32_t(ids->r), ids->rot,
+                                          static_cast<const int8_t*>(db), ids->first_entry_id, n, code_dot, mask_dot,
+                                          ld, hipStream_t(stream)));
+  }
   const uint32_t rows_pad = uint32_t(blocks_for(rows) * 32);
   hipError_t e = imc::launch_expand(static_cast<const int8_t*>(qop), uint32_t(q), uint32_t(ids->r), ids->rot,
                                     c->rot_op, rows_pad, hipStream_t(stream));
   if (e != hipSuccess) return IMC_EDEVICE;
   e = imc::launch_dot(c->rot_op, uint32_t(rows), rows_pad / 32, static_cast<const int8_t*>(db), ids->first_entry_id,
-                      n, code_dot, mask_dot, ld, hipStream_t(stream), c->dot_variant);
+                      n, code_dot, mask_dot, ld, hipStream_t(stream), v);
   return dev_status(e);
+}
+
+imc_status imc_dot_shares_rows(imc_ctx* c, int party, const void* qop, size_t q, const imc_row* rows, size_t nrows,
+                               const void* db, size_t capacity, uint64_t first_entry_id, size_t n, uint16_t* code_dot,
+                               uint16_t* mask_dot, size_t ld, imc_stream stream) {
+  if (!c || party < 0 || party > 2) return IMC_EINVAL;
+  if (nrows == 0 || n == 0) return IMC_OK;
+  if (!qop || !rows || !db || !code_dot || !mask_dot || q == 0) return IMC_EINVAL;
+  if (!aligned(qop, 16) || !aligned(rows, 8) || !aligned(db, 256) || !aligned(code_dot, 2) || !aligned(mask_dot, 2))
+    return IMC_EINVAL;
+  if (first_entry_id % 64) return IMC_EINVAL;
+  if (nrows > c->max_rows) return IMC_ESHAPE;
+  if (ld < n) return IMC_ESHAPE;
+  if (first_entry_id > capacity || n > capacity - first_entry_id) return IMC_ESHAPE;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  const uint32_t rows_pad = uint32_t(blocks_for(nrows) * 32);
+  hipError_t e = imc::launch_expand_rows(static_cast<const int8_t*>(qop), uint32_t(q), rows, uint32_t(nrows), c->rot_op,
+                                         rows_pad, hipStream_t(stream));
+  if (e != hipSuccess) return IMC_EDEVICE;
+  int v = c->dot_variant;
+  if ((v & 0xF) == IMC_DOT_TILES_AUTO || (v & 0xF) == IMC_DOT_TILES_ROTATION)
+    v = (v & ~0xF) | IMC_DOT_TILES_EXPANDED_256x128;
+  e = imc::launch_dot(c->rot_op, uint32_t(nrows), rows_pad / 32, static_cast<const int8_t*>(db), first_entry_id, n,
+                      code_dot, mask_dot, ld, hipStream_t(stream), v);
+  return dev_status(e);
+}
+
+imc_status imc_set_dot_tiles(imc_ctx* c, uint32_t flags) {
+  if (!c) return IMC_EINVAL;
+  if ((flags & ~0x1Fu) != 0 || (flags & 0xFu) > IMC_DOT_TILES_MAX) return IMC_EUNSUPPORTED;
+  c->dot_variant = int(flags);
+  return IMC_OK;
 }
 
 imc_status imc_reshare(imc_ctx* c, const uint16_t* const add_code[3], const uint16_t* const add_mask[3], size_t rows,
@@ -259,9 +304,13 @@ imc_status imc_open(imc_ctx* c, int kind, const void* const rep[3], size_t count
 imc_status imc_append_db(imc_ctx* c, const void* const qraw[3], size_t qi, void* const db[3], size_t capacity,
                          uint64_t entry_id, imc_stream stream) {
   if (!c || !qraw || !db) return IMC_EINVAL;
+  int held = 0;
   for (int p = 0; p < 3; ++p) {
-    if (!qraw[p] || !db[p] || !aligned(db[p], 256) || !aligned(qraw[p], 2)) return IMC_EINVAL;
+    if (!db[p]) continue;   // region not held on this device
+    if (!qraw[p] || !aligned(db[p], 256) || !aligned(qraw[p], 2)) return IMC_EINVAL;
+    ++held;
   }
+  if (!held) return IMC_EINVAL;
   if (entry_id >= capacity) return IMC_ESHAPE;
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;

@@ -22,6 +22,12 @@ hipError_t launch_append(const uint16_t* const raw[3], uint64_t qi, uint8_t* con
 
 hipError_t launch_expand(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, int8_t* a, uint32_t rows_pad,
                          hipStream_t s);
+bool rot_dot_applies(uint32_t r);
+hipError_t launch_rot_dot(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+                          uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
+                          hipStream_t s);
+hipError_t launch_expand_rows(const int8_t* qop, uint32_t q, const imc_row* rows, uint32_t nrows, int8_t* a,
+                              uint32_t rows_pad, hipStream_t s);
 hipError_t launch_dot(const int8_t* a, uint32_t rows, uint32_t a_blocks, const int8_t* b, uint64_t first_entry,
                       uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld, hipStream_t s, int variant);
 

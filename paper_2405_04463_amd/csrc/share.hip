@@ -68,6 +68,7 @@ __global__ void __launch_bounds__(256) share_db_kernel(Key dk, const uint64_t* _
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
     int pm = (p + 2) % 3;
+    if (!db.p[p]) continue;   // this party's region is not held here
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       store_chunk(db.p[p], e, vec, 2 * a + h, &comps[p][16 * h]);                 // x_p at k = i
@@ -138,6 +139,7 @@ __global__ void __launch_bounds__(256) append_kernel(RawIn raw, uint64_t qi, DbO
   int t = blockIdx.x * blockDim.x + threadIdx.x;   // one 16-element chunk of one (party, vec, half)
   if (t >= 3 * 2 * 2 * 800) return;
   int c = t % 800, h = (t / 800) % 2, vec = (t / 1600) % 2, p = t / 3200;
+  if (!db.p[p]) return;   // this party's region is not held here
   const uint16_t* src = raw.p[p] + qi * (2 * 2 * kCodeBits) + size_t(vec) * 2 * kCodeBits + size_t(h) * kCodeBits + 16 * c;
   uint16_t v[16];
 #pragma unroll

@@ -23,12 +23,13 @@ def _dev(device):
 class SharedDB:
     """The three parties' database regions (one device buffer each)."""
 
-    def __init__(self, ctx: Context, capacity: int, device=0):
+    def __init__(self, ctx: Context, capacity: int, device=0, parties=(0, 1, 2)):
         self.ctx = ctx
         self.capacity = capacity
         self.n = 0
         nb = db_bytes(capacity)
-        self.regions = [torch.empty(nb, dtype=torch.uint8, device=_dev(device)) for _ in range(3)]
+        self.regions = [torch.empty(nb, dtype=torch.uint8, device=_dev(device)) if p in parties else None
+                        for p in range(3)]
 
     def enroll(self, codes, masks, first: int | None = None, stream=None):
         """Share packed device codes/masks [n, 200] (uint64 as int64) into slots first.."""

@@ -1,0 +1,114 @@
+"""Batched uneven steps (one dot launch over the rows of many batches) against
+per-batch launches, the oracle, and HIP-graph replays; bit-exact."""
+import numpy as np
+import pytest
+
+import oracle as orc
+import workload as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def env(keys):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_04463_amd as imc
+    from paper_2405_04463_amd.batch import Batch, BatchSet
+    from paper_2405_04463_amd.pipeline import SharedDB
+
+    dealer, party = keys
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=1024)
+    n, first = 200, 64
+    dc, dm = wl.gen_codes(61, first, n)
+    db = SharedDB(ctx, first + n)
+    d64 = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()  # noqa: E731
+    db.enroll(d64(dc), d64(dm), first)
+    batches = [Batch(3, wl.rotations(31), 500), Batch(2, [0], 510), Batch(4, wl.rotations(15), 520),
+               Batch(1, wl.rotations(31), 530), Batch(5, [0], 540)]
+    qc, qm = wl.gen_codes(61, 0, sum(b.q for b in batches), query=True)
+    qc[1], qm[1] = wl.plant(61, 1, dc[7], dm[7], 4, h=0.2)       # batch 0, query 1 at rotation 4
+    qc[3], qm[3] = wl.plant(61, 3, dc[150], dm[150], 0, h=0.3)   # batch 1, query 0 (R = 1)
+    bs = BatchSet(ctx, batches, d64(qc), d64(qm))
+    torch.cuda.synchronize()
+    yield dict(imc=imc, ctx=ctx, db=db, bs=bs, batches=batches, qc=qc, qm=qm, dc=dc, dm=dm, n=n, first=first,
+               dealer=dealer, party=party)
+    ctx.close()
+
+
+def _u16(t):
+    return t.cpu().numpy().view(np.uint16)
+
+
+def test_batched_equals_plain_and_oracle(env):
+    from paper_2405_04463_amd.batch import BatchedStep
+
+    e = env
+    st = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], e["n"], parties=(0, 1, 2), compare=True)
+    st.run()
+    torch.cuda.synchronize()
+    got = {p: (_u16(st.dot_code[p]).copy(), _u16(st.dot_mask[p]).copy()) for p in range(3)}
+    dup_b = [[pb["dup"][p].cpu().numpy().copy() for p in range(3)] for pb in st.per_batch]
+    st.run_plain()
+    torch.cuda.synchronize()
+    for p in range(3):
+        assert np.array_equal(_u16(st.dot_code[p]), got[p][0]) and np.array_equal(_u16(st.dot_mask[p]), got[p][1])
+    # party 0 and 2 dot shares vs the oracle, batch by batch
+    dsh = orc.share(e["dealer"], orc.DOM_SHARE_DB, e["dc"], e["dm"], e["first"])
+    q0 = 0
+    for bi, b in enumerate(e["batches"]):
+        qsh = orc.share(e["dealer"], orc.DOM_SHARE_QUERY, e["qc"][q0:q0 + b.q], e["qm"][q0:q0 + b.q], b.qid_base)
+        r0 = e["bs"].rbase[bi]
+        for p in (0, 2):
+            rc, rm = orc.local_dot(p, qsh, b.rot, dsh)
+            assert np.array_equal(got[p][0][r0:r0 + b.rows, :e["n"]], rc), (bi, p)
+            assert np.array_equal(got[p][1][r0:r0 + b.rows, :e["n"]], rm), (bi, p)
+        # opened per-batch decision vs the plaintext oracle
+        _, _, _, dup = orc.plain(e["qc"][q0:q0 + b.q], e["qm"][q0:q0 + b.q], b.rot, e["dc"], e["dm"])
+        opened = dup_b[bi][0][0] ^ dup_b[bi][1][0] ^ dup_b[bi][2][0]
+        assert np.array_equal(opened, dup), bi
+        q0 += b.q
+    assert dup_b[0][0][0][1] ^ dup_b[0][1][0][1] ^ dup_b[0][2][0][1] == 1
+    assert dup_b[1][0][0][0] ^ dup_b[1][1][0][0] ^ dup_b[1][2][0][0] == 1
+
+
+def test_chunked_db_walk_equals_one_pass(env):
+    from paper_2405_04463_amd.batch import BatchedStep
+
+    e = env
+    one = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], e["n"], parties=(1,))
+    one.run()
+    torch.cuda.synchronize()
+    ref = _u16(one.dot_code[1]).copy()
+    ch = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], e["n"], chunk=64, parties=(1,))
+    outs = []
+    for c0, m in ch._chunks():
+        e["ctx"].dot_shares_rows(1, e["bs"].op[1], e["bs"].q, e["bs"].rows, e["bs"].nrows, e["db"].regions[1],
+                                 e["db"].capacity, e["first"] + c0, m, ch.dot_code[1], ch.dot_mask[1], ch.ld)
+        torch.cuda.synchronize()
+        outs.append(_u16(ch.dot_code[1])[:, :m].copy())
+    assert np.array_equal(np.concatenate(outs, axis=1), ref[:, :e["n"]])
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_graph_replay_matches_eager(env, persistent):
+    from paper_2405_04463_amd.batch import BatchedStep
+
+    e = env
+    imc = e["imc"]
+    e["ctx"].set_dot_tiles(imc.DOT_TILES_EXPANDED_256x128 | (imc.DOT_PERSISTENT if persistent else 0))
+    st = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], e["n"], parties=(0,))
+    st.run()
+    torch.cuda.synchronize()
+    ref = (_u16(st.dot_code[0]).copy(), _u16(st.dot_mask[0]).copy())
+    st.capture()
+    for i in range(3):
+        st.dot_code[0].zero_()
+        st.dot_mask[0].zero_()
+        st.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(_u16(st.dot_code[0]), ref[0]) and np.array_equal(_u16(st.dot_mask[0]), ref[1]), i
+        st.run_plain()           # eager work between replays
+        torch.cuda.synchronize()
+    e["ctx"].set_dot_tiles(imc.DOT_TILES_AUTO)

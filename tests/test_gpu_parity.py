@@ -112,11 +112,12 @@ def _setup(imc, ctx, seed, n, q, first=0, cap=None):
     return dc, dm, qc, qm, db, qs
 
 
-@pytest.mark.parametrize("tiles", [0, 2, 3])
+@pytest.mark.parametrize("tiles", [0, 1, 2, 3])
 @pytest.mark.parametrize("q,rot,n,first", [
     (9, list(range(-15, 16)), 300, 64),   # 279 rows: 2 row tiles of 256, ragged; 3 column tiles, ragged
     (1, [0], 1, 0),                        # a single comparison
     (2, [-3, 7], 129, 0),                  # one past a column tile
+    (12, list(range(-12, 12)), 200, 0),    # r = 24: rotation-aware tiles, queries straddle row tiles
 ])
 def test_dot_shares_matches_oracle(imc, keys, q, rot, n, first, tiles):
     from paper_2405_04463_amd.pipeline import alloc_check
