@@ -1,0 +1,270 @@
+"""Continuous-batching uniqueness service, three parties simulated on one GPU.
+
+Requests (one iris code + mask, checked at R rotations) arrive over time.
+The database shares stay resident in HBM, split into fixed chunks of `chunk`
+entries (a multiple of 64).  A cursor walks the chunks cyclically; on each
+tick every admitted request that still needs the cursor's chunk contributes
+its R rows to ONE batched dot launch per party (`imc_dot_shares_rows`),
+then each request reshares and compares its rows, writing its match words
+into its own full-database match buffer at the chunk's word offset.  A
+request admitted while others are in flight joins at the current chunk (its
+work overlaps theirs on the device) and completes after one full cycle; its
+OR-tree then runs once over its whole match buffer and the result is opened.
+Unique requests (dup = 0) are appended to the database.
+
+Because every random value is addressed by (query id, rotation, entry, gate)
+and the OR-tree runs over the request's complete buffer, a request's shares
+and result are the same alone and in any mix, whatever chunk it starts at.
+A request checks the entries enrolled when it was admitted; requests in
+flight at the same time are not compared with each other (in-batch matching
+is not implemented).
+
+Admission: a request needs a free slot (slots bound the rows of a tick) and
+its per-request buffers must fit in free HBM above a reserve.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import OPEN_U8_XOR, Context, make_ids, or_tree_ws_bytes
+
+ROW = 102400
+RAW = 2 * 2 * 12800 * 2
+
+
+@dataclass
+class Request:
+    rid: int
+    qid: int
+    code: np.ndarray          # packed u64 [200]
+    mask: np.ndarray
+    arrival: float = 0.0      # seconds from the start of the run
+    # filled by the server
+    slot: int = -1
+    snapshot: int = 0         # database entries this request is checked against
+    remaining: set = field(default_factory=set)
+    admitted_at: float = -1.0
+    done_at: float = -1.0
+    dup: int = -1
+    entry: int = -1           # database slot when appended
+    dup_shares: np.ndarray | None = None   # [3] components of the result
+
+
+class Server:
+    def __init__(self, ctx: Context, db, rot, chunk: int = 65536, slots: int = 64, max_entries: int | None = None,
+                 hbm_reserve: int = 4 << 30, append: bool = True, keep_shares: bool = False, device=0):
+        assert chunk % 64 == 0
+        self.ctx, self.db, self.rot = ctx, db, list(rot)
+        self.R = len(self.rot)
+        self.chunk, self.slots = chunk, slots
+        self.append_uniques, self.keep_shares = append, keep_shares
+        self.hbm_reserve = hbm_reserve
+        self.max_entries = max_entries or db.capacity
+        d = torch.device("cuda", device)
+        self.dev = d
+        self.nw_full = (self.max_entries + 63) // 64
+        rows = slots * self.R
+        self.ld = chunk
+        i16 = lambda *s: torch.empty(*s, dtype=torch.int16, device=d)  # noqa: E731
+        # slot-indexed query shares (operand row = slot)
+        self.op = [torch.empty(slots * ROW, dtype=torch.uint8, device=d) for _ in range(3)]
+        self.raw = [torch.empty(slots * RAW // 2, dtype=torch.int16, device=d) for _ in range(3)]
+        # tick buffers: dot outputs of all slots' rows for one chunk
+        self.dot_code = [i16(rows, self.ld) for _ in range(3)]
+        self.dot_mask = [i16(rows, self.ld) for _ in range(3)]
+        # a small ring of row tables: the host fills one while earlier copies may
+        # still be reading the others; a table is reused only after its copy ended
+        self.ring = 4
+        self.rows_host = [torch.empty(rows, 2, dtype=torch.int32).pin_memory() for _ in range(self.ring)]
+        self.rows_dev = [torch.empty(rows, 2, dtype=torch.int32, device=d) for _ in range(self.ring)]
+        self.rows_ev = [None] * self.ring
+        self.tick_ev = deque()          # the host runs at most two ticks ahead of the GPU
+        # per-slot buffers
+        self.msg = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(slots)]
+        self.rep_code = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(slots)]
+        self.rep_mask = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(slots)]
+        self.match = [None] * slots     # [3] x [2, R, nw_full] int64, allocated on admission
+        self.dup = [[torch.empty(2, 1, dtype=torch.uint8, device=d) for _ in range(3)] for _ in range(slots)]
+        self.ws = torch.empty(max(8, or_tree_ws_bytes(1, self.R, self.nw_full)), dtype=torch.uint8, device=d)
+        self.open_dev = torch.empty(slots, dtype=torch.uint8, device=d)
+        self.open_host = torch.empty(slots, dtype=torch.uint8).pin_memory()
+        self.free = list(range(slots))[::-1]
+        self.active: dict[int, Request] = {}
+        self.finishing: list = []       # (request, event)
+        self.queue: deque = deque()
+        self.cursor = 0
+        self.done: list = []
+        self.t0 = time.perf_counter()
+        self.ticks = 0
+        self.cmps = 0
+
+    # ---------------------------------------------------------------- helpers
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def request_bytes(self) -> int:
+        return 3 * 2 * self.R * self.nw_full * 8
+
+    def n_chunks(self) -> int:
+        return (self.db.n + self.chunk - 1) // self.chunk
+
+    def submit(self, req: Request):
+        self.queue.append(req)
+
+    # -------------------------------------------------------------- admission
+    def _admit(self):
+        now = self.now()
+        while self.queue and self.free and self.queue[0].arrival <= now:
+            free_b, _ = torch.cuda.mem_get_info(self.dev)
+            if free_b - self.request_bytes() < self.hbm_reserve:
+                break
+            req = self.queue.popleft()
+            slot = self.free.pop()
+            req.slot = slot
+            req.snapshot = self.db.n
+            req.remaining = set(range((req.snapshot + self.chunk - 1) // self.chunk))
+            req.admitted_at = now
+            c = torch.from_numpy(np.ascontiguousarray(req.code).view(np.int64).reshape(1, 200)).to(self.dev)
+            m = torch.from_numpy(np.ascontiguousarray(req.mask).view(np.int64).reshape(1, 200)).to(self.dev)
+            self.ctx.share_query(c, m, 1, req.qid, [o.data_ptr() + slot * ROW for o in self.op],
+                                 [r.data_ptr() + slot * RAW for r in self.raw])
+            self.match[slot] = [torch.zeros(2, self.R, self.nw_full, dtype=torch.int64, device=self.dev)
+                                for _ in range(3)]
+            self.active[slot] = req
+
+    # ------------------------------------------------------------------ tick
+    def tick(self) -> bool:
+        """Admit, then process the cursor's chunk for every request needing it.
+        Returns False when there was nothing to do."""
+        self._admit()
+        self._poll()
+        if not self.active:
+            return bool(self.finishing)
+        nch = self.n_chunks()
+        # advance the cursor to the next chunk some active request still needs
+        for _ in range(nch):
+            if any(self.cursor in r.remaining for r in self.active.values()):
+                break
+            self.cursor = (self.cursor + 1) % nch
+        j = self.cursor
+        reqs = [r for r in self.active.values() if j in r.remaining]
+        first = j * self.chunk
+        n_max = max(min(self.chunk, r.snapshot - first) for r in reqs)
+        while len(self.tick_ev) >= 2:
+            self.tick_ev.popleft().synchronize()
+        # one batched dot launch per party over every participating request's rows
+        b = self.ticks % self.ring
+        if self.rows_ev[b] is not None:
+            self.rows_ev[b].synchronize()
+        table = np.array([(r.slot, int(sft)) for r in reqs for sft in self.rot], dtype=np.int32)
+        k = table.shape[0]
+        self.rows_host[b][:k].copy_(torch.from_numpy(table))
+        self.rows_dev[b][:k].copy_(self.rows_host[b][:k], non_blocking=True)
+        self.rows_ev[b] = torch.cuda.Event()
+        self.rows_ev[b].record()
+        for p in range(3):
+            self.ctx.dot_shares_rows(p, self.op[p], self.slots, self.rows_dev[b], k, self.db.regions[p],
+                                     self.db.capacity, first, n_max, self.dot_code[p], self.dot_mask[p], self.ld)
+        # per request: reshare and compare its rows into its match buffer
+        for i, r in enumerate(reqs):
+            n_j = min(self.chunk, r.snapshot - first)
+            ids = make_ids(r.qid, self.rot, first)
+            off = 2 * i * self.R * self.ld
+            add_c = [self.dot_code[p].data_ptr() + off for p in range(3)]
+            add_m = [self.dot_mask[p].data_ptr() + off for p in range(3)]
+            s = r.slot
+            self.ctx.reshare(add_c, add_m, self.R, n_j, self.ld, ids, self.msg[s], self.rep_code[s],
+                             self.rep_mask[s])
+            mw = [m.data_ptr() + 8 * (first // 64) for m in self.match[s]]
+            self.ctx.compare_threshold(self.rep_code[s], self.rep_mask[s], self.R, n_j, self.ld, ids, mw,
+                                       self.nw_full)
+            r.remaining.discard(j)
+            self.cmps += self.R * n_j
+            if not r.remaining:
+                self._finish(r)
+        self.cursor = (j + 1) % max(1, self.n_chunks())
+        self.ticks += 1
+        ev = torch.cuda.Event()
+        ev.record()
+        self.tick_ev.append(ev)
+        return True
+
+    def _finish(self, r: Request):
+        s = r.slot
+        ids = make_ids(r.qid, self.rot, 0)
+        nw = (r.snapshot + 63) // 64
+        self.ctx.or_tree(self.match[s], 1, nw, self.nw_full, ids, self.ws, self.ws.numel(), self.dup[s])
+        self.ctx.open(OPEN_U8_XOR, self.dup[s], 1, self.open_dev.data_ptr() + s, 0)
+        self.open_host[s:s + 1].copy_(self.open_dev[s:s + 1], non_blocking=True)
+        if self.keep_shares:
+            r.dup_shares = torch.stack([d[0, 0] for d in self.dup[s]])
+        ev = torch.cuda.Event()
+        ev.record()
+        del self.active[s]
+        self.finishing.append((r, ev))
+
+    def _poll(self):
+        keep = []
+        for r, ev in self.finishing:
+            if not ev.query():
+                keep.append((r, ev))
+                continue
+            r.dup = int(self.open_host[r.slot].item())
+            r.done_at = self.now()
+            if self.keep_shares:
+                r.dup_shares = r.dup_shares.cpu().numpy()
+                r.match = [m.cpu().numpy() for m in self.match[r.slot]]
+            if r.dup == 0 and self.append_uniques and self.db.n < self.max_entries:
+                raw = [x.data_ptr() + r.slot * RAW for x in self.raw]
+                r.entry = self.db.n
+                self.ctx.append_db(raw, 0, self.db.regions, self.db.capacity, r.entry)
+                self.db.n += 1
+            self.match[r.slot] = None
+            self.free.append(r.slot)
+            self.done.append(r)
+        self.finishing = keep
+
+    # ------------------------------------------------------------------- run
+    def run(self, requests, until_idle: bool = True, timeout: float = 600.0):
+        """Feed requests (sorted by arrival) and tick until all are done."""
+        for r in sorted(requests, key=lambda x: x.arrival):
+            self.submit(r)
+        self.t0 = time.perf_counter()
+        total = len(self.queue)
+        while len(self.done) < total:
+            if self.now() > timeout:
+                raise TimeoutError("serving run exceeded its time limit")
+            busy = self.tick()
+            if not busy:
+                if self.finishing:
+                    torch.cuda.synchronize()
+                elif self.queue:
+                    wait = self.queue[0].arrival - self.now()
+                    if wait > 0:
+                        time.sleep(min(wait, 0.01))
+        torch.cuda.synchronize()
+        return self.done
+
+
+def plain_check(ctx: Context, db, req: Request, rot, buf_cache: dict):
+    """The per-query path: one request checked alone against the whole
+    database in one pass (its own dot launches, no batching)."""
+    from .pipeline import SharedQueries, alloc_check, open_dup, run_check
+
+    n = db.n
+    key = (len(rot), n)
+    if key not in buf_cache:
+        buf_cache.clear()
+        buf_cache[key] = alloc_check(1, len(rot), n)
+    buf = buf_cache[key]
+    c = torch.from_numpy(np.ascontiguousarray(req.code).view(np.int64).reshape(1, 200)).cuda()
+    m = torch.from_numpy(np.ascontiguousarray(req.mask).view(np.int64).reshape(1, 200)).cuda()
+    qs = SharedQueries(ctx, c, m, req.qid)
+    run_check(ctx, qs, rot, db, 0, n, buf)
+    out, _ = open_dup(ctx, buf, 1, check=0)
+    return qs, out

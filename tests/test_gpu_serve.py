@@ -1,0 +1,102 @@
+"""Continuous-batching service: results are the same alone, in a mix (joining
+mid-cycle at another chunk) and on the plain per-query path; opened results
+agree with the oracle; unique requests are appended."""
+import numpy as np
+import pytest
+
+import oracle as orc
+import workload as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+ROT = [-2, 0, 3]
+N0, CHUNK = 600, 128          # 5 chunks, the last one ragged
+
+
+@pytest.fixture(scope="module")
+def env(keys):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_04463_amd as imc
+
+    dealer, party = keys
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=16 * len(ROT))
+    dc, dm = wl.gen_codes(71, 0, N0)
+    qc, qm = wl.gen_codes(71, 0, 8, query=True)
+    qc[0], qm[0] = wl.plant(71, 0, dc[300], dm[300], 3, h=0.2)     # X: matches entry 300
+    qc[1], qm[1] = wl.plant(71, 1, dc[599], dm[599], -2, h=0.3)    # matches the ragged last chunk
+    yield dict(imc=imc, ctx=ctx, dc=dc, dm=dm, qc=qc, qm=qm, dealer=dealer, party=party)
+    ctx.close()
+
+
+def _db(e, capacity=N0 + 16):
+    from paper_2405_04463_amd.pipeline import SharedDB
+
+    db = SharedDB(e["ctx"], capacity)
+    d64 = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()  # noqa: E731
+    db.enroll(d64(e["dc"]), d64(e["dm"]), 0)
+    torch.cuda.synchronize()
+    return db
+
+
+def _req(e, i, qid):
+    from paper_2405_04463_amd.serve import Request
+
+    return Request(rid=i, qid=qid, code=e["qc"][i].copy(), mask=e["qm"][i].copy())
+
+
+def _drive(srv, reqs_at_tick):
+    """Submit requests at given tick numbers and tick until all are done."""
+    total = len(srv.done) + sum(len(v) for v in reqs_at_tick.values())
+    t = 0
+    while len(srv.done) < total:
+        for r in reqs_at_tick.get(t, []):
+            srv.submit(r)
+        if not srv.tick():
+            torch.cuda.synchronize()
+        t += 1
+        assert t < 1000
+    torch.cuda.synchronize()
+    return {r.rid: r for r in srv.done}
+
+
+def test_same_alone_in_mix_and_plain(env):
+    from paper_2405_04463_amd.serve import Server, plain_check
+
+    e = env
+    db = _db(e)
+    alone = _drive(Server(e["ctx"], db, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True),
+                   {0: [_req(e, 0, 1000)]})[0]
+    db2 = _db(e)
+    mixed = _drive(Server(e["ctx"], db2, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True),
+                   {0: [_req(e, i, 1000 + i) for i in (1, 2, 3)], 2: [_req(e, 0, 1000)], 3: [_req(e, 4, 1004)]})
+    x = mixed[0]
+    assert alone.dup == x.dup == 1
+    assert np.array_equal(alone.dup_shares, x.dup_shares)
+    for p in range(3):
+        assert np.array_equal(alone.match[p], x.match[p])
+    # the plain per-query path: one request, whole database, one pass
+    qs, out = plain_check(e["ctx"], db2, _req(e, 0, 1000), ROT, {})
+    torch.cuda.synchronize()
+    assert int(out.cpu()[0]) == 1
+    # every opened result against the plaintext decision on the admitted snapshot
+    for rid, r in mixed.items():
+        _, _, _, dup = orc.plain(e["qc"][rid:rid + 1], e["qm"][rid:rid + 1], ROT, e["dc"], e["dm"])
+        assert r.dup == int(dup[0]), rid
+    assert mixed[1].dup == 1
+
+
+def test_unique_requests_are_appended(env):
+    from paper_2405_04463_amd.serve import Request, Server
+
+    e = env
+    db = _db(e)
+    srv = Server(e["ctx"], db, ROT, chunk=CHUNK, slots=8, append=True)
+    done = _drive(srv, {0: [_req(e, 5, 2005)]})
+    y = done[5]
+    assert y.dup == 0 and y.entry == N0 and db.n == N0 + 1
+    # a later request carrying the same code and mask now matches the appended entry
+    z = Request(rid=9, qid=2009, code=e["qc"][5].copy(), mask=e["qm"][5].copy())
+    done = _drive(srv, {0: [z]})
+    assert done[9].dup == 1 and done[9].snapshot == N0 + 1 and db.n == N0 + 1
