@@ -375,12 +375,26 @@ def run_serve(args):
     }, (None, None, None)
 
 
+def run_copy_probe(args):
+    """A plain device-to-device copy of a known size (calibrates the HBM
+    byte counters): 1 GiB read and 1 GiB written per copy."""
+    import torch
+
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": 1 << 30, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["full", "party", "batched", "serve"], default="full")
+    ap.add_argument("--workload", choices=["full", "party", "batched", "serve", "copy-probe"], default="full")
     ap.add_argument("--n-batches", type=int, default=200)
     ap.add_argument("--chunk", type=int, default=65536)
     ap.add_argument("--slots", type=int, default=64)
@@ -391,6 +405,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dot-tiles", type=int, default=0, help="dot kernel tile configuration (IMC_DOT_TILES_*)")
     args = ap.parse_args()
+    if args.workload == "copy-probe":
+        run_copy_probe(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the protocol's three parties are simulated on it "
               "(multi-GPU party transport is not part of this build)", file=sys.stderr)

@@ -52,8 +52,9 @@ __device__ __forceinline__ uint64_t after(uint64_t pos, uint64_t dep) {
 }
 
 __device__ __forceinline__ void gen3(Blk3& b, const Keys3& keys, uint64_t stream, uint64_t pos) {
-#pragma unroll
-  for (int k = 0; k < 3; ++k) chacha12(keys.k[k], stream, pos, b.w[k]);
+  const Key* const ks[3] = {&keys.k[0], &keys.k[1], &keys.k[2]};
+  const uint64_t st[3] = {stream, stream, stream}, ps[3] = {pos, pos, pos};
+  chacha12_n<3>(ks, st, ps, b.w);
 }
 
 __device__ __forceinline__ uint64_t word64(const uint32_t* w, int u) {
@@ -149,12 +150,19 @@ __device__ __forceinline__ void bit_inject(const Keys3& keys, uint64_t stream, u
   uint64_t bA0 = 0, bA1 = 0, bB0 = 0, bB1 = 0;   // borrows of (V - c0) and (. - c2) for t = 0, 1
 #pragma unroll
   for (int g = 0; g < (K + 7) / 8; ++g) {          // 8 bits per ChaCha block
-    uint32_t C0[16], C2[16], W0[16], W1[16];
+    uint32_t blk[4][16];
     const uint64_t dep = bA0 ^ bB1;
-    chacha12(keys.k[0], stream, after(base + uint64_t(c0w / 8 + g), dep), C0);
-    chacha12(keys.k[2], stream, after(base + uint64_t(c2w / 8 + g), dep), C2);
-    chacha12(keys.k[2], stream, after(base + uint64_t(w0w / 8 + g), dep), W0);
-    chacha12(keys.k[2], stream, after(base + uint64_t(w1w / 8 + g), dep), W1);
+    {
+      const Key* const ks[4] = {&keys.k[0], &keys.k[2], &keys.k[2], &keys.k[2]};
+      const uint64_t st[4] = {stream, stream, stream, stream};
+      const uint64_t ps[4] = {after(base + uint64_t(c0w / 8 + g), dep), after(base + uint64_t(c2w / 8 + g), dep),
+                              after(base + uint64_t(w0w / 8 + g), dep), after(base + uint64_t(w1w / 8 + g), dep)};
+      chacha12_n<4>(ks, st, ps, blk);
+    }
+    const uint32_t* C0 = blk[0];
+    const uint32_t* C2 = blk[1];
+    const uint32_t* W0 = blk[2];
+    const uint32_t* W1 = blk[3];
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
       const int j = 8 * g + jj;
@@ -358,8 +366,11 @@ __global__ void __launch_bounds__(256) reshare_kernel(ReshareArgs a) {
     ld16(a.add_mask[p] + off, nval, vec, zm[p]);
   }
   uint32_t F[3][16];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) chacha12(a.keys.k[k], stream, e0 >> 4, F[k]);
+  {
+    const Key* const ks[3] = {&a.keys.k[0], &a.keys.k[1], &a.keys.k[2]};
+    const uint64_t st[3] = {stream, stream, stream}, ps[3] = {e0 >> 4, e0 >> 4, e0 >> 4};
+    chacha12_n<3>(ks, st, ps, F);
+  }
   uint16_t oc[3][16], om[3][16];
 #pragma unroll
   for (int p = 0; p < 3; ++p) {

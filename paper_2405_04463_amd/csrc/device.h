@@ -62,6 +62,43 @@ __device__ __forceinline__ void chacha12(const Key& key, uint64_t stream, uint64
   out[8] = x8 + key.w[4]; out[9] = x9 + key.w[5]; out[10] = x10 + key.w[6]; out[11] = x11 + key.w[7];
   out[12] = x12 + i12; out[13] = x13 + i13; out[14] = x14 + i14; out[15] = x15 + i15;
 }
+// N ChaCha12 blocks (keys, streams and positions may differ) in one round
+// loop, so the N independent states interleave (4N quarter-rounds per step).
+template <int N>
+__device__ __forceinline__ void chacha12_n(const Key* const keys[N], const uint64_t stream[N], const uint64_t pos[N],
+                                           uint32_t out[N][16]) {
+  uint32_t x[N][16];
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    x[b][0] = 0x61707865u; x[b][1] = 0x3320646eu; x[b][2] = 0x79622d32u; x[b][3] = 0x6b206574u;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[b][4 + i] = keys[b]->w[i];
+    x[b][12] = uint32_t(pos[b]); x[b][13] = uint32_t(pos[b] >> 32);
+    x[b][14] = uint32_t(stream[b]); x[b][15] = uint32_t(stream[b] >> 32);
+  }
+#pragma unroll 1
+  for (int r = 0; r < 6; ++r) {
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      IMC_QR(x[b][0], x[b][4], x[b][8], x[b][12]) IMC_QR(x[b][1], x[b][5], x[b][9], x[b][13])
+      IMC_QR(x[b][2], x[b][6], x[b][10], x[b][14]) IMC_QR(x[b][3], x[b][7], x[b][11], x[b][15])
+    }
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      IMC_QR(x[b][0], x[b][5], x[b][10], x[b][15]) IMC_QR(x[b][1], x[b][6], x[b][11], x[b][12])
+      IMC_QR(x[b][2], x[b][7], x[b][8], x[b][13]) IMC_QR(x[b][3], x[b][4], x[b][9], x[b][14])
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    out[b][0] = x[b][0] + 0x61707865u; out[b][1] = x[b][1] + 0x3320646eu;
+    out[b][2] = x[b][2] + 0x79622d32u; out[b][3] = x[b][3] + 0x6b206574u;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out[b][4 + i] = x[b][4 + i] + keys[b]->w[i];
+    out[b][12] = x[b][12] + uint32_t(pos[b]); out[b][13] = x[b][13] + uint32_t(pos[b] >> 32);
+    out[b][14] = x[b][14] + uint32_t(stream[b]); out[b][15] = x[b][15] + uint32_t(stream[b] >> 32);
+  }
+}
 #undef IMC_QR
 
 __device__ __forceinline__ uint64_t row_stream(uint32_t dom, uint64_t qid, int rot) {

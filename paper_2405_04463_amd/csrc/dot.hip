@@ -306,8 +306,8 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotA
   constexpr int kBStage = kBChunks * 16;
   static_assert(kBChunks % kThreads == 0, "B chunks must divide evenly");
   extern __shared__ __align__(16) int8_t lds[];
-  int8_t* bst = lds;                                           // 2 B stages
-  int8_t* ast = lds + 2 * kBStage;                             // 2 A segment buffers
+  int8_t* bst = lds;                                           // 3 B stages
+  int8_t* ast = lds + 3 * kBStage;                             // 2 A segment buffers
   const uint32_t abuf = args.max_q * 2 * kSegBytes;            // bytes per A buffer
 
   const int tid = threadIdx.x;
@@ -393,51 +393,63 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotA
   _Pragma("unroll") for (int c_ = 0; c_ < ACH; ++c_)                                  \
       if (adst[c_] >= 0) *reinterpret_cast<v4i*>(ast + (BUF) * abuf + adst[c_]) = ra[c_];
 
-  // prologue: segment 0 of A and step 0 of B staged; B steps 1..NSETS in registers
+  // Pipeline: B data for step j is global-loaded NSETS iterations ahead into
+  // register set (j - 2) % NSETS, written to LDS stage j % 3 two iterations
+  // ahead, and its fragments are read one iteration ahead (while the MFMAs
+  // of the current step run).  Stage (k+2)%3 is overwritten at iteration k;
+  // it was last read at iteration k-2.
+  v4i falo[WM], fahi[WM], fblo[WN], fbhi[WN];     // fragments of the current step
+  v4i nalo[WM], nahi[WM], nblo[WN], nbhi[WN];     // fragments of the next step
+#define IMC_FRAGS(ALO, AHI, BLO, BHI, K)                                              \
+  {                                                                                   \
+    const int kk_ = (K);                                                              \
+    const int seg_ = kk_ / kSegSteps, ts_ = kk_ - seg_ * kSegSteps;                   \
+    const int8_t* sb_ = bst + (kk_ % 3) * kBStage;                                    \
+    const int8_t* sa_ = ast + (seg_ & 1) * abuf + 32 * ts_;                           \
+    _Pragma("unroll") for (int x_ = 0; x_ < WM; ++x_) {                               \
+      const int32_t* pa_ = reinterpret_cast<const int32_t*>(sa_ + a_off[x_]);         \
+      const int32_t* ph_ = reinterpret_cast<const int32_t*>(sa_ + a_off[x_] + kSegBytes); \
+      ALO[x_] = v4i{pa_[0], pa_[1], pa_[2], pa_[3]};                                  \
+      AHI[x_] = v4i{ph_[0], ph_[1], ph_[2], ph_[3]};                                  \
+    }                                                                                 \
+    _Pragma("unroll") for (int y_ = 0; y_ < WN; ++y_) {                               \
+      const int8_t* pb_ = sb_ + (wn * WN + y_) * 2048 + lane * 16;                    \
+      BLO[y_] = *reinterpret_cast<const v4i*>(pb_);                                   \
+      BHI[y_] = *reinterpret_cast<const v4i*>(pb_ + 1024);                            \
+    }                                                                                 \
+  }
+
+  // prologue: A segment 0; B steps 0 and 1 in stages 0 and 1; steps 2.. in registers
   IMC_ALOAD(0)
   IMC_ASTORE(0)
   {
     v4i r0[kBPerThread];
     IMC_BLOAD(r0, 0)
     IMC_BSTORE(r0, 0)
+    IMC_BLOAD(r0, 1)
+    IMC_BSTORE(r0, 1)
   }
 #pragma unroll
-  for (int set = 0; set < NSETS; ++set) { IMC_BLOAD(rs[set], set + 1) }
+  for (int set = 0; set < NSETS; ++set) { IMC_BLOAD(rs[set], set + 2) }
   IMC_ALOAD(1)
   __syncthreads();
+  IMC_FRAGS(falo, fahi, fblo, fbhi, 0)
 
   for (int k0 = 0; k0 < kSteps; k0 += NSETS) {
 #pragma unroll
     for (int uu = 0; uu < NSETS; ++uu) {
       const int k = k0 + uu;
       const int seg = k / kSegSteps, ts = k - seg * kSegSteps;
-      {
-        const int8_t* sb = bst + (uu & 1) * kBStage;
-        const int8_t* sa = ast + (seg & 1) * abuf + 32 * ts;
-        v4i alo[WM], ahi[WM], blo[WN], bhi[WN];
+      IMC_FRAGS(nalo, nahi, nblo, nbhi, min(k + 1, kSteps - 1))
 #pragma unroll
-        for (int x = 0; x < WM; ++x) {
-          const int32_t* pa = reinterpret_cast<const int32_t*>(sa + a_off[x]);
-          const int32_t* ph = reinterpret_cast<const int32_t*>(sa + a_off[x] + kSegBytes);
-          alo[x] = v4i{pa[0], pa[1], pa[2], pa[3]};
-          ahi[x] = v4i{ph[0], ph[1], ph[2], ph[3]};
-        }
+      for (int x = 0; x < WM; ++x)
 #pragma unroll
         for (int y = 0; y < WN; ++y) {
-          const int8_t* pb = sb + (wn * WN + y) * 2048 + lane * 16;
-          blo[y] = *reinterpret_cast<const v4i*>(pb);
-          bhi[y] = *reinterpret_cast<const v4i*>(pb + 1024);
+          acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fblo[y], acc0[x][y], 0, 0, 0);
+          acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fbhi[y], acc1[x][y], 0, 0, 0);
+          acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fahi[x], fblo[y], acc1[x][y], 0, 0, 0);
         }
-#pragma unroll
-        for (int x = 0; x < WM; ++x)
-#pragma unroll
-          for (int y = 0; y < WN; ++y) {
-            acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo[x], blo[y], acc0[x][y], 0, 0, 0);
-            acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo[x], bhi[y], acc1[x][y], 0, 0, 0);
-            acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ahi[x], blo[y], acc1[x][y], 0, 0, 0);
-          }
-      }
-      IMC_BSTORE(rs[uu], (uu + 1) & 1)
+      IMC_BSTORE(rs[uu], (k + 2) % 3)             // step k + 2
       // mid-segment: the next segment's query bytes go to the other A buffer
       // (last read during the previous segment), then its loads are issued
       // for the segment after it.
@@ -446,9 +458,14 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotA
         IMC_ALOAD(min(seg + 2, kSteps / kSegSteps - 1))
       }
       __syncthreads();
-      IMC_BLOAD(rs[uu], min(k + 1 + NSETS, kSteps - 1))
+      IMC_BLOAD(rs[uu], min(k + 2 + NSETS, kSteps - 1))
+#pragma unroll
+      for (int x = 0; x < WM; ++x) { falo[x] = nalo[x]; fahi[x] = nahi[x]; }
+#pragma unroll
+      for (int y = 0; y < WN; ++y) { fblo[y] = nblo[y]; fbhi[y] = nbhi[y]; }
     }
   }
+#undef IMC_FRAGS
 #undef IMC_BLOAD
 #undef IMC_BSTORE
 #undef IMC_ALOAD
@@ -529,7 +546,7 @@ hipError_t launch_rot_dot(const int8_t* qop, uint32_t q, uint32_t r, const int8_
   for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) d.rot[i] = i < int(r) ? rot[i] : 0;
   const uint32_t ntg = (d.nt + 7) / 8;
   const dim3 grid(ntg * 8 * d.mt, 1, 2);
-  const size_t lds = 2 * size_t(kBN / 32) * 2 * 2 * 32 * 16 + 2 * size_t(d.max_q) * 2 * kSegBytes;
+  const size_t lds = 3 * size_t(kBN / 32) * 2 * 2 * 32 * 16 + 2 * size_t(d.max_q) * 2 * kSegBytes;
   auto kern = rot_dot_kernel<WM, WN, WAVES_M, WAVES_N, NSETS, ACH>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));

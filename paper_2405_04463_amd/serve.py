@@ -57,13 +57,14 @@ class Request:
 
 class Server:
     def __init__(self, ctx: Context, db, rot, chunk: int = 65536, slots: int = 64, max_entries: int | None = None,
-                 hbm_reserve: int = 4 << 30, append: bool = True, keep_shares: bool = False, device=0):
+                 hbm_reserve: float = 0.01, append: bool = True, keep_shares: bool = False, device=0):
+        """hbm_reserve: fraction of the device's memory kept free by admission."""
         assert chunk % 64 == 0
         self.ctx, self.db, self.rot = ctx, db, list(rot)
         self.R = len(self.rot)
         self.chunk, self.slots = chunk, slots
         self.append_uniques, self.keep_shares = append, keep_shares
-        self.hbm_reserve = hbm_reserve
+        self.hbm_reserve = int(hbm_reserve * torch.cuda.mem_get_info(device)[1])
         self.max_entries = max_entries or db.capacity
         d = torch.device("cuda", device)
         self.dev = d
@@ -116,6 +117,13 @@ class Server:
     def submit(self, req: Request):
         self.queue.append(req)
 
+    def state(self) -> dict:
+        free_b, total_b = torch.cuda.mem_get_info(self.dev)
+        return {"queued": len(self.queue), "active": len(self.active), "finishing": len(self.finishing),
+                "done": len(self.done), "free_slots": len(self.free), "cursor": self.cursor, "ticks": self.ticks,
+                "db_n": self.db.n, "hbm_free": free_b, "hbm_total": total_b, "reserve": self.hbm_reserve,
+                "next_arrival": self.queue[0].arrival if self.queue else None, "now": self.now()}
+
     # -------------------------------------------------------------- admission
     def _admit(self):
         now = self.now()
@@ -140,11 +148,13 @@ class Server:
     # ------------------------------------------------------------------ tick
     def tick(self) -> bool:
         """Admit, then process the cursor's chunk for every request needing it.
-        Returns False when there was nothing to do."""
+        Returns False when nothing was launched (the caller then waits for the
+        device or for the next arrival; finished requests are collected by the
+        next tick)."""
         self._admit()
         self._poll()
         if not self.active:
-            return bool(self.finishing)
+            return False
         nch = self.n_chunks()
         # advance the cursor to the next chunk some active request still needs
         for _ in range(nch):

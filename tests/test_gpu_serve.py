@@ -56,7 +56,7 @@ def _drive(srv, reqs_at_tick):
         if not srv.tick():
             torch.cuda.synchronize()
         t += 1
-        assert t < 1000
+        assert t < 1000, srv.state()
     torch.cuda.synchronize()
     return {r.rid: r for r in srv.done}
 
