@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 DOM_SHARE_DB, DOM_SHARE_QUERY = 1, 2
+DOM_GALOIS_DB, DOM_GALOIS_QUERY = 6, 7
 N_GATES = 94   # AND gates per comparison: 33 (Lift) + 61 (MSB)
 
 
@@ -50,6 +51,7 @@ def lib():
         _lib.orc_prf_u64.restype = ctypes.c_uint64
         _lib.orc_threads.restype = ctypes.c_int
         _lib.orc_compare.restype = ctypes.c_int
+        _lib.orc_test_gr_inv.restype = ctypes.c_int
     return _lib
 
 
@@ -212,15 +214,64 @@ def t_compare_one(d, x, seed):
     return m, mlo.value, yo.value, counts, depth.value
 
 
-def protocol(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_base=0, first_entry=0):
+def galois_share(dealer_key: bytes, dom: int, codes, masks, first_id: int):
+    """Shamir shares over Z_2^16[X]/(X^2-X-1): [n, 2 (code, mask), 3 (party), L],
+    party p's share of pair i at positions (2i, 2i+1)."""
+    n = codes.shape[0]
+    out = np.zeros((n, 2, 3, L), dtype=np.uint16)
+    lib().orc_galois_share(ctypes.c_char_p(bytes(dealer_key)), ctypes.c_int(dom), _p(np.ascontiguousarray(codes)),
+                           _p(np.ascontiguousarray(masks)), ctypes.c_long(n), ctypes.c_uint64(first_id), _p(out))
+    return out
+
+
+def galois_local_dot(p: int, qsh, rot, dsh):
+    """Party p's additive shares of the code and mask dots from Galois shares."""
+    nq, n, r = qsh.shape[0], dsh.shape[0], len(rot)
+    oc = np.zeros((nq * r, n), dtype=np.uint16)
+    om = np.zeros((nq * r, n), dtype=np.uint16)
+    lib().orc_galois_local_dot(ctypes.c_int(p), _p(np.ascontiguousarray(qsh)), ctypes.c_int(nq), _p(_rot(rot)),
+                               ctypes.c_int(r), _p(np.ascontiguousarray(dsh)), ctypes.c_long(n), _p(oc), _p(om))
+    return oc, om
+
+
+def galois_points():
+    """(alpha [3, 2], lambda [3, 2]) as (c0, c1) coefficient pairs."""
+    a = np.zeros(6, dtype=np.uint16)
+    lam = np.zeros(6, dtype=np.uint16)
+    lib().orc_galois_points(_p(a), _p(lam))
+    return a.reshape(3, 2), lam.reshape(3, 2)
+
+
+def t_gr_mul(a, b):
+    a = np.asarray(a, dtype=np.uint16)
+    b = np.asarray(b, dtype=np.uint16)
+    out = np.zeros(2, dtype=np.uint16)
+    lib().orc_test_gr_mul(_p(a), _p(b), _p(out))
+    return out
+
+
+def t_gr_inv(a):
+    a = np.asarray(a, dtype=np.uint16)
+    out = np.zeros(2, dtype=np.uint16)
+    ok = lib().orc_test_gr_inv(_p(a), _p(out))
+    return out if ok else None
+
+
+def protocol(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_base=0, first_entry=0, scheme="aby3"):
     """The whole shared protocol on the CPU: share, per-party local dots,
     reshare, compare, OR-tree.  Returns a dict of every intermediate."""
     nq, r = qc.shape[0], len(rot)
-    qsh = share(dealer_key, DOM_SHARE_QUERY, qc, qm, qid_base)
-    dsh = share(dealer_key, DOM_SHARE_DB, dc, dm, first_entry)
+    if scheme == "galois":
+        qsh = galois_share(dealer_key, DOM_GALOIS_QUERY, qc, qm, qid_base)
+        dsh = galois_share(dealer_key, DOM_GALOIS_DB, dc, dm, first_entry)
+        dot = galois_local_dot
+    else:
+        qsh = share(dealer_key, DOM_SHARE_QUERY, qc, qm, qid_base)
+        dsh = share(dealer_key, DOM_SHARE_DB, dc, dm, first_entry)
+        dot = local_dot
     zc, zm = [], []
     for p in range(3):
-        c, m = local_dot(p, qsh, rot, dsh)
+        c, m = dot(p, qsh, rot, dsh)
         zc.append(c)
         zm.append(m)
     zc = np.stack(zc)

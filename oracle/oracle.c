@@ -22,6 +22,12 @@
  *       Lift of ml to Z_2^32 [App. D "Lift"], ConstLift of the code dot
  *       [App. D "ConstLift", Sec. 5.1], MSB by BitExtract [App. D, Sec. 5.2],
  *       OR-tree [Sec. 4.2], opening.
+ *   O3  the dot product on Shamir shares over the Galois ring
+ *       Z_2^16[X]/(X^2 - X - 1) [Sec. 4.3.2]: dealer sharing of packed
+ *       bit pairs with degree-1 polynomials at the points 1, X, 1 + X,
+ *       Lagrange-premultiplied query shares, constant terms of the ring
+ *       products summed into additive shares; resharing, comparison and
+ *       OR-tree then run as in O2.
  *
  * Readings of the paper taken here (each is listed in the design notes):
  *   - parties are 0-based: party p holds components (x_p, x_{p-1 mod 3})
@@ -61,6 +67,8 @@
 #define DOM_RESHARE 3u
 #define DOM_CMP 4u
 #define DOM_OR 5u
+#define DOM_GALOIS_DB 6u
+#define DOM_GALOIS_QUERY 7u
 
 /* Circuit layout of one comparison (gate numbers index the PRF tape). */
 #define LIFT_M 17            /* Lift extracts bits {17,16}: 33 AND gates */
@@ -604,6 +612,150 @@ void orc_or_tree(const uint8_t* keys, const uint64_t* match, int nq, int r, long
     free(cur);
   }
   if (and_words) *and_words = tot;
+}
+
+/* ------------------------------------------------------------------ */
+/* Shamir sharing over the Galois ring GR = Z_2^16[X]/(X^2 - X - 1)    */
+/* [Sec. 4.3.2, "Optimized 3-party Shamir over Galois Rings" and       */
+/* "Iris Membership using Shamir Sharing over Galois Rings"].          */
+/*                                                                      */
+/* Two consecutive elements of the encoded vector form one ring element */
+/* g = x[2i] + x[2i+1] X.  The dealer shares g with a degree-1          */
+/* polynomial f(Y) = g + r Y (r uniform in GR) and gives party p the    */
+/* evaluation f(alpha_p); the secret sits at Y = 0.  Party p multiplies */
+/* its query share by its Lagrange coefficient lambda_p (interpolation  */
+/* at 0 from alpha_0..alpha_2); the constant term of lambda_p g_p h_p,  */
+/* summed over the packed pairs, is party p's additive share of the     */
+/* dot product, because the three products are points of a degree-2     */
+/* polynomial whose value at 0 is g h.                                  */
+/* ------------------------------------------------------------------ */
+typedef struct { uint16_t c0, c1; } gr;   /* c0 + c1 X */
+
+static gr gr_make(uint16_t c0, uint16_t c1) { gr a = {c0, c1}; return a; }
+static gr gr_add(gr a, gr b) { return gr_make((uint16_t)(a.c0 + b.c0), (uint16_t)(a.c1 + b.c1)); }
+static gr gr_sub(gr a, gr b) { return gr_make((uint16_t)(a.c0 - b.c0), (uint16_t)(a.c1 - b.c1)); }
+
+/* (a0 + a1 X)(b0 + b1 X) = a0 b0 + (a0 b1 + a1 b0) X + a1 b1 X^2, and
+ * X^2 = X + 1 in the quotient ring. */
+static gr gr_mul(gr a, gr b) {
+  uint32_t x0 = (uint32_t)a.c0 * b.c0, x1 = (uint32_t)a.c0 * b.c1 + (uint32_t)a.c1 * b.c0;
+  uint32_t x2 = (uint32_t)a.c1 * b.c1;
+  return gr_make((uint16_t)(x0 + x2), (uint16_t)(x1 + x2));
+}
+
+/* Inverse: (a0 + a1 X)(c0 + c1 X) = 1 is the linear system
+ *   a0 c0 + a1 c1 = 1,   a1 c0 + (a0 + a1) c1 = 0,
+ * solvable iff its determinant a0 (a0 + a1) - a1^2 is odd (a unit of
+ * Z_2^16).  Returns 0 if a is not a unit. */
+static int gr_inv(gr a, gr* out) {
+  uint16_t det = (uint16_t)((uint32_t)a.c0 * (uint16_t)(a.c0 + a.c1) - (uint32_t)a.c1 * a.c1);
+  if (!(det & 1u)) return 0;
+  uint16_t y = 1;   /* Newton iteration for 1/det mod 2^16: each step doubles the correct bits */
+  for (int it = 0; it < 5; ++it) y = (uint16_t)(y * (uint16_t)(2u - (uint32_t)det * y));
+  *out = gr_make((uint16_t)((uint32_t)(uint16_t)(a.c0 + a.c1) * y), (uint16_t)(-(uint32_t)a.c1 * y));
+  return 1;
+}
+
+/* Evaluation points: an exceptional sequence {0, 1, X, 1 + X} (pairwise
+ * differences are units); 0 carries the secret, party p uses alpha_p. */
+static gr gr_alpha(int p) {
+  return p == 0 ? gr_make(1, 0) : p == 1 ? gr_make(0, 1) : gr_make(1, 1);
+}
+
+/* Lagrange coefficient of party p for interpolation at 0 from alpha_0..2:
+ * lambda_p = prod_{j != p} alpha_j / (alpha_j - alpha_p). */
+static gr gr_lambda(int p) {
+  gr l = gr_make(1, 0);
+  for (int j = 0; j < 3; ++j) {
+    if (j == p) continue;
+    gr inv;
+    if (!gr_inv(gr_sub(gr_alpha(j), gr_alpha(p)), &inv)) abort();   /* cannot happen: exceptional sequence */
+    l = gr_mul(l, gr_mul(gr_alpha(j), inv));
+  }
+  return l;
+}
+
+/* Share n vectors: out is [n][vec 2][party 3][L] u16; party p's share of
+ * pair i is (out[2i], out[2i+1]) = g_i + r_i alpha_p.  r_i = (u16 number 2i,
+ * u16 number 2i+1) of the dealer stream (dom<<56)|(vec<<52)|id. */
+void orc_galois_share(const uint8_t* dealer_key, int dom, const uint64_t* codes, const uint64_t* masks,
+                      long n, uint64_t first_id, uint16_t* out) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (long e = 0; e < n; ++e) {
+    uint16_t x[2][ORC_L];
+    orc_encode(codes + (size_t)e * ORC_W, masks + (size_t)e * ORC_W, x[0], x[1]);
+    uint64_t id = (first_id + (uint64_t)e) & 0xFFFFFFFFFFFFull;
+    for (int vec = 0; vec < 2; ++vec) {
+      uint16_t* o = out + ((size_t)e * 2 + vec) * 3 * ORC_L;
+      uint64_t st = ((uint64_t)dom << 56) | ((uint64_t)vec << 52) | id;
+      uint32_t b[16];
+      for (int i = 0; i < ORC_L / 2; ++i) {
+        if ((i & 15) == 0) prf_block(dealer_key, st, (uint64_t)(i >> 4), b);   /* 16 pairs per block */
+        uint32_t w = b[i & 15];
+        gr r = gr_make((uint16_t)(w & 0xFFFF), (uint16_t)(w >> 16));
+        gr g = gr_make(x[vec][2 * i], x[vec][2 * i + 1]);
+        for (int p = 0; p < 3; ++p) {
+          gr sh = gr_add(g, gr_mul(r, gr_alpha(p)));
+          o[(size_t)p * ORC_L + 2 * i] = sh.c0;
+          o[(size_t)p * ORC_L + 2 * i + 1] = sh.c1;
+        }
+      }
+    }
+  }
+}
+
+/* Party p's additive share of <x, y> for every query row and entry:
+ *   z_p = sum_i const( (lambda_p g_i) h_i )   (mod 2^16)
+ * with g_i the party's share of query pair i (after rotating the share
+ * vector: rotations move whole 4-element columns, so pairs stay pairs) and
+ * h_i its share of the entry's pair i.  qsh: [nq][2][3][L], dsh: [n][2][3][L]
+ * as written by orc_galois_share.  out_code/out_mask: [rows][n]. */
+void orc_galois_local_dot(int p, const uint16_t* qsh, int nq, const int* rot, int r,
+                          const uint16_t* dsh, long n, uint16_t* out_code, uint16_t* out_mask) {
+  long rows = (long)nq * r;
+  gr lam = gr_lambda(p);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (long row = 0; row < rows; ++row) {
+    int qi = (int)(row / r), s = rot[row % r];
+    static __thread gr g[2][ORC_L / 2];   /* lambda_p times the rotated share */
+    for (int vec = 0; vec < 2; ++vec) {
+      const uint16_t* q = qsh + (((size_t)qi * 2 + vec) * 3 + p) * ORC_L;
+      for (int i = 0; i < ORC_L / 2; ++i)
+        g[vec][i] = gr_mul(lam, gr_make(q[rot_src(2 * i, s)], q[rot_src(2 * i + 1, s)]));
+    }
+    for (long e = 0; e < n; ++e) {
+      for (int vec = 0; vec < 2; ++vec) {
+        const uint16_t* d = dsh + (((size_t)e * 2 + vec) * 3 + p) * ORC_L;
+        uint16_t z = 0;
+        for (int i = 0; i < ORC_L / 2; ++i) z = (uint16_t)(z + gr_mul(g[vec][i], gr_make(d[2 * i], d[2 * i + 1])).c0);
+        uint16_t* o = vec ? out_mask : out_code;
+        o[(size_t)row * n + e] = z;
+      }
+    }
+  }
+}
+
+/* Test hooks for the ring arithmetic. */
+void orc_test_gr_mul(const uint16_t* a, const uint16_t* b, uint16_t* out) {
+  gr z = gr_mul(gr_make(a[0], a[1]), gr_make(b[0], b[1]));
+  out[0] = z.c0;
+  out[1] = z.c1;
+}
+int orc_test_gr_inv(const uint16_t* a, uint16_t* out) {
+  gr z;
+  if (!gr_inv(gr_make(a[0], a[1]), &z)) return 0;
+  out[0] = z.c0;
+  out[1] = z.c1;
+  return 1;
+}
+void orc_galois_points(uint16_t* alpha, uint16_t* lambda) {
+  for (int p = 0; p < 3; ++p) {
+    gr a = gr_alpha(p), l = gr_lambda(p);
+    alpha[2 * p] = a.c0;
+    alpha[2 * p + 1] = a.c1;
+    lambda[2 * p] = l.c0;
+    lambda[2 * p + 1] = l.c1;
+  }
 }
 
 /* ------------------------------------------------------------------ */
