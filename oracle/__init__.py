@@ -257,6 +257,50 @@ def t_gr_inv(a):
     return out if ok else None
 
 
+def mask_in_batch(match, q: int, r: int, word: int):
+    """Clear shared match bits of columns j >= qi in `word` of rows qi*r+ri (copy)."""
+    out = np.ascontiguousarray(match, dtype=np.uint64).copy()
+    lib().orc_mask_in_batch(_p(out), ctypes.c_int(q), ctypes.c_int(r), ctypes.c_long(out.shape[-1]),
+                            ctypes.c_long(word))
+    return out
+
+
+def or_bits(keys: bytes, a, b, id_: int):
+    """Shared OR of two bit sharings [3, count] (0/1 bytes)."""
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    out = np.zeros_like(a)
+    lib().orc_or_bits(ctypes.c_char_p(bytes(keys)), _p(a), _p(b), ctypes.c_long(a.shape[1]), ctypes.c_uint64(id_),
+                      _p(out))
+    return out
+
+
+BATCH_ENTRY_BASE = 1 << 47    # entry ids of in-batch columns (distinct randomness from database entries)
+
+
+def protocol_in_batch(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_base=0, scheme="aby3"):
+    """Protocol run where each query is also compared with the earlier queries
+    of its batch: database part as `protocol`; batch part with the queries'
+    own shares as entries (ids BATCH_ENTRY_BASE + j), columns j >= qi cleared,
+    its OR-tree, then one OR gate per query combining both decisions."""
+    q, r = qc.shape[0], len(rot)
+    res = protocol(dealer_key, keys, qc, qm, rot, dc, dm, qid_base=qid_base, first_entry=0, scheme=scheme)
+    qsh = res["qsh"]
+    dot = galois_local_dot if scheme == "galois" else local_dot
+    zc, zm = [], []
+    for p in range(3):
+        c, m = dot(p, qsh, rot, qsh)
+        zc.append(c)
+        zm.append(m)
+    rc, rm = reshare(keys, np.stack(zc), np.stack(zm), q, rot, qid_base, BATCH_ENTRY_BASE)
+    bm = compare(keys, rc, rm, q, rot, qid_base, BATCH_ENTRY_BASE)
+    bm = mask_in_batch(bm, q, r, 0)
+    dup_b, _ = or_tree(keys, bm, q, r, qid_base + (1 << 46))
+    dup = or_bits(keys, res["dup"], dup_b, qid_base)
+    res.update(batch_match=bm, dup_db=res["dup"], dup_batch=dup_b, dup=dup)
+    return res
+
+
 def protocol(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_base=0, first_entry=0, scheme="aby3"):
     """The whole shared protocol on the CPU: share, per-party local dots,
     reshare, compare, OR-tree.  Returns a dict of every intermediate."""

@@ -69,6 +69,7 @@
 #define DOM_OR 5u
 #define DOM_GALOIS_DB 6u
 #define DOM_GALOIS_QUERY 7u
+#define DOM_OR_PAIRS 8u
 
 /* Circuit layout of one comparison (gate numbers index the PRF tape). */
 #define LIFT_M 17            /* Lift extracts bits {17,16}: 33 AND gates */
@@ -612,6 +613,45 @@ void orc_or_tree(const uint8_t* keys, const uint64_t* match, int nq, int r, long
     free(cur);
   }
   if (and_words) *and_words = tot;
+}
+
+/* ------------------------------------------------------------------ */
+/* In-batch matching and combining decisions [Sec. 6.3: the queries of a */
+/* batch are also matched with each other; a person's query covers both  */
+/* eyes].  Query i of a batch is compared with the earlier queries j < i  */
+/* only: the shared match bits of columns j >= i are replaced by public   */
+/* zeros (every component cleared).  Two shared decisions are combined    */
+/* with one OR gate, x OR y = x ^ y ^ (x AND y).                          */
+/* ------------------------------------------------------------------ */
+
+/* match: [3][q*r][nw] components; clears bits j >= qi of word `word` in
+ * every row qi*r + ri. */
+void orc_mask_in_batch(uint64_t* match, int q, int r, long nw, long word) {
+  long rows = (long)q * r;
+  for (int p = 0; p < 3; ++p)
+    for (long row = 0; row < rows; ++row) {
+      int qi = (int)(row / r);
+      uint64_t keep = qi >= 64 ? ~0ull : ((1ull << qi) - 1);   /* columns j < qi */
+      match[((size_t)p * rows + row) * nw + word] &= keep;
+    }
+}
+
+/* a, b, out: [3][count] bit components (0/1 bytes).  AND randomness of
+ * element i: bit i%64 of u64 word i/64 of stream (DOM_OR_PAIRS<<56)|id. */
+void orc_or_bits(const uint8_t* keys, const uint8_t* a, const uint8_t* b, long count, uint64_t id, uint8_t* out) {
+  uint64_t st = ((uint64_t)DOM_OR_PAIRS << 56) | (id & 0xFFFFFFFFFFFFull);
+  for (long i = 0; i < count; ++i) {
+    uint8_t f[3];
+    for (int k = 0; k < 3; ++k) f[k] = (uint8_t)((prf_u64_at(keys + 32 * k, st, 0, (uint64_t)(i >> 6)) >> (i & 63)) & 1u);
+    bsh x, y;
+    for (int p = 0; p < 3; ++p) {
+      x.c[p] = a[(size_t)p * count + i];
+      y.c[p] = b[(size_t)p * count + i];
+    }
+    x.depth = y.depth = 0;
+    bsh z = band(x, y, f, NULL);
+    for (int p = 0; p < 3; ++p) out[(size_t)p * count + i] = (uint8_t)(x.c[p] ^ y.c[p] ^ z.c[p]);
+  }
 }
 
 /* ------------------------------------------------------------------ */
