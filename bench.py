@@ -24,8 +24,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MFMA_I8_PEAK_TOPS = 5000.0      # MI355X dense int8, tera-ops/s (MAC = 2 ops)
+# HBM traffic of one launch of the rotation-aware dot kernel (one party, 1,984
+# rows x 300,000 entries) from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch, mean of 6 dispatches), each scaled by what the
+# same counter reads for a 1 GiB device-to-device copy (FETCH_SIZE 524,302 KiB,
+# WRITE_SIZE 1,048,576 KiB).  Valid only for the kernel sources it was taken on.
+DOT_TRAFFIC = {
+    "sources": {"paper_2405_04463_amd/csrc/rot_dot.hip":
+                "7a7ddcc20211c99ace441cbe7b4f5c49a692e7c1d6b804df5435364dff4826a2",
+                "paper_2405_04463_amd/csrc/device.h":
+                "3e53df8914cf80bb8a047b8fe1f898529ac56bcc5dfdbef638b8d1cac403cbf4"},
+    "rows": 1984, "n_db": 300_000,
+    "fetch_kib": 16_902_297.6, "write_kib": 2_329_111.2,
+    "fetch_scale": 1_048_576 / 524_302.0, "write_scale": 1.0,
+}
+
 HBM_PEAK_GBS = 8000.0
 OPS_PER_CMP_PARTY = 2 * 2 * 12800 * 3 * 2   # (code, mask) x K=25,600 x 3 limb products x 2 ops = 307,200
+DB_BYTES_PER_ENTRY_PARTY = 4 * 2 * 12800      # 4 limb planes x K=25,600 bytes = 102,400
+
+
+def dot_traffic(rows, n_db, dot_tiles):
+    """HBM bytes per dot launch from the stored counter passes, or None when
+    the workload, the kernel configuration or its sources differ."""
+    t = DOT_TRAFFIC
+    if rows != t["rows"] or n_db != t["n_db"] or dot_tiles not in (0, 4):
+        return None
+    for rel, digest in t["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
 
 
 def log(msg):
@@ -50,7 +79,7 @@ def enroll_db(ctx, db, seed, n, chunk=32768):
     torch.cuda.synchronize()
 
 
-def cpu_baseline(w, qc, qm, sample_q=4, sample_n=8192):
+def cpu_baseline(w, qc, qm, sample_q=4, sample_n=8192, galois=False):
     """The oracle's step (local dots of all parties, reshare, compare, OR-tree)
     on a bounded sample of the same workload; shares made before timing."""
     import oracle as orc
@@ -58,12 +87,18 @@ def cpu_baseline(w, qc, qm, sample_q=4, sample_n=8192):
 
     dealer, party = keys()
     dc, dm = wl.gen_codes(w.seed, 0, sample_n)
-    qsh = orc.share(dealer, orc.DOM_SHARE_QUERY, qc[:sample_q], qm[:sample_q], 0)
-    dsh = orc.share(dealer, orc.DOM_SHARE_DB, dc, dm, 0)
+    if galois:
+        qsh = orc.galois_share(dealer, orc.DOM_GALOIS_QUERY, qc[:sample_q], qm[:sample_q], 0)
+        dsh = orc.galois_share(dealer, orc.DOM_GALOIS_DB, dc, dm, 0)
+        local_dot = orc.galois_local_dot
+    else:
+        qsh = orc.share(dealer, orc.DOM_SHARE_QUERY, qc[:sample_q], qm[:sample_q], 0)
+        dsh = orc.share(dealer, orc.DOM_SHARE_DB, dc, dm, 0)
+        local_dot = orc.local_dot
     t0 = time.perf_counter()
     zc, zm = [], []
     for p in range(3):
-        c, m = orc.local_dot(p, qsh, w.rot, dsh)
+        c, m = local_dot(p, qsh, w.rot, dsh)
         zc.append(c)
         zm.append(m)
     rc, rm = orc.reshare(party, np.stack(zc), np.stack(zm), sample_q, w.rot, 0, 0)
@@ -115,12 +150,15 @@ def run_full(args):
 
     w = wl.full_protocol(n_db=args.n_db, n_q=args.n_q)
     dealer, party = keys()
+    galois = args.scheme == "galois"
     ctx = imc.Context(imc.Keys(dealer, party), max_rows=w.rows, dot_tiles=args.dot_tiles)
-    log(f"enrolling {w.n_db} entries x 3 parties ({3 * imc.db_bytes(w.n_db) / 1e9:.1f} GB)")
-    db = SharedDB(ctx, w.n_db)
+    nbytes = imc.galois_db_bytes(w.n_db) if galois else imc.db_bytes(w.n_db)
+    log(f"enrolling {w.n_db} entries x 3 parties ({3 * nbytes / 1e9:.1f} GB, {args.scheme} shares)")
+    db = SharedDB(ctx, w.n_db, galois=galois)
     enroll_db(ctx, db, w.seed, w.n_db)
     qc, qm = wl.make_queries(w)
-    qs = SharedQueries(ctx, torch.from_numpy(qc.view(np.int64)).cuda(), torch.from_numpy(qm.view(np.int64)).cuda(), 0)
+    qs = SharedQueries(ctx, torch.from_numpy(qc.view(np.int64)).cuda(), torch.from_numpy(qm.view(np.int64)).cuda(), 0,
+                       galois=galois)
     buf = alloc_check(w.n_q, len(w.rot), w.n_db)
     torch.cuda.synchronize()
     log("first step + verification against the oracle")
@@ -137,7 +175,7 @@ def run_full(args):
             if events is not None:
                 events[p][0].record(stream)
             ctx.dot_shares(p, qs.op[p], qs.q, ids, db.regions[p], db.capacity, w.n_db, buf.dot_code[p],
-                           buf.dot_mask[p], buf.ld, stream)
+                           buf.dot_mask[p], buf.ld, stream, galois=galois)
             if events is not None:
                 events[p][1].record(stream)
         ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, w.n_db, buf.ld, ids, buf.msg, buf.rep_code, buf.rep_mask,
@@ -167,8 +205,11 @@ def run_full(args):
     ncmp = w.rows * w.n_db
     ms = total / args.steps * 1e3
     dot_avg_s = float(np.mean(dot_ms)) / 1e3
-    ops = ncmp * OPS_PER_CMP_PARTY
+    ops = ncmp * (OPS_PER_CMP_PARTY // 2 if galois else OPS_PER_CMP_PARTY)
     achieved = ops / dot_avg_s / 1e12
+    traffic = None if galois else dot_traffic(w.rows, w.n_db, args.dot_tiles)
+    entry_bytes = DB_BYTES_PER_ENTRY_PARTY // 2 if galois else DB_BYTES_PER_ENTRY_PARTY
+    alg_bytes = w.n_db * entry_bytes + 2 * 2 * w.rows * w.n_db   # DB region read + u16 outputs
     res = {
         "metric": "shared iris comparisons/sec on 1 MI355X (bit-exact); p50/p99 query latency",
         "value": ncmp / (total / args.steps),
@@ -176,14 +217,17 @@ def run_full(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
         "config": {"workload": f"3-party protocol on one GPU: DB {w.n_db} entries per party, {w.n_q} queries x "
-                               f"{len(w.rot)} rotations ({w.rows} rows)",
-                   "rows": w.rows, "db_entries": w.n_db, "parties": 3},
+                               f"{len(w.rot)} rotations ({w.rows} rows)"
+                               + (", dot products on Galois-ring Shamir shares" if galois else ""),
+                   "rows": w.rows, "db_entries": w.n_db, "parties": 3, "sharing": args.scheme},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                        "note": "one batch of all queries per step; per-query latency = step latency"},
-        "roofline": {"bound": "mfma", "kernel": "dot_shares (one party: rotation expand + i8 MFMA dot)",
+        "roofline": {"bound": "mfma", "kernel": "dot_shares (one party, i8 MFMA over byte limbs)",
                      "achieved": achieved, "peak": MFMA_I8_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / MFMA_I8_PEAK_TOPS, "traffic": None,
-                     "ops_per_launch": ops, "avg_launch_ms": dot_avg_s * 1e3},
+                     "frac": achieved / MFMA_I8_PEAK_TOPS, "traffic": traffic,
+                     "ops_per_launch": ops, "avg_launch_ms": dot_avg_s * 1e3,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "hbm_gbs": None if traffic is None else traffic / dot_avg_s / 1e9},
         "verification": ver,
     }
     return res, (w, qc, qm)
@@ -254,12 +298,15 @@ def run_batched(args):
     nq = sum(b.q for b in batches)
     nrows = sum(b.rows for b in batches)
     ctx = imc.Context(imc.Keys(dealer, party), max_rows=nrows)
-    db = SharedDB(ctx, args.n_db, parties=(0,))
-    log(f"enrolling {args.n_db} entries (party 0, {imc.db_bytes(args.n_db) / 1e9:.1f} GB); "
+    galois = args.scheme == "galois"
+    db = SharedDB(ctx, args.n_db, parties=(0,), galois=galois)
+    nbytes = imc.galois_db_bytes(args.n_db) if galois else imc.db_bytes(args.n_db)
+    log(f"enrolling {args.n_db} entries (party 0, {nbytes / 1e9:.1f} GB, {args.scheme} shares); "
         f"{len(batches)} batches, {nq} queries, {nrows} rows")
     enroll_db(ctx, db, 0x1A150004, args.n_db)
     qc, qm = wl.gen_codes(0x1A150004, 0, nq, query=True)
-    bs = BatchSet(ctx, batches, torch.from_numpy(qc.view(np.int64)).cuda(), torch.from_numpy(qm.view(np.int64)).cuda())
+    bs = BatchSet(ctx, batches, torch.from_numpy(qc.view(np.int64)).cuda(), torch.from_numpy(qm.view(np.int64)).cuda(),
+                  galois=galois)
     st = BatchedStep(ctx, bs, db, 0, args.n_db, chunk=args.chunk, parties=(0,))
     probe = BatchedStep(ctx, bs, db, 0, min(args.n_db, 16384), parties=(0,))
     tuner = DotTuner()
@@ -295,7 +342,7 @@ def run_batched(args):
         "dtype": "u16", "data": "synthetic",
         "config": {"workload": f"{len(batches)} uneven batches (1..64 queries, 1/15/31 rotations, {nrows} rows) vs "
                                f"party-local DB {args.n_db} entries, dot products only",
-                   "chunk": args.chunk, "dot_config": int(best)},
+                   "chunk": args.chunk, "dot_config": int(best), "sharing": args.scheme},
         "plain": {"value": ncmp / t_p, "ms_per_step": t_p * 1e3, "same_outputs": same},
         "speedup_vs_plain": t_p / t_b,
     }, (None, None, None)
@@ -314,9 +361,11 @@ def run_serve(args):
     dealer, party = keys()
     rot = wl.ROT31
     ctx = imc.Context(imc.Keys(dealer, party), max_rows=args.slots * len(rot))
+    galois = args.scheme == "galois"
     cap = args.n_db + 20000
-    db = SharedDB(ctx, cap)
-    log(f"enrolling {args.n_db} entries x 3 parties ({3 * imc.db_bytes(cap) / 1e9:.1f} GB reserved)")
+    db = SharedDB(ctx, cap, galois=galois)
+    nbytes = imc.galois_db_bytes(cap) if galois else imc.db_bytes(cap)
+    log(f"enrolling {args.n_db} entries x 3 parties ({3 * nbytes / 1e9:.1f} GB reserved, {args.scheme} shares)")
     enroll_db(ctx, db, 0x1A150005, args.n_db)
     db.n = args.n_db
     rng = np.random.default_rng(5)
@@ -369,7 +418,7 @@ def run_serve(args):
         "data": "synthetic",
         "config": {"workload": f"continuous-batching service, 3 parties on one GPU, DB {args.n_db} entries per party "
                                f"(+ appends), 31 rotations, Poisson arrivals {args.rates}/s for {args.duration} s",
-                   "chunk": args.chunk, "slots": args.slots},
+                   "chunk": args.chunk, "slots": args.slots, "sharing": args.scheme},
         "latency_ms": {"p50": out["lambda"][top]["p50_ms"], "p99": out["lambda"][top]["p99_ms"], "at_lambda": top},
         "serve": out,
     }, (None, None, None)
@@ -404,6 +453,8 @@ def main():
     ap.add_argument("--n-q", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dot-tiles", type=int, default=0, help="dot kernel tile configuration (IMC_DOT_TILES_*)")
+    ap.add_argument("--scheme", choices=["replicated", "galois"], default="replicated",
+                    help="sharing of the dot-product operands (full, batched and serve workloads)")
     args = ap.parse_args()
     if args.workload == "copy-probe":
         run_copy_probe(args)
@@ -428,7 +479,7 @@ def main():
         res, (w, qc, qm) = run_serve(args)
     if not args.no_cpu_baseline and w is not None:
         log("timing the oracle on a bounded sample")
-        res["cpu_baseline"] = cpu_baseline(w, qc, qm)
+        res["cpu_baseline"] = cpu_baseline(w, qc, qm, galois=args.workload == "full" and args.scheme == "galois")
     print(json.dumps(res), flush=True)
 
 

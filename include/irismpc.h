@@ -62,13 +62,17 @@ typedef int imc_status;
  * identical results; they differ in tiling and in how rotations are formed. */
 #define IMC_DOT_TILES_AUTO 0             /* ROTATION when r >= 24, else EXPANDED_256x128 */
 #define IMC_DOT_TILES_EXPANDED_256x128 1 /* rotated rows expanded into scratch; 256 x 128 tiles,
-                                            8 waves of 64 x 64, loads 4 K-steps ahead */
+                                            8 waves of 64 x 64, global loads 4 K-steps ahead */
 #define IMC_DOT_TILES_EXPANDED_128x128 2 /* as 1 with 128 x 128 tiles, 4 waves */
-#define IMC_DOT_TILES_EXPANDED_P2 3      /* as 1 with loads 2 K-steps ahead */
+#define IMC_DOT_TILES_EXPANDED_SHALLOW 3 /* as 1 with global loads 3 K-steps ahead */
 #define IMC_DOT_TILES_ROTATION 4         /* 256 x 128 tiles; each tile's queries staged unrotated in
                                             LDS per 800-byte segment, rotations read in place
                                             (used when r >= 24, else as AUTO) */
-#define IMC_DOT_TILES_MAX 4
+#define IMC_DOT_TILES_ROTATION_DEEP 5    /* as 4 with database loads issued 10 K-steps ahead
+                                            instead of 6 */
+#define IMC_DOT_TILES_ROTATION_LDSCOPY 6 /* as 4 with both operands copied from HBM straight into
+                                            LDS (8 database stages, no staging registers) */
+#define IMC_DOT_TILES_MAX 6
 #define IMC_DOT_PERSISTENT 0x10          /* bit 4: expanded tilings run a persistent grid (one
                                             workgroup per CU walking its XCD's tile sequence) */
 
@@ -239,6 +243,92 @@ imc_status imc_open(imc_ctx* ctx, int kind, const void* const rep[3], size_t cou
  * or a held region without its qraw), IMC_ESHAPE (entry_id >= capacity). */
 imc_status imc_append_db(imc_ctx* ctx, const void* const qraw[3], size_t qi, void* const db[3],
                          size_t db_capacity, uint64_t entry_id, imc_stream stream);
+
+/* In-batch matching (Sec. 6.3: the queries of a batch are also matched with
+ * each other).  The batch's queries are compared as entries (their raw
+ * shares appended to a region with imc_append_db, compared under entry ids
+ * distinct from the database's) and query qi may only match the earlier
+ * queries j < qi: this call turns the shared match bits of columns j >= qi in
+ * word `word` of every row qi*r + ri into public zeros (all components of both
+ * planes of match[p], [2][q*r][mw_ld], are cleared).  q <= 64 (one word of
+ * columns).  Errors: IMC_EINVAL (null, unaligned, q > 64, r outside 1..32),
+ * IMC_ESHAPE (word >= mw_ld). */
+imc_status imc_mask_in_batch(imc_ctx* ctx, uint64_t* const match[3], size_t q, size_t r, size_t mw_ld, size_t word,
+                             imc_stream stream);
+
+/* Shared OR of two bit sharings (Sec. 4.2's x OR y = x ^ y ^ (x AND y), one
+ * AND gate per element): combines two decisions, e.g. a query's database and
+ * in-batch results, or the two eyes of a person.  a[p], b[p], out[p]: device
+ * u8 [2][count] (own component, then component p-1; 0/1).  The gate of
+ * element i draws bit i%64 of word i/64 of the PRF stream (8 << 56 | id); use
+ * a distinct id per combination.  Errors: IMC_EINVAL (null). */
+imc_status imc_or_bits(imc_ctx* ctx, const uint8_t* const a[3], const uint8_t* const b[3], size_t count,
+                       uint64_t id, uint8_t* const out[3], imc_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Galois-ring Shamir form of the dot products (Sec. 4.3.2, "Optimized
+ * 3-party Shamir over Galois Rings" and "Iris Membership using Shamir
+ * Sharing over Galois Rings").  Two consecutive elements of the encoded
+ * vector (masked code bits or mask bits in Z_2^16) form one element
+ * g = x_2i + x_2i+1 X of GR = Z_2^16[X]/(X^2 - X - 1); the dealer shares it
+ * with a degree-1 polynomial g + r Y and party p (p = 0, 1, 2) holds its value
+ * at alpha_p = 1, X, 1 + X.  The query side stores lambda_p times the share,
+ * lambda_p being party p's Lagrange coefficient for interpolation at 0, so the
+ * constant term of the ring product with the entry's share, summed over the
+ * 6,400 pairs, is party p's 3-party additive share of the dot product: the
+ * same kind of output as imc_dot_shares, consumed by imc_reshare,
+ * imc_compare_threshold and the rest unchanged.  A party stores one share
+ * instead of two (51,200 B per entry instead of 102,400) and computes one
+ * length-12,800 dot per vector instead of one of length 25,600.
+ * Rotations move whole 4-element columns, so pairs stay pairs and rotating a
+ * party's share vector rotates the secret.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of one party's Galois-form region for `capacity` entries: blocks of
+ * 32 entries [plane 4][k-chunk 800][slot 32][16 B] (planes as in
+ * imc_share_db). */
+size_t imc_galois_db_bytes(size_t capacity);
+/* Bytes of one party's Galois query operand / plain query shares for q queries. */
+size_t imc_galois_query_op_bytes(size_t q);
+size_t imc_galois_query_raw_bytes(size_t q);
+
+/* Enrolment in the Galois form: entry e's code and mask pairs are shared with
+ * dealer randomness r (ChaCha12, its own PRF domain, keyed by entry id) and
+ * party p's region db[p] (imc_galois_db_bytes(db_capacity) bytes, alignment
+ * 256, or NULL when not held here) receives its share coefficients, element
+ * 2i = constant coefficient and 2i+1 = X coefficient of pair i, as balanced
+ * byte limbs.  Errors as imc_share_db. */
+imc_status imc_galois_share_db(imc_ctx* ctx, const uint64_t* codes, const uint64_t* masks, size_t n,
+                               uint64_t first_entry_id, void* const db[3], size_t db_capacity,
+                               imc_stream stream);
+
+/* Query sharing in the Galois form.  qop[p]: device i8 [q][plane 4][12800],
+ * lambda_p times party p's share (coefficients as above).  qraw[p] (optional):
+ * device u16 [q][vec 2][12800], the plain share, for imc_galois_append_db.
+ * Errors as imc_share_query. */
+imc_status imc_galois_share_query(imc_ctx* ctx, const uint64_t* codes, const uint64_t* masks, size_t q,
+                                  uint64_t query_id_base, void* const qop[3], void* const qraw[3],
+                                  imc_stream stream);
+
+/* Party-local dot products in the Galois form: for every row (query qi at
+ * rotation rot[ri]) and entry e, code_dot = sum_k a_k b_k mod 2^16 over the
+ * 12,800 coefficients of party p's premultiplied rotated query share a and
+ * entry share b (the constant terms of the ring products), and mask_dot
+ * likewise.  Arguments, layouts, tile configurations and errors as
+ * imc_dot_shares, with Galois-form operand and region. */
+imc_status imc_galois_dot_shares(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_ids* ids,
+                                 const void* db, size_t db_capacity, size_t n, uint16_t* code_dot,
+                                 uint16_t* mask_dot, size_t ld, imc_stream stream);
+
+/* imc_dot_shares_rows for Galois-form operands and regions. */
+imc_status imc_galois_dot_shares_rows(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_row* rows,
+                                      size_t nrows, const void* db, size_t db_capacity, uint64_t first_entry_id,
+                                      size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
+                                      imc_stream stream);
+
+/* imc_append_db for Galois-form plain query shares and regions. */
+imc_status imc_galois_append_db(imc_ctx* ctx, const void* const qraw[3], size_t qi, void* const db[3],
+                                size_t db_capacity, uint64_t entry_id, imc_stream stream);
 
 #ifdef __cplusplus
 }

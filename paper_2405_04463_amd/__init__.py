@@ -23,11 +23,13 @@ EXPORTS = [
     "imc_create", "imc_destroy", "imc_strerror", "imc_db_bytes", "imc_query_op_bytes", "imc_query_raw_bytes",
     "imc_or_tree_ws_bytes", "imc_share_db", "imc_share_query", "imc_dot_shares", "imc_reshare",
     "imc_compare_threshold", "imc_or_tree", "imc_open", "imc_append_db", "imc_dot_shares_rows",
-    "imc_set_dot_tiles",
+    "imc_set_dot_tiles", "imc_galois_db_bytes", "imc_galois_query_op_bytes", "imc_galois_query_raw_bytes",
+    "imc_galois_share_db", "imc_galois_share_query", "imc_galois_dot_shares", "imc_galois_dot_shares_rows",
+    "imc_galois_append_db", "imc_mask_in_batch", "imc_or_bits",
 ]
 
-DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_P2, DOT_TILES_ROTATION = (
-    0, 1, 2, 3, 4)
+(DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW, DOT_TILES_ROTATION,
+ DOT_TILES_ROTATION_DEEP, DOT_TILES_ROTATION_LDSCOPY) = (0, 1, 2, 3, 4, 5, 6)
 DOT_PERSISTENT = 0x10
 
 
@@ -80,7 +82,8 @@ def lib():
         L.imc_destroy.restype = None
         L.imc_strerror.argtypes = [st]
         L.imc_strerror.restype = ctypes.c_char_p
-        for f in ("imc_db_bytes", "imc_query_op_bytes", "imc_query_raw_bytes"):
+        for f in ("imc_db_bytes", "imc_query_op_bytes", "imc_query_raw_bytes", "imc_galois_db_bytes",
+                  "imc_galois_query_op_bytes", "imc_galois_query_raw_bytes"):
             getattr(L, f).argtypes = [sz]
             getattr(L, f).restype = sz
         L.imc_or_tree_ws_bytes.argtypes = [sz, sz, sz]
@@ -96,6 +99,13 @@ def lib():
         L.imc_dot_shares_rows.argtypes = [_VP, ctypes.c_int, _VP, sz, _VP, sz, _VP, sz, ctypes.c_uint64, sz, _VP, _VP,
                                           sz, _VP]
         L.imc_set_dot_tiles.argtypes = [_VP, ctypes.c_uint32]
+        L.imc_galois_share_db.argtypes = L.imc_share_db.argtypes
+        L.imc_galois_share_query.argtypes = L.imc_share_query.argtypes
+        L.imc_galois_dot_shares.argtypes = L.imc_dot_shares.argtypes
+        L.imc_galois_dot_shares_rows.argtypes = L.imc_dot_shares_rows.argtypes
+        L.imc_galois_append_db.argtypes = L.imc_append_db.argtypes
+        L.imc_mask_in_batch.argtypes = [_VP, _P3, sz, sz, sz, sz, _VP]
+        L.imc_or_bits.argtypes = [_VP, _P3, _P3, sz, ctypes.c_uint64, _P3, _VP]
         for f in EXPORTS:
             if f not in ("imc_destroy", "imc_strerror") and not f.endswith("_bytes"):
                 getattr(L, f).restype = st
@@ -162,6 +172,18 @@ def query_raw_bytes(q: int) -> int:
     return lib().imc_query_raw_bytes(q)
 
 
+def galois_db_bytes(capacity: int) -> int:
+    return lib().imc_galois_db_bytes(capacity)
+
+
+def galois_query_op_bytes(q: int) -> int:
+    return lib().imc_galois_query_op_bytes(q)
+
+
+def galois_query_raw_bytes(q: int) -> int:
+    return lib().imc_galois_query_raw_bytes(q)
+
+
 def or_tree_ws_bytes(q: int, r: int, nw: int) -> int:
     return lib().imc_or_tree_ws_bytes(q, r, nw)
 
@@ -204,29 +226,33 @@ class Context:
         except Exception:  # noqa: BLE001 - interpreter shutdown
             pass
 
-    # -- imc_share_db
-    def share_db(self, codes, masks, n, first_entry_id, db3, capacity, stream=None):
-        return _check(lib().imc_share_db(self._h, addr(codes), addr(masks), n, first_entry_id, _p3(db3), capacity,
-                                         _stream(stream)), "imc_share_db")
+    # -- imc_share_db / imc_galois_share_db
+    def share_db(self, codes, masks, n, first_entry_id, db3, capacity, stream=None, galois=False):
+        f = "imc_galois_share_db" if galois else "imc_share_db"
+        return _check(getattr(lib(), f)(self._h, addr(codes), addr(masks), n, first_entry_id, _p3(db3), capacity,
+                                        _stream(stream)), f)
 
-    # -- imc_share_query
-    def share_query(self, codes, masks, q, query_id_base, qop3, qraw3=None, stream=None):
+    # -- imc_share_query / imc_galois_share_query
+    def share_query(self, codes, masks, q, query_id_base, qop3, qraw3=None, stream=None, galois=False):
+        f = "imc_galois_share_query" if galois else "imc_share_query"
         raw = _p3(qraw3) if qraw3 is not None else None
-        return _check(lib().imc_share_query(self._h, addr(codes), addr(masks), q, query_id_base, _p3(qop3),
-                                            ctypes.cast(raw, _VP) if raw is not None else None, _stream(stream)),
-                      "imc_share_query")
+        return _check(getattr(lib(), f)(self._h, addr(codes), addr(masks), q, query_id_base, _p3(qop3),
+                                        ctypes.cast(raw, _VP) if raw is not None else None, _stream(stream)), f)
 
-    # -- imc_dot_shares
-    def dot_shares(self, party, qop, q, ids: imc_ids, db, capacity, n, code_dot, mask_dot, ld, stream=None):
-        return _check(lib().imc_dot_shares(self._h, party, addr(qop), q, ctypes.byref(ids), addr(db), capacity, n,
-                                           addr(code_dot), addr(mask_dot), ld, _stream(stream)), "imc_dot_shares")
+    # -- imc_dot_shares / imc_galois_dot_shares
+    def dot_shares(self, party, qop, q, ids: imc_ids, db, capacity, n, code_dot, mask_dot, ld, stream=None,
+                   galois=False):
+        f = "imc_galois_dot_shares" if galois else "imc_dot_shares"
+        return _check(getattr(lib(), f)(self._h, party, addr(qop), q, ctypes.byref(ids), addr(db), capacity, n,
+                                        addr(code_dot), addr(mask_dot), ld, _stream(stream)), f)
 
-    # -- imc_dot_shares_rows (rows: device int32 tensor [nrows, 2] = (query_index, rot))
+    # -- imc_dot_shares_rows / imc_galois_dot_shares_rows
+    #    (rows: device int32 tensor [nrows, 2] = (query_index, rot))
     def dot_shares_rows(self, party, qop, q, rows, nrows, db, capacity, first_entry_id, n, code_dot, mask_dot, ld,
-                        stream=None):
-        return _check(lib().imc_dot_shares_rows(self._h, party, addr(qop), q, addr(rows), nrows, addr(db), capacity,
-                                                first_entry_id, n, addr(code_dot), addr(mask_dot), ld,
-                                                _stream(stream)), "imc_dot_shares_rows")
+                        stream=None, galois=False):
+        f = "imc_galois_dot_shares_rows" if galois else "imc_dot_shares_rows"
+        return _check(getattr(lib(), f)(self._h, party, addr(qop), q, addr(rows), nrows, addr(db), capacity,
+                                        first_entry_id, n, addr(code_dot), addr(mask_dot), ld, _stream(stream)), f)
 
     # -- imc_set_dot_tiles
     def set_dot_tiles(self, flags: int):
@@ -248,6 +274,16 @@ class Context:
         return _check(lib().imc_or_tree(self._h, _p3(match3), q, nw, mw_ld, ctypes.byref(ids), addr(ws), ws_bytes,
                                         _p3(dup3), _stream(stream)), "imc_or_tree")
 
+    # -- imc_mask_in_batch
+    def mask_in_batch(self, match3, q, r, mw_ld, word, stream=None):
+        return _check(lib().imc_mask_in_batch(self._h, _p3(match3), q, r, mw_ld, word, _stream(stream)),
+                      "imc_mask_in_batch")
+
+    # -- imc_or_bits
+    def or_bits(self, a3, b3, count, id_, out3, stream=None):
+        return _check(lib().imc_or_bits(self._h, _p3(a3), _p3(b3), count, id_, _p3(out3), _stream(stream)),
+                      "imc_or_bits")
+
     # -- imc_open (returns the status: IMC_ECORRUPT is reported, not raised)
     def open(self, kind, rep3, count, out, check=0, stream=None):
         s = lib().imc_open(self._h, kind, _p3(rep3), count, addr(out), int(check), _stream(stream))
@@ -255,7 +291,7 @@ class Context:
             raise IMCError(s, "imc_open")
         return s
 
-    # -- imc_append_db
-    def append_db(self, qraw3, qi, db3, capacity, entry_id, stream=None):
-        return _check(lib().imc_append_db(self._h, _p3(qraw3), qi, _p3(db3), capacity, entry_id, _stream(stream)),
-                      "imc_append_db")
+    # -- imc_append_db / imc_galois_append_db
+    def append_db(self, qraw3, qi, db3, capacity, entry_id, stream=None, galois=False):
+        f = "imc_galois_append_db" if galois else "imc_append_db"
+        return _check(getattr(lib(), f)(self._h, _p3(qraw3), qi, _p3(db3), capacity, entry_id, _stream(stream)), f)

@@ -19,7 +19,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from . import Context, make_ids, or_tree_ws_bytes, query_op_bytes
+from . import Context, galois_query_op_bytes, make_ids, or_tree_ws_bytes, query_op_bytes
 
 
 @dataclass
@@ -40,23 +40,26 @@ def _dev(device):
 class BatchSet:
     """Shared queries of several batches and their row table."""
 
-    def __init__(self, ctx: Context, batches: list, codes, masks, device=0, stream=None):
-        """codes/masks: device int64 [sum q_b, 200], batch after batch."""
+    def __init__(self, ctx: Context, batches: list, codes, masks, device=0, stream=None, galois: bool = False):
+        """codes/masks: device int64 [sum q_b, 200], batch after batch.
+        galois: share the queries as Galois-ring Shamir operands."""
         self.batches = batches
+        self.galois = galois
         self.q = sum(b.q for b in batches)
         assert codes.shape[0] == self.q
         d = _dev(device)
-        self.op = [torch.empty(max(1, query_op_bytes(self.q)), dtype=torch.uint8, device=d) for _ in range(3)]
+        self.row_bytes = galois_query_op_bytes(1) if galois else query_op_bytes(1)
+        self.op = [torch.empty(max(1, self.q * self.row_bytes), dtype=torch.uint8, device=d) for _ in range(3)]
         self.qbase, self.rbase = [], []
         qi = ri = 0
         table = []
         for b in batches:
             self.qbase.append(qi)
             self.rbase.append(ri)
-            off = qi * 102400
+            off = qi * self.row_bytes
             # each batch has its own id range: share it into its slice of the operand
             ctx.share_query(codes[qi:qi + b.q], masks[qi:qi + b.q], b.q, b.qid_base,
-                            [o.data_ptr() + off for o in self.op], None, stream)
+                            [o.data_ptr() + off for o in self.op], None, stream, galois=galois)
             for j in range(b.q):
                 for s in b.rot:
                     table.append((qi + j, int(s)))
@@ -74,6 +77,7 @@ class BatchedStep:
     def __init__(self, ctx: Context, bs: BatchSet, db, first_entry: int, n: int, chunk: int | None = None,
                  parties=(0,), compare: bool = False, device=0):
         assert first_entry % 64 == 0
+        assert bs.galois == bool(getattr(db, "galois", False)), "query and database sharing differ"
         self.ctx, self.bs, self.db = ctx, bs, db
         self.first, self.n = first_entry, n
         self.chunk = min(n, chunk or n)
@@ -114,7 +118,8 @@ class BatchedStep:
         for c0, m in self._chunks():
             for p in self.parties:
                 ctx.dot_shares_rows(p, bs.op[p], bs.q, bs.rows, bs.nrows, db.regions[p], db.capacity,
-                                    self.first + c0, m, self.dot_code[p], self.dot_mask[p], self.ld, stream)
+                                    self.first + c0, m, self.dot_code[p], self.dot_mask[p], self.ld, stream,
+                                    galois=bs.galois)
         if self.compare:
             self._compare_all(stream)
 
@@ -124,12 +129,13 @@ class BatchedStep:
         for c0, m in self._chunks():
             for bi, b in enumerate(bs.batches):
                 ids = make_ids(b.qid_base, b.rot, self.first + c0)
-                off = bs.qbase[bi] * 102400
+                off = bs.qbase[bi] * bs.row_bytes
                 r0 = bs.rbase[bi]
                 for p in self.parties:
                     ctx.dot_shares(p, bs.op[p].data_ptr() + off, b.q, ids, db.regions[p], db.capacity, m,
                                    self.dot_code[p].data_ptr() + 2 * r0 * self.ld,
-                                   self.dot_mask[p].data_ptr() + 2 * r0 * self.ld, self.ld, stream)
+                                   self.dot_mask[p].data_ptr() + 2 * r0 * self.ld, self.ld, stream,
+                                   galois=bs.galois)
         if self.compare:
             self._compare_all(stream)
 

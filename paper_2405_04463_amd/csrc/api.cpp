@@ -82,6 +82,9 @@ const char* imc_strerror(imc_status s) {
 size_t imc_db_bytes(size_t capacity) { return blocks_for(capacity) * imc::kBlockBytes; }
 size_t imc_query_op_bytes(size_t q) { return q * imc::kQopRowBytes; }
 size_t imc_query_raw_bytes(size_t q) { return q * 2 * 2 * imc::kCodeBits * sizeof(uint16_t); }
+size_t imc_galois_db_bytes(size_t capacity) { return blocks_for(capacity) * imc::Geo<imc::kKGalois>::kBlockBytes; }
+size_t imc_galois_query_op_bytes(size_t q) { return q * imc::Geo<imc::kKGalois>::kQopRowBytes; }
+size_t imc_galois_query_raw_bytes(size_t q) { return q * 2 * imc::kCodeBits * sizeof(uint16_t); }
 size_t imc_or_tree_ws_bytes(size_t q, size_t r, size_t nw) { return imc::or_tree_ws_bytes(q, r, nw); }
 
 imc_status imc_create(const imc_params* p, int device, imc_ctx** out) {
@@ -125,8 +128,10 @@ void imc_destroy(imc_ctx* c) {
   delete c;
 }
 
-imc_status imc_share_db(imc_ctx* c, const uint64_t* codes, const uint64_t* masks, size_t n, uint64_t first,
-                        void* const db[3], size_t capacity, imc_stream stream) {
+namespace {
+
+imc_status share_db_impl(imc_ctx* c, const uint64_t* codes, const uint64_t* masks, size_t n, uint64_t first,
+                         void* const db[3], size_t capacity, imc_stream stream, bool galois) {
   if (!c || !db) return IMC_EINVAL;
   if (n && (!codes || !masks)) return IMC_EINVAL;
   int held = 0;
@@ -141,11 +146,12 @@ imc_status imc_share_db(imc_ctx* c, const uint64_t* codes, const uint64_t* masks
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;
   uint8_t* d[3] = {static_cast<uint8_t*>(db[0]), static_cast<uint8_t*>(db[1]), static_cast<uint8_t*>(db[2])};
+  if (galois) return dev_status(imc::launch_galois_share_db(c->dealer, codes, masks, n, first, d, hipStream_t(stream)));
   return dev_status(imc::launch_share_db(c->dealer, codes, masks, n, first, d, hipStream_t(stream)));
 }
 
-imc_status imc_share_query(imc_ctx* c, const uint64_t* codes, const uint64_t* masks, size_t q, uint64_t qid_base,
-                           void* const qop[3], void* const qraw[3], imc_stream stream) {
+imc_status share_query_impl(imc_ctx* c, const uint64_t* codes, const uint64_t* masks, size_t q, uint64_t qid_base,
+                            void* const qop[3], void* const qraw[3], imc_stream stream, bool galois) {
   if (!c || !qop) return IMC_EINVAL;
   if (q && (!codes || !masks)) return IMC_EINVAL;
   if (!aligned(codes, 8) || !aligned(masks, 8)) return IMC_EINVAL;
@@ -160,13 +166,16 @@ imc_status imc_share_query(imc_ctx* c, const uint64_t* codes, const uint64_t* ma
   uint16_t* raw[3] = {nullptr, nullptr, nullptr};
   if (qraw)
     for (int p = 0; p < 3; ++p) raw[p] = static_cast<uint16_t*>(qraw[p]);
+  if (galois)
+    return dev_status(imc::launch_galois_share_query(c->dealer, codes, masks, q, qid_base, op, qraw ? raw : nullptr,
+                                                     hipStream_t(stream)));
   return dev_status(imc::launch_share_query(c->dealer, codes, masks, q, qid_base, op, qraw ? raw : nullptr,
                                             hipStream_t(stream)));
 }
 
-imc_status imc_dot_shares(imc_ctx* c, int party, const void* qop, size_t q, const imc_ids* ids, const void* db,
-                          size_t capacity, size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
-                          imc_stream stream) {
+imc_status dot_shares_impl(imc_ctx* c, int party, const void* qop, size_t q, const imc_ids* ids, const void* db,
+                           size_t capacity, size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
+                           imc_stream stream, bool galois) {
   if (!c || party < 0 || party > 2) return IMC_EINVAL;
   imc_status st = check_ids(ids);
   if (st != IMC_OK) return st;
@@ -181,24 +190,30 @@ imc_status imc_dot_shares(imc_ctx* c, int party, const void* qop, size_t q, cons
   if (!g.ok) return IMC_EDEVICE;
   const int v = c->dot_variant;
   const int tiles = v & 0xF;
-  if ((tiles == IMC_DOT_TILES_AUTO || tiles == IMC_DOT_TILES_ROTATION) && imc::rot_dot_applies(uint32_t(ids->r))) {
+  const bool rot_tiles = tiles == IMC_DOT_TILES_AUTO || tiles == IMC_DOT_TILES_ROTATION ||
+                         tiles == IMC_DOT_TILES_ROTATION_DEEP || tiles == IMC_DOT_TILES_ROTATION_LDSCOPY;
+  if (rot_tiles && imc::rot_dot_applies(uint32_t(ids->r))) {
     // rotations read straight from the unrotated operand staged in LDS
     return dev_status(imc::launch_rot_dot(static_cast<const int8_t*>(qop), uint32_t(q), uint32_t(ids->r), ids->rot,
                                           static_cast<const int8_t*>(db), ids->first_entry_id, n, code_dot, mask_dot,
-                                          ld, hipStream_t(stream)));
+                                          ld, hipStream_t(stream),
+                                          tiles == IMC_DOT_TILES_ROTATION_DEEP      ? 1
+                                          : tiles == IMC_DOT_TILES_ROTATION_LDSCOPY ? 2
+                                                                                    : 0,
+                                          galois));
   }
   const uint32_t rows_pad = uint32_t(blocks_for(rows) * 32);
   hipError_t e = imc::launch_expand(static_cast<const int8_t*>(qop), uint32_t(q), uint32_t(ids->r), ids->rot,
-                                    c->rot_op, rows_pad, hipStream_t(stream));
+                                    c->rot_op, rows_pad, hipStream_t(stream), galois);
   if (e != hipSuccess) return IMC_EDEVICE;
   e = imc::launch_dot(c->rot_op, uint32_t(rows), rows_pad / 32, static_cast<const int8_t*>(db), ids->first_entry_id,
-                      n, code_dot, mask_dot, ld, hipStream_t(stream), v);
+                      n, code_dot, mask_dot, ld, hipStream_t(stream), v, galois);
   return dev_status(e);
 }
 
-imc_status imc_dot_shares_rows(imc_ctx* c, int party, const void* qop, size_t q, const imc_row* rows, size_t nrows,
-                               const void* db, size_t capacity, uint64_t first_entry_id, size_t n, uint16_t* code_dot,
-                               uint16_t* mask_dot, size_t ld, imc_stream stream) {
+imc_status dot_shares_rows_impl(imc_ctx* c, int party, const void* qop, size_t q, const imc_row* rows, size_t nrows,
+                                const void* db, size_t capacity, uint64_t first_entry_id, size_t n,
+                                uint16_t* code_dot, uint16_t* mask_dot, size_t ld, imc_stream stream, bool galois) {
   if (!c || party < 0 || party > 2) return IMC_EINVAL;
   if (nrows == 0 || n == 0) return IMC_OK;
   if (!qop || !rows || !db || !code_dot || !mask_dot || q == 0) return IMC_EINVAL;
@@ -212,14 +227,108 @@ imc_status imc_dot_shares_rows(imc_ctx* c, int party, const void* qop, size_t q,
   if (!g.ok) return IMC_EDEVICE;
   const uint32_t rows_pad = uint32_t(blocks_for(nrows) * 32);
   hipError_t e = imc::launch_expand_rows(static_cast<const int8_t*>(qop), uint32_t(q), rows, uint32_t(nrows), c->rot_op,
-                                         rows_pad, hipStream_t(stream));
+                                         rows_pad, hipStream_t(stream), galois);
   if (e != hipSuccess) return IMC_EDEVICE;
   int v = c->dot_variant;
-  if ((v & 0xF) == IMC_DOT_TILES_AUTO || (v & 0xF) == IMC_DOT_TILES_ROTATION)
+  if ((v & 0xF) == IMC_DOT_TILES_AUTO || (v & 0xF) >= IMC_DOT_TILES_ROTATION)
     v = (v & ~0xF) | IMC_DOT_TILES_EXPANDED_256x128;
   e = imc::launch_dot(c->rot_op, uint32_t(nrows), rows_pad / 32, static_cast<const int8_t*>(db), first_entry_id, n,
-                      code_dot, mask_dot, ld, hipStream_t(stream), v);
+                      code_dot, mask_dot, ld, hipStream_t(stream), v, galois);
   return dev_status(e);
+}
+
+imc_status append_impl(imc_ctx* c, const void* const qraw[3], size_t qi, void* const db[3], size_t capacity,
+                       uint64_t entry_id, imc_stream stream, bool galois) {
+  if (!c || !qraw || !db) return IMC_EINVAL;
+  int held = 0;
+  for (int p = 0; p < 3; ++p) {
+    if (!db[p]) continue;   // region not held on this device
+    if (!qraw[p] || !aligned(db[p], 256) || !aligned(qraw[p], 2)) return IMC_EINVAL;
+    ++held;
+  }
+  if (!held) return IMC_EINVAL;
+  if (entry_id >= capacity) return IMC_ESHAPE;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  const uint16_t* raw[3] = {static_cast<const uint16_t*>(qraw[0]), static_cast<const uint16_t*>(qraw[1]),
+                            static_cast<const uint16_t*>(qraw[2])};
+  uint8_t* d[3] = {static_cast<uint8_t*>(db[0]), static_cast<uint8_t*>(db[1]), static_cast<uint8_t*>(db[2])};
+  if (galois) return dev_status(imc::launch_galois_append(raw, qi, d, entry_id, hipStream_t(stream)));
+  return dev_status(imc::launch_append(raw, qi, d, entry_id, hipStream_t(stream)));
+}
+
+}  // namespace
+
+imc_status imc_share_db(imc_ctx* c, const uint64_t* codes, const uint64_t* masks, size_t n, uint64_t first,
+                        void* const db[3], size_t capacity, imc_stream stream) {
+  return share_db_impl(c, codes, masks, n, first, db, capacity, stream, false);
+}
+imc_status imc_galois_share_db(imc_ctx* c, const uint64_t* codes, const uint64_t* masks, size_t n, uint64_t first,
+                               void* const db[3], size_t capacity, imc_stream stream) {
+  return share_db_impl(c, codes, masks, n, first, db, capacity, stream, true);
+}
+imc_status imc_share_query(imc_ctx* c, const uint64_t* codes, const uint64_t* masks, size_t q, uint64_t qid_base,
+                           void* const qop[3], void* const qraw[3], imc_stream stream) {
+  return share_query_impl(c, codes, masks, q, qid_base, qop, qraw, stream, false);
+}
+imc_status imc_galois_share_query(imc_ctx* c, const uint64_t* codes, const uint64_t* masks, size_t q,
+                                  uint64_t qid_base, void* const qop[3], void* const qraw[3], imc_stream stream) {
+  return share_query_impl(c, codes, masks, q, qid_base, qop, qraw, stream, true);
+}
+imc_status imc_dot_shares(imc_ctx* c, int party, const void* qop, size_t q, const imc_ids* ids, const void* db,
+                          size_t capacity, size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
+                          imc_stream stream) {
+  return dot_shares_impl(c, party, qop, q, ids, db, capacity, n, code_dot, mask_dot, ld, stream, false);
+}
+imc_status imc_galois_dot_shares(imc_ctx* c, int party, const void* qop, size_t q, const imc_ids* ids, const void* db,
+                                 size_t capacity, size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
+                                 imc_stream stream) {
+  return dot_shares_impl(c, party, qop, q, ids, db, capacity, n, code_dot, mask_dot, ld, stream, true);
+}
+imc_status imc_dot_shares_rows(imc_ctx* c, int party, const void* qop, size_t q, const imc_row* rows, size_t nrows,
+                               const void* db, size_t capacity, uint64_t first_entry_id, size_t n, uint16_t* code_dot,
+                               uint16_t* mask_dot, size_t ld, imc_stream stream) {
+  return dot_shares_rows_impl(c, party, qop, q, rows, nrows, db, capacity, first_entry_id, n, code_dot, mask_dot, ld,
+                              stream, false);
+}
+imc_status imc_galois_dot_shares_rows(imc_ctx* c, int party, const void* qop, size_t q, const imc_row* rows,
+                                      size_t nrows, const void* db, size_t capacity, uint64_t first_entry_id,
+                                      size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
+                                      imc_stream stream) {
+  return dot_shares_rows_impl(c, party, qop, q, rows, nrows, db, capacity, first_entry_id, n, code_dot, mask_dot, ld,
+                              stream, true);
+}
+imc_status imc_append_db(imc_ctx* c, const void* const qraw[3], size_t qi, void* const db[3], size_t capacity,
+                         uint64_t entry_id, imc_stream stream) {
+  return append_impl(c, qraw, qi, db, capacity, entry_id, stream, false);
+}
+imc_status imc_galois_append_db(imc_ctx* c, const void* const qraw[3], size_t qi, void* const db[3], size_t capacity,
+                                uint64_t entry_id, imc_stream stream) {
+  return append_impl(c, qraw, qi, db, capacity, entry_id, stream, true);
+}
+
+imc_status imc_mask_in_batch(imc_ctx* c, uint64_t* const match[3], size_t q, size_t r, size_t mw_ld, size_t word,
+                             imc_stream stream) {
+  if (!c || !match) return IMC_EINVAL;
+  for (int p = 0; p < 3; ++p)
+    if (!match[p] || !aligned(match[p], 8)) return IMC_EINVAL;
+  if (q > 64 || r < 1 || r > IMC_MAX_ROT) return IMC_EINVAL;
+  if (word >= mw_ld) return IMC_ESHAPE;
+  if (q == 0) return IMC_OK;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  return dev_status(imc::launch_mask_in_batch(match, q, uint32_t(r), mw_ld, word, hipStream_t(stream)));
+}
+
+imc_status imc_or_bits(imc_ctx* c, const uint8_t* const a[3], const uint8_t* const b[3], size_t count, uint64_t id,
+                       uint8_t* const out[3], imc_stream stream) {
+  if (!c || !a || !b || !out) return IMC_EINVAL;
+  for (int p = 0; p < 3; ++p)
+    if (!a[p] || !b[p] || !out[p]) return IMC_EINVAL;
+  if (count == 0) return IMC_OK;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  return dev_status(imc::launch_or_bits(c->party, a, b, count, id, out, hipStream_t(stream)));
 }
 
 imc_status imc_set_dot_tiles(imc_ctx* c, uint32_t flags) {
@@ -301,23 +410,5 @@ imc_status imc_open(imc_ctx* c, int kind, const void* const rep[3], size_t count
   return bad ? IMC_ECORRUPT : IMC_OK;
 }
 
-imc_status imc_append_db(imc_ctx* c, const void* const qraw[3], size_t qi, void* const db[3], size_t capacity,
-                         uint64_t entry_id, imc_stream stream) {
-  if (!c || !qraw || !db) return IMC_EINVAL;
-  int held = 0;
-  for (int p = 0; p < 3; ++p) {
-    if (!db[p]) continue;   // region not held on this device
-    if (!qraw[p] || !aligned(db[p], 256) || !aligned(qraw[p], 2)) return IMC_EINVAL;
-    ++held;
-  }
-  if (!held) return IMC_EINVAL;
-  if (entry_id >= capacity) return IMC_ESHAPE;
-  DeviceGuard g(c->device);
-  if (!g.ok) return IMC_EDEVICE;
-  const uint16_t* raw[3] = {static_cast<const uint16_t*>(qraw[0]), static_cast<const uint16_t*>(qraw[1]),
-                            static_cast<const uint16_t*>(qraw[2])};
-  uint8_t* d[3] = {static_cast<uint8_t*>(db[0]), static_cast<uint8_t*>(db[1]), static_cast<uint8_t*>(db[2])};
-  return dev_status(imc::launch_append(raw, qi, d, entry_id, hipStream_t(stream)));
-}
 
 }  // extern "C"

@@ -487,6 +487,65 @@ __global__ void __launch_bounds__(64) or_final_kernel(OrFinalArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// In-batch matching (Sec. 6.3): query qi of a batch is compared with the
+// earlier queries j < qi only.  The shared match bits of columns j >= qi in
+// word `word` of every row qi*r + ri become public zeros: every component of
+// both planes is cleared.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) mask_in_batch_kernel(uint64_t* m0, uint64_t* m1, uint64_t* m2, uint64_t q,
+                                                            uint32_t r, uint64_t mw_ld, uint64_t word) {
+  const uint64_t rows = q * r;
+  const uint64_t row = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (row >= rows) return;
+  const uint64_t qi = row / r;
+  const uint64_t keep = qi >= 64 ? ~0ull : ((1ull << qi) - 1);
+  uint64_t* m[3] = {m0, m1, m2};
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int plane = 0; plane < 2; ++plane) m[p][(plane * rows + row) * mw_ld + word] &= keep;
+}
+
+// Shared OR of two bit sharings, one AND gate per element: z = x ^ y ^ (x AND y).
+// The gate of element i takes bit i%64 of u64 word i/64 of stream
+// (kDomOrPairs << 56 | id) from every key.  a, b, out: u8 [2][count].
+struct OrBitsArgs {
+  Keys3 keys;
+  const uint8_t* a[3];
+  const uint8_t* b[3];
+  uint8_t* out[3];
+  uint64_t count, id;
+};
+
+__global__ void __launch_bounds__(256) or_bits_kernel(OrBitsArgs a) {
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.count) return;
+  const uint64_t stream = (uint64_t(kDomOrPairs) << 56) | (a.id & 0xFFFFFFFFFFFFull);
+  const uint64_t t = i >> 6;
+  uint64_t f[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint32_t F[16];
+    chacha12(a.keys.k[k], stream, t >> 3, F);
+    const int u = int(t & 7);
+    f[k] = ((uint64_t(F[2 * u]) | (uint64_t(F[2 * u + 1]) << 32)) >> (i & 63)) & 1u;
+  }
+  B3 x, y;
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    x.c[p] = a.a[p][i] & 1u;
+    y.c[p] = a.b[p][i] & 1u;
+  }
+  const B3 z = bx(bx(x, y), band(x, y, f[0], f[1], f[2]));
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const int pm = (p + 2) % 3;
+    a.out[p][i] = uint8_t(z.c[p] & 1u);
+    a.out[p][a.count + i] = uint8_t(z.c[pm] & 1u);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Open: out = x_0 op x_1 op x_2 from each party's own component; with check,
 // count positions where party p's copy of x_{p-1} differs from party p-1's.
 // ---------------------------------------------------------------------------
@@ -645,6 +704,31 @@ hipError_t launch_open(int kind, const void* const rep[3], uint64_t count, void*
                          (const uint32_t*)rep[1], (const uint32_t*)rep[2], count, (uint32_t*)out, check, bad);
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_in_batch(uint64_t* const match[3], uint64_t q, uint32_t r, uint64_t mw_ld, uint64_t word,
+                                hipStream_t s) {
+  const uint64_t rows = q * r;
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(mask_in_batch_kernel, dim3(unsigned((rows + 255) / 256)), dim3(256), 0, s, match[0], match[1],
+                     match[2], q, r, mw_ld, word);
+  return hipGetLastError();
+}
+
+hipError_t launch_or_bits(const Keys3& keys, const uint8_t* const x[3], const uint8_t* const y[3], uint64_t count,
+                          uint64_t id, uint8_t* const out[3], hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  OrBitsArgs a;
+  a.keys = keys;
+  for (int p = 0; p < 3; ++p) {
+    a.a[p] = x[p];
+    a.b[p] = y[p];
+    a.out[p] = out[p];
+  }
+  a.count = count;
+  a.id = id;
+  hipLaunchKernelGGL(or_bits_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

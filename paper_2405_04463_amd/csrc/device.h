@@ -19,14 +19,33 @@ constexpr size_t kBlockBytes = kPlanes * kPlaneBlockBytes;              // 32 en
 constexpr size_t kEntryBytes = kBlockBytes / 32;                       // 102,400
 constexpr size_t kQopRowBytes = size_t(kPlanes) * kK;                  // 102,400
 
+// Operand geometry of one dot product with K byte-limb elements per vector
+// and plane: K = 25,600 for the replicated form ([own | previous] halves) and
+// 12,800 for the Galois-ring Shamir form (one share).
+template <int K>
+struct Geo {
+  static constexpr int kK = K;
+  static constexpr int kChunks = K / 16;                                      // 16-byte k-chunks per plane
+  static constexpr size_t kPlaneBlockBytes = size_t(kChunks) * 32 * 16;       // 32 entries
+  static constexpr size_t kBlockBytes = kPlanes * kPlaneBlockBytes;
+  static constexpr size_t kQopRowBytes = size_t(kPlanes) * K;
+  static_assert(K % kRowLen == 0 && K % 32 == 0, "K spans whole angular rows");
+};
+constexpr int kKGalois = kCodeBits;                                           // 12,800
+
 // PRF domains: high byte of the 64-bit stream id.
 constexpr uint32_t kDomShareDb = 1, kDomShareQuery = 2, kDomReshare = 3, kDomCmp = 4, kDomOr = 5;
+constexpr uint32_t kDomGaloisDb = 6, kDomGaloisQuery = 7, kDomOrPairs = 8;
 
 // Per 64-entry group, each key's tape holds u64 words (8 per ChaCha block):
 // words 0..32 = AND gates 0..32 (Lift), words 40..100 = AND gates 33..93 (MSB),
 // words 104.. = BitInject values; 32 blocks reserved per group.
 constexpr int kTapeBlocksPerGroup = 32;
 constexpr int kTapeCA = 104, kTapeCB = 119, kTapeW0A = 136, kTapeW0B = 151, kTapeW1A = 168, kTapeW1B = 183;
+
+// MFMA operand and accumulator vectors.
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
 struct Key {
   uint32_t w[8];

@@ -13,8 +13,6 @@
 
 namespace imc {
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
 // Rotation expand: query operand rows (row-major, unrotated) -> rotated rows
@@ -24,15 +22,17 @@ struct Rot {
   int8_t s[IMC_MAX_ROT_DEV];
 };
 
+template <int K>
 __global__ void __launch_bounds__(256) expand_kernel(const int8_t* __restrict__ qop, uint32_t q, uint32_t r, Rot rot,
                                                      uint32_t rows_pad, int8_t* __restrict__ a) {
+  using G = Geo<K>;
   uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  uint64_t total = uint64_t(rows_pad) * kPlanes * kChunks;
+  uint64_t total = uint64_t(rows_pad) * kPlanes * G::kChunks;
   if (t >= total) return;
   uint32_t slot = uint32_t(t % 32);
   uint64_t rest = t / 32;
-  uint32_t kc = uint32_t(rest % kChunks);
-  rest /= kChunks;
+  uint32_t kc = uint32_t(rest % G::kChunks);
+  rest /= G::kChunks;
   uint32_t plane = uint32_t(rest % kPlanes);
   uint32_t rb = uint32_t(rest / kPlanes);
   uint32_t row = rb * 32 + slot;
@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(256) expand_kernel(const int8_t* __restrict__ 
     uint32_t k0 = kc * 16;
     uint32_t h = k0 / kCodeBits, i0 = k0 - h * kCodeBits;
     uint32_t rrow = i0 / kRowLen, w0 = i0 - rrow * kRowLen;
-    const int8_t* src = qop + uint64_t(qi) * kQopRowBytes + uint64_t(plane) * kK + h * kCodeBits + rrow * kRowLen;
+    const int8_t* src = qop + uint64_t(qi) * G::kQopRowBytes + uint64_t(plane) * G::kK + h * kCodeBits + rrow * kRowLen;
     uint32_t wv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -53,23 +53,25 @@ __global__ void __launch_bounds__(256) expand_kernel(const int8_t* __restrict__ 
     }
     v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
   }
-  *reinterpret_cast<uint4*>(a + uint64_t(rb) * kBlockBytes + uint64_t(plane) * kPlaneBlockBytes + uint64_t(kc) * 512 +
+  *reinterpret_cast<uint4*>(a + uint64_t(rb) * G::kBlockBytes + uint64_t(plane) * G::kPlaneBlockBytes + uint64_t(kc) * 512 +
                             slot * 16) = v;
 }
 
 // Same, with an explicit row table (query index, rotation) per row: rows of
 // many uneven batches expanded into one operand.  A row whose query index is
 // out of range becomes a zero row.
+template <int K>
 __global__ void __launch_bounds__(256) expand_rows_kernel(const int8_t* __restrict__ qop, uint32_t q,
                                                           const imc_row* __restrict__ rows, uint32_t nrows,
                                                           uint32_t rows_pad, int8_t* __restrict__ a) {
+  using G = Geo<K>;
   uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  uint64_t total = uint64_t(rows_pad) * kPlanes * kChunks;
+  uint64_t total = uint64_t(rows_pad) * kPlanes * G::kChunks;
   if (t >= total) return;
   uint32_t slot = uint32_t(t % 32);
   uint64_t rest = t / 32;
-  uint32_t kc = uint32_t(rest % kChunks);
-  rest /= kChunks;
+  uint32_t kc = uint32_t(rest % G::kChunks);
+  rest /= G::kChunks;
   uint32_t plane = uint32_t(rest % kPlanes);
   uint32_t rb = uint32_t(rest / kPlanes);
   uint32_t row = rb * 32 + slot;
@@ -80,7 +82,7 @@ __global__ void __launch_bounds__(256) expand_rows_kernel(const int8_t* __restri
     uint32_t k0 = kc * 16;
     uint32_t h = k0 / kCodeBits, i0 = k0 - h * kCodeBits;
     uint32_t rrow = i0 / kRowLen, w0 = i0 - rrow * kRowLen;
-    const int8_t* src = qop + uint64_t(qi) * kQopRowBytes + uint64_t(plane) * kK + h * kCodeBits + rrow * kRowLen;
+    const int8_t* src = qop + uint64_t(qi) * G::kQopRowBytes + uint64_t(plane) * G::kK + h * kCodeBits + rrow * kRowLen;
     uint32_t wv[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -90,7 +92,7 @@ __global__ void __launch_bounds__(256) expand_rows_kernel(const int8_t* __restri
     }
     v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
   }
-  *reinterpret_cast<uint4*>(a + uint64_t(rb) * kBlockBytes + uint64_t(plane) * kPlaneBlockBytes + uint64_t(kc) * 512 +
+  *reinterpret_cast<uint4*>(a + uint64_t(rb) * G::kBlockBytes + uint64_t(plane) * G::kPlaneBlockBytes + uint64_t(kc) * 512 +
                             slot * 16) = v;
 }
 
@@ -100,8 +102,9 @@ __global__ void __launch_bounds__(256) expand_rows_kernel(const int8_t* __restri
 // each).  Per K-step (32 bytes of k per plane) the workgroup stages its
 // operand slices in LDS once -- A: BM/32 row-blocks, B: BN/32 entry-blocks,
 // each 2 planes x 2 k-chunks x 32 slots x 16 B, i.e. exactly the tiled HBM
-// layout -- so fragment reads are 1 KB contiguous per wave.  Two LDS stages and
-// two register sets keep the global loads two steps ahead.  blockIdx.z = 0
+// layout -- so fragment reads are 1 KB contiguous per wave.  Three LDS stages
+// and NSETS register sets keep the global loads NSETS + 2 steps ahead and the
+// fragment reads one step ahead of the MFMAs.  blockIdx.z = 0
 // code, 1 mask.
 // ---------------------------------------------------------------------------
 struct DotArgs {
@@ -129,9 +132,10 @@ struct DotCfg {
   static_assert(kChunksPerStep % kThreads == 0, "chunks must divide evenly");
 };
 
-template <int WM, int WN, int WAVES_M, int WAVES_N, int NSETS>
+template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int NSETS>
 __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) dot_kernel(DotArgs args) {
   using C = DotCfg<WM, WN, WAVES_M, WAVES_N>;
+  using G = Geo<K>;
   extern __shared__ __align__(16) int8_t lds[];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -163,13 +167,13 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) dot_kernel(DotArgs arg
     if (blk < C::kABlk) {
       uint32_t rb = u * C::kABlk + blk;
       rb = rb < args.a_blocks ? rb : args.a_blocks - 1;
-      base = args.a + size_t(rb) * kBlockBytes;
+      base = args.a + size_t(rb) * G::kBlockBytes;
     } else {
       uint64_t cb = uint64_t(t) * C::kBBlk + (blk - C::kABlk);
       cb = cb < args.b_blocks ? cb : args.b_blocks - 1;
-      base = args.b + size_t(args.b_block0 + cb) * kBlockBytes;
+      base = args.b + size_t(args.b_block0 + cb) * G::kBlockBytes;
     }
-    src[j] = base + size_t(2 * vec + plane) * kPlaneBlockBytes + size_t(kcl) * 512 + slot * 16;
+    src[j] = base + size_t(2 * vec + plane) * G::kPlaneBlockBytes + size_t(kcl) * 512 + slot * 16;
   }
 
   v16i acc0[WM][WN], acc1[WM][WN];
@@ -180,7 +184,7 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) dot_kernel(DotArgs arg
 #pragma unroll
       for (int e = 0; e < 16; ++e) { acc0[x][y][e] = 0; acc1[x][y][e] = 0; }
 
-  constexpr int kSteps = kChunks / 2;   // 800 steps of 32 bytes of k
+  constexpr int kSteps = G::kChunks / 2;   // steps of 32 bytes of k
   static_assert(kSteps % NSETS == 0, "the K loop is unrolled by NSETS");
   v4i rs[NSETS][C::kPerThread];
 #define IMC_GLOAD(R, KS)                                                              \
@@ -189,50 +193,63 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) dot_kernel(DotArgs arg
 #define IMC_LSTORE(R, STAGE)                                                          \
   _Pragma("unroll") for (int c_ = 0; c_ < C::kPerThread; ++c_)                        \
       *reinterpret_cast<v4i*>(lds + (STAGE) * C::kStageBytes + (tid + c_ * C::kThreads) * 16) = R[c_];
-#define IMC_COMPUTE(STAGE)                                                            \
+#define IMC_FRAGS(ALO, AHI, BLO, BHI, STAGE)                                          \
   {                                                                                   \
     const int8_t* st_ = lds + (STAGE) * C::kStageBytes;                               \
-    v4i alo_[WM], ahi_[WM], blo_[WN], bhi_[WN];                                       \
     _Pragma("unroll") for (int x_ = 0; x_ < WM; ++x_) {                               \
       const int8_t* p_ = st_ + (wm * WM + x_) * 2048 + lane * 16;                     \
-      alo_[x_] = *reinterpret_cast<const v4i*>(p_);                                   \
-      ahi_[x_] = *reinterpret_cast<const v4i*>(p_ + 1024);                            \
+      ALO[x_] = *reinterpret_cast<const v4i*>(p_);                                    \
+      AHI[x_] = *reinterpret_cast<const v4i*>(p_ + 1024);                             \
     }                                                                                 \
     _Pragma("unroll") for (int y_ = 0; y_ < WN; ++y_) {                               \
       const int8_t* p_ = st_ + (C::kABlk + wn * WN + y_) * 2048 + lane * 16;          \
-      blo_[y_] = *reinterpret_cast<const v4i*>(p_);                                   \
-      bhi_[y_] = *reinterpret_cast<const v4i*>(p_ + 1024);                            \
-    }                                                                                 \
-    _Pragma("unroll") for (int x_ = 0; x_ < WM; ++x_)                                 \
-    _Pragma("unroll") for (int y_ = 0; y_ < WN; ++y_) {                               \
-      acc0[x_][y_] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo_[x_], blo_[y_], acc0[x_][y_], 0, 0, 0); \
-      acc1[x_][y_] = __builtin_amdgcn_mfma_i32_32x32x32_i8(alo_[x_], bhi_[y_], acc1[x_][y_], 0, 0, 0); \
-      acc1[x_][y_] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ahi_[x_], blo_[y_], acc1[x_][y_], 0, 0, 0); \
+      BLO[y_] = *reinterpret_cast<const v4i*>(p_);                                    \
+      BHI[y_] = *reinterpret_cast<const v4i*>(p_ + 1024);                             \
     }                                                                                 \
   }
 
-  // Global loads run NSETS steps ahead of the LDS write (register sets), the
-  // LDS write one step ahead of the MFMAs (two stages).  Step j (j >= 1) lives
-  // in register set (j - 1) % NSETS.  Indices past the last step are clamped
-  // (redundant reloads instead of branches keep the sets in VGPRs).
+  // Pipeline over three LDS stages: step j is global-loaded NSETS iterations
+  // ahead into register set (j - 2) % NSETS, written to stage j % 3 two
+  // iterations ahead, and its fragments are read from LDS one iteration ahead,
+  // while the MFMAs of the current step run.  Iteration k overwrites stage
+  // (k + 2) % 3, last read at iteration k - 2.  Indices past the last step
+  // are clamped (redundant reloads instead of branches keep the sets in VGPRs).
+  v4i falo[WM], fahi[WM], fblo[WN], fbhi[WN];     // fragments of the current step
+  v4i nalo[WM], nahi[WM], nblo[WN], nbhi[WN];     // fragments of the next step
   {
     v4i r0[C::kPerThread];
     IMC_GLOAD(r0, 0)
     IMC_LSTORE(r0, 0)
+    IMC_GLOAD(r0, 1)
+    IMC_LSTORE(r0, 1)
   }
 #pragma unroll
-  for (int set = 0; set < NSETS; ++set) { IMC_GLOAD(rs[set], set + 1) }
+  for (int set = 0; set < NSETS; ++set) { IMC_GLOAD(rs[set], set + 2) }
   __syncthreads();
+  IMC_FRAGS(falo, fahi, fblo, fbhi, 0)
   for (int k0 = 0; k0 < kSteps; k0 += NSETS) {
 #pragma unroll
-    for (int u = 0; u < NSETS; ++u) {
-      const int k = k0 + u;
-      IMC_COMPUTE(u & 1)
-      IMC_LSTORE(rs[u], (u + 1) & 1)             // step k + 1
+    for (int uu = 0; uu < NSETS; ++uu) {
+      const int k = k0 + uu;
+      IMC_FRAGS(nalo, nahi, nblo, nbhi, (k + 1) % 3)
+#pragma unroll
+      for (int x = 0; x < WM; ++x)
+#pragma unroll
+        for (int y = 0; y < WN; ++y) {
+          acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fblo[y], acc0[x][y], 0, 0, 0);
+          acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fbhi[y], acc1[x][y], 0, 0, 0);
+          acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fahi[x], fblo[y], acc1[x][y], 0, 0, 0);
+        }
+      IMC_LSTORE(rs[uu], (k + 2) % 3)             // step k + 2
       __syncthreads();
-      IMC_GLOAD(rs[u], min(k + 1 + NSETS, kSteps - 1))
+      IMC_GLOAD(rs[uu], min(k + 2 + NSETS, kSteps - 1))
+#pragma unroll
+      for (int x = 0; x < WM; ++x) { falo[x] = nalo[x]; fahi[x] = nahi[x]; }
+#pragma unroll
+      for (int y = 0; y < WN; ++y) { fblo[y] = nblo[y]; fbhi[y] = nbhi[y]; }
     }
   }
+#undef IMC_FRAGS
 #undef IMC_GLOAD
 #undef IMC_LSTORE
 #undef IMC_COMPUTE
@@ -260,236 +277,20 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) dot_kernel(DotArgs arg
 }
 
 hipError_t launch_expand(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, int8_t* a, uint32_t rows_pad,
-                         hipStream_t s) {
+                         hipStream_t s, bool galois) {
   Rot rr;
   for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) rr.s[i] = i < int(r) ? rot[i] : 0;
-  uint64_t total = uint64_t(rows_pad) * kPlanes * kChunks;
-  hipLaunchKernelGGL(expand_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, qop, q, r, rr, rows_pad, a);
+  const uint64_t chunks = galois ? Geo<kKGalois>::kChunks : Geo<kK>::kChunks;
+  const uint64_t total = uint64_t(rows_pad) * kPlanes * chunks;
+  const dim3 grid(unsigned((total + 255) / 256));
+  if (galois)
+    hipLaunchKernelGGL(expand_kernel<kKGalois>, grid, dim3(256), 0, s, qop, q, r, rr, rows_pad, a);
+  else
+    hipLaunchKernelGGL(expand_kernel<kK>, grid, dim3(256), 0, s, qop, q, r, rr, rows_pad, a);
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Rotation-aware dot kernel.  Rows are (query, rotation) pairs, so a 256-row
-// tile holds only ceil(256/R) + 1 distinct queries.  The K loop walks the 32
-// angular-row segments of 800 bytes (16 rows x 2 halves); for each segment the
-// workgroup keeps every tile query's bytes of that segment in LDS with 64
-// bytes of circular padding on both sides (928 B per plane), and a lane reads
-// its rotated fragment directly: rotation s shifts the segment by 4s bytes,
-// so the 16 bytes at (32t + 16g - 4s) are four aligned dword reads.  Only the
-// database operand streams through LDS per K-step.  Query segments are loaded
-// into registers one segment ahead and written into the other of two LDS
-// buffers half-way through the current segment.
-// ---------------------------------------------------------------------------
-struct RotDotArgs {
-  const int8_t* qop;     // unrotated query operand, row-major [q][plane 4][25600]
-  const int8_t* b;       // party's database region
-  uint16_t* out[2];
-  uint64_t ld;
-  uint32_t rows, q, r;
-  uint64_t b_block0, b_blocks, n;
-  uint32_t mt, nt;
-  uint32_t max_q;        // query slots per tile (LDS sizing)
-  int8_t rot[IMC_MAX_ROT_DEV];
-};
-
-constexpr int kSegPad = 64;                       // >= 4 * 15 and a multiple of 16
-constexpr int kSegBytes = kRowLen + 2 * kSegPad;  // 928
-constexpr int kSegChunks = kSegBytes / 16;        // 58
-
-template <int WM, int WN, int WAVES_M, int WAVES_N, int NSETS, int ACH>
-__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotArgs args) {
-  constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N;
-  constexpr int kThreads = 64 * WAVES_M * WAVES_N;
-  constexpr int kBBlk = kBN / 32;
-  constexpr int kBChunks = kBBlk * 2 * 2 * 32;                 // per K-step
-  constexpr int kBPerThread = kBChunks / kThreads;
-  constexpr int kBStage = kBChunks * 16;
-  static_assert(kBChunks % kThreads == 0, "B chunks must divide evenly");
-  extern __shared__ __align__(16) int8_t lds[];
-  int8_t* bst = lds;                                           // 3 B stages
-  int8_t* ast = lds + 3 * kBStage;                             // 2 A segment buffers
-  const uint32_t abuf = args.max_q * 2 * kSegBytes;            // bytes per A buffer
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-  const int vec = blockIdx.z;
-  const uint32_t i = blockIdx.x;
-  const uint32_t xcd = i & 7, s8 = i >> 3;
-  const uint32_t u = s8 % args.mt, tg = s8 / args.mt;
-  const uint32_t t = tg * 8 + xcd;
-  if (t >= args.nt) return;
-
-  const uint32_t m0 = u * kBM;
-  const uint32_t q_lo = m0 / args.r;
-  const uint32_t last_row = min(m0 + kBM, args.rows) - 1;
-  const uint32_t nq = last_row / args.r - q_lo + 1;            // <= max_q
-
-  // Per-lane A fragment offsets (bytes into an A buffer) for its row-blocks.
-  int a_off[WM];
-#pragma unroll
-  for (int x = 0; x < WM; ++x) {
-    const uint32_t row = m0 + (wm * WM + x) * 32 + (lane & 31);
-    int slot = 0, sft = 0;
-    if (row < args.rows) {
-      slot = int(row / args.r - q_lo);
-      sft = 4 * args.rot[row % args.r];
-    }
-    a_off[x] = slot * 2 * kSegBytes + kSegPad - sft + 16 * (lane >> 5);
-  }
-
-  // B staging sources (database tile), as in dot_kernel.
-  const int8_t* bsrc[kBPerThread];
-#pragma unroll
-  for (int j = 0; j < kBPerThread; ++j) {
-    const int c = tid + j * kThreads;
-    const int blk = c >> 7, rem = c & 127;
-    const int plane = rem >> 6, kcl = (rem >> 5) & 1, slot = rem & 31;
-    uint64_t cb = uint64_t(t) * kBBlk + blk;
-    cb = cb < args.b_blocks ? cb : args.b_blocks - 1;
-    bsrc[j] = args.b + size_t(args.b_block0 + cb) * kBlockBytes + size_t(2 * vec + plane) * kPlaneBlockBytes +
-              size_t(kcl) * 512 + slot * 16;
-  }
-  // A staging: chunk c of a segment buffer = (query slot, plane, 16-byte piece).
-  const int a_chunks = int(nq) * 2 * kSegChunks;
-  const int8_t* asrc[ACH];
-  int adst[ACH];
-#pragma unroll
-  for (int j = 0; j < ACH; ++j) {
-    int c = tid + j * kThreads;
-    const bool ok = c < a_chunks;
-    c = ok ? c : 0;
-    const int qs = c / (2 * kSegChunks), rem = c % (2 * kSegChunks);
-    const int pl = rem / kSegChunks, piece = rem % kSegChunks;
-    const int src_off = ((piece * 16 - kSegPad) % kRowLen + kRowLen) % kRowLen;   // circular
-    asrc[j] = args.qop + size_t(q_lo + qs) * kQopRowBytes + size_t(2 * vec + pl) * kK + src_off;
-    adst[j] = ok ? (qs * 2 * kSegBytes + pl * kSegBytes + piece * 16) : -1;
-  }
-
-  v16i acc0[WM][WN], acc1[WM][WN];
-#pragma unroll
-  for (int x = 0; x < WM; ++x)
-#pragma unroll
-    for (int y = 0; y < WN; ++y)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) { acc0[x][y][e] = 0; acc1[x][y][e] = 0; }
-
-  constexpr int kSteps = kChunks / 2;        // 800
-  constexpr int kSegSteps = kRowLen / 32;    // 25 K-steps per segment
-  static_assert(kSteps % NSETS == 0, "the K loop is unrolled by NSETS");
-  v4i rs[NSETS][kBPerThread];
-  v4i ra[ACH];
-
-#define IMC_BLOAD(R, KS)                                                              \
-  _Pragma("unroll") for (int c_ = 0; c_ < kBPerThread; ++c_)                          \
-      R[c_] = *reinterpret_cast<const v4i*>(bsrc[c_] + size_t(2 * (KS)) * 512);
-#define IMC_BSTORE(R, STAGE)                                                          \
-  _Pragma("unroll") for (int c_ = 0; c_ < kBPerThread; ++c_)                          \
-      *reinterpret_cast<v4i*>(bst + (STAGE) * kBStage + (tid + c_ * kThreads) * 16) = R[c_];
-#define IMC_ALOAD(SEG)                                                                \
-  _Pragma("unroll") for (int c_ = 0; c_ < ACH; ++c_)                                  \
-      ra[c_] = *reinterpret_cast<const v4i*>(asrc[c_] + size_t(SEG) * kRowLen);
-#define IMC_ASTORE(BUF)                                                               \
-  _Pragma("unroll") for (int c_ = 0; c_ < ACH; ++c_)                                  \
-      if (adst[c_] >= 0) *reinterpret_cast<v4i*>(ast + (BUF) * abuf + adst[c_]) = ra[c_];
-
-  // Pipeline: B data for step j is global-loaded NSETS iterations ahead into
-  // register set (j - 2) % NSETS, written to LDS stage j % 3 two iterations
-  // ahead, and its fragments are read one iteration ahead (while the MFMAs
-  // of the current step run).  Stage (k+2)%3 is overwritten at iteration k;
-  // it was last read at iteration k-2.
-  v4i falo[WM], fahi[WM], fblo[WN], fbhi[WN];     // fragments of the current step
-  v4i nalo[WM], nahi[WM], nblo[WN], nbhi[WN];     // fragments of the next step
-#define IMC_FRAGS(ALO, AHI, BLO, BHI, K)                                              \
-  {                                                                                   \
-    const int kk_ = (K);                                                              \
-    const int seg_ = kk_ / kSegSteps, ts_ = kk_ - seg_ * kSegSteps;                   \
-    const int8_t* sb_ = bst + (kk_ % 3) * kBStage;                                    \
-    const int8_t* sa_ = ast + (seg_ & 1) * abuf + 32 * ts_;                           \
-    _Pragma("unroll") for (int x_ = 0; x_ < WM; ++x_) {                               \
-      const int32_t* pa_ = reinterpret_cast<const int32_t*>(sa_ + a_off[x_]);         \
-      const int32_t* ph_ = reinterpret_cast<const int32_t*>(sa_ + a_off[x_] + kSegBytes); \
-      ALO[x_] = v4i{pa_[0], pa_[1], pa_[2], pa_[3]};                                  \
-      AHI[x_] = v4i{ph_[0], ph_[1], ph_[2], ph_[3]};                                  \
-    }                                                                                 \
-    _Pragma("unroll") for (int y_ = 0; y_ < WN; ++y_) {                               \
-      const int8_t* pb_ = sb_ + (wn * WN + y_) * 2048 + lane * 16;                    \
-      BLO[y_] = *reinterpret_cast<const v4i*>(pb_);                                   \
-      BHI[y_] = *reinterpret_cast<const v4i*>(pb_ + 1024);                            \
-    }                                                                                 \
-  }
-
-  // prologue: A segment 0; B steps 0 and 1 in stages 0 and 1; steps 2.. in registers
-  IMC_ALOAD(0)
-  IMC_ASTORE(0)
-  {
-    v4i r0[kBPerThread];
-    IMC_BLOAD(r0, 0)
-    IMC_BSTORE(r0, 0)
-    IMC_BLOAD(r0, 1)
-    IMC_BSTORE(r0, 1)
-  }
-#pragma unroll
-  for (int set = 0; set < NSETS; ++set) { IMC_BLOAD(rs[set], set + 2) }
-  IMC_ALOAD(1)
-  __syncthreads();
-  IMC_FRAGS(falo, fahi, fblo, fbhi, 0)
-
-  for (int k0 = 0; k0 < kSteps; k0 += NSETS) {
-#pragma unroll
-    for (int uu = 0; uu < NSETS; ++uu) {
-      const int k = k0 + uu;
-      const int seg = k / kSegSteps, ts = k - seg * kSegSteps;
-      IMC_FRAGS(nalo, nahi, nblo, nbhi, min(k + 1, kSteps - 1))
-#pragma unroll
-      for (int x = 0; x < WM; ++x)
-#pragma unroll
-        for (int y = 0; y < WN; ++y) {
-          acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fblo[y], acc0[x][y], 0, 0, 0);
-          acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fbhi[y], acc1[x][y], 0, 0, 0);
-          acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fahi[x], fblo[y], acc1[x][y], 0, 0, 0);
-        }
-      IMC_BSTORE(rs[uu], (k + 2) % 3)             // step k + 2
-      // mid-segment: the next segment's query bytes go to the other A buffer
-      // (last read during the previous segment), then its loads are issued
-      // for the segment after it.
-      if (ts == kSegSteps / 2 && seg + 1 < kSteps / kSegSteps) {
-        IMC_ASTORE((seg + 1) & 1)
-        IMC_ALOAD(min(seg + 2, kSteps / kSegSteps - 1))
-      }
-      __syncthreads();
-      IMC_BLOAD(rs[uu], min(k + 2 + NSETS, kSteps - 1))
-#pragma unroll
-      for (int x = 0; x < WM; ++x) { falo[x] = nalo[x]; fahi[x] = nahi[x]; }
-#pragma unroll
-      for (int y = 0; y < WN; ++y) { fblo[y] = nblo[y]; fbhi[y] = nbhi[y]; }
-    }
-  }
-#undef IMC_FRAGS
-#undef IMC_BLOAD
-#undef IMC_BSTORE
-#undef IMC_ALOAD
-#undef IMC_ASTORE
-
-  uint16_t* out = args.out[vec];
-#pragma unroll
-  for (int x = 0; x < WM; ++x)
-#pragma unroll
-    for (int y = 0; y < WN; ++y) {
-      const uint64_t col = uint64_t(t) * kBN + (wn * WN + y) * 32 + (lane & 31);
-      if (col >= args.n) continue;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const uint32_t row = m0 + (wm * WM + x) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        if (row < args.rows) {
-          const uint32_t z = uint32_t(acc0[x][y][e]) + (uint32_t(acc1[x][y][e]) << 8);
-          out[uint64_t(row) * args.ld + col] = uint16_t(z);
-        }
-      }
-    }
-}
-
-template <int WM, int WN, int WAVES_M, int WAVES_N, int NSETS>
+template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int NSETS>
 static hipError_t launch_dot_cfg(DotArgs d, uint32_t rows, uint64_t n, hipStream_t s, bool persistent) {
   using C = DotCfg<WM, WN, WAVES_M, WAVES_N>;
   d.mt = (rows + C::kBM - 1) / C::kBM;
@@ -508,8 +309,8 @@ static hipError_t launch_dot_cfg(DotArgs d, uint32_t rows, uint64_t n, hipStream
     }
   }
   const dim3 grid(blocks, 1, 2);
-  const size_t lds = 2 * size_t(C::kStageBytes);
-  auto kern = dot_kernel<WM, WN, WAVES_M, WAVES_N, NSETS>;
+  const size_t lds = 3 * size_t(C::kStageBytes);
+  auto kern = dot_kernel<K, WM, WN, WAVES_M, WAVES_N, NSETS>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (e != hipSuccess) return e;
@@ -517,54 +318,31 @@ static hipError_t launch_dot_cfg(DotArgs d, uint32_t rows, uint64_t n, hipStream
   return hipGetLastError();
 }
 
-bool rot_dot_applies(uint32_t r) { return r >= 24; }
-
-hipError_t launch_rot_dot(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
-                          uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
-                          hipStream_t s) {
-  constexpr int WM = 2, WN = 2, WAVES_M = 4, WAVES_N = 2, NSETS = 4, ACH = 3;
-  constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N, kThreads = 64 * WAVES_M * WAVES_N;
-  const uint32_t rows = q * r;
-  if (rows == 0 || n == 0) return hipSuccess;
-  if (!rot_dot_applies(r)) return hipErrorInvalidValue;
-  RotDotArgs d;
-  d.qop = qop;
-  d.b = b;
-  d.out[0] = code;
-  d.out[1] = mask;
-  d.ld = ld;
-  d.rows = rows;
-  d.q = q;
-  d.r = r;
-  d.b_block0 = first_entry / 32;
-  d.b_blocks = (n + 31) / 32;
-  d.n = n;
-  d.mt = (rows + kBM - 1) / kBM;
-  d.nt = uint32_t((n + kBN - 1) / kBN);
-  d.max_q = (kBM + r - 1) / r + 1;
-  if (int(d.max_q) * 2 * kSegChunks > ACH * kThreads) return hipErrorInvalidValue;
-  for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) d.rot[i] = i < int(r) ? rot[i] : 0;
-  const uint32_t ntg = (d.nt + 7) / 8;
-  const dim3 grid(ntg * 8 * d.mt, 1, 2);
-  const size_t lds = 3 * size_t(kBN / 32) * 2 * 2 * 32 * 16 + 2 * size_t(d.max_q) * 2 * kSegBytes;
-  auto kern = rot_dot_kernel<WM, WN, WAVES_M, WAVES_N, NSETS, ACH>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, d);
+hipError_t launch_expand_rows(const int8_t* qop, uint32_t q, const imc_row* rows, uint32_t nrows, int8_t* a,
+                              uint32_t rows_pad, hipStream_t s, bool galois) {
+  const uint64_t chunks = galois ? Geo<kKGalois>::kChunks : Geo<kK>::kChunks;
+  const uint64_t total = uint64_t(rows_pad) * kPlanes * chunks;
+  const dim3 grid(unsigned((total + 255) / 256));
+  if (galois)
+    hipLaunchKernelGGL(expand_rows_kernel<kKGalois>, grid, dim3(256), 0, s, qop, q, rows, nrows, rows_pad, a);
+  else
+    hipLaunchKernelGGL(expand_rows_kernel<kK>, grid, dim3(256), 0, s, qop, q, rows, nrows, rows_pad, a);
   return hipGetLastError();
 }
 
-hipError_t launch_expand_rows(const int8_t* qop, uint32_t q, const imc_row* rows, uint32_t nrows, int8_t* a,
-                              uint32_t rows_pad, hipStream_t s) {
-  uint64_t total = uint64_t(rows_pad) * kPlanes * kChunks;
-  hipLaunchKernelGGL(expand_rows_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, qop, q, rows, nrows,
-                     rows_pad, a);
-  return hipGetLastError();
+template <int K>
+static hipError_t launch_dot_k(DotArgs d, uint32_t rows, uint64_t n, hipStream_t s, int variant) {
+  const bool persistent = (variant & IMC_DOT_PERSISTENT) != 0;
+  switch (variant & 0xF) {
+    case 2: return launch_dot_cfg<K, 2, 2, 2, 2, 2>(d, rows, n, s, persistent);    // 128 x 128, 4 waves of 64 x 64
+    case 3: return launch_dot_cfg<K, 2, 2, 4, 2, 1>(d, rows, n, s, persistent);    // 256 x 128, loads 3 steps ahead
+    default: return launch_dot_cfg<K, 2, 2, 4, 2, 2>(d, rows, n, s, persistent);   // 256 x 128, loads 4 steps ahead
+  }
 }
 
 hipError_t launch_dot(const int8_t* a, uint32_t rows, uint32_t a_blocks, const int8_t* b, uint64_t first_entry,
-                      uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld, hipStream_t s, int variant) {
+                      uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld, hipStream_t s, int variant,
+                      bool galois) {
   if (rows == 0 || n == 0) return hipSuccess;
   DotArgs d;
   d.a = a;
@@ -577,12 +355,7 @@ hipError_t launch_dot(const int8_t* a, uint32_t rows, uint32_t a_blocks, const i
   d.b_block0 = first_entry / 32;
   d.b_blocks = (n + 31) / 32;
   d.n = n;
-  const bool persistent = (variant & IMC_DOT_PERSISTENT) != 0;
-  switch (variant & 0xF) {
-    case 2: return launch_dot_cfg<2, 2, 2, 2, 2>(d, rows, n, s, persistent);    // 128 x 128, 4 waves of 64 x 64
-    case 3: return launch_dot_cfg<2, 2, 4, 2, 2>(d, rows, n, s, persistent);    // 256 x 128, 8 waves, 2-step prefetch
-    default: return launch_dot_cfg<2, 2, 4, 2, 4>(d, rows, n, s, persistent);   // 256 x 128, 8 waves, 4-step prefetch
-  }
+  return galois ? launch_dot_k<kKGalois>(d, rows, n, s, variant) : launch_dot_k<kK>(d, rows, n, s, variant);
 }
 
 }  // namespace imc

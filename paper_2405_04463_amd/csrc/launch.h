@@ -19,17 +19,24 @@ hipError_t launch_share_db(const Key& dk, const uint64_t* codes, const uint64_t*
 hipError_t launch_share_query(const Key& dk, const uint64_t* codes, const uint64_t* masks, uint64_t q,
                               uint64_t qid_base, int8_t* const op[3], uint16_t* const raw[3], hipStream_t s);
 hipError_t launch_append(const uint16_t* const raw[3], uint64_t qi, uint8_t* const db[3], uint64_t e, hipStream_t s);
+hipError_t launch_galois_share_db(const Key& dk, const uint64_t* codes, const uint64_t* masks, uint64_t n,
+                                  uint64_t first, uint8_t* const db[3], hipStream_t s);
+hipError_t launch_galois_share_query(const Key& dk, const uint64_t* codes, const uint64_t* masks, uint64_t q,
+                                     uint64_t qid_base, int8_t* const op[3], uint16_t* const raw[3], hipStream_t s);
+hipError_t launch_galois_append(const uint16_t* const raw[3], uint64_t qi, uint8_t* const db[3], uint64_t e,
+                                hipStream_t s);
 
 hipError_t launch_expand(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, int8_t* a, uint32_t rows_pad,
-                         hipStream_t s);
+                         hipStream_t s, bool galois);
 bool rot_dot_applies(uint32_t r);
 hipError_t launch_rot_dot(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
                           uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
-                          hipStream_t s);
+                          hipStream_t s, int kind, bool galois);
 hipError_t launch_expand_rows(const int8_t* qop, uint32_t q, const imc_row* rows, uint32_t nrows, int8_t* a,
-                              uint32_t rows_pad, hipStream_t s);
+                              uint32_t rows_pad, hipStream_t s, bool galois);
 hipError_t launch_dot(const int8_t* a, uint32_t rows, uint32_t a_blocks, const int8_t* b, uint64_t first_entry,
-                      uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld, hipStream_t s, int variant);
+                      uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld, hipStream_t s, int variant,
+                      bool galois);
 
 hipError_t launch_reshare(const Keys3& keys, const uint16_t* const add_code[3], const uint16_t* const add_mask[3],
                           uint64_t rows, uint64_t n, uint64_t ld, const imc_ids_dev& ids, uint16_t* const msg[3],
@@ -40,6 +47,10 @@ hipError_t launch_compare(const Keys3& keys, const uint16_t* const rep_code[3], 
 size_t or_tree_ws_bytes(uint64_t q, uint64_t r, uint64_t nw);
 hipError_t launch_or_tree(const Keys3& keys, const uint64_t* const match[3], uint64_t q, uint64_t nw, uint64_t mw_ld,
                           const imc_ids_dev& ids, void* ws, uint8_t* const dup[3], hipStream_t s);
+hipError_t launch_mask_in_batch(uint64_t* const match[3], uint64_t q, uint32_t r, uint64_t mw_ld, uint64_t word,
+                                hipStream_t s);
+hipError_t launch_or_bits(const Keys3& keys, const uint8_t* const x[3], const uint8_t* const y[3], uint64_t count,
+                          uint64_t id, uint8_t* const out[3], hipStream_t s);
 hipError_t launch_open(int kind, const void* const rep[3], uint64_t count, void* out, int check,
                        unsigned long long* bad, hipStream_t s);
 

@@ -1,0 +1,541 @@
+// rot_dot.hip -- rotation-aware variant of the party-local dot products
+// (Alg. 3; App. C).  Same arithmetic as the expanded kernel (balanced byte
+// limbs, i8 MFMA with i32 accumulation, three products into two
+// accumulators); the query rotations (Sec. 3: circular shifts of the
+// angular axis, party-local because sharing is elementwise) are applied
+// while reading the query operand from LDS instead of being materialised.
+#include "device.h"
+#include "launch.h"
+
+namespace imc {
+
+// ---------------------------------------------------------------------------
+// Rotation-aware dot kernel.  Rows are (query, rotation) pairs, so a 256-row
+// tile holds only ceil(256/R) + 1 distinct queries.  The K loop walks the 32
+// angular-row segments of 800 bytes (16 rows x 2 halves); for each segment the
+// workgroup keeps every tile query's bytes of that segment in LDS with 64
+// bytes of circular padding on both sides (928 B per plane), and a lane reads
+// its rotated fragment directly: rotation s shifts the segment by 4s bytes,
+// so the 16 bytes at (32t + 16g - 4s) are four aligned dword reads.  Only the
+// database operand streams through LDS per K-step.  Query segments are loaded
+// into registers one segment ahead and written into the other of two LDS
+// buffers half-way through the current segment.
+// ---------------------------------------------------------------------------
+struct RotDotArgs {
+  const int8_t* qop;     // unrotated query operand, row-major [q][plane 4][25600]
+  const int8_t* b;       // party's database region
+  uint16_t* out[2];
+  uint64_t ld;
+  uint32_t rows, q, r;
+  uint64_t b_block0, b_blocks, n;
+  uint32_t mt, nt;
+  uint32_t max_q;        // query slots per tile (LDS sizing)
+  int8_t rot[IMC_MAX_ROT_DEV];
+};
+
+constexpr int kSegPad = 64;                       // >= 4 * 15 and a multiple of 16
+constexpr int kSegBytes = kRowLen + 2 * kSegPad;  // 928
+constexpr int kSegChunks = kSegBytes / 16;        // 58
+
+template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int NSETS, int ACH>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotArgs args) {
+  using G = Geo<K>;
+  constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N;
+  constexpr int kThreads = 64 * WAVES_M * WAVES_N;
+  constexpr int kBBlk = kBN / 32;
+  constexpr int kBChunks = kBBlk * 2 * 2 * 32;                 // per K-step
+  constexpr int kBPerThread = kBChunks / kThreads;
+  constexpr int kBStage = kBChunks * 16;
+  static_assert(kBChunks % kThreads == 0, "B chunks must divide evenly");
+  extern __shared__ __align__(16) int8_t lds[];
+  int8_t* bst = lds;                                           // 3 B stages
+  int8_t* ast = lds + 3 * kBStage;                             // 2 A segment buffers
+  const uint32_t abuf = args.max_q * 2 * kSegBytes;            // bytes per A buffer
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+  const int vec = blockIdx.z;
+  const uint32_t i = blockIdx.x;
+  const uint32_t xcd = i & 7, s8 = i >> 3;
+  const uint32_t u = s8 % args.mt, tg = s8 / args.mt;
+  const uint32_t t = tg * 8 + xcd;
+  if (t >= args.nt) return;
+
+  const uint32_t m0 = u * kBM;
+  const uint32_t q_lo = m0 / args.r;
+  const uint32_t last_row = min(m0 + kBM, args.rows) - 1;
+  const uint32_t nq = last_row / args.r - q_lo + 1;            // <= max_q
+
+  // Per-lane A fragment offsets (bytes into an A buffer) for its row-blocks.
+  int a_off[WM];
+#pragma unroll
+  for (int x = 0; x < WM; ++x) {
+    const uint32_t row = m0 + (wm * WM + x) * 32 + (lane & 31);
+    int slot = 0, sft = 0;
+    if (row < args.rows) {
+      slot = int(row / args.r - q_lo);
+      sft = 4 * args.rot[row % args.r];
+    }
+    a_off[x] = slot * 2 * kSegBytes + kSegPad - sft + 16 * (lane >> 5);
+  }
+
+  // B staging sources (database tile), as in dot_kernel.
+  const int8_t* bsrc[kBPerThread];
+#pragma unroll
+  for (int j = 0; j < kBPerThread; ++j) {
+    const int c = tid + j * kThreads;
+    const int blk = c >> 7, rem = c & 127;
+    const int plane = rem >> 6, kcl = (rem >> 5) & 1, slot = rem & 31;
+    uint64_t cb = uint64_t(t) * kBBlk + blk;
+    cb = cb < args.b_blocks ? cb : args.b_blocks - 1;
+    bsrc[j] = args.b + size_t(args.b_block0 + cb) * G::kBlockBytes + size_t(2 * vec + plane) * G::kPlaneBlockBytes +
+              size_t(kcl) * 512 + slot * 16;
+  }
+  // A staging: chunk c of a segment buffer = (query slot, plane, 16-byte piece).
+  const int a_chunks = int(nq) * 2 * kSegChunks;
+  const int8_t* asrc[ACH];
+  int adst[ACH];
+#pragma unroll
+  for (int j = 0; j < ACH; ++j) {
+    int c = tid + j * kThreads;
+    const bool ok = c < a_chunks;
+    c = ok ? c : 0;
+    const int qs = c / (2 * kSegChunks), rem = c % (2 * kSegChunks);
+    const int pl = rem / kSegChunks, piece = rem % kSegChunks;
+    const int src_off = ((piece * 16 - kSegPad) % kRowLen + kRowLen) % kRowLen;   // circular
+    asrc[j] = args.qop + size_t(q_lo + qs) * G::kQopRowBytes + size_t(2 * vec + pl) * G::kK + src_off;
+    adst[j] = ok ? (qs * 2 * kSegBytes + pl * kSegBytes + piece * 16) : -1;
+  }
+
+  v16i acc0[WM][WN], acc1[WM][WN];
+#pragma unroll
+  for (int x = 0; x < WM; ++x)
+#pragma unroll
+    for (int y = 0; y < WN; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) { acc0[x][y][e] = 0; acc1[x][y][e] = 0; }
+
+  constexpr int kSteps = G::kChunks / 2;        // 800 or 400
+  constexpr int kSegSteps = kRowLen / 32;    // 25 K-steps per segment
+  static_assert(kSteps % NSETS == 0, "the K loop is unrolled by NSETS");
+  v4i rs[NSETS][kBPerThread];
+  v4i ra[ACH];
+
+#define IMC_BLOAD(R, KS)                                                              \
+  _Pragma("unroll") for (int c_ = 0; c_ < kBPerThread; ++c_)                          \
+      R[c_] = *reinterpret_cast<const v4i*>(bsrc[c_] + size_t(2 * (KS)) * 512);
+#define IMC_BSTORE(R, STAGE)                                                          \
+  _Pragma("unroll") for (int c_ = 0; c_ < kBPerThread; ++c_)                          \
+      *reinterpret_cast<v4i*>(bst + (STAGE) * kBStage + (tid + c_ * kThreads) * 16) = R[c_];
+#define IMC_ALOAD(SEG)                                                                \
+  _Pragma("unroll") for (int c_ = 0; c_ < ACH; ++c_)                                  \
+      ra[c_] = *reinterpret_cast<const v4i*>(asrc[c_] + size_t(SEG) * kRowLen);
+#define IMC_ASTORE(BUF)                                                               \
+  _Pragma("unroll") for (int c_ = 0; c_ < ACH; ++c_)                                  \
+      if (adst[c_] >= 0) *reinterpret_cast<v4i*>(ast + (BUF) * abuf + adst[c_]) = ra[c_];
+
+  // Pipeline: B data for step j is global-loaded NSETS iterations ahead into
+  // register set (j - 2) % NSETS, written to LDS stage j % 3 two iterations
+  // ahead, and its fragments are read one iteration ahead (while the MFMAs
+  // of the current step run).  Stage (k+2)%3 is overwritten at iteration k;
+  // it was last read at iteration k-2.
+  v4i falo[WM], fahi[WM], fblo[WN], fbhi[WN];     // fragments of the current step
+  v4i nalo[WM], nahi[WM], nblo[WN], nbhi[WN];     // fragments of the next step
+#define IMC_FRAGS(ALO, AHI, BLO, BHI, K)                                              \
+  {                                                                                   \
+    const int kk_ = (K);                                                              \
+    const int seg_ = kk_ / kSegSteps, ts_ = kk_ - seg_ * kSegSteps;                   \
+    const int8_t* sb_ = bst + (kk_ % 3) * kBStage;                                    \
+    const int8_t* sa_ = ast + (seg_ & 1) * abuf + 32 * ts_;                           \
+    _Pragma("unroll") for (int x_ = 0; x_ < WM; ++x_) {                               \
+      const int32_t* pa_ = reinterpret_cast<const int32_t*>(sa_ + a_off[x_]);         \
+      const int32_t* ph_ = reinterpret_cast<const int32_t*>(sa_ + a_off[x_] + kSegBytes); \
+      ALO[x_] = v4i{pa_[0], pa_[1], pa_[2], pa_[3]};                                  \
+      AHI[x_] = v4i{ph_[0], ph_[1], ph_[2], ph_[3]};                                  \
+    }                                                                                 \
+    _Pragma("unroll") for (int y_ = 0; y_ < WN; ++y_) {                               \
+      const int8_t* pb_ = sb_ + (wn * WN + y_) * 2048 + lane * 16;                    \
+      BLO[y_] = *reinterpret_cast<const v4i*>(pb_);                                   \
+      BHI[y_] = *reinterpret_cast<const v4i*>(pb_ + 1024);                            \
+    }                                                                                 \
+  }
+
+  // prologue: A segment 0; B steps 0 and 1 in stages 0 and 1; steps 2.. in registers
+  IMC_ALOAD(0)
+  IMC_ASTORE(0)
+  {
+    v4i r0[kBPerThread];
+    IMC_BLOAD(r0, 0)
+    IMC_BSTORE(r0, 0)
+    IMC_BLOAD(r0, 1)
+    IMC_BSTORE(r0, 1)
+  }
+#pragma unroll
+  for (int set = 0; set < NSETS; ++set) { IMC_BLOAD(rs[set], set + 2) }
+  IMC_ALOAD(1)
+  __syncthreads();
+  IMC_FRAGS(falo, fahi, fblo, fbhi, 0)
+
+  for (int k0 = 0; k0 < kSteps; k0 += NSETS) {
+#pragma unroll
+    for (int uu = 0; uu < NSETS; ++uu) {
+      const int k = k0 + uu;
+      const int seg = k / kSegSteps, ts = k - seg * kSegSteps;
+      IMC_FRAGS(nalo, nahi, nblo, nbhi, min(k + 1, kSteps - 1))
+#pragma unroll
+      for (int x = 0; x < WM; ++x)
+#pragma unroll
+        for (int y = 0; y < WN; ++y) {
+          acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fblo[y], acc0[x][y], 0, 0, 0);
+          acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fbhi[y], acc1[x][y], 0, 0, 0);
+          acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fahi[x], fblo[y], acc1[x][y], 0, 0, 0);
+        }
+      IMC_BSTORE(rs[uu], (k + 2) % 3)             // step k + 2
+      // mid-segment: the next segment's query bytes go to the other A buffer
+      // (last read during the previous segment), then its loads are issued
+      // for the segment after it.
+      if (ts == kSegSteps / 2 && seg + 1 < kSteps / kSegSteps) {
+        IMC_ASTORE((seg + 1) & 1)
+        IMC_ALOAD(min(seg + 2, kSteps / kSegSteps - 1))
+      }
+      __syncthreads();
+      IMC_BLOAD(rs[uu], min(k + 2 + NSETS, kSteps - 1))
+#pragma unroll
+      for (int x = 0; x < WM; ++x) { falo[x] = nalo[x]; fahi[x] = nahi[x]; }
+#pragma unroll
+      for (int y = 0; y < WN; ++y) { fblo[y] = nblo[y]; fbhi[y] = nbhi[y]; }
+    }
+  }
+#undef IMC_FRAGS
+#undef IMC_BLOAD
+#undef IMC_BSTORE
+#undef IMC_ALOAD
+#undef IMC_ASTORE
+
+  uint16_t* out = args.out[vec];
+#pragma unroll
+  for (int x = 0; x < WM; ++x)
+#pragma unroll
+    for (int y = 0; y < WN; ++y) {
+      const uint64_t col = uint64_t(t) * kBN + (wn * WN + y) * 32 + (lane & 31);
+      if (col >= args.n) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const uint32_t row = m0 + (wm * WM + x) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (row < args.rows) {
+          const uint32_t z = uint32_t(acc0[x][y][e]) + (uint32_t(acc1[x][y][e]) << 8);
+          out[uint64_t(row) * args.ld + col] = uint16_t(z);
+        }
+      }
+    }
+}
+
+bool rot_dot_applies(uint32_t r) { return r >= 24; }
+
+// ---------------------------------------------------------------------------
+// The same rotation-aware tiling with the operands copied HBM -> LDS by the
+// load units themselves (global_load_lds_dwordx4): no staging registers and
+// no LDS store instructions, so the database stream can run S - 3 K-steps
+// ahead through S LDS stages.  Each wave issues an identical sequence of
+// copies (one per K-step for the database, ACH per query segment, inactive
+// lanes copying a valid source into the buffer's unused tail), so a per-wave
+// vmcnt wait of S - 3 guarantees that the copy of step k + 2 has landed
+// before the barrier that precedes its fragment reads.  The barriers are
+// bare s_barrier instructions: a workgroup fence would wait for every
+// outstanding copy.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  // gfx9 s_waitcnt: vmcnt bits 3:0 and 15:14, expcnt 6:4 (7 = no wait), lgkmcnt 11:8 (15 = no wait)
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Wait for every outstanding LDS read (and nothing else).
+__device__ __forceinline__ void wait_lds() {
+  __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4) | (0 << 8));
+}
+
+__device__ __forceinline__ void bar() {
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ void copy16(const int8_t* g, int8_t* l) {
+  __builtin_amdgcn_global_load_lds(static_cast<const void*>(g), (__attribute__((address_space(3))) void*)(l), 16, 0,
+                                   0);
+}
+
+template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int S, int ACH>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_dma_kernel(RotDotArgs args) {
+  using G = Geo<K>;
+  constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N;
+  constexpr int kThreads = 64 * WAVES_M * WAVES_N;
+  constexpr int kBBlk = kBN / 32;
+  constexpr int kBChunks = kBBlk * 2 * 2 * 32;                 // per K-step
+  constexpr int kBPerThread = kBChunks / kThreads;
+  constexpr int kBStage = kBChunks * 16;
+  constexpr int kABuf = ACH * kThreads * 16;                   // A buffer incl. the unused tail
+  static_assert(kBChunks % kThreads == 0, "B chunks must divide evenly");
+  static_assert(S >= 4, "at least one copy in flight beyond the two read-ahead stages");
+  // the wait for step k + 2 must also cover the query segment copied at mid-segment
+  static_assert(S <= 12, "query segment copy must precede the copy waited for at the segment end");
+  extern __shared__ __align__(16) int8_t lds[];
+  int8_t* bst = lds;                                           // S B stages
+  int8_t* ast = lds + S * kBStage;                             // 2 A segment buffers
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+  const int vec = blockIdx.z;
+  const uint32_t i = blockIdx.x;
+  const uint32_t xcd = i & 7, s8 = i >> 3;
+  const uint32_t u = s8 % args.mt, tg = s8 / args.mt;
+  const uint32_t t = tg * 8 + xcd;
+  if (t >= args.nt) return;
+
+  const uint32_t m0 = u * kBM;
+  const uint32_t q_lo = m0 / args.r;
+  const uint32_t last_row = min(m0 + kBM, args.rows) - 1;
+  const uint32_t nq = last_row / args.r - q_lo + 1;            // <= max_q
+
+  int a_off[WM];
+#pragma unroll
+  for (int x = 0; x < WM; ++x) {
+    const uint32_t row = m0 + (wm * WM + x) * 32 + (lane & 31);
+    int slot = 0, sft = 0;
+    if (row < args.rows) {
+      slot = int(row / args.r - q_lo);
+      sft = 4 * args.rot[row % args.r];
+    }
+    a_off[x] = slot * 2 * kSegBytes + kSegPad - sft + 16 * (lane >> 5);
+  }
+
+  const int8_t* bsrc[kBPerThread];
+#pragma unroll
+  for (int j = 0; j < kBPerThread; ++j) {
+    const int c = tid + j * kThreads;
+    const int blk = c >> 7, rem = c & 127;
+    const int plane = rem >> 6, kcl = (rem >> 5) & 1, slot = rem & 31;
+    uint64_t cb = uint64_t(t) * kBBlk + blk;
+    cb = cb < args.b_blocks ? cb : args.b_blocks - 1;
+    bsrc[j] = args.b + size_t(args.b_block0 + cb) * G::kBlockBytes + size_t(2 * vec + plane) * G::kPlaneBlockBytes +
+              size_t(kcl) * 512 + slot * 16;
+  }
+  // A chunk c of a segment buffer = (query slot, plane, 16-byte piece) lands at
+  // byte 16 c; chunks past the tile's queries copy piece 0 of slot 0.
+  const int a_chunks = int(nq) * 2 * kSegChunks;
+  const int8_t* asrc[ACH];
+#pragma unroll
+  for (int j = 0; j < ACH; ++j) {
+    int c = tid + j * kThreads;
+    c = c < a_chunks ? c : 0;
+    const int qs = c / (2 * kSegChunks), rem = c % (2 * kSegChunks);
+    const int pl = rem / kSegChunks, piece = rem % kSegChunks;
+    const int src_off = ((piece * 16 - kSegPad) % kRowLen + kRowLen) % kRowLen;   // circular
+    asrc[j] = args.qop + size_t(q_lo + qs) * G::kQopRowBytes + size_t(2 * vec + pl) * G::kK + src_off;
+  }
+
+  v16i acc0[WM][WN], acc1[WM][WN];
+#pragma unroll
+  for (int x = 0; x < WM; ++x)
+#pragma unroll
+    for (int y = 0; y < WN; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) { acc0[x][y][e] = 0; acc1[x][y][e] = 0; }
+
+  constexpr int kSteps = G::kChunks / 2;        // 800 or 400
+  constexpr int kSegSteps = kRowLen / 32;    // 25 K-steps per segment
+  constexpr int kSegs = kSteps / kSegSteps;  // 32 or 16
+
+  // wave-uniform LDS bases of this wave's copies
+  const int wbase = wave * 64 * 16;
+#define IMC_BCOPY(KS)                                                                 \
+  {                                                                                   \
+    const int ks_ = (KS);                                                             \
+    _Pragma("unroll") for (int c_ = 0; c_ < kBPerThread; ++c_)                        \
+      copy16(bsrc[c_] + size_t(2 * ks_) * 512,                                        \
+             bst + (ks_ % S) * kBStage + c_ * kThreads * 16 + wbase);                 \
+  }
+#define IMC_ACOPY(SEG, BUF)                                                           \
+  _Pragma("unroll") for (int c_ = 0; c_ < ACH; ++c_)                                  \
+    copy16(asrc[c_] + size_t(SEG) * kRowLen, ast + (BUF) * kABuf + c_ * kThreads * 16 + wbase);
+
+  v4i falo[WM], fahi[WM], fblo[WN], fbhi[WN];
+  v4i nalo[WM], nahi[WM], nblo[WN], nbhi[WN];
+#define IMC_FRAGS(ALO, AHI, BLO, BHI, K)                                              \
+  {                                                                                   \
+    const int kk_ = (K);                                                              \
+    const int seg_ = kk_ / kSegSteps, ts_ = kk_ - seg_ * kSegSteps;                   \
+    const int8_t* sb_ = bst + (kk_ % S) * kBStage;                                    \
+    const int8_t* sa_ = ast + (seg_ & 1) * kABuf + 32 * ts_;                          \
+    _Pragma("unroll") for (int x_ = 0; x_ < WM; ++x_) {                               \
+      const int32_t* pa_ = reinterpret_cast<const int32_t*>(sa_ + a_off[x_]);         \
+      const int32_t* ph_ = reinterpret_cast<const int32_t*>(sa_ + a_off[x_] + kSegBytes); \
+      ALO[x_] = v4i{pa_[0], pa_[1], pa_[2], pa_[3]};                                  \
+      AHI[x_] = v4i{ph_[0], ph_[1], ph_[2], ph_[3]};                                  \
+    }                                                                                 \
+    _Pragma("unroll") for (int y_ = 0; y_ < WN; ++y_) {                               \
+      const int8_t* pb_ = sb_ + (wn * WN + y_) * 2048 + lane * 16;                    \
+      BLO[y_] = *reinterpret_cast<const v4i*>(pb_);                                   \
+      BHI[y_] = *reinterpret_cast<const v4i*>(pb_ + 1024);                            \
+    }                                                                                 \
+  }
+
+  // prologue: A segment 0, B steps 0 .. S - 2; all landed before the first reads
+  IMC_ACOPY(0, 0)
+#pragma unroll
+  for (int j = 0; j < S - 1; ++j) IMC_BCOPY(j)
+  wait_vm<0>();
+  bar();
+  IMC_FRAGS(falo, fahi, fblo, fbhi, 0)
+
+  // One K-step: copies for later steps, the next step's fragment reads (issued
+  // before the MFMAs so that they complete under them), the MFMAs, then the
+  // wait for the copy of step k + 2 and the barrier.  Unrolled by two so the
+  // current / next fragment registers alternate without moves.
+#define IMC_STEP(CUR, NXT, K)                                                         \
+  {                                                                                   \
+    const int k_ = (K);                                                               \
+    const int seg_ = k_ / kSegSteps, ts_ = k_ - seg_ * kSegSteps;                     \
+    wait_lds(); /* this step's fragments, read during the previous step */            \
+    if (ts_ == kSegSteps / 2 && seg_ + 1 < kSegs) IMC_ACOPY(seg_ + 1, (seg_ + 1) & 1) \
+    const bool more_ = k_ + S - 1 < kSteps;                                           \
+    if (more_) IMC_BCOPY(k_ + S - 1)                                                  \
+    IMC_FRAGS(NXT##alo, NXT##ahi, NXT##blo, NXT##bhi, min(k_ + 1, kSteps - 1))         \
+    __builtin_amdgcn_sched_barrier(0);                                                \
+    _Pragma("unroll") for (int x = 0; x < WM; ++x)                                    \
+    _Pragma("unroll") for (int y = 0; y < WN; ++y) {                                  \
+      acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(CUR##alo[x], CUR##blo[y], acc0[x][y], 0, 0, 0); \
+      acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(CUR##alo[x], CUR##bhi[y], acc1[x][y], 0, 0, 0); \
+      acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(CUR##ahi[x], CUR##blo[y], acc1[x][y], 0, 0, 0); \
+    }                                                                                 \
+    if (more_)                                                                        \
+      wait_vm<S - 3>();                                                               \
+    else                                                                              \
+      wait_vm<0>();                                                                   \
+    bar();                                                                            \
+  }
+  static_assert(kSteps % 2 == 0, "the K loop is unrolled by two");
+  for (int k = 0; k < kSteps; k += 2) {
+    IMC_STEP(f, n, k)
+    IMC_STEP(n, f, k + 1)
+  }
+#undef IMC_STEP
+  wait_vm<0>();
+#undef IMC_FRAGS
+#undef IMC_BCOPY
+#undef IMC_ACOPY
+
+  uint16_t* out = args.out[vec];
+#pragma unroll
+  for (int x = 0; x < WM; ++x)
+#pragma unroll
+    for (int y = 0; y < WN; ++y) {
+      const uint64_t col = uint64_t(t) * kBN + (wn * WN + y) * 32 + (lane & 31);
+      if (col >= args.n) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const uint32_t row = m0 + (wm * WM + x) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (row < args.rows) {
+          const uint32_t z = uint32_t(acc0[x][y][e]) + (uint32_t(acc1[x][y][e]) << 8);
+          out[uint64_t(row) * args.ld + col] = uint16_t(z);
+        }
+      }
+    }
+}
+
+template <int K, int NSETS>
+static hipError_t launch_rot_cfg(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+                                 uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
+                                 hipStream_t s) {
+  constexpr int WM = 2, WN = 2, WAVES_M = 4, WAVES_N = 2, ACH = 3;
+  constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N, kThreads = 64 * WAVES_M * WAVES_N;
+  const uint32_t rows = q * r;
+  if (rows == 0 || n == 0) return hipSuccess;
+  if (!rot_dot_applies(r)) return hipErrorInvalidValue;
+  RotDotArgs d;
+  d.qop = qop;
+  d.b = b;
+  d.out[0] = code;
+  d.out[1] = mask;
+  d.ld = ld;
+  d.rows = rows;
+  d.q = q;
+  d.r = r;
+  d.b_block0 = first_entry / 32;
+  d.b_blocks = (n + 31) / 32;
+  d.n = n;
+  d.mt = (rows + kBM - 1) / kBM;
+  d.nt = uint32_t((n + kBN - 1) / kBN);
+  d.max_q = (kBM + r - 1) / r + 1;
+  if (int(d.max_q) * 2 * kSegChunks > ACH * kThreads) return hipErrorInvalidValue;
+  for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) d.rot[i] = i < int(r) ? rot[i] : 0;
+  const uint32_t ntg = (d.nt + 7) / 8;
+  const dim3 grid(ntg * 8 * d.mt, 1, 2);
+  const size_t lds = 3 * size_t(kBN / 32) * 2 * 2 * 32 * 16 + 2 * size_t(d.max_q) * 2 * kSegBytes;
+  auto kern = rot_dot_kernel<K, WM, WN, WAVES_M, WAVES_N, NSETS, ACH>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, d);
+  return hipGetLastError();
+}
+
+template <int K>
+static hipError_t launch_rot_dma(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+                                 uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
+                                 hipStream_t s) {
+  constexpr int WM = 2, WN = 2, WAVES_M = 4, WAVES_N = 2, S = 8, ACH = 3;
+  constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N, kThreads = 64 * WAVES_M * WAVES_N;
+  const uint32_t rows = q * r;
+  if (rows == 0 || n == 0) return hipSuccess;
+  if (!rot_dot_applies(r)) return hipErrorInvalidValue;
+  RotDotArgs d;
+  d.qop = qop;
+  d.b = b;
+  d.out[0] = code;
+  d.out[1] = mask;
+  d.ld = ld;
+  d.rows = rows;
+  d.q = q;
+  d.r = r;
+  d.b_block0 = first_entry / 32;
+  d.b_blocks = (n + 31) / 32;
+  d.n = n;
+  d.mt = (rows + kBM - 1) / kBM;
+  d.nt = uint32_t((n + kBN - 1) / kBN);
+  d.max_q = (kBM + r - 1) / r + 1;
+  if (int(d.max_q) * 2 * kSegChunks > ACH * kThreads) return hipErrorInvalidValue;
+  for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) d.rot[i] = i < int(r) ? rot[i] : 0;
+  const uint32_t ntg = (d.nt + 7) / 8;
+  const dim3 grid(ntg * 8 * d.mt, 1, 2);
+  const size_t lds = size_t(S) * (kBN / 32) * 2 * 2 * 32 * 16 + 2 * size_t(ACH) * kThreads * 16;
+  auto kern = rot_dot_dma_kernel<K, WM, WN, WAVES_M, WAVES_N, S, ACH>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_rot_dot(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+                          uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
+                          hipStream_t s, int kind, bool galois) {
+  if (galois) {
+    switch (kind) {
+      case 1: return launch_rot_cfg<kKGalois, 8>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
+      case 2: return launch_rot_dma<kKGalois>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
+      default: return launch_rot_cfg<kKGalois, 4>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
+    }
+  }
+  switch (kind) {
+    case 1: return launch_rot_cfg<kK, 8>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);  // loads 10 steps ahead
+    case 2: return launch_rot_dma<kK>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);     // LDS copies, 8 stages
+    default: return launch_rot_cfg<kK, 4>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s); // loads 6 steps ahead
+  }
+}
+
+}  // namespace imc

@@ -10,24 +10,28 @@ from dataclasses import dataclass
 
 import torch
 
-from . import (OPEN_U8_XOR, OPEN_U16_ADD, OPEN_U64_XOR, Context, db_bytes, make_ids, or_tree_ws_bytes,
-               query_op_bytes, query_raw_bytes)
+from . import (OPEN_U8_XOR, OPEN_U16_ADD, OPEN_U64_XOR, Context, db_bytes, galois_db_bytes, galois_query_op_bytes,
+               galois_query_raw_bytes, make_ids, or_tree_ws_bytes, query_op_bytes, query_raw_bytes)
 
 ROW_BYTES = 102400
 
 
 def _dev(device):
+    if isinstance(device, torch.device):
+        return device
     return torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
 
 
 class SharedDB:
-    """The three parties' database regions (one device buffer each)."""
+    """The three parties' database regions (one device buffer each).
+    galois=True holds Shamir shares over the Galois ring (half the bytes)."""
 
-    def __init__(self, ctx: Context, capacity: int, device=0, parties=(0, 1, 2)):
+    def __init__(self, ctx: Context, capacity: int, device=0, parties=(0, 1, 2), galois: bool = False):
         self.ctx = ctx
         self.capacity = capacity
+        self.galois = galois
         self.n = 0
-        nb = db_bytes(capacity)
+        nb = galois_db_bytes(capacity) if galois else db_bytes(capacity)
         self.regions = [torch.empty(nb, dtype=torch.uint8, device=_dev(device)) if p in parties else None
                         for p in range(3)]
 
@@ -35,13 +39,14 @@ class SharedDB:
         """Share packed device codes/masks [n, 200] (uint64 as int64) into slots first.."""
         n = codes.shape[0]
         first = self.n if first is None else first
-        self.ctx.share_db(codes, masks, n, first, self.regions, self.capacity, stream)
+        self.ctx.share_db(codes, masks, n, first, self.regions, self.capacity, stream, galois=self.galois)
         self.n = max(self.n, first + n)
         return first
 
     def append(self, qs: "SharedQueries", qi: int, stream=None) -> int:
+        assert qs.galois == self.galois
         e = self.n
-        self.ctx.append_db(qs.raw, qi, self.regions, self.capacity, e, stream)
+        self.ctx.append_db(qs.raw, qi, self.regions, self.capacity, e, stream, galois=self.galois)
         self.n += 1
         return e
 
@@ -49,14 +54,18 @@ class SharedDB:
 class SharedQueries:
     """Shares of q queries: each party's dot operand and raw shares."""
 
-    def __init__(self, ctx: Context, codes, masks, query_id_base: int, device=0, keep_raw: bool = True, stream=None):
+    def __init__(self, ctx: Context, codes, masks, query_id_base: int, device=0, keep_raw: bool = True, stream=None,
+                 galois: bool = False):
         self.q = codes.shape[0]
         self.qid_base = query_id_base
+        self.galois = galois
         d = _dev(device)
-        self.op = [torch.empty(max(1, query_op_bytes(self.q)), dtype=torch.uint8, device=d) for _ in range(3)]
-        self.raw = ([torch.empty(max(1, query_raw_bytes(self.q)) // 2, dtype=torch.int16, device=d) for _ in range(3)]
+        ob = galois_query_op_bytes(self.q) if galois else query_op_bytes(self.q)
+        rb = galois_query_raw_bytes(self.q) if galois else query_raw_bytes(self.q)
+        self.op = [torch.empty(max(1, ob), dtype=torch.uint8, device=d) for _ in range(3)]
+        self.raw = ([torch.empty(max(2, rb) // 2, dtype=torch.int16, device=d) for _ in range(3)]
                     if keep_raw else None)
-        ctx.share_query(codes, masks, self.q, query_id_base, self.op, self.raw, stream)
+        ctx.share_query(codes, masks, self.q, query_id_base, self.op, self.raw, stream, galois=galois)
 
 
 @dataclass
@@ -97,10 +106,11 @@ def alloc_check(q: int, r: int, n: int, device=0) -> CheckBuffers:
 def run_check(ctx: Context, qs: SharedQueries, rot, db: SharedDB, first_entry: int, n: int, buf: CheckBuffers,
               or_tree: bool = True, stream=None):
     """Alg. 3 for queries qs at rotations rot against entries first_entry..+n."""
+    assert qs.galois == db.galois
     ids = make_ids(qs.qid_base, rot, first_entry)
     for p in range(3):
         ctx.dot_shares(p, qs.op[p], qs.q, ids, db.regions[p], db.capacity, n, buf.dot_code[p], buf.dot_mask[p],
-                       buf.ld, stream)
+                       buf.ld, stream, galois=db.galois)
     ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, n, buf.ld, ids, buf.msg, buf.rep_code, buf.rep_mask, stream)
     ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, n, buf.ld, ids, buf.match, buf.nw, stream)
     if or_tree:
@@ -127,3 +137,38 @@ def open_dots(ctx: Context, buf: CheckBuffers, check: int = 1, stream=None):
     s1 = ctx.open(OPEN_U16_ADD, buf.rep_code, buf.rows * buf.ld, outc, check, stream)
     s2 = ctx.open(OPEN_U16_ADD, buf.rep_mask, buf.rows * buf.ld, outm, check, stream)
     return outc, outm, (s1, s2)
+
+
+# In-batch matching (Sec. 6.3): the batch's queries are compared with each
+# other as entries, under entry ids distinct from the database's and an
+# OR-tree query-id offset distinct from the database tree's.
+BATCH_ENTRY_BASE = 1 << 47
+BATCH_OR_QID_OFFSET = 1 << 46
+
+
+def run_in_batch(ctx: Context, qs: SharedQueries, rot, buf_db: CheckBuffers, stream=None):
+    """Query qi of the batch is also compared with queries j < qi.  buf_db
+    holds the database check of the same queries (its dup); returns the
+    buffers of the batch part, whose `final` holds dup_db OR dup_batch."""
+    assert qs.raw is not None and 0 < qs.q <= 64
+    q, r = qs.q, len(rot)
+    region = SharedDB(ctx, 64, galois=qs.galois, device=buf_db.dup[0].device)
+    for j in range(q):
+        ctx.append_db(qs.raw, j, region.regions, region.capacity, j, stream, galois=qs.galois)
+    region.n = q
+    buf = alloc_check(q, r, q, device=buf_db.dup[0].device)
+    ids0 = make_ids(qs.qid_base, rot, 0)
+    for p in range(3):
+        ctx.dot_shares(p, qs.op[p], q, ids0, region.regions[p], region.capacity, q, buf.dot_code[p],
+                       buf.dot_mask[p], buf.ld, stream, galois=qs.galois)
+    ids = make_ids(qs.qid_base, rot, BATCH_ENTRY_BASE)
+    ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, q, buf.ld, ids, buf.msg, buf.rep_code, buf.rep_mask, stream)
+    ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, q, buf.ld, ids, buf.match, buf.nw, stream)
+    ctx.mask_in_batch(buf.match, q, r, buf.nw, 0, stream)
+    ids_or = make_ids(qs.qid_base + BATCH_OR_QID_OFFSET, rot, BATCH_ENTRY_BASE)
+    ctx.or_tree(buf.match, q, 1, buf.nw, ids_or, buf.ws, buf.ws.numel(), buf.dup, stream)
+    final = [torch.empty(2, q, dtype=torch.uint8, device=buf_db.dup[0].device) for _ in range(3)]
+    ctx.or_bits(buf_db.dup, buf.dup, q, qs.qid_base, final, stream)
+    buf.final = final
+    buf.region = region
+    return buf

@@ -33,8 +33,10 @@ import torch
 
 from . import OPEN_U8_XOR, Context, make_ids, or_tree_ws_bytes
 
-ROW = 102400
-RAW = 2 * 2 * 12800 * 2
+ROW = 102400                 # query operand bytes per query (replicated form)
+RAW = 2 * 2 * 12800 * 2      # raw query share bytes per query (replicated form)
+GALOIS_ROW = 51200           # the same for Galois-ring Shamir shares
+GALOIS_RAW = 2 * 12800 * 2
 
 
 @dataclass
@@ -61,6 +63,9 @@ class Server:
         """hbm_reserve: fraction of the device's memory kept free by admission."""
         assert chunk % 64 == 0
         self.ctx, self.db, self.rot = ctx, db, list(rot)
+        self.galois = bool(getattr(db, "galois", False))
+        self.row_bytes = GALOIS_ROW if self.galois else ROW
+        self.raw_bytes = GALOIS_RAW if self.galois else RAW
         self.R = len(self.rot)
         self.chunk, self.slots = chunk, slots
         self.append_uniques, self.keep_shares = append, keep_shares
@@ -73,8 +78,8 @@ class Server:
         self.ld = chunk
         i16 = lambda *s: torch.empty(*s, dtype=torch.int16, device=d)  # noqa: E731
         # slot-indexed query shares (operand row = slot)
-        self.op = [torch.empty(slots * ROW, dtype=torch.uint8, device=d) for _ in range(3)]
-        self.raw = [torch.empty(slots * RAW // 2, dtype=torch.int16, device=d) for _ in range(3)]
+        self.op = [torch.empty(slots * self.row_bytes, dtype=torch.uint8, device=d) for _ in range(3)]
+        self.raw = [torch.empty(slots * self.raw_bytes // 2, dtype=torch.int16, device=d) for _ in range(3)]
         # tick buffers: dot outputs of all slots' rows for one chunk
         self.dot_code = [i16(rows, self.ld) for _ in range(3)]
         self.dot_mask = [i16(rows, self.ld) for _ in range(3)]
@@ -139,8 +144,8 @@ class Server:
             req.admitted_at = now
             c = torch.from_numpy(np.ascontiguousarray(req.code).view(np.int64).reshape(1, 200)).to(self.dev)
             m = torch.from_numpy(np.ascontiguousarray(req.mask).view(np.int64).reshape(1, 200)).to(self.dev)
-            self.ctx.share_query(c, m, 1, req.qid, [o.data_ptr() + slot * ROW for o in self.op],
-                                 [r.data_ptr() + slot * RAW for r in self.raw])
+            self.ctx.share_query(c, m, 1, req.qid, [o.data_ptr() + slot * self.row_bytes for o in self.op],
+                                 [r.data_ptr() + slot * self.raw_bytes for r in self.raw], galois=self.galois)
             self.match[slot] = [torch.zeros(2, self.R, self.nw_full, dtype=torch.int64, device=self.dev)
                                 for _ in range(3)]
             self.active[slot] = req
@@ -179,7 +184,8 @@ class Server:
         self.rows_ev[b].record()
         for p in range(3):
             self.ctx.dot_shares_rows(p, self.op[p], self.slots, self.rows_dev[b], k, self.db.regions[p],
-                                     self.db.capacity, first, n_max, self.dot_code[p], self.dot_mask[p], self.ld)
+                                     self.db.capacity, first, n_max, self.dot_code[p], self.dot_mask[p], self.ld,
+                                     galois=self.galois)
         # per request: reshare and compare its rows into its match buffer
         for i, r in enumerate(reqs):
             n_j = min(self.chunk, r.snapshot - first)
@@ -230,9 +236,9 @@ class Server:
                 r.dup_shares = r.dup_shares.cpu().numpy()
                 r.match = [m.cpu().numpy() for m in self.match[r.slot]]
             if r.dup == 0 and self.append_uniques and self.db.n < self.max_entries:
-                raw = [x.data_ptr() + r.slot * RAW for x in self.raw]
+                raw = [x.data_ptr() + r.slot * self.raw_bytes for x in self.raw]
                 r.entry = self.db.n
-                self.ctx.append_db(raw, 0, self.db.regions, self.db.capacity, r.entry)
+                self.ctx.append_db(raw, 0, self.db.regions, self.db.capacity, r.entry, galois=self.galois)
                 self.db.n += 1
             self.match[r.slot] = None
             self.free.append(r.slot)
@@ -274,7 +280,7 @@ def plain_check(ctx: Context, db, req: Request, rot, buf_cache: dict):
     buf = buf_cache[key]
     c = torch.from_numpy(np.ascontiguousarray(req.code).view(np.int64).reshape(1, 200)).cuda()
     m = torch.from_numpy(np.ascontiguousarray(req.mask).view(np.int64).reshape(1, 200)).cuda()
-    qs = SharedQueries(ctx, c, m, req.qid)
+    qs = SharedQueries(ctx, c, m, req.qid, galois=bool(getattr(db, "galois", False)))
     run_check(ctx, qs, rot, db, 0, n, buf)
     out, _ = open_dup(ctx, buf, 1, check=0)
     return qs, out

@@ -112,7 +112,7 @@ def _setup(imc, ctx, seed, n, q, first=0, cap=None):
     return dc, dm, qc, qm, db, qs
 
 
-@pytest.mark.parametrize("tiles", [0, 1, 2, 3])
+@pytest.mark.parametrize("tiles", [0, 1, 2, 3, 5, 6])
 @pytest.mark.parametrize("q,rot,n,first", [
     (9, list(range(-15, 16)), 300, 64),   # 279 rows: 2 row tiles of 256, ragged; 3 column tiles, ragged
     (1, [0], 1, 0),                        # a single comparison

@@ -30,10 +30,10 @@ def env(keys):
     ctx.close()
 
 
-def _db(e, capacity=N0 + 16):
+def _db(e, capacity=N0 + 16, galois=False):
     from paper_2405_04463_amd.pipeline import SharedDB
 
-    db = SharedDB(e["ctx"], capacity)
+    db = SharedDB(e["ctx"], capacity, galois=galois)
     d64 = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()  # noqa: E731
     db.enroll(d64(e["dc"]), d64(e["dm"]), 0)
     torch.cuda.synchronize()
@@ -61,14 +61,15 @@ def _drive(srv, reqs_at_tick):
     return {r.rid: r for r in srv.done}
 
 
-def test_same_alone_in_mix_and_plain(env):
+@pytest.mark.parametrize("galois", [False, True])
+def test_same_alone_in_mix_and_plain(env, galois):
     from paper_2405_04463_amd.serve import Server, plain_check
 
     e = env
-    db = _db(e)
+    db = _db(e, galois=galois)
     alone = _drive(Server(e["ctx"], db, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True),
                    {0: [_req(e, 0, 1000)]})[0]
-    db2 = _db(e)
+    db2 = _db(e, galois=galois)
     mixed = _drive(Server(e["ctx"], db2, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True),
                    {0: [_req(e, i, 1000 + i) for i in (1, 2, 3)], 2: [_req(e, 0, 1000)], 3: [_req(e, 4, 1004)]})
     x = mixed[0]
@@ -87,11 +88,12 @@ def test_same_alone_in_mix_and_plain(env):
     assert mixed[1].dup == 1
 
 
-def test_unique_requests_are_appended(env):
+@pytest.mark.parametrize("galois", [False, True])
+def test_unique_requests_are_appended(env, galois):
     from paper_2405_04463_amd.serve import Request, Server
 
     e = env
-    db = _db(e)
+    db = _db(e, galois=galois)
     srv = Server(e["ctx"], db, ROT, chunk=CHUNK, slots=8, append=True)
     done = _drive(srv, {0: [_req(e, 5, 2005)]})
     y = done[5]
