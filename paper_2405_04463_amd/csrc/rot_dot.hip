@@ -447,11 +447,10 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_dma_kernel(Rot
     }
 }
 
-template <int K, int NSETS>
+template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int NSETS, int ACH>
 static hipError_t launch_rot_cfg(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
                                  uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
                                  hipStream_t s) {
-  constexpr int WM = 2, WN = 2, WAVES_M = 4, WAVES_N = 2, ACH = 3;
   constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N, kThreads = 64 * WAVES_M * WAVES_N;
   const uint32_t rows = q * r;
   if (rows == 0 || n == 0) return hipSuccess;
@@ -524,17 +523,19 @@ static hipError_t launch_rot_dma(const int8_t* qop, uint32_t q, uint32_t r, cons
 hipError_t launch_rot_dot(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
                           uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
                           hipStream_t s, int kind, bool galois) {
+  // 0: 8 waves of 64 x 64, loads 6 steps ahead; 1: loads 10 steps ahead;
+  // 2: HBM -> LDS copies, 8 stages
   if (galois) {
     switch (kind) {
-      case 1: return launch_rot_cfg<kKGalois, 8>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
+      case 1: return launch_rot_cfg<kKGalois, 2, 2, 4, 2, 8, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
       case 2: return launch_rot_dma<kKGalois>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
-      default: return launch_rot_cfg<kKGalois, 4>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
+      default: return launch_rot_cfg<kKGalois, 2, 2, 4, 2, 4, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
     }
   }
   switch (kind) {
-    case 1: return launch_rot_cfg<kK, 8>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);  // loads 10 steps ahead
-    case 2: return launch_rot_dma<kK>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);     // LDS copies, 8 stages
-    default: return launch_rot_cfg<kK, 4>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s); // loads 6 steps ahead
+    case 1: return launch_rot_cfg<kK, 2, 2, 4, 2, 8, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
+    case 2: return launch_rot_dma<kK>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
+    default: return launch_rot_cfg<kK, 2, 2, 4, 2, 4, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
   }
 }
 
