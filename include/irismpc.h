@@ -68,11 +68,13 @@ typedef int imc_status;
 #define IMC_DOT_TILES_ROTATION 4         /* 256 x 128 tiles; each tile's queries staged unrotated in
                                             LDS per 800-byte segment, rotations read in place
                                             (used when r >= 24, else as AUTO) */
-#define IMC_DOT_TILES_ROTATION_DEEP 5    /* as 4 with database loads issued 10 K-steps ahead
-                                            instead of 6 */
+                                         /* 5: not used */
 #define IMC_DOT_TILES_ROTATION_LDSCOPY 6 /* as 4 with both operands copied from HBM straight into
                                             LDS (8 database stages, no staging registers) */
-#define IMC_DOT_TILES_MAX 6
+#define IMC_DOT_TILES_ROTATION_DIRECT 7  /* as 4 with each wave loading its database fragments
+                                            straight into registers (only the query segments
+                                            pass through LDS; two barriers per 25 K-steps) */
+#define IMC_DOT_TILES_MAX 7
 #define IMC_DOT_PERSISTENT 0x10          /* bit 4: expanded tilings run a persistent grid (one
                                             workgroup per CU walking its XCD's tile sequence) */
 

@@ -29,7 +29,7 @@ EXPORTS = [
 ]
 
 (DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW, DOT_TILES_ROTATION,
- DOT_TILES_ROTATION_DEEP, DOT_TILES_ROTATION_LDSCOPY) = (0, 1, 2, 3, 4, 5, 6)
+ DOT_TILES_ROTATION_LDSCOPY, DOT_TILES_ROTATION_DIRECT) = (0, 1, 2, 3, 4, 6, 7)
 DOT_PERSISTENT = 0x10
 
 

@@ -62,6 +62,11 @@ imc_status check_ids(const imc_ids* ids) {
 
 size_t blocks_for(size_t capacity) { return (capacity + 31) / 32; }
 
+bool tiles_ok(uint32_t flags) {
+  const uint32_t t = flags & 0xFu;
+  return (flags & ~0x1Fu) == 0 && t <= IMC_DOT_TILES_MAX && t != 5;
+}
+
 }  // namespace
 
 extern "C" {
@@ -91,7 +96,7 @@ imc_status imc_create(const imc_params* p, int device, imc_ctx** out) {
   if (!p || !out) return IMC_EINVAL;
   *out = nullptr;
   if (p->code_bits != IMC_CODE_BITS || p->thr_a != 16384u) return IMC_EUNSUPPORTED;
-  if ((p->flags & ~0x1Fu) != 0 || (p->flags & 0xFu) > IMC_DOT_TILES_MAX) return IMC_EUNSUPPORTED;
+  if (!tiles_ok(p->flags)) return IMC_EUNSUPPORTED;
   if (p->max_rows == 0) return IMC_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess) return IMC_EDEVICE;
@@ -191,15 +196,15 @@ imc_status dot_shares_impl(imc_ctx* c, int party, const void* qop, size_t q, con
   const int v = c->dot_variant;
   const int tiles = v & 0xF;
   const bool rot_tiles = tiles == IMC_DOT_TILES_AUTO || tiles == IMC_DOT_TILES_ROTATION ||
-                         tiles == IMC_DOT_TILES_ROTATION_DEEP || tiles == IMC_DOT_TILES_ROTATION_LDSCOPY;
+                         tiles == IMC_DOT_TILES_ROTATION_LDSCOPY || tiles == IMC_DOT_TILES_ROTATION_DIRECT;
   if (rot_tiles && imc::rot_dot_applies(uint32_t(ids->r))) {
     // rotations read straight from the unrotated operand staged in LDS
     return dev_status(imc::launch_rot_dot(static_cast<const int8_t*>(qop), uint32_t(q), uint32_t(ids->r), ids->rot,
                                           static_cast<const int8_t*>(db), ids->first_entry_id, n, code_dot, mask_dot,
                                           ld, hipStream_t(stream),
-                                          tiles == IMC_DOT_TILES_ROTATION_DEEP      ? 1
-                                          : tiles == IMC_DOT_TILES_ROTATION_LDSCOPY ? 2
-                                                                                    : 0,
+                                          tiles == IMC_DOT_TILES_ROTATION_LDSCOPY  ? 2
+                                          : tiles == IMC_DOT_TILES_ROTATION_DIRECT ? 3
+                                                                                   : 0,
                                           galois));
   }
   const uint32_t rows_pad = uint32_t(blocks_for(rows) * 32);
@@ -333,7 +338,7 @@ imc_status imc_or_bits(imc_ctx* c, const uint8_t* const a[3], const uint8_t* con
 
 imc_status imc_set_dot_tiles(imc_ctx* c, uint32_t flags) {
   if (!c) return IMC_EINVAL;
-  if ((flags & ~0x1Fu) != 0 || (flags & 0xFu) > IMC_DOT_TILES_MAX) return IMC_EUNSUPPORTED;
+  if (!tiles_ok(flags)) return IMC_EUNSUPPORTED;
   c->dot_variant = int(flags);
   return IMC_OK;
 }

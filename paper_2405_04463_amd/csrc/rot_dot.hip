@@ -37,6 +37,31 @@ constexpr int kSegPad = 64;                       // >= 4 * 15 and a multiple of
 constexpr int kSegBytes = kRowLen + 2 * kSegPad;  // 928
 constexpr int kSegChunks = kSegBytes / 16;        // 58
 
+// Waits and barriers with explicit counts (the kernels below keep copies and
+// reads in flight across them).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  // gfx9 s_waitcnt: vmcnt bits 3:0 and 15:14, expcnt 6:4 (7 = no wait), lgkmcnt 11:8 (15 = no wait)
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Wait for every outstanding LDS read (and nothing else).
+__device__ __forceinline__ void wait_lds() {
+  __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4) | (0 << 8));
+}
+
+__device__ __forceinline__ void bar() {
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ void copy16(const int8_t* g, int8_t* l) {
+  __builtin_amdgcn_global_load_lds(static_cast<const void*>(g), (__attribute__((address_space(3))) void*)(l), 16, 0,
+                                   0);
+}
+
 template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int NSETS, int ACH>
 __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotArgs args) {
   using G = Geo<K>;
@@ -234,6 +259,185 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotA
 bool rot_dot_applies(uint32_t r) { return r >= 24; }
 
 // ---------------------------------------------------------------------------
+// The same rotation-aware tiling with the database fragments loaded by every
+// wave straight from HBM (through its L1/L2) into registers D K-steps ahead:
+// a fragment is 1 KB contiguous in the tiled layout, and the WAVES_M waves
+// that share a column block hit the same lines.  Only the query segments go
+// through LDS, so there is no per-step barrier: two per 25-step segment,
+// around the store of the next segment into the other A buffer.
+// ---------------------------------------------------------------------------
+template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int D, int ACH>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_gb_kernel(RotDotArgs args) {
+  using G = Geo<K>;
+  constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N;
+  constexpr int kThreads = 64 * WAVES_M * WAVES_N;
+  constexpr int kBBlk = kBN / 32;
+  extern __shared__ __align__(16) int8_t lds[];
+  int8_t* ast = lds;                                           // 2 A segment buffers
+  const uint32_t abuf = args.max_q * 2 * kSegBytes;            // bytes per A buffer
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+  const int vec = blockIdx.z;
+  const uint32_t i = blockIdx.x;
+  const uint32_t xcd = i & 7, s8 = i >> 3;
+  const uint32_t u = s8 % args.mt, tg = s8 / args.mt;
+  const uint32_t t = tg * 8 + xcd;
+  if (t >= args.nt) return;
+
+  const uint32_t m0 = u * kBM;
+  const uint32_t q_lo = m0 / args.r;
+  const uint32_t last_row = min(m0 + kBM, args.rows) - 1;
+  const uint32_t nq = last_row / args.r - q_lo + 1;            // <= max_q
+
+  int a_off[WM];
+#pragma unroll
+  for (int x = 0; x < WM; ++x) {
+    const uint32_t row = m0 + (wm * WM + x) * 32 + (lane & 31);
+    int slot = 0, sft = 0;
+    if (row < args.rows) {
+      slot = int(row / args.r - q_lo);
+      sft = 4 * args.rot[row % args.r];
+    }
+    a_off[x] = slot * 2 * kSegBytes + kSegPad - sft + 16 * (lane >> 5);
+  }
+
+  // This lane's 16 bytes of the lo-plane fragment of each of the wave's column
+  // blocks at K-step 0; step k adds 1 KB, the hi plane one plane block.
+  const int8_t* bfr[WN];
+#pragma unroll
+  for (int y = 0; y < WN; ++y) {
+    uint64_t cb = uint64_t(t) * kBBlk + wn * WN + y;
+    cb = cb < args.b_blocks ? cb : args.b_blocks - 1;
+    bfr[y] = args.b + size_t(args.b_block0 + cb) * G::kBlockBytes + size_t(2 * vec) * G::kPlaneBlockBytes + lane * 16;
+  }
+  const int a_chunks = int(nq) * 2 * kSegChunks;
+  const int8_t* asrc[ACH];
+  int adst[ACH];
+#pragma unroll
+  for (int j = 0; j < ACH; ++j) {
+    int c = tid + j * kThreads;
+    const bool ok = c < a_chunks;
+    c = ok ? c : 0;
+    const int qs = c / (2 * kSegChunks), rem = c % (2 * kSegChunks);
+    const int pl = rem / kSegChunks, piece = rem % kSegChunks;
+    const int src_off = ((piece * 16 - kSegPad) % kRowLen + kRowLen) % kRowLen;   // circular
+    asrc[j] = args.qop + size_t(q_lo + qs) * G::kQopRowBytes + size_t(2 * vec + pl) * G::kK + src_off;
+    adst[j] = ok ? (qs * 2 * kSegBytes + pl * kSegBytes + piece * 16) : -1;
+  }
+
+  v16i acc0[WM][WN], acc1[WM][WN];
+#pragma unroll
+  for (int x = 0; x < WM; ++x)
+#pragma unroll
+    for (int y = 0; y < WN; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) { acc0[x][y][e] = 0; acc1[x][y][e] = 0; }
+
+  constexpr int kSteps = G::kChunks / 2;        // 800 or 400
+  constexpr int kSegSteps = kRowLen / 32;       // 25 K-steps per segment
+  static_assert(kSteps % D == 0, "the K loop is unrolled by D");
+  v4i bl[D][WN], bh[D][WN];                     // database fragments, set = step % D
+  v4i ra[ACH];
+
+#define IMC_BLOAD(SET, KS)                                                            \
+  _Pragma("unroll") for (int y_ = 0; y_ < WN; ++y_) {                                 \
+    const int8_t* p_ = bfr[y_] + size_t(KS) * 1024;                                   \
+    bl[SET][y_] = *reinterpret_cast<const v4i*>(p_);                                  \
+    bh[SET][y_] = *reinterpret_cast<const v4i*>(p_ + G::kPlaneBlockBytes);            \
+  }
+#define IMC_ALOAD(SEG)                                                                \
+  _Pragma("unroll") for (int c_ = 0; c_ < ACH; ++c_)                                  \
+      ra[c_] = *reinterpret_cast<const v4i*>(asrc[c_] + size_t(SEG) * kRowLen);
+#define IMC_ASTORE(BUF)                                                               \
+  _Pragma("unroll") for (int c_ = 0; c_ < ACH; ++c_)                                  \
+      if (adst[c_] >= 0) *reinterpret_cast<v4i*>(ast + (BUF) * abuf + adst[c_]) = ra[c_];
+#define IMC_AFRAGS(ALO, AHI, K)                                                       \
+  {                                                                                   \
+    const int kk_ = (K);                                                              \
+    const int seg_ = kk_ / kSegSteps, ts_ = kk_ - seg_ * kSegSteps;                   \
+    const int8_t* sa_ = ast + (seg_ & 1) * abuf + 32 * ts_;                           \
+    _Pragma("unroll") for (int x_ = 0; x_ < WM; ++x_) {                               \
+      const int32_t* pa_ = reinterpret_cast<const int32_t*>(sa_ + a_off[x_]);         \
+      const int32_t* ph_ = reinterpret_cast<const int32_t*>(sa_ + a_off[x_] + kSegBytes); \
+      ALO[x_] = v4i{pa_[0], pa_[1], pa_[2], pa_[3]};                                  \
+      AHI[x_] = v4i{ph_[0], ph_[1], ph_[2], ph_[3]};                                  \
+    }                                                                                 \
+  }
+
+  // prologue: A segment 0 in buffer 0, segment 1 in registers; database
+  // fragments of steps 0 .. D-1 in flight
+  IMC_ALOAD(0)
+  IMC_ASTORE(0)
+  IMC_ALOAD(1)
+#pragma unroll
+  for (int set = 0; set < D; ++set) { IMC_BLOAD(set, set) }
+  __syncthreads();
+  v4i falo[WM], fahi[WM], nalo[WM], nahi[WM];
+  IMC_AFRAGS(falo, fahi, 0)
+
+  // One K-step: the next step's A fragments are read first (pinned ahead of
+  // the MFMAs, so they complete under them), then the MFMAs of this step,
+  // then the database fragments of step k + D are requested into the set
+  // this step consumed.  Two A register sets alternate (the loop is unrolled
+  // by D, which is even).
+#define IMC_GSTEP(CUR, NXT, UU)                                                       \
+  {                                                                                   \
+    const int k_ = k0 + (UU);                                                         \
+    const int seg_ = k_ / kSegSteps, ts_ = k_ - seg_ * kSegSteps;                     \
+    wait_lds(); /* this step's A fragments, read during the previous step */          \
+    if (ts_ == kSegSteps / 2 && seg_ + 1 < kSteps / kSegSteps) {                      \
+      /* every wave is past its last read of the other A buffer (segment seg-1): */   \
+      /* store segment seg+1 there and make it visible before the segment ends */     \
+      __syncthreads();                                                                \
+      IMC_ASTORE((seg_ + 1) & 1)                                                      \
+      __syncthreads();                                                                \
+      IMC_ALOAD(min(seg_ + 2, kSteps / kSegSteps - 1))                                \
+    }                                                                                 \
+    IMC_AFRAGS(NXT##alo, NXT##ahi, min(k_ + 1, kSteps - 1))                            \
+    __builtin_amdgcn_sched_barrier(0);                                                \
+    _Pragma("unroll") for (int x = 0; x < WM; ++x)                                    \
+    _Pragma("unroll") for (int y = 0; y < WN; ++y) {                                  \
+      acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(CUR##alo[x], bl[UU][y], acc0[x][y], 0, 0, 0); \
+      acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(CUR##alo[x], bh[UU][y], acc1[x][y], 0, 0, 0); \
+      acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(CUR##ahi[x], bl[UU][y], acc1[x][y], 0, 0, 0); \
+    }                                                                                 \
+    IMC_BLOAD(UU, min(k_ + D, kSteps - 1))                                            \
+  }
+  static_assert(D % 2 == 0, "A register sets alternate");
+  for (int k0 = 0; k0 < kSteps; k0 += D) {
+#pragma unroll
+    for (int h = 0; h < D; h += 2) {
+      IMC_GSTEP(f, n, h)
+      IMC_GSTEP(n, f, h + 1)
+    }
+  }
+#undef IMC_GSTEP
+#undef IMC_AFRAGS
+#undef IMC_BLOAD
+#undef IMC_ALOAD
+#undef IMC_ASTORE
+
+  uint16_t* out = args.out[vec];
+#pragma unroll
+  for (int x = 0; x < WM; ++x)
+#pragma unroll
+    for (int y = 0; y < WN; ++y) {
+      const uint64_t col = uint64_t(t) * kBN + (wn * WN + y) * 32 + (lane & 31);
+      if (col >= args.n) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const uint32_t row = m0 + (wm * WM + x) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (row < args.rows) {
+          const uint32_t z = uint32_t(acc0[x][y][e]) + (uint32_t(acc1[x][y][e]) << 8);
+          out[uint64_t(row) * args.ld + col] = uint16_t(z);
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // The same rotation-aware tiling with the operands copied HBM -> LDS by the
 // load units themselves (global_load_lds_dwordx4): no staging registers and
 // no LDS store instructions, so the database stream can run S - 3 K-steps
@@ -245,28 +449,6 @@ bool rot_dot_applies(uint32_t r) { return r >= 24; }
 // bare s_barrier instructions: a workgroup fence would wait for every
 // outstanding copy.
 // ---------------------------------------------------------------------------
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  // gfx9 s_waitcnt: vmcnt bits 3:0 and 15:14, expcnt 6:4 (7 = no wait), lgkmcnt 11:8 (15 = no wait)
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
-
-// Wait for every outstanding LDS read (and nothing else).
-__device__ __forceinline__ void wait_lds() {
-  __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4) | (0 << 8));
-}
-
-__device__ __forceinline__ void bar() {
-  __builtin_amdgcn_sched_barrier(0);
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-__device__ __forceinline__ void copy16(const int8_t* g, int8_t* l) {
-  __builtin_amdgcn_global_load_lds(static_cast<const void*>(g), (__attribute__((address_space(3))) void*)(l), 16, 0,
-                                   0);
-}
 
 template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int S, int ACH>
 __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_dma_kernel(RotDotArgs args) {
@@ -520,21 +702,57 @@ static hipError_t launch_rot_dma(const int8_t* qop, uint32_t q, uint32_t r, cons
   return hipGetLastError();
 }
 
+template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int D, int ACH>
+static hipError_t launch_rot_gb(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+                                uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
+                                hipStream_t s) {
+  constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N, kThreads = 64 * WAVES_M * WAVES_N;
+  const uint32_t rows = q * r;
+  if (rows == 0 || n == 0) return hipSuccess;
+  if (!rot_dot_applies(r)) return hipErrorInvalidValue;
+  RotDotArgs d;
+  d.qop = qop;
+  d.b = b;
+  d.out[0] = code;
+  d.out[1] = mask;
+  d.ld = ld;
+  d.rows = rows;
+  d.q = q;
+  d.r = r;
+  d.b_block0 = first_entry / 32;
+  d.b_blocks = (n + 31) / 32;
+  d.n = n;
+  d.mt = (rows + kBM - 1) / kBM;
+  d.nt = uint32_t((n + kBN - 1) / kBN);
+  d.max_q = (kBM + r - 1) / r + 1;
+  if (int(d.max_q) * 2 * kSegChunks > ACH * kThreads) return hipErrorInvalidValue;
+  for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) d.rot[i] = i < int(r) ? rot[i] : 0;
+  const uint32_t ntg = (d.nt + 7) / 8;
+  const dim3 grid(ntg * 8 * d.mt, 1, 2);
+  const size_t lds = 2 * size_t(d.max_q) * 2 * kSegBytes;
+  auto kern = rot_dot_gb_kernel<K, WM, WN, WAVES_M, WAVES_N, D, ACH>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, d);
+  return hipGetLastError();
+}
+
 hipError_t launch_rot_dot(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
                           uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
                           hipStream_t s, int kind, bool galois) {
-  // 0: 8 waves of 64 x 64, loads 6 steps ahead; 1: loads 10 steps ahead;
-  // 2: HBM -> LDS copies, 8 stages
+  // 0: 8 waves of 64 x 64, loads 6 steps ahead; 2: HBM -> LDS copies, 8
+  // stages; 3: database fragments straight into registers
   if (galois) {
     switch (kind) {
-      case 1: return launch_rot_cfg<kKGalois, 2, 2, 4, 2, 8, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
       case 2: return launch_rot_dma<kKGalois>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
+      case 3: return launch_rot_gb<kKGalois, 2, 2, 4, 2, 4, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
       default: return launch_rot_cfg<kKGalois, 2, 2, 4, 2, 4, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
     }
   }
   switch (kind) {
-    case 1: return launch_rot_cfg<kK, 2, 2, 4, 2, 8, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
     case 2: return launch_rot_dma<kK>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
+    case 3: return launch_rot_gb<kK, 2, 2, 4, 2, 4, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
     default: return launch_rot_cfg<kK, 2, 2, 4, 2, 4, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
   }
 }

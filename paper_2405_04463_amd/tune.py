@@ -13,9 +13,9 @@ import os
 import torch
 
 from . import (DOT_PERSISTENT, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_SHALLOW,
-               DOT_TILES_ROTATION, DOT_TILES_ROTATION_DEEP, DOT_TILES_ROTATION_LDSCOPY)
+               DOT_TILES_ROTATION, DOT_TILES_ROTATION_DIRECT, DOT_TILES_ROTATION_LDSCOPY)
 
-CANDIDATES_UNIFORM = [DOT_TILES_ROTATION, DOT_TILES_ROTATION_DEEP, DOT_TILES_ROTATION_LDSCOPY,
+CANDIDATES_UNIFORM = [DOT_TILES_ROTATION, DOT_TILES_ROTATION_LDSCOPY, DOT_TILES_ROTATION_DIRECT,
                       DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_256x128 | DOT_PERSISTENT,
                       DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW]
 CANDIDATES_ROWS = [DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_256x128 | DOT_PERSISTENT,

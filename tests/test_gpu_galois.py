@@ -112,7 +112,7 @@ def _setup(ctx, seed, n, q, first=0):
     return dc, dm, qc, qm, db, qs
 
 
-@pytest.mark.parametrize("tiles", [0, 1, 2, 5, 6])
+@pytest.mark.parametrize("tiles", [0, 1, 2, 6, 7])
 @pytest.mark.parametrize("q,rot,n,first", [
     (9, list(range(-15, 16)), 300, 64),   # 279 rows: 2 row tiles, ragged; 3 column tiles, ragged
     (2, [-3, 7], 129, 0),                  # expanded path, one past a column tile

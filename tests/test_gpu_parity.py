@@ -112,7 +112,7 @@ def _setup(imc, ctx, seed, n, q, first=0, cap=None):
     return dc, dm, qc, qm, db, qs
 
 
-@pytest.mark.parametrize("tiles", [0, 1, 2, 3, 5, 6])
+@pytest.mark.parametrize("tiles", [0, 1, 2, 3, 6, 7])
 @pytest.mark.parametrize("q,rot,n,first", [
     (9, list(range(-15, 16)), 300, 64),   # 279 rows: 2 row tiles of 256, ragged; 3 column tiles, ragged
     (1, [0], 1, 0),                        # a single comparison
@@ -225,3 +225,8 @@ def test_argument_errors(ctx, imc):
     assert e.value.status == imc.IMC_ESHAPE
     # empty work is a no-op
     ctx.dot_shares(0, op, 0, imc.make_ids(0, [0]), region, 64, 64, buf.dot_code[0], buf.dot_mask[0], buf.ld)
+    # tile configurations outside the supported set
+    for bad in (5, 8, 0x20):
+        with pytest.raises(imc.IMCError) as e:
+            ctx.set_dot_tiles(bad)
+        assert e.value.status == imc.IMC_EUNSUPPORTED
