@@ -28,15 +28,15 @@ MFMA_I8_PEAK_TOPS = 5000.0      # MI355X dense int8, tera-ops/s (MAC = 2 ops)
 # rows x 300,000 entries) from two rocprofv3 --pmc passes (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch, mean of 6 dispatches), each scaled by what the
 # same counter reads for a 1 GiB device-to-device copy (FETCH_SIZE 524,302 KiB,
-# WRITE_SIZE 1,048,576 KiB).  Valid only for the kernel sources it was taken on.
+# WRITE_SIZE 1,048,580 KiB).  Valid only for the kernel sources it was taken on.
 DOT_TRAFFIC = {
     "sources": {"paper_2405_04463_amd/csrc/rot_dot.hip":
-                "7a7ddcc20211c99ace441cbe7b4f5c49a692e7c1d6b804df5435364dff4826a2",
+                "8484bb95adf9305c1adba6300296d7761aa7d5e110e6159ffcb7fc53471c28e5",
                 "paper_2405_04463_amd/csrc/device.h":
-                "3e53df8914cf80bb8a047b8fe1f898529ac56bcc5dfdbef638b8d1cac403cbf4"},
+                "01f9dd36d63565b5c861295fe075b1a5243fe589572217901aa318eb708a8a23"},
     "rows": 1984, "n_db": 300_000,
-    "fetch_kib": 16_902_297.6, "write_kib": 2_329_111.2,
-    "fetch_scale": 1_048_576 / 524_302.0, "write_scale": 1.0,
+    "fetch_kib": 16_902_200.0, "write_kib": 2_329_190.0,
+    "fetch_scale": 1_048_576 / 524_302.0, "write_scale": 1_048_576 / 1_048_580.0,
 }
 
 HBM_PEAK_GBS = 8000.0
