@@ -291,7 +291,6 @@ def run_batched(args):
     import workload as wl
     from paper_2405_04463_amd.batch import BatchedStep, BatchSet, uneven_batches
     from paper_2405_04463_amd.pipeline import SharedDB
-    from paper_2405_04463_amd.tune import DotTuner
 
     dealer, party = keys()
     batches = uneven_batches(args.n_batches, seed=0x1A150004)
@@ -308,11 +307,8 @@ def run_batched(args):
     bs = BatchSet(ctx, batches, torch.from_numpy(qc.view(np.int64)).cuda(), torch.from_numpy(qm.view(np.int64)).cuda(),
                   galois=galois)
     st = BatchedStep(ctx, bs, db, 0, args.n_db, chunk=args.chunk, parties=(0,))
-    probe = BatchedStep(ctx, bs, db, 0, min(args.n_db, 16384), parties=(0,))
-    tuner = DotTuner()
-    best, times = tuner.tune(ctx, lambda: probe.run(), nrows, 0)
-    log(f"autotuned dot configuration {best}: {times}")
-    del probe
+    mode, best, times = st.autotune(probe_n=16384)
+    log(f"autotuned: mode {mode}, dot configuration {best}; probe ms {times}")
     torch.cuda.empty_cache()
     st.run()
     torch.cuda.synchronize()
@@ -342,7 +338,7 @@ def run_batched(args):
         "dtype": "u16", "data": "synthetic",
         "config": {"workload": f"{len(batches)} uneven batches (1..64 queries, 1/15/31 rotations, {nrows} rows) vs "
                                f"party-local DB {args.n_db} entries, dot products only",
-                   "chunk": args.chunk, "dot_config": int(best), "sharing": args.scheme},
+                   "chunk": args.chunk, "batched_mode": mode, "dot_config": int(best), "sharing": args.scheme},
         "plain": {"value": ncmp / t_p, "ms_per_step": t_p * 1e3, "same_outputs": same},
         "speedup_vs_plain": t_p / t_b,
     }, (None, None, None)

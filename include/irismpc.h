@@ -60,20 +60,22 @@ typedef int imc_status;
 
 /* Dot-product kernel configurations (imc_params.flags bits 0-3).  All give
  * identical results; they differ in tiling and in how rotations are formed. */
-#define IMC_DOT_TILES_AUTO 0             /* ROTATION when r >= 24, else EXPANDED_256x128 */
+#define IMC_DOT_TILES_AUTO 0             /* ROTATION when r >= 13, else EXPANDED_256x128 */
 #define IMC_DOT_TILES_EXPANDED_256x128 1 /* rotated rows expanded into scratch; 256 x 128 tiles,
                                             8 waves of 64 x 64, global loads 4 K-steps ahead */
 #define IMC_DOT_TILES_EXPANDED_128x128 2 /* as 1 with 128 x 128 tiles, 4 waves */
 #define IMC_DOT_TILES_EXPANDED_SHALLOW 3 /* as 1 with global loads 3 K-steps ahead */
 #define IMC_DOT_TILES_ROTATION 4         /* 256 x 128 tiles; each tile's queries staged unrotated in
                                             LDS per 800-byte segment, rotations read in place
-                                            (used when r >= 24, else as AUTO) */
+                                            (used when r >= 13, else as AUTO) */
                                          /* 5: not used */
 #define IMC_DOT_TILES_ROTATION_LDSCOPY 6 /* as 4 with both operands copied from HBM straight into
-                                            LDS (8 database stages, no staging registers) */
+                                            LDS (8 database stages, no staging registers);
+                                            used when r >= 22, else as AUTO */
 #define IMC_DOT_TILES_ROTATION_DIRECT 7  /* as 4 with each wave loading its database fragments
                                             straight into registers (only the query segments
-                                            pass through LDS; two barriers per 25 K-steps) */
+                                            pass through LDS; two barriers per 25 K-steps);
+                                            used when r >= 22, else as AUTO */
 #define IMC_DOT_TILES_MAX 7
 #define IMC_DOT_PERSISTENT 0x10          /* bit 4: expanded tilings run a persistent grid (one
                                             workgroup per CU walking its XCD's tile sequence) */
@@ -183,6 +185,16 @@ imc_status imc_dot_shares(imc_ctx* ctx, int party, const void* qop, size_t q, co
 imc_status imc_dot_shares_rows(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_row* rows,
                                size_t nrows, const void* db, size_t db_capacity, uint64_t first_entry_id,
                                size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld, imc_stream stream);
+
+/* imc_dot_shares over gathered queries: query i of the call (i < q) is row
+ * qidx[i] of qop (qidx: DEVICE array of q u32; rows may repeat or come in any
+ * order), every query at the rotations of ids; output row i*r + ri.  Lets a
+ * serving loop run the queries of its active slots as one uniform launch
+ * (the rotation-aware kernel when ids->r >= 13).  The caller guarantees every
+ * qidx[i] is a row of qop.  Errors as imc_dot_shares; null qidx -> EINVAL. */
+imc_status imc_dot_shares_gather(imc_ctx* ctx, int party, const void* qop, const uint32_t* qidx, size_t q,
+                                 const imc_ids* ids, const void* db, size_t db_capacity, size_t n,
+                                 uint16_t* code_dot, uint16_t* mask_dot, size_t ld, imc_stream stream);
 
 /* Select the dot-product configuration of an existing context (same values as
  * imc_params.flags bits 0-4).  Errors: IMC_EUNSUPPORTED. */
@@ -321,6 +333,11 @@ imc_status imc_galois_share_query(imc_ctx* ctx, const uint64_t* codes, const uin
 imc_status imc_galois_dot_shares(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_ids* ids,
                                  const void* db, size_t db_capacity, size_t n, uint16_t* code_dot,
                                  uint16_t* mask_dot, size_t ld, imc_stream stream);
+
+/* imc_dot_shares_gather for Galois-form operands and regions. */
+imc_status imc_galois_dot_shares_gather(imc_ctx* ctx, int party, const void* qop, const uint32_t* qidx, size_t q,
+                                        const imc_ids* ids, const void* db, size_t db_capacity, size_t n,
+                                        uint16_t* code_dot, uint16_t* mask_dot, size_t ld, imc_stream stream);
 
 /* imc_dot_shares_rows for Galois-form operands and regions. */
 imc_status imc_galois_dot_shares_rows(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_row* rows,

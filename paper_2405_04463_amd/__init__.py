@@ -25,7 +25,8 @@ EXPORTS = [
     "imc_compare_threshold", "imc_or_tree", "imc_open", "imc_append_db", "imc_dot_shares_rows",
     "imc_set_dot_tiles", "imc_galois_db_bytes", "imc_galois_query_op_bytes", "imc_galois_query_raw_bytes",
     "imc_galois_share_db", "imc_galois_share_query", "imc_galois_dot_shares", "imc_galois_dot_shares_rows",
-    "imc_galois_append_db", "imc_mask_in_batch", "imc_or_bits",
+    "imc_galois_append_db", "imc_mask_in_batch", "imc_or_bits", "imc_dot_shares_gather",
+    "imc_galois_dot_shares_gather",
 ]
 
 (DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW, DOT_TILES_ROTATION,
@@ -105,6 +106,9 @@ def lib():
         L.imc_galois_dot_shares_rows.argtypes = L.imc_dot_shares_rows.argtypes
         L.imc_galois_append_db.argtypes = L.imc_append_db.argtypes
         L.imc_mask_in_batch.argtypes = [_VP, _P3, sz, sz, sz, sz, _VP]
+        L.imc_dot_shares_gather.argtypes = [_VP, ctypes.c_int, _VP, _VP, sz, ctypes.POINTER(imc_ids), _VP, sz, sz, _VP,
+                                            _VP, sz, _VP]
+        L.imc_galois_dot_shares_gather.argtypes = L.imc_dot_shares_gather.argtypes
         L.imc_or_bits.argtypes = [_VP, _P3, _P3, sz, ctypes.c_uint64, _P3, _VP]
         for f in EXPORTS:
             if f not in ("imc_destroy", "imc_strerror") and not f.endswith("_bytes"):
@@ -245,6 +249,13 @@ class Context:
         f = "imc_galois_dot_shares" if galois else "imc_dot_shares"
         return _check(getattr(lib(), f)(self._h, party, addr(qop), q, ctypes.byref(ids), addr(db), capacity, n,
                                         addr(code_dot), addr(mask_dot), ld, _stream(stream)), f)
+
+    # -- imc_dot_shares_gather / imc_galois_dot_shares_gather (qidx: device uint32/int32 tensor [q])
+    def dot_shares_gather(self, party, qop, qidx, q, ids: imc_ids, db, capacity, n, code_dot, mask_dot, ld,
+                          stream=None, galois=False):
+        f = "imc_galois_dot_shares_gather" if galois else "imc_dot_shares_gather"
+        return _check(getattr(lib(), f)(self._h, party, addr(qop), addr(qidx), q, ctypes.byref(ids), addr(db),
+                                        capacity, n, addr(code_dot), addr(mask_dot), ld, _stream(stream)), f)
 
     # -- imc_dot_shares_rows / imc_galois_dot_shares_rows
     #    (rows: device int32 tensor [nrows, 2] = (query_index, rot))

@@ -1,12 +1,15 @@
 """Batching of uneven query batches (buffers and call sequence only).
 
 A *batch* is q queries checked at one rotation list (R = len(rot)) with
-consecutive query ids.  A step over many batches puts all their rows, batch
-after batch, into one row table (query operand index, rotation) and computes
-every party's dot products for all rows with ONE launch per database chunk
-(`imc_dot_shares_rows`), so the database streams from HBM once per chunk for
-all batches instead of once per batch.  Resharing, comparison and the OR-tree
-are elementwise per comparison and run per batch on the batch's row range.
+consecutive query ids.  A step over many batches computes every party's dot
+products for all their rows with one launch per database chunk per rotation
+list ("grouped": the batches of one list are contiguous, so the launch is a
+uniform `imc_dot_shares` and lists of 13 or more rotations get the
+rotation-aware kernel), or with ONE launch per chunk over a row table of all
+rows ("rows": `imc_dot_shares_rows`).  Either way the database streams from
+HBM once per chunk (per list) for all batches instead of once per batch.
+Resharing, comparison and the OR-tree are elementwise per comparison and run
+per batch on the batch's row range.
 
 `BatchedStep.capture()` records a whole step in a HIP graph (through torch's
 graph API); `replay()` re-runs it.  Per-batch plain launches (`run_plain`) are
@@ -38,7 +41,14 @@ def _dev(device):
 
 
 class BatchSet:
-    """Shared queries of several batches and their row table."""
+    """Shared queries of several batches and their row table.
+
+    The operand (and the row ranges of the outputs) is laid out grouped by
+    rotation list, batch order kept within a group, so the batches of one
+    rotation list are contiguous: a group can then run as one uniform
+    `imc_dot_shares` call.  qbase[b] / rbase[b] are batch b's first operand row
+    and output row; groups[i] = (rotation list, first batch slot, queries,
+    first output row)."""
 
     def __init__(self, ctx: Context, batches: list, codes, masks, device=0, stream=None, galois: bool = False):
         """codes/masks: device int64 [sum q_b, 200], batch after batch.
@@ -50,21 +60,28 @@ class BatchSet:
         d = _dev(device)
         self.row_bytes = galois_query_op_bytes(1) if galois else query_op_bytes(1)
         self.op = [torch.empty(max(1, self.q * self.row_bytes), dtype=torch.uint8, device=d) for _ in range(3)]
-        self.qbase, self.rbase = [], []
+        src = np.cumsum([0] + [b.q for b in batches])[:-1]          # batch b's first row of codes
+        order = sorted(range(len(batches)), key=lambda b: (-len(batches[b].rot), tuple(batches[b].rot), b))
+        self.qbase, self.rbase = [0] * len(batches), [0] * len(batches)
+        self.groups = []
         qi = ri = 0
         table = []
-        for b in batches:
-            self.qbase.append(qi)
-            self.rbase.append(ri)
+        for b in order:
+            bt = batches[b]
+            key = tuple(int(v) for v in bt.rot)
+            if not self.groups or self.groups[-1][0] != key:
+                self.groups.append([key, qi, 0, ri])
+            self.groups[-1][2] += bt.q
+            self.qbase[b], self.rbase[b] = qi, ri
             off = qi * self.row_bytes
             # each batch has its own id range: share it into its slice of the operand
-            ctx.share_query(codes[qi:qi + b.q], masks[qi:qi + b.q], b.q, b.qid_base,
+            ctx.share_query(codes[src[b]:src[b] + bt.q], masks[src[b]:src[b] + bt.q], bt.q, bt.qid_base,
                             [o.data_ptr() + off for o in self.op], None, stream, galois=galois)
-            for j in range(b.q):
-                for s in b.rot:
-                    table.append((qi + j, int(s)))
-            qi += b.q
-            ri += b.rows
+            for j in range(bt.q):
+                for sft in bt.rot:
+                    table.append((qi + j, int(sft)))
+            qi += bt.q
+            ri += bt.rows
         self.nrows = ri
         self.rows = torch.tensor(np.array(table, dtype=np.int32).reshape(-1, 2), device=d)
 
@@ -75,7 +92,7 @@ class BatchedStep:
     comparison per batch."""
 
     def __init__(self, ctx: Context, bs: BatchSet, db, first_entry: int, n: int, chunk: int | None = None,
-                 parties=(0,), compare: bool = False, device=0):
+                 parties=(0,), compare: bool = False, device=0, mode: str = "grouped"):
         assert first_entry % 64 == 0
         assert bs.galois == bool(getattr(db, "galois", False)), "query and database sharing differ"
         self.ctx, self.bs, self.db = ctx, bs, db
@@ -84,6 +101,7 @@ class BatchedStep:
         self.chunk = ((self.chunk + 63) // 64) * 64 if self.chunk < n else self.chunk
         self.parties = tuple(parties)
         self.compare = compare
+        self.mode = mode
         d = _dev(device)
         self.ld = ((self.chunk + 63) // 64) * 64
         self.nw = self.ld // 64
@@ -113,15 +131,51 @@ class BatchedStep:
             c0 += self.chunk
 
     def run(self, stream=None):
-        """Batched form: one dot launch per party per chunk over all rows."""
+        """Batched form.  mode "rows": one dot launch per party per chunk over
+        the row table of all batches; mode "grouped": one launch per rotation
+        list per party per chunk (uniform rotations, so the rotation-aware
+        kernel serves every list of 13 or more rotations)."""
         ctx, bs, db = self.ctx, self.bs, self.db
         for c0, m in self._chunks():
             for p in self.parties:
-                ctx.dot_shares_rows(p, bs.op[p], bs.q, bs.rows, bs.nrows, db.regions[p], db.capacity,
-                                    self.first + c0, m, self.dot_code[p], self.dot_mask[p], self.ld, stream,
-                                    galois=bs.galois)
+                if self.mode == "rows":
+                    ctx.dot_shares_rows(p, bs.op[p], bs.q, bs.rows, bs.nrows, db.regions[p], db.capacity,
+                                        self.first + c0, m, self.dot_code[p], self.dot_mask[p], self.ld, stream,
+                                        galois=bs.galois)
+                    continue
+                for rot, q0, qn, r0 in bs.groups:
+                    ids = make_ids(0, rot, self.first + c0)
+                    ctx.dot_shares(p, bs.op[p].data_ptr() + q0 * bs.row_bytes, qn, ids, db.regions[p], db.capacity,
+                                   m, self.dot_code[p].data_ptr() + 2 * r0 * self.ld,
+                                   self.dot_mask[p].data_ptr() + 2 * r0 * self.ld, self.ld, stream, galois=bs.galois)
         if self.compare:
             self._compare_all(stream)
+
+    def autotune(self, probe_n: int = 16384, reps: int = 2):
+        """Time every (mode, tile configuration) on a probe slice of the
+        database and keep the fastest; returns (mode, flags, {(mode, flags): ms})."""
+        from .tune import CANDIDATES_ROWS, CANDIDATES_UNIFORM
+
+        probe = BatchedStep(self.ctx, self.bs, self.db, self.first, min(self.n, probe_n), parties=self.parties[:1])
+        times = {}
+        for mode, cands in (("rows", CANDIDATES_ROWS), ("grouped", CANDIDATES_UNIFORM)):
+            probe.mode = mode
+            for c in cands:
+                self.ctx.set_dot_tiles(c)
+                probe.run()
+                torch.cuda.synchronize()
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+                for a, b in ev:
+                    a.record()
+                    probe.run()
+                    b.record()
+                torch.cuda.synchronize()
+                times[(mode, c)] = min(a.elapsed_time(b) for a, b in ev)
+        mode, flags = min(times, key=times.get)
+        self.mode = mode
+        self.ctx.set_dot_tiles(flags)
+        del probe
+        return mode, flags, times
 
     def run_plain(self, stream=None):
         """Plain form: one dot launch per batch per party per chunk."""

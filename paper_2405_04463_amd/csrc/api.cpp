@@ -178,10 +178,11 @@ imc_status share_query_impl(imc_ctx* c, const uint64_t* codes, const uint64_t* m
                                             hipStream_t(stream)));
 }
 
-imc_status dot_shares_impl(imc_ctx* c, int party, const void* qop, size_t q, const imc_ids* ids, const void* db,
-                           size_t capacity, size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
-                           imc_stream stream, bool galois) {
+imc_status dot_shares_impl(imc_ctx* c, int party, const void* qop, const uint32_t* qidx, size_t q, const imc_ids* ids,
+                           const void* db, size_t capacity, size_t n, uint16_t* code_dot, uint16_t* mask_dot,
+                           size_t ld, imc_stream stream, bool galois) {
   if (!c || party < 0 || party > 2) return IMC_EINVAL;
+  if (qidx && !aligned(qidx, 4)) return IMC_EINVAL;
   imc_status st = check_ids(ids);
   if (st != IMC_OK) return st;
   const size_t rows = q * size_t(ids->r);
@@ -197,18 +198,15 @@ imc_status dot_shares_impl(imc_ctx* c, int party, const void* qop, size_t q, con
   const int tiles = v & 0xF;
   const bool rot_tiles = tiles == IMC_DOT_TILES_AUTO || tiles == IMC_DOT_TILES_ROTATION ||
                          tiles == IMC_DOT_TILES_ROTATION_LDSCOPY || tiles == IMC_DOT_TILES_ROTATION_DIRECT;
-  if (rot_tiles && imc::rot_dot_applies(uint32_t(ids->r))) {
+  const int kind = tiles == IMC_DOT_TILES_ROTATION_LDSCOPY ? 2 : tiles == IMC_DOT_TILES_ROTATION_DIRECT ? 3 : 0;
+  if (rot_tiles && imc::rot_dot_applies(uint32_t(ids->r), kind)) {
     // rotations read straight from the unrotated operand staged in LDS
-    return dev_status(imc::launch_rot_dot(static_cast<const int8_t*>(qop), uint32_t(q), uint32_t(ids->r), ids->rot,
+    return dev_status(imc::launch_rot_dot(static_cast<const int8_t*>(qop), qidx, uint32_t(q), uint32_t(ids->r), ids->rot,
                                           static_cast<const int8_t*>(db), ids->first_entry_id, n, code_dot, mask_dot,
-                                          ld, hipStream_t(stream),
-                                          tiles == IMC_DOT_TILES_ROTATION_LDSCOPY  ? 2
-                                          : tiles == IMC_DOT_TILES_ROTATION_DIRECT ? 3
-                                                                                   : 0,
-                                          galois));
+                                          ld, hipStream_t(stream), kind, galois));
   }
   const uint32_t rows_pad = uint32_t(blocks_for(rows) * 32);
-  hipError_t e = imc::launch_expand(static_cast<const int8_t*>(qop), uint32_t(q), uint32_t(ids->r), ids->rot,
+  hipError_t e = imc::launch_expand(static_cast<const int8_t*>(qop), qidx, uint32_t(q), uint32_t(ids->r), ids->rot,
                                     c->rot_op, rows_pad, hipStream_t(stream), galois);
   if (e != hipSuccess) return IMC_EDEVICE;
   e = imc::launch_dot(c->rot_op, uint32_t(rows), rows_pad / 32, static_cast<const int8_t*>(db), ids->first_entry_id,
@@ -283,12 +281,24 @@ imc_status imc_galois_share_query(imc_ctx* c, const uint64_t* codes, const uint6
 imc_status imc_dot_shares(imc_ctx* c, int party, const void* qop, size_t q, const imc_ids* ids, const void* db,
                           size_t capacity, size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
                           imc_stream stream) {
-  return dot_shares_impl(c, party, qop, q, ids, db, capacity, n, code_dot, mask_dot, ld, stream, false);
+  return dot_shares_impl(c, party, qop, nullptr, q, ids, db, capacity, n, code_dot, mask_dot, ld, stream, false);
 }
 imc_status imc_galois_dot_shares(imc_ctx* c, int party, const void* qop, size_t q, const imc_ids* ids, const void* db,
                                  size_t capacity, size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
                                  imc_stream stream) {
-  return dot_shares_impl(c, party, qop, q, ids, db, capacity, n, code_dot, mask_dot, ld, stream, true);
+  return dot_shares_impl(c, party, qop, nullptr, q, ids, db, capacity, n, code_dot, mask_dot, ld, stream, true);
+}
+imc_status imc_dot_shares_gather(imc_ctx* c, int party, const void* qop, const uint32_t* qidx, size_t q,
+                                 const imc_ids* ids, const void* db, size_t capacity, size_t n, uint16_t* code_dot,
+                                 uint16_t* mask_dot, size_t ld, imc_stream stream) {
+  if (!qidx) return IMC_EINVAL;
+  return dot_shares_impl(c, party, qop, qidx, q, ids, db, capacity, n, code_dot, mask_dot, ld, stream, false);
+}
+imc_status imc_galois_dot_shares_gather(imc_ctx* c, int party, const void* qop, const uint32_t* qidx, size_t q,
+                                        const imc_ids* ids, const void* db, size_t capacity, size_t n,
+                                        uint16_t* code_dot, uint16_t* mask_dot, size_t ld, imc_stream stream) {
+  if (!qidx) return IMC_EINVAL;
+  return dot_shares_impl(c, party, qop, qidx, q, ids, db, capacity, n, code_dot, mask_dot, ld, stream, true);
 }
 imc_status imc_dot_shares_rows(imc_ctx* c, int party, const void* qop, size_t q, const imc_row* rows, size_t nrows,
                                const void* db, size_t capacity, uint64_t first_entry_id, size_t n, uint16_t* code_dot,

@@ -23,8 +23,9 @@ struct Rot {
 };
 
 template <int K>
-__global__ void __launch_bounds__(256) expand_kernel(const int8_t* __restrict__ qop, uint32_t q, uint32_t r, Rot rot,
-                                                     uint32_t rows_pad, int8_t* __restrict__ a) {
+__global__ void __launch_bounds__(256) expand_kernel(const int8_t* __restrict__ qop, const uint32_t* __restrict__ qidx,
+                                                     uint32_t q, uint32_t r, Rot rot, uint32_t rows_pad,
+                                                     int8_t* __restrict__ a) {
   using G = Geo<K>;
   uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   uint64_t total = uint64_t(rows_pad) * kPlanes * G::kChunks;
@@ -39,6 +40,7 @@ __global__ void __launch_bounds__(256) expand_kernel(const int8_t* __restrict__ 
   uint4 v = make_uint4(0, 0, 0, 0);
   if (row < q * r) {
     uint32_t qi = row / r, ri = row % r;
+    if (qidx) qi = qidx[qi];
     int s = rot.s[ri];
     uint32_t k0 = kc * 16;
     uint32_t h = k0 / kCodeBits, i0 = k0 - h * kCodeBits;
@@ -276,17 +278,17 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) dot_kernel(DotArgs arg
   }
 }
 
-hipError_t launch_expand(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, int8_t* a, uint32_t rows_pad,
-                         hipStream_t s, bool galois) {
+hipError_t launch_expand(const int8_t* qop, const uint32_t* qidx, uint32_t q, uint32_t r, const int8_t* rot, int8_t* a,
+                         uint32_t rows_pad, hipStream_t s, bool galois) {
   Rot rr;
   for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) rr.s[i] = i < int(r) ? rot[i] : 0;
   const uint64_t chunks = galois ? Geo<kKGalois>::kChunks : Geo<kK>::kChunks;
   const uint64_t total = uint64_t(rows_pad) * kPlanes * chunks;
   const dim3 grid(unsigned((total + 255) / 256));
   if (galois)
-    hipLaunchKernelGGL(expand_kernel<kKGalois>, grid, dim3(256), 0, s, qop, q, r, rr, rows_pad, a);
+    hipLaunchKernelGGL(expand_kernel<kKGalois>, grid, dim3(256), 0, s, qop, qidx, q, r, rr, rows_pad, a);
   else
-    hipLaunchKernelGGL(expand_kernel<kK>, grid, dim3(256), 0, s, qop, q, r, rr, rows_pad, a);
+    hipLaunchKernelGGL(expand_kernel<kK>, grid, dim3(256), 0, s, qop, qidx, q, r, rr, rows_pad, a);
   return hipGetLastError();
 }
 

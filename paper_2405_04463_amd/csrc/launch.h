@@ -26,10 +26,11 @@ hipError_t launch_galois_share_query(const Key& dk, const uint64_t* codes, const
 hipError_t launch_galois_append(const uint16_t* const raw[3], uint64_t qi, uint8_t* const db[3], uint64_t e,
                                 hipStream_t s);
 
-hipError_t launch_expand(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, int8_t* a, uint32_t rows_pad,
-                         hipStream_t s, bool galois);
-bool rot_dot_applies(uint32_t r);
-hipError_t launch_rot_dot(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+hipError_t launch_expand(const int8_t* qop, const uint32_t* qidx, uint32_t q, uint32_t r, const int8_t* rot, int8_t* a,
+                         uint32_t rows_pad, hipStream_t s, bool galois);
+bool rot_dot_applies(uint32_t r, int kind);
+hipError_t launch_rot_dot(const int8_t* qop, const uint32_t* qidx, uint32_t q, uint32_t r, const int8_t* rot,
+                          const int8_t* b,
                           uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
                           hipStream_t s, int kind, bool galois);
 hipError_t launch_expand_rows(const int8_t* qop, uint32_t q, const imc_row* rows, uint32_t nrows, int8_t* a,

@@ -22,7 +22,8 @@ namespace imc {
 // buffers half-way through the current segment.
 // ---------------------------------------------------------------------------
 struct RotDotArgs {
-  const int8_t* qop;     // unrotated query operand, row-major [q][plane 4][25600]
+  const int8_t* qop;     // unrotated query operand, row-major [q][plane 4][K]
+  const uint32_t* qidx;  // optional: query i of the call is operand row qidx[i]
   const int8_t* b;       // party's database region
   uint16_t* out[2];
   uint64_t ld;
@@ -129,7 +130,8 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotA
     const int qs = c / (2 * kSegChunks), rem = c % (2 * kSegChunks);
     const int pl = rem / kSegChunks, piece = rem % kSegChunks;
     const int src_off = ((piece * 16 - kSegPad) % kRowLen + kRowLen) % kRowLen;   // circular
-    asrc[j] = args.qop + size_t(q_lo + qs) * G::kQopRowBytes + size_t(2 * vec + pl) * G::kK + src_off;
+    const uint32_t qrow = args.qidx ? args.qidx[q_lo + qs] : q_lo + qs;
+    asrc[j] = args.qop + size_t(qrow) * G::kQopRowBytes + size_t(2 * vec + pl) * G::kK + src_off;
     adst[j] = ok ? (qs * 2 * kSegBytes + pl * kSegBytes + piece * 16) : -1;
   }
 
@@ -256,7 +258,10 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotA
     }
 }
 
-bool rot_dot_applies(uint32_t r) { return r >= 24; }
+// The query slots of a 256-row tile (ceil(256 / r) + 1 of them) must fit the
+// A staging of the configuration: 3 chunks per thread up to 13 queries (r >= 22),
+// 5 up to 22 queries (r >= 13, default configuration only).
+bool rot_dot_applies(uint32_t r, int kind) { return kind == 0 ? r >= 13 : r >= 22; }
 
 // ---------------------------------------------------------------------------
 // The same rotation-aware tiling with the database fragments loaded by every
@@ -323,7 +328,8 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_gb_kernel(RotD
     const int qs = c / (2 * kSegChunks), rem = c % (2 * kSegChunks);
     const int pl = rem / kSegChunks, piece = rem % kSegChunks;
     const int src_off = ((piece * 16 - kSegPad) % kRowLen + kRowLen) % kRowLen;   // circular
-    asrc[j] = args.qop + size_t(q_lo + qs) * G::kQopRowBytes + size_t(2 * vec + pl) * G::kK + src_off;
+    const uint32_t qrow = args.qidx ? args.qidx[q_lo + qs] : q_lo + qs;
+    asrc[j] = args.qop + size_t(qrow) * G::kQopRowBytes + size_t(2 * vec + pl) * G::kK + src_off;
     adst[j] = ok ? (qs * 2 * kSegBytes + pl * kSegBytes + piece * 16) : -1;
   }
 
@@ -517,7 +523,8 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_dma_kernel(Rot
     const int qs = c / (2 * kSegChunks), rem = c % (2 * kSegChunks);
     const int pl = rem / kSegChunks, piece = rem % kSegChunks;
     const int src_off = ((piece * 16 - kSegPad) % kRowLen + kRowLen) % kRowLen;   // circular
-    asrc[j] = args.qop + size_t(q_lo + qs) * G::kQopRowBytes + size_t(2 * vec + pl) * G::kK + src_off;
+    const uint32_t qrow = args.qidx ? args.qidx[q_lo + qs] : q_lo + qs;
+    asrc[j] = args.qop + size_t(qrow) * G::kQopRowBytes + size_t(2 * vec + pl) * G::kK + src_off;
   }
 
   v16i acc0[WM][WN], acc1[WM][WN];
@@ -630,15 +637,17 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_dma_kernel(Rot
 }
 
 template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int NSETS, int ACH>
-static hipError_t launch_rot_cfg(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+static hipError_t launch_rot_cfg(const int8_t* qop, const uint32_t* qidx, uint32_t q, uint32_t r, const int8_t* rot,
+                                 const int8_t* b,
                                  uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
                                  hipStream_t s) {
   constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N, kThreads = 64 * WAVES_M * WAVES_N;
   const uint32_t rows = q * r;
   if (rows == 0 || n == 0) return hipSuccess;
-  if (!rot_dot_applies(r)) return hipErrorInvalidValue;
+  if (r < 13) return hipErrorInvalidValue;
   RotDotArgs d;
   d.qop = qop;
+  d.qidx = qidx;
   d.b = b;
   d.out[0] = code;
   d.out[1] = mask;
@@ -666,16 +675,18 @@ static hipError_t launch_rot_cfg(const int8_t* qop, uint32_t q, uint32_t r, cons
 }
 
 template <int K>
-static hipError_t launch_rot_dma(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+static hipError_t launch_rot_dma(const int8_t* qop, const uint32_t* qidx, uint32_t q, uint32_t r, const int8_t* rot,
+                                 const int8_t* b,
                                  uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
                                  hipStream_t s) {
   constexpr int WM = 2, WN = 2, WAVES_M = 4, WAVES_N = 2, S = 8, ACH = 3;
   constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N, kThreads = 64 * WAVES_M * WAVES_N;
   const uint32_t rows = q * r;
   if (rows == 0 || n == 0) return hipSuccess;
-  if (!rot_dot_applies(r)) return hipErrorInvalidValue;
+  if (r < 13) return hipErrorInvalidValue;
   RotDotArgs d;
   d.qop = qop;
+  d.qidx = qidx;
   d.b = b;
   d.out[0] = code;
   d.out[1] = mask;
@@ -703,15 +714,17 @@ static hipError_t launch_rot_dma(const int8_t* qop, uint32_t q, uint32_t r, cons
 }
 
 template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int D, int ACH>
-static hipError_t launch_rot_gb(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+static hipError_t launch_rot_gb(const int8_t* qop, const uint32_t* qidx, uint32_t q, uint32_t r, const int8_t* rot,
+                                 const int8_t* b,
                                 uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
                                 hipStream_t s) {
   constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N, kThreads = 64 * WAVES_M * WAVES_N;
   const uint32_t rows = q * r;
   if (rows == 0 || n == 0) return hipSuccess;
-  if (!rot_dot_applies(r)) return hipErrorInvalidValue;
+  if (r < 13) return hipErrorInvalidValue;
   RotDotArgs d;
   d.qop = qop;
+  d.qidx = qidx;
   d.b = b;
   d.out[0] = code;
   d.out[1] = mask;
@@ -738,22 +751,27 @@ static hipError_t launch_rot_gb(const int8_t* qop, uint32_t q, uint32_t r, const
   return hipGetLastError();
 }
 
-hipError_t launch_rot_dot(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+hipError_t launch_rot_dot(const int8_t* qop, const uint32_t* qidx, uint32_t q, uint32_t r, const int8_t* rot,
+                          const int8_t* b,
                           uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
                           hipStream_t s, int kind, bool galois) {
   // 0: 8 waves of 64 x 64, loads 6 steps ahead; 2: HBM -> LDS copies, 8
   // stages; 3: database fragments straight into registers
   if (galois) {
     switch (kind) {
-      case 2: return launch_rot_dma<kKGalois>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
-      case 3: return launch_rot_gb<kKGalois, 2, 2, 4, 2, 4, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
-      default: return launch_rot_cfg<kKGalois, 2, 2, 4, 2, 4, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
+      case 2: return launch_rot_dma<kKGalois>(qop, qidx, q, r, rot, b, first_entry, n, code, mask, ld, s);
+      case 3: return launch_rot_gb<kKGalois, 2, 2, 4, 2, 4, 3>(qop, qidx, q, r, rot, b, first_entry, n, code, mask, ld, s);
+      default:
+        if (r >= 22) return launch_rot_cfg<kKGalois, 2, 2, 4, 2, 4, 3>(qop, qidx, q, r, rot, b, first_entry, n, code, mask, ld, s);
+        return launch_rot_cfg<kKGalois, 2, 2, 4, 2, 4, 5>(qop, qidx, q, r, rot, b, first_entry, n, code, mask, ld, s);
     }
   }
   switch (kind) {
-    case 2: return launch_rot_dma<kK>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
-    case 3: return launch_rot_gb<kK, 2, 2, 4, 2, 4, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
-    default: return launch_rot_cfg<kK, 2, 2, 4, 2, 4, 3>(qop, q, r, rot, b, first_entry, n, code, mask, ld, s);
+    case 2: return launch_rot_dma<kK>(qop, qidx, q, r, rot, b, first_entry, n, code, mask, ld, s);
+    case 3: return launch_rot_gb<kK, 2, 2, 4, 2, 4, 3>(qop, qidx, q, r, rot, b, first_entry, n, code, mask, ld, s);
+    default:
+      if (r >= 22) return launch_rot_cfg<kK, 2, 2, 4, 2, 4, 3>(qop, qidx, q, r, rot, b, first_entry, n, code, mask, ld, s);
+      return launch_rot_cfg<kK, 2, 2, 4, 2, 4, 5>(qop, qidx, q, r, rot, b, first_entry, n, code, mask, ld, s);
   }
 }
 

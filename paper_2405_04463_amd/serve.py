@@ -4,7 +4,8 @@ Requests (one iris code + mask, checked at R rotations) arrive over time.
 The database shares stay resident in HBM, split into fixed chunks of `chunk`
 entries (a multiple of 64).  A cursor walks the chunks cyclically; on each
 tick every admitted request that still needs the cursor's chunk contributes
-its R rows to ONE batched dot launch per party (`imc_dot_shares_rows`),
+its R rows to ONE batched dot launch per party (`imc_dot_shares_gather` over
+the active slots, or `imc_dot_shares_rows` over a row table),
 then each request reshares and compares its rows, writing its match words
 into its own full-database match buffer at the chunk's word offset.  A
 request admitted while others are in flight joins at the current chunk (its
@@ -59,8 +60,13 @@ class Request:
 
 class Server:
     def __init__(self, ctx: Context, db, rot, chunk: int = 65536, slots: int = 64, max_entries: int | None = None,
-                 hbm_reserve: float = 0.01, append: bool = True, keep_shares: bool = False, device=0):
-        """hbm_reserve: fraction of the device's memory kept free by admission."""
+                 hbm_reserve: float = 0.01, append: bool = True, keep_shares: bool = False, device=0,
+                 gather: bool = True):
+        """hbm_reserve: fraction of the device's memory kept free by admission.
+        gather: run each tick's dot products as one gathered uniform launch
+        (`imc_dot_shares_gather`); otherwise through a row table
+        (`imc_dot_shares_rows`)."""
+        self.gather = gather
         assert chunk % 64 == 0
         self.ctx, self.db, self.rot = ctx, db, list(rot)
         self.galois = bool(getattr(db, "galois", False))
@@ -176,16 +182,30 @@ class Server:
         b = self.ticks % self.ring
         if self.rows_ev[b] is not None:
             self.rows_ev[b].synchronize()
-        table = np.array([(r.slot, int(sft)) for r in reqs for sft in self.rot], dtype=np.int32)
-        k = table.shape[0]
-        self.rows_host[b][:k].copy_(torch.from_numpy(table))
-        self.rows_dev[b][:k].copy_(self.rows_host[b][:k], non_blocking=True)
+        if self.gather:
+            # the participating slots as a gather list: every request has the same
+            # rotations, so this is one uniform launch (rotation-aware kernel)
+            table = np.array([r.slot for r in reqs], dtype=np.int32)
+            k = table.shape[0]
+            self.rows_host[b].view(-1)[:k].copy_(torch.from_numpy(table))
+            self.rows_dev[b].view(-1)[:k].copy_(self.rows_host[b].view(-1)[:k], non_blocking=True)
+        else:
+            table = np.array([(r.slot, int(sft)) for r in reqs for sft in self.rot], dtype=np.int32)
+            k = table.shape[0]
+            self.rows_host[b][:k].copy_(torch.from_numpy(table))
+            self.rows_dev[b][:k].copy_(self.rows_host[b][:k], non_blocking=True)
         self.rows_ev[b] = torch.cuda.Event()
         self.rows_ev[b].record()
+        ids_t = make_ids(0, self.rot, first)
         for p in range(3):
-            self.ctx.dot_shares_rows(p, self.op[p], self.slots, self.rows_dev[b], k, self.db.regions[p],
-                                     self.db.capacity, first, n_max, self.dot_code[p], self.dot_mask[p], self.ld,
-                                     galois=self.galois)
+            if self.gather:
+                self.ctx.dot_shares_gather(p, self.op[p], self.rows_dev[b], k, ids_t, self.db.regions[p],
+                                           self.db.capacity, n_max, self.dot_code[p], self.dot_mask[p], self.ld,
+                                           galois=self.galois)
+            else:
+                self.ctx.dot_shares_rows(p, self.op[p], self.slots, self.rows_dev[b], k, self.db.regions[p],
+                                         self.db.capacity, first, n_max, self.dot_code[p], self.dot_mask[p], self.ld,
+                                         galois=self.galois)
         # per request: reshare and compare its rows into its match buffer
         for i, r in enumerate(reqs):
             n_j = min(self.chunk, r.snapshot - first)

@@ -49,7 +49,7 @@ class DotTuner:
             ctx.set_dot_tiles(self.cache[k]["best"])
             return self.cache[k]["best"], self.cache[k]["ms"]
         if candidates is None:
-            candidates = CANDIDATES_UNIFORM if r >= 24 else CANDIDATES_ROWS
+            candidates = CANDIDATES_UNIFORM if r >= 13 else CANDIDATES_ROWS
         times = {}
         for c in candidates:
             ctx.set_dot_tiles(c)

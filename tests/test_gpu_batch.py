@@ -26,7 +26,7 @@ def env(keys):
     d64 = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()  # noqa: E731
     db.enroll(d64(dc), d64(dm), first)
     batches = [Batch(3, wl.rotations(31), 500), Batch(2, [0], 510), Batch(4, wl.rotations(15), 520),
-               Batch(1, wl.rotations(31), 530), Batch(5, [0], 540)]
+               Batch(1, wl.rotations(31), 530), Batch(5, [0], 540), Batch(19, wl.rotations(15), 550)]
     qc, qm = wl.gen_codes(61, 0, sum(b.q for b in batches), query=True)
     qc[1], qm[1] = wl.plant(61, 1, dc[7], dm[7], 4, h=0.2)       # batch 0, query 1 at rotation 4
     qc[3], qm[3] = wl.plant(61, 3, dc[150], dm[150], 0, h=0.3)   # batch 1, query 0 (R = 1)
@@ -41,11 +41,12 @@ def _u16(t):
     return t.cpu().numpy().view(np.uint16)
 
 
-def test_batched_equals_plain_and_oracle(env):
+@pytest.mark.parametrize("mode", ["grouped", "rows"])
+def test_batched_equals_plain_and_oracle(env, mode):
     from paper_2405_04463_amd.batch import BatchedStep
 
     e = env
-    st = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], e["n"], parties=(0, 1, 2), compare=True)
+    st = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], e["n"], parties=(0, 1, 2), compare=True, mode=mode)
     st.run()
     torch.cuda.synchronize()
     got = {p: (_u16(st.dot_code[p]).copy(), _u16(st.dot_mask[p]).copy()) for p in range(3)}
@@ -91,14 +92,14 @@ def test_chunked_db_walk_equals_one_pass(env):
     assert np.array_equal(np.concatenate(outs, axis=1), ref[:, :e["n"]])
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_graph_replay_matches_eager(env, persistent):
+@pytest.mark.parametrize("mode,tiles", [("rows", 1), ("rows", 0x11), ("grouped", 0)])
+def test_graph_replay_matches_eager(env, mode, tiles):
     from paper_2405_04463_amd.batch import BatchedStep
 
     e = env
     imc = e["imc"]
-    e["ctx"].set_dot_tiles(imc.DOT_TILES_EXPANDED_256x128 | (imc.DOT_PERSISTENT if persistent else 0))
-    st = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], e["n"], parties=(0,))
+    e["ctx"].set_dot_tiles(tiles)
+    st = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], e["n"], parties=(0,), mode=mode)
     n = e["n"]
     st.run()
     torch.cuda.synchronize()

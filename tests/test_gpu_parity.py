@@ -118,6 +118,8 @@ def _setup(imc, ctx, seed, n, q, first=0, cap=None):
     (1, [0], 1, 0),                        # a single comparison
     (2, [-3, 7], 129, 0),                  # one past a column tile
     (12, list(range(-12, 12)), 200, 0),    # r = 24: rotation-aware tiles, queries straddle row tiles
+    (20, list(range(-7, 8)), 130, 64),     # r = 15: 22 query slots per 256-row tile (5 staging chunks)
+    (18, list(range(-6, 7)), 70, 0),       # r = 13: the smallest rotation count of the rotation-aware path
 ])
 def test_dot_shares_matches_oracle(imc, keys, q, rot, n, first, tiles):
     from paper_2405_04463_amd.pipeline import alloc_check
@@ -136,6 +138,33 @@ def test_dot_shares_matches_oracle(imc, keys, q, rot, n, first, tiles):
         rc, rm = orc.local_dot(p, qsh, rot, dsh)
         assert np.array_equal(u16(buf.dot_code[p])[:, :n], rc), f"party {p} code"
         assert np.array_equal(u16(buf.dot_mask[p])[:, :n], rm), f"party {p} mask"
+    ctx.close()
+
+
+@pytest.mark.parametrize("rot", [list(range(-15, 16)), [-1, 2]])
+def test_dot_shares_gather_matches_oracle(imc, keys, rot):
+    """Gathered queries (repeated, out of order) at uniform rotations: the
+    rotation-aware kernel for 31 rotations, the expanded path for 2."""
+    from paper_2405_04463_amd.pipeline import alloc_check
+
+    dealer, party = keys
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=512)
+    n, first = 150, 64
+    dc, dm, qc, qm, db, qs = _setup(imc, ctx, 44, n, 6, first)
+    qsh = orc.share(dealer, orc.DOM_SHARE_QUERY, qc, qm, 100)
+    dsh = orc.share(dealer, orc.DOM_SHARE_DB, dc, dm, first)
+    order = [5, 0, 3, 3, 1, 4, 2, 0, 5, 1]
+    qidx = torch.tensor(order, dtype=torch.int32, device="cuda")
+    buf = alloc_check(len(order), len(rot), n)
+    ids = imc.make_ids(0, rot, first)
+    for p in (0, 2):
+        ctx.dot_shares_gather(p, qs.op[p], qidx, len(order), ids, db.regions[p], db.capacity, n, buf.dot_code[p],
+                              buf.dot_mask[p], buf.ld)
+    torch.cuda.synchronize()
+    for p in (0, 2):
+        rc, rm = orc.local_dot(p, qsh[order], rot, dsh)
+        assert np.array_equal(u16(buf.dot_code[p])[:, :n], rc), p
+        assert np.array_equal(u16(buf.dot_mask[p])[:, :n], rm), p
     ctx.close()
 
 

@@ -61,16 +61,16 @@ def _drive(srv, reqs_at_tick):
     return {r.rid: r for r in srv.done}
 
 
-@pytest.mark.parametrize("galois", [False, True])
-def test_same_alone_in_mix_and_plain(env, galois):
+@pytest.mark.parametrize("galois,gather", [(False, True), (True, True), (False, False)])
+def test_same_alone_in_mix_and_plain(env, galois, gather):
     from paper_2405_04463_amd.serve import Server, plain_check
 
     e = env
     db = _db(e, galois=galois)
-    alone = _drive(Server(e["ctx"], db, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True),
+    alone = _drive(Server(e["ctx"], db, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True, gather=gather),
                    {0: [_req(e, 0, 1000)]})[0]
     db2 = _db(e, galois=galois)
-    mixed = _drive(Server(e["ctx"], db2, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True),
+    mixed = _drive(Server(e["ctx"], db2, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True, gather=gather),
                    {0: [_req(e, i, 1000 + i) for i in (1, 2, 3)], 2: [_req(e, 0, 1000)], 3: [_req(e, 4, 1004)]})
     x = mixed[0]
     assert alone.dup == x.dup == 1
