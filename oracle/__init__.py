@@ -25,7 +25,11 @@ _lib = None
 
 DOM_SHARE_DB, DOM_SHARE_QUERY = 1, 2
 DOM_GALOIS_DB, DOM_GALOIS_QUERY = 6, 7
+DOM_SHARE32_DB, DOM_SHARE32_QUERY = 12, 13
 N_GATES = 94   # AND gates per comparison: 33 (Lift) + 61 (MSB)
+# comparison variants (oracle.c, "Comparison variants")
+CMPV_PLAIN, CMPV_LIFT18, CMPV_CONST32 = 1, 2, 3
+COMPARE_SETTINGS = ("mpclift", "plain", "lift18", "constlift", "nolift")
 
 
 def build_lib() -> str:
@@ -52,6 +56,8 @@ def lib():
         _lib.orc_threads.restype = ctypes.c_int
         _lib.orc_compare.restype = ctypes.c_int
         _lib.orc_test_gr_inv.restype = ctypes.c_int
+        _lib.orc_compare_variant.restype = ctypes.c_int
+        _lib.orc_test_compare_variant.restype = ctypes.c_int
     return _lib
 
 
@@ -147,6 +153,66 @@ def compare(keys: bytes, d_comp, x_comp, nq, rot, qid_base, first_entry, want_au
     return match
 
 
+def compare_variant(keys: bytes, variant: int, d_comp, x_comp, ml_pub, nq, rot, qid_base, first_entry,
+                    want_aux=False):
+    """Comparison variant (CMPV_*) over [3, rows, n] components: d_comp the
+    code dot (u16 or u32), x_comp ml (u16 for LIFT18, u32 for CONST32, None
+    for PLAIN), ml_pub [rows, n] the public ml (PLAIN).  Returns the match
+    components [3, rows, nw]; with want_aux also y components and counts."""
+    _, rows, n = d_comp.shape
+    nw = (n + 63) // 64
+    d32 = np.ascontiguousarray(d_comp.astype(np.uint32))
+    x32 = None if x_comp is None else np.ascontiguousarray(x_comp.astype(np.uint32))
+    mlp = None if ml_pub is None else np.ascontiguousarray(np.asarray(ml_pub, dtype=np.int32))
+    match = np.zeros((3, rows, nw), dtype=np.uint64)
+    y = np.zeros((3, rows, n), dtype=np.uint32) if want_aux else None
+    counts = np.zeros(4, dtype=np.int64)
+    rc = lib().orc_compare_variant(ctypes.c_int(variant), ctypes.c_char_p(bytes(keys)), _p(d32), _p(x32), _p(mlp),
+                                   ctypes.c_int(nq), _p(_rot(rot)), ctypes.c_int(len(rot)), ctypes.c_long(n),
+                                   ctypes.c_uint64(qid_base), ctypes.c_uint64(first_entry), _p(match), _p(y),
+                                   _p(counts))
+    if rc != 0:
+        raise ValueError("bad variant or first_entry not a multiple of 64")
+    if want_aux:
+        return match, y, counts
+    return match
+
+
+def share32(dealer_key: bytes, dom: int, codes, masks, first_id: int):
+    """Shares over Z_2^32: uint32 [n, 2, 3, L]."""
+    n = codes.shape[0]
+    out = np.zeros((n, 2, 3, L), dtype=np.uint32)
+    lib().orc_share32(ctypes.c_char_p(bytes(dealer_key)), ctypes.c_int(dom), _p(np.ascontiguousarray(codes)),
+                      _p(np.ascontiguousarray(masks)), ctypes.c_long(n), ctypes.c_uint64(first_id), _p(out))
+    return out
+
+
+def local_dot32(p: int, qsh, rot, dsh):
+    """Party p's additive shares over Z_2^32: (code, mask) uint32 [rows, n]."""
+    nq, n = qsh.shape[0], dsh.shape[0]
+    rows = nq * len(rot)
+    oc = np.zeros((rows, n), dtype=np.uint32)
+    om = np.zeros((rows, n), dtype=np.uint32)
+    lib().orc_local_dot32(ctypes.c_int(p), _p(np.ascontiguousarray(qsh)), ctypes.c_int(nq), _p(_rot(rot)),
+                          ctypes.c_int(len(rot)), _p(np.ascontiguousarray(dsh)), ctypes.c_long(n), _p(oc), _p(om))
+    return oc, om
+
+
+def reshare32(keys: bytes, z_code, z_mask, nq, rot, qid_base, first_entry):
+    """Resharing over Z_2^32 of [3, rows, n] u32 additive shares (either may
+    be None): re-randomised components."""
+    ref = z_code if z_code is not None else z_mask
+    _, rows, n = ref.shape
+    oc = np.zeros_like(ref) if z_code is not None else None
+    om = np.zeros_like(ref) if z_mask is not None else None
+    zc = None if z_code is None else np.ascontiguousarray(z_code)
+    zm = None if z_mask is None else np.ascontiguousarray(z_mask)
+    lib().orc_reshare32(ctypes.c_char_p(bytes(keys)), _p(zc), _p(zm), ctypes.c_int(nq), _p(_rot(rot)),
+                        ctypes.c_int(len(rot)), ctypes.c_long(n), ctypes.c_uint64(qid_base),
+                        ctypes.c_uint64(first_entry), _p(oc), _p(om))
+    return oc, om
+
+
 def or_tree(keys: bytes, match, nq, r, qid_base):
     """match [3, nq*r, nw] -> dup components [3, nq] (0/1) and the number of
     word-wide AND gates."""
@@ -212,6 +278,19 @@ def t_compare_one(d, x, seed):
     m = lib().orc_test_compare_one(_p(d), _p(x), ctypes.c_uint64(seed), ctypes.byref(mlo), ctypes.byref(yo),
                                    _p(counts), ctypes.byref(depth))
     return m, mlo.value, yo.value, counts, depth.value
+
+
+def t_compare_variant(variant, d, x, ml_pub, seed):
+    """One comparison of a variant on explicit components (u32) with seeded
+    randomness: (opened bit, opened y, counts, depth)."""
+    d = np.asarray(d, dtype=np.uint32)
+    x = np.asarray(x, dtype=np.uint32)
+    yo = ctypes.c_uint32(0)
+    counts = np.zeros(4, dtype=np.int64)
+    depth = ctypes.c_int(0)
+    m = lib().orc_test_compare_variant(ctypes.c_int(variant), _p(d), _p(x), ctypes.c_uint32(ml_pub),
+                                       ctypes.c_uint64(seed), ctypes.byref(yo), _p(counts), ctypes.byref(depth))
+    return m, yo.value, counts, depth.value
 
 
 def galois_share(dealer_key: bytes, dom: int, codes, masks, first_id: int):
@@ -301,9 +380,17 @@ def protocol_in_batch(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_b
     return res
 
 
-def protocol(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_base=0, first_entry=0, scheme="aby3"):
+def protocol(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_base=0, first_entry=0, scheme="aby3",
+             compare_setting="mpclift"):
     """The whole shared protocol on the CPU: share, per-party local dots,
-    reshare, compare, OR-tree.  Returns a dict of every intermediate."""
+    reshare, compare, OR-tree.  Returns a dict of every intermediate.
+
+    compare_setting: "mpclift" (ml and dot over Z_2^16, ml lifted to
+    Z_2^32); "plain" (masks public, Alg. 2: ml in plain, code dot only);
+    "lift18" (ml lifted to Z_2^18 only); "constlift" (ml by a dot product
+    over Z_2^32, code dot over Z_2^16); "nolift" (both dots over Z_2^32)."""
+    if compare_setting not in COMPARE_SETTINGS:
+        raise ValueError(compare_setting)
     nq, r = qc.shape[0], len(rot)
     if scheme == "galois":
         qsh = galois_share(dealer_key, DOM_GALOIS_QUERY, qc, qm, qid_base)
@@ -321,7 +408,34 @@ def protocol(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_base=0, fi
     zc = np.stack(zc)
     zm = np.stack(zm)
     rc, rm = reshare(keys, zc, zm, nq, rot, qid_base, first_entry)
-    match, ml, y, counts = compare(keys, rc, rm, nq, rot, qid_base, first_entry, want_aux=True)
+    out = dict(qsh=qsh, dsh=dsh, z_code=zc, z_mask=zm, rep_code=rc, rep_mask=rm)
+    if compare_setting == "mpclift":
+        match, ml, y, counts = compare(keys, rc, rm, nq, rot, qid_base, first_entry, want_aux=True)
+        out.update(ml_lift=ml)
+    elif compare_setting == "plain":
+        _, ml_pub, _, _ = plain(qc, qm, rot, dc, dm)
+        match, y, counts = compare_variant(keys, CMPV_PLAIN, rc, None, ml_pub, nq, rot, qid_base, first_entry,
+                                           want_aux=True)
+        out.update(ml_pub=ml_pub)
+    elif compare_setting == "lift18":
+        match, y, counts = compare_variant(keys, CMPV_LIFT18, rc, rm, None, nq, rot, qid_base, first_entry,
+                                           want_aux=True)
+    else:
+        q32 = share32(dealer_key, DOM_SHARE32_QUERY, qc, qm, qid_base)
+        d32 = share32(dealer_key, DOM_SHARE32_DB, dc, dm, first_entry)
+        zc32, zm32 = [], []
+        for p in range(3):
+            c, m = local_dot32(p, q32, rot, d32)
+            zc32.append(c)
+            zm32.append(m)
+        zc32, zm32 = np.stack(zc32), np.stack(zm32)
+        rc32, rm32 = reshare32(keys, zc32 if compare_setting == "nolift" else None, zm32, nq, rot, qid_base,
+                               first_entry)
+        dcomp = rc32 if compare_setting == "nolift" else rc
+        match, y, counts = compare_variant(keys, CMPV_CONST32, dcomp, rm32, None, nq, rot, qid_base, first_entry,
+                                           want_aux=True)
+        out.update(qsh32=q32, dsh32=d32, z_code32=zc32, z_mask32=zm32, rep_mask32=rm32,
+                   rep_code32=rc32)
     dup, or_words = or_tree(keys, match, nq, r, qid_base)
-    return dict(qsh=qsh, dsh=dsh, z_code=zc, z_mask=zm, rep_code=rc, rep_mask=rm, match=match,
-                ml_lift=ml, y=y, counts=counts, dup=dup, or_words=or_words)
+    out.update(match=match, y=y, counts=counts, dup=dup, or_words=or_words)
+    return out

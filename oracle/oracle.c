@@ -28,6 +28,11 @@
  *       Lagrange-premultiplied query shares, constant terms of the ring
  *       products summed into additive shares; resharing, comparison and
  *       OR-tree then run as in O2.
+ *   O4  comparison variants [Sec. 4.3 Alg. 2; Sec. 5.1-5.2; Sec. 6.2]:
+ *       masks in plain (public ml, MSB over Z_2^16), Lift of ml to Z_2^18
+ *       only, and ml computed by a dot product over Z_2^32 (ConstLift;
+ *       NoLift when the code dot is also over Z_2^32), with the sharing,
+ *       local dot and resharing over Z_2^32 they need.
  *
  * Readings of the paper taken here (each is listed in the design notes):
  *   - parties are 0-based: party p holds components (x_p, x_{p-1 mod 3})
@@ -41,7 +46,9 @@
  *     (the shifted carry vector has a public zero at bit 0), i.e. 2m-1;
  *     for an MSB over a k-bit ring this is the paper's 2k-3 [Sec. 4.3.1,
  *     Sec. 5.2].  Lift extracts bits {17,16}: m = 17, 33 gates.
- *   - threshold a/b = 2^14 / 2^16 = 1 - 2*3/8 exactly [Sec. 5].
+ *   - threshold a/b = 2^14 / 2^16 = 1 - 2*3/8 exactly [Sec. 5]; with masks
+ *     in plain the public term is floor(ml / 4): Lemma 1's ceiling is off by
+ *     one whenever f ml is not an integer [Sec. 4.3.1].
  *   - the PRF "RNG.Gen" [App. D] is ChaCha with 12 rounds (block function
  *     of Bernstein's ChaCha, state layout as in RFC 8439), addressed by a
  *     64-bit stream id and a 64-bit position; the addressing of every
@@ -799,6 +806,270 @@ void orc_galois_points(uint16_t* alpha, uint16_t* lambda) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Comparison variants [Sec. 4.3 Alg. 2 and Sec. 4.3.1 (masks in       */
+/* plain); Sec. 5.1-5.2 (lifting versus a larger dot-product ring); the */
+/* comparison benchmark of Sec. 6.2, Table 3].  The threshold 1 - 2*3/8 is 1/4   */
+/* exactly, so every variant decides 4 dot > ml (with ml = 0 no match).  */
+/*                                                                      */
+/*   PLAIN    masks public: ml is a public integer, the code dot stays   */
+/*            in Z_2^16 and the bit is MSB_16(floor(ml / 4) - dot),      */
+/*            BitExtract with m = 15: 29 AND gates.                      */
+/*   LIFT18   masks shared: ml is lifted from Z_2^16 to Z_2^18 (the      */
+/*            Lift of App. D with m = 2: bits 17 and 16 injected into    */
+/*            Z_2^1 and Z_2^2), the dot is ConstLifted by b = 4 and      */
+/*            a = 1; MSB over 18 bits.  33 + 33 AND gates.                */
+/*   CONST32  ml is computed over Z_2^32 by a dot product in the larger  */
+/*            ring, so only the code dot is lifted (ConstLift by 2^16,   */
+/*            free); MSB over 32 bits: 61 AND gates.  The same circuit   */
+/*            serves the NoLift setting (code dot also over Z_2^32),     */
+/*            since 2^16 dot mod 2^32 depends only on dot mod 2^16.      */
+/*                                                                      */
+/* Randomness: stream (domain of the variant, qid, rot), the per-group  */
+/* tape of MPCLift (32 blocks per 64-entry group), laid out as          */
+/*   PLAIN    MSB (m = 15)  words 0..29                                  */
+/*   LIFT18   Lift (m = 17) words 0..33, MSB (m = 17) words 40..73,      */
+/*            inject A (bit 17 -> Z_2^1): key_0 c0 word 80; key_2 c2 80,  */
+/*            w0 81, w1 82; inject B (bit 16 -> Z_2^2): key_0 c0 words    */
+/*            88..89; key_2 c2 88..89, w0 90..91, w1 92..93               */
+/*   CONST32  MSB (m = 31)  words 0..61                                  */
+/* ------------------------------------------------------------------ */
+#define CMPV_PLAIN 1
+#define CMPV_LIFT18 2
+#define CMPV_CONST32 3
+#define DOM_CMP_PLAIN 9u
+#define DOM_CMP_LIFT18 10u
+#define DOM_CMP_CONST32 11u
+
+static uint32_t cmpv_dom(int v) {
+  return v == CMPV_PLAIN ? DOM_CMP_PLAIN : v == CMPV_LIFT18 ? DOM_CMP_LIFT18 : DOM_CMP_CONST32;
+}
+
+/* Tape blocks per key a variant reads. */
+static int cmpv_blocks(int v) { return v == CMPV_PLAIN ? 4 : v == CMPV_LIFT18 ? 12 : 8; }
+
+/* One comparison.  d: code-dot components (Z_2^16 for PLAIN and LIFT18;
+ * Z_2^16 or Z_2^32 for CONST32); x: ml components (Z_2^16 for LIFT18,
+ * Z_2^32 for CONST32; unused for PLAIN); ml_pub: public ml (PLAIN).
+ * Returns the shared match bit; y_out: components of the value whose MSB
+ * is taken. */
+static bsh compare_variant_one(int v, const uint32_t d[3], const uint32_t x[3], uint32_t ml_pub,
+                               const crand* rnd, uint32_t* y_out, ccount* cnt) {
+  bsh r[33];
+  uint32_t y[3];
+  if (v == CMPV_PLAIN) {
+    /* public minus shared: the constant enters component 0 only */
+    uint32_t t = ml_pub / 4u;
+    for (int p = 0; p < 3; ++p) y[p] = ((p == 0 ? t : 0u) - d[p]) & 0xFFFFu;
+    bit_extract(y, 15, 0, 0, rnd, r, cnt);
+    if (y_out) for (int p = 0; p < 3; ++p) y_out[p] = y[p];
+    return r[15];
+  }
+  if (v == CMPV_LIFT18) {
+    uint32_t S[3] = {x[0] & 0xFFFFu, x[1] & 0xFFFFu, x[2] & 0xFFFFu};
+    bit_extract(S, 17, 0, 0, rnd, r, cnt);
+    bsh hi = r[17], lo = r[16];
+    int d_inj = (hi.depth > lo.depth ? hi.depth : lo.depth) + 2;
+    uint32_t A[3], B[3];
+    bit_inject(hi, 1, rnd->c0[0], rnd->c2[0], rnd->w0[0], rnd->w1[0], A, cnt);
+    bit_inject(lo, 2, rnd->c0[1], rnd->c2[1], rnd->w0[1], rnd->w1[1], B, cnt);
+    for (int p = 0; p < 3; ++p) {
+      uint32_t ml = S[p] - (A[p] << 17) - (B[p] << 16);     /* [ml]_{2^18} */
+      y[p] = (ml - ((d[p] & 0xFFFFu) << 2)) & 0x3FFFFu;     /* a [ml] - b [dot], a = 1, b = 4 */
+    }
+    bit_extract(y, 17, 40, d_inj, rnd, r, cnt);
+    if (y_out) for (int p = 0; p < 3; ++p) y_out[p] = y[p];
+    return r[17];
+  }
+  for (int p = 0; p < 3; ++p) y[p] = (x[p] << 14) - (d[p] << 16);   /* a = 2^14, b = 2^16 over Z_2^32 */
+  bit_extract(y, 31, 0, 0, rnd, r, cnt);
+  if (y_out) for (int p = 0; p < 3; ++p) y_out[p] = y[p];
+  return r[31];
+}
+
+static void gather_rand_variant(int v, const uint64_t tape[3][TAPE_WORDS], int o, crand* rnd) {
+  memset(rnd, 0, sizeof(*rnd));
+  int words = 8 * cmpv_blocks(v);
+  for (int w = 0; w < N_GATE_WORDS && w < words; ++w)
+    for (int k = 0; k < 3; ++k) rnd->g[w][k] = (uint8_t)((tape[k][w] >> o) & 1u);
+  if (v != CMPV_LIFT18) return;
+  const int kk[2] = {1, 2}, bc0[2] = {80, 88}, bc2[2] = {80, 88}, bw0[2] = {81, 90}, bw1[2] = {82, 92};
+  for (int i = 0; i < 2; ++i) {
+    uint32_t c0 = 0, c2 = 0, w0 = 0, w1 = 0;
+    for (int j = 0; j < kk[i]; ++j) {
+      c0 |= (uint32_t)((tape[0][bc0[i] + j] >> o) & 1u) << j;
+      c2 |= (uint32_t)((tape[2][bc2[i] + j] >> o) & 1u) << j;
+      w0 |= (uint32_t)((tape[2][bw0[i] + j] >> o) & 1u) << j;
+      w1 |= (uint32_t)((tape[2][bw1[i] + j] >> o) & 1u) << j;
+    }
+    rnd->c0[i] = c0; rnd->c2[i] = c2; rnd->w0[i] = w0; rnd->w1[i] = w1;
+  }
+}
+
+/* rows x n comparisons of variant v.  d_comp, x_comp: [3][rows][n] u32
+ * components (x_comp unused for PLAIN); ml_pub: [rows][n] public ml (PLAIN
+ * only).  match: [3][rows][nw] u64 components as in orc_compare; y_out
+ * (optional) [3][rows][n] u32; counts[4] = {AND gates, bits sent by party
+ * 0, 1, 2}.  first_entry must be a multiple of 64. */
+int orc_compare_variant(int v, const uint8_t* keys, const uint32_t* d_comp, const uint32_t* x_comp,
+                        const int32_t* ml_pub, int nq, const int* rot, int r, long n, uint64_t qid_base,
+                        uint64_t first_entry, uint64_t* match, uint32_t* y_out, long* counts) {
+  if (first_entry % 64) return -1;
+  if (v < CMPV_PLAIN || v > CMPV_CONST32) return -2;
+  long rows = (long)nq * r;
+  long nw = (n + 63) / 64;
+  int nblk = cmpv_blocks(v);
+  long tot_and = 0, tot_bits[3] = {0, 0, 0};
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : tot_and)
+  for (long row = 0; row < rows; ++row) {
+    uint64_t qid = qid_base + (uint64_t)(row / r);
+    uint64_t st = row_stream(cmpv_dom(v), qid, rot[row % r]);
+    ccount cnt = {0, {0, 0, 0}};
+    static __thread uint64_t tape[3][TAPE_WORDS];
+    for (long w = 0; w < nw; ++w) {
+      uint64_t G = (first_entry >> 6) + (uint64_t)w;
+      for (int k = 0; k < 3; ++k)
+        for (int blk = 0; blk < nblk; ++blk) {
+          uint32_t b[16];
+          prf_block(keys + 32 * k, st, G * TAPE_BLOCKS_PER_GROUP + (uint64_t)blk, b);
+          for (int u = 0; u < 8; ++u)
+            tape[k][8 * blk + u] = (uint64_t)b[2 * u] | ((uint64_t)b[2 * u + 1] << 32);
+        }
+      uint64_t mw[3] = {0, 0, 0};
+      for (int o = 0; o < 64; ++o) {
+        long j = w * 64 + o;
+        if (j >= n) break;
+        uint32_t d[3], x[3] = {0, 0, 0};
+        for (int p = 0; p < 3; ++p) {
+          size_t idx = ((size_t)p * rows + row) * n + j;
+          d[p] = d_comp[idx];
+          if (x_comp) x[p] = x_comp[idx];
+        }
+        uint32_t mlp = ml_pub ? (uint32_t)ml_pub[(size_t)row * n + j] : 0u;
+        crand rnd;
+        gather_rand_variant(v, tape, o, &rnd);
+        uint32_t yv[3];
+        bsh mb = compare_variant_one(v, d, x, mlp, &rnd, yv, &cnt);
+        for (int p = 0; p < 3; ++p) {
+          mw[p] |= (uint64_t)mb.c[p] << o;
+          if (y_out) y_out[((size_t)p * rows + row) * n + j] = yv[p];
+        }
+      }
+      for (int p = 0; p < 3; ++p) match[((size_t)p * rows + row) * nw + w] = mw[p];
+    }
+    tot_and += cnt.and_gates;
+#pragma omp critical
+    { for (int p = 0; p < 3; ++p) tot_bits[p] += cnt.bits_sent[p]; }
+  }
+  if (counts) { counts[0] = tot_and; counts[1] = tot_bits[0]; counts[2] = tot_bits[1]; counts[3] = tot_bits[2]; }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Dot products over Z_2^32 [Sec. 5.1, "Lifting vs. Larger             */
+/* Dot-Product": computing ml (ConstLift) or both values (NoLift) in    */
+/* the larger ring removes the Lift at the price of a wider dot].       */
+/* Same steps as the Z_2^16 versions with 32-bit components.            */
+/* ------------------------------------------------------------------ */
+#define DOM_SHARE32_DB 12u
+#define DOM_SHARE32_QUERY 13u
+#define DOM_RESHARE32 14u
+
+/* out: [n][vec 2][comp 3][L] u32.  comp0, comp1 are dealer-PRF streams
+ * (stream (dom<<56)|(vec<<52)|(comp<<48)|id, one block per 16 elements),
+ * comp2 = x - comp0 - comp1 (mod 2^32); x is the masked-bit encoding of the
+ * code (vec 0) or the mask bit (vec 1). */
+void orc_share32(const uint8_t* dealer_key, int dom, const uint64_t* codes, const uint64_t* masks,
+                 long n, uint64_t first_id, uint32_t* out) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (long e = 0; e < n; ++e) {
+    const uint64_t* code = codes + (size_t)e * ORC_W;
+    const uint64_t* mask = masks + (size_t)e * ORC_W;
+    uint64_t id = (first_id + (uint64_t)e) & 0xFFFFFFFFFFFFull;
+    for (int vec = 0; vec < 2; ++vec) {
+      uint32_t* o = out + ((size_t)e * 2 + vec) * 3 * ORC_L;
+      uint64_t s0 = ((uint64_t)dom << 56) | ((uint64_t)vec << 52) | (0ull << 48) | id;
+      uint64_t s1 = ((uint64_t)dom << 56) | ((uint64_t)vec << 52) | (1ull << 48) | id;
+      uint32_t b0[16], b1[16];
+      for (int i = 0; i < ORC_L; ++i) {
+        if ((i & 15) == 0) {
+          prf_block(dealer_key, s0, (uint64_t)(i >> 4), b0);
+          prf_block(dealer_key, s1, (uint64_t)(i >> 4), b1);
+        }
+        int a = getbit(code, i), ma = getbit(mask, i);
+        uint32_t x = vec ? (uint32_t)ma : (uint32_t)(ma - 2 * (a & ma));
+        uint32_t c0 = b0[i & 15], c1 = b1[i & 15];
+        o[i] = c0;
+        o[ORC_L + i] = c1;
+        o[2 * ORC_L + i] = x - c0 - c1;
+      }
+    }
+  }
+}
+
+/* As orc_local_dot over Z_2^32: qsh [nq][2][3][L], dsh [n][2][3][L] u32;
+ * out_code/out_mask [rows][n] u32 (either may be NULL to skip). */
+void orc_local_dot32(int p, const uint32_t* qsh, int nq, const int* rot, int r,
+                     const uint32_t* dsh, long n, uint32_t* out_code, uint32_t* out_mask) {
+  int pm = (p + 2) % 3;
+  long rows = (long)nq * r;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (long row = 0; row < rows; ++row) {
+    int qi = (int)(row / r), s = rot[row % r];
+    static __thread uint32_t xr[2][2][ORC_L];
+    for (int vec = 0; vec < 2; ++vec) {
+      const uint32_t* q = qsh + ((size_t)qi * 2 + vec) * 3 * ORC_L;
+      for (int i = 0; i < ORC_L; ++i) {
+        int j = rot_src(i, s);
+        xr[vec][0][i] = q[p * ORC_L + j];
+        xr[vec][1][i] = q[pm * ORC_L + j];
+      }
+    }
+    for (long e = 0; e < n; ++e)
+      for (int vec = 0; vec < 2; ++vec) {
+        uint32_t* o = vec ? out_mask : out_code;
+        if (!o) continue;
+        const uint32_t* d = dsh + ((size_t)e * 2 + vec) * 3 * ORC_L;
+        const uint32_t* yp = d + p * ORC_L;
+        const uint32_t* ypm = d + pm * ORC_L;
+        uint32_t z = 0;
+        for (int i = 0; i < ORC_L; ++i)
+          z += xr[vec][0][i] * yp[i] + xr[vec][1][i] * yp[i] + xr[vec][0][i] * ypm[i];
+        o[(size_t)row * n + e] = z;
+      }
+  }
+}
+
+/* Resharing over Z_2^32: z_p + F(key_p) - F(key_{p-1}).  Randomness: stream
+ * (DOM_RESHARE32, qid, rot), position entry>>3, u32 word 2*(entry&7) for the
+ * code and 2*(entry&7)+1 for the mask.  z/out: [3][rows][n] u32; a NULL
+ * vector is skipped. */
+void orc_reshare32(const uint8_t* keys, const uint32_t* z_code, const uint32_t* z_mask,
+                   int nq, const int* rot, int r, long n, uint64_t qid_base, uint64_t first_entry,
+                   uint32_t* out_code, uint32_t* out_mask) {
+  long rows = (long)nq * r;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (long row = 0; row < rows; ++row) {
+    uint64_t qid = qid_base + (uint64_t)(row / r);
+    uint64_t st = row_stream(DOM_RESHARE32, qid, rot[row % r]);
+    uint32_t blk[3][16];
+    uint64_t have = ~0ull;
+    for (long j = 0; j < n; ++j) {
+      uint64_t e = first_entry + (uint64_t)j;
+      if ((e >> 3) != have) {
+        for (int k = 0; k < 3; ++k) prf_block(keys + 32 * k, st, e >> 3, blk[k]);
+        have = e >> 3;
+      }
+      for (int p = 0; p < 3; ++p) {
+        int pm = (p + 2) % 3;
+        size_t o = ((size_t)p * rows + row) * n + j;
+        if (z_code) out_code[o] = z_code[o] + blk[p][2 * (e & 7)] - blk[pm][2 * (e & 7)];
+        if (z_mask) out_mask[o] = z_mask[o] + blk[p][2 * (e & 7) + 1] - blk[pm][2 * (e & 7) + 1];
+      }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------ */
 /* Test hooks: the sub-protocols on explicit randomness, for pinning.   */
 /* ------------------------------------------------------------------ */
 
@@ -877,6 +1148,24 @@ int orc_test_compare_one(const uint16_t* d, const uint16_t* x, uint64_t seed,
   if (depth) *depth = mb.depth;
   if (ml_open) *ml_open = ml[0] + ml[1] + ml[2];
   if (y_open) *y_open = y[0] + y[1] + y[2];
+  if (counts) { counts[0] = cnt.and_gates; for (int p = 0; p < 3; ++p) counts[1 + p] = cnt.bits_sent[p]; }
+  return mb.c[0] ^ mb.c[1] ^ mb.c[2];
+}
+
+/* One comparison of variant v on explicit components with seeded
+ * randomness; returns the opened match bit, optionally the opened value
+ * whose MSB is taken (mod the variant's ring), the counts and the depth. */
+int orc_test_compare_variant(int v, const uint32_t* d, const uint32_t* x, uint32_t ml_pub, uint64_t seed,
+                             uint32_t* y_open, long* counts, int* depth) {
+  crand rnd; uint64_t s = seed; random_crand(&s, &rnd);
+  ccount cnt = {0, {0, 0, 0}};
+  uint32_t y[3];
+  bsh mb = compare_variant_one(v, d, x, ml_pub, &rnd, y, &cnt);
+  if (depth) *depth = mb.depth;
+  if (y_open) {
+    uint32_t ring = v == CMPV_PLAIN ? 0xFFFFu : v == CMPV_LIFT18 ? 0x3FFFFu : 0xFFFFFFFFu;
+    *y_open = (y[0] + y[1] + y[2]) & ring;
+  }
   if (counts) { counts[0] = cnt.and_gates; for (int p = 0; p < 3; ++p) counts[1 + p] = cnt.bits_sent[p]; }
   return mb.c[0] ^ mb.c[1] ^ mb.c[2];
 }
