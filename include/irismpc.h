@@ -167,7 +167,9 @@ imc_status imc_share_query(imc_ctx* ctx, const uint64_t* codes, const uint64_t* 
  * party p's additive share of <c', C'_e> and of ml before re-randomisation.
  * Rotating shares rotates the secret (sharing is elementwise, Sec. 3).
  * qop: party p's operand from imc_share_query; db: party p's region;
- * code_dot, mask_dot: device u16 [q*ids->r][ld], ld >= n.
+ * code_dot, mask_dot: device u16 [q*ids->r][ld], ld >= n.  mask_dot may be
+ * NULL: then only the code dot is computed (the setting with masks in plain,
+ * Sec. 4.3 Alg. 2, where ml is public; see imc_plain_ml).
  * Errors: IMC_EINVAL (party, rotation, first_entry_id % 64), IMC_ESHAPE
  * (q*r > max_rows, ld < n, first+n > capacity). */
 imc_status imc_dot_shares(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_ids* ids,
@@ -206,7 +208,10 @@ imc_status imc_set_dot_tiles(imc_ctx* ctx, uint32_t flags);
  * rotation, entry)) and sends the result to party p+1: msg[p] is device u16
  * [2][rows][ld] (code, mask).  rep_code[p], rep_mask[p]: device u16
  * [2][rows][ld]: plane 0 = own re-randomised share, plane 1 = the one
- * received from party p-1.  rows must equal q * ids->r for some q. */
+ * received from party p-1.  rows must equal q * ids->r for some q.
+ * add_mask may be NULL (masks in plain: no mask dot); then only the code
+ * shares are reshared, rep_mask is ignored and the mask plane of msg[p] is
+ * left untouched. */
 imc_status imc_reshare(imc_ctx* ctx, const uint16_t* const add_code[3], const uint16_t* const add_mask[3],
                        size_t rows, size_t n, size_t ld, const imc_ids* ids, uint16_t* const msg[3],
                        uint16_t* const rep_code[3], uint16_t* const rep_mask[3], imc_stream stream);
@@ -225,6 +230,51 @@ imc_status imc_compare_threshold(imc_ctx* ctx, const uint16_t* const rep_code[3]
                                  const uint16_t* const rep_mask[3], size_t rows, size_t n, size_t ld,
                                  const imc_ids* ids, uint64_t* const match[3], size_t mw_ld,
                                  imc_stream stream);
+
+/* Other settings of the threshold comparison (Sec. 4.3 Alg. 2 and Sec. 4.3.1;
+ * Sec. 5.1-5.2; the settings compared in Sec. 6.2).  The threshold 1 - 2*3/8
+ * is 1/4 exactly, so every setting decides match <=> 4 dot > ml.
+ *   IMC_CMP_PLAIN_MASK  masks public: ml_pub (device u16 [rows][ld], from
+ *                       imc_plain_ml) is a public integer, the code dot is
+ *                       shared over Z_2^16; [match] = MSB_16(floor(ml/4) -
+ *                       [dot]), 29 AND gates.  rep_mask is ignored.
+ *   IMC_CMP_LIFT18      ml shared over Z_2^16 (rep_mask u16 as from
+ *                       imc_reshare) and lifted to Z_2^18 only (the Lift of
+ *                       App. D with m = 2), the dot ConstLifted by b = 4,
+ *                       a = 1: [match] = MSB_18([ml'] - 4 [dot]), 66 AND gates.
+ *   IMC_CMP_CONST32     ml shared over Z_2^32 (rep_mask device u32
+ *                       [2][rows][ld], from a dot product over Z_2^32), so no
+ *                       Lift: [match] = MSB_32(2^14 [ml] - 2^16 [dot]), 61 AND
+ *                       gates.  The code dot may be over Z_2^16 (ConstLift)
+ *                       or Z_2^32 (code_bits = 32: NoLift); both give the same
+ *                       bit, 2^16 dot mod 2^32 depending on dot mod 2^16 only.
+ * rep_code[p]: [2][rows][ld] components as from imc_reshare, u16 (code_bits
+ * 16) or u32 (code_bits 32, IMC_CMP_CONST32 only).  match[p], ids, the output
+ * layout and the first_entry_id alignment are as imc_compare_threshold.  Each
+ * setting draws its randomness from its own PRF domain.
+ * Errors: IMC_EINVAL (null, unaligned, unknown variant, code_bits), IMC_ESHAPE. */
+#define IMC_CMP_PLAIN_MASK 1
+#define IMC_CMP_LIFT18 2
+#define IMC_CMP_CONST32 3
+imc_status imc_compare_variant(imc_ctx* ctx, int variant, const void* const rep_code[3], int code_bits,
+                               const void* const rep_mask[3], const uint16_t* ml_pub, size_t rows, size_t n,
+                               size_t ld, const imc_ids* ids, uint64_t* const match[3], size_t mw_ld,
+                               imc_stream stream);
+
+/* Public mask overlap for the setting with masks in plain (Sec. 4.3 Alg. 2:
+ * the masks travel in plain, so every party computes ml = |m' AND M| for
+ * itself; Sec. 3 for m' and ml).  Two steps:
+ * imc_rotate_masks: masks device u64 [q][200] (packed query masks) ->
+ *   out device u64 [q*ids->r][200], row qi*r + ri = the mask at rotation
+ *   ids->rot[ri].  Errors: IMC_EINVAL (null, unaligned, rotations).
+ * imc_plain_ml: row_masks device u64 [rows][200] (rotated query masks),
+ *   db_masks device u64 [n][200] (entry masks) -> ml device u16 [rows][ld]
+ *   (ld >= n), ml[row][e] = popcount(row_masks[row] AND db_masks[e]).
+ *   Errors: IMC_EINVAL (null, unaligned), IMC_ESHAPE (ld < n). */
+imc_status imc_rotate_masks(imc_ctx* ctx, const uint64_t* masks, size_t q, const imc_ids* ids, uint64_t* out,
+                            imc_stream stream);
+imc_status imc_plain_ml(imc_ctx* ctx, const uint64_t* row_masks, size_t rows, const uint64_t* db_masks, size_t n,
+                        uint16_t* ml, size_t ld, imc_stream stream);
 
 /* OR-tree (Sec. 4.2; Alg. 3 return): dup[q] = OR over rotations and entries
  * of the shared match bits, as a binary tree of x OR y = x ^ y ^ (x AND y):

@@ -26,12 +26,13 @@ EXPORTS = [
     "imc_set_dot_tiles", "imc_galois_db_bytes", "imc_galois_query_op_bytes", "imc_galois_query_raw_bytes",
     "imc_galois_share_db", "imc_galois_share_query", "imc_galois_dot_shares", "imc_galois_dot_shares_rows",
     "imc_galois_append_db", "imc_mask_in_batch", "imc_or_bits", "imc_dot_shares_gather",
-    "imc_galois_dot_shares_gather",
+    "imc_galois_dot_shares_gather", "imc_compare_variant", "imc_rotate_masks", "imc_plain_ml",
 ]
 
 (DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW, DOT_TILES_ROTATION,
  DOT_TILES_ROTATION_LDSCOPY, DOT_TILES_ROTATION_DIRECT) = (0, 1, 2, 3, 4, 6, 7)
 DOT_PERSISTENT = 0x10
+CMP_PLAIN_MASK, CMP_LIFT18, CMP_CONST32 = 1, 2, 3   # imc_compare_variant settings
 
 
 class IMCError(RuntimeError):
@@ -92,7 +93,7 @@ def lib():
         L.imc_share_db.argtypes = [_VP, _VP, _VP, sz, ctypes.c_uint64, _P3, sz, _VP]
         L.imc_share_query.argtypes = [_VP, _VP, _VP, sz, ctypes.c_uint64, _P3, _VP, _VP]
         L.imc_dot_shares.argtypes = [_VP, ctypes.c_int, _VP, sz, ctypes.POINTER(imc_ids), _VP, sz, sz, _VP, _VP, sz, _VP]
-        L.imc_reshare.argtypes = [_VP, _P3, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _P3, _P3, _P3, _VP]
+        L.imc_reshare.argtypes = [_VP, _P3, _VP, sz, sz, sz, ctypes.POINTER(imc_ids), _P3, _P3, _VP, _VP]
         L.imc_compare_threshold.argtypes = [_VP, _P3, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _P3, sz, _VP]
         L.imc_or_tree.argtypes = [_VP, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, sz, _P3, _VP]
         L.imc_open.argtypes = [_VP, ctypes.c_int, _P3, sz, _VP, ctypes.c_int, _VP]
@@ -110,6 +111,10 @@ def lib():
                                             _VP, sz, _VP]
         L.imc_galois_dot_shares_gather.argtypes = L.imc_dot_shares_gather.argtypes
         L.imc_or_bits.argtypes = [_VP, _P3, _P3, sz, ctypes.c_uint64, _P3, _VP]
+        L.imc_compare_variant.argtypes = [_VP, ctypes.c_int, _P3, ctypes.c_int, _VP, _VP, sz, sz, sz,
+                                          ctypes.POINTER(imc_ids), _P3, sz, _VP]
+        L.imc_rotate_masks.argtypes = [_VP, _VP, sz, ctypes.POINTER(imc_ids), _VP, _VP]
+        L.imc_plain_ml.argtypes = [_VP, _VP, sz, _VP, sz, _VP, sz, _VP]
         for f in EXPORTS:
             if f not in ("imc_destroy", "imc_strerror") and not f.endswith("_bytes"):
                 getattr(L, f).restype = st
@@ -269,10 +274,29 @@ class Context:
     def set_dot_tiles(self, flags: int):
         return _check(lib().imc_set_dot_tiles(self._h, flags), "imc_set_dot_tiles")
 
-    # -- imc_reshare
+    # -- imc_reshare (add_mask3 / rep_mask3 None: code shares only)
     def reshare(self, add_code3, add_mask3, rows, n, ld, ids: imc_ids, msg3, rep_code3, rep_mask3, stream=None):
-        return _check(lib().imc_reshare(self._h, _p3(add_code3), _p3(add_mask3), rows, n, ld, ctypes.byref(ids),
-                                        _p3(msg3), _p3(rep_code3), _p3(rep_mask3), _stream(stream)), "imc_reshare")
+        am = ctypes.cast(_p3(add_mask3), _VP) if add_mask3 is not None else None
+        rm = ctypes.cast(_p3(rep_mask3), _VP) if rep_mask3 is not None else None
+        return _check(lib().imc_reshare(self._h, _p3(add_code3), am, rows, n, ld, ctypes.byref(ids),
+                                        _p3(msg3), _p3(rep_code3), rm, _stream(stream)), "imc_reshare")
+
+    # -- imc_compare_variant (variant CMP_*; rep_mask3 None for CMP_PLAIN_MASK)
+    def compare_variant(self, variant, rep_code3, code_bits, rep_mask3, ml_pub, rows, n, ld, ids: imc_ids, match3,
+                        mw_ld, stream=None):
+        rm = ctypes.cast(_p3(rep_mask3), _VP) if rep_mask3 is not None else None
+        return _check(lib().imc_compare_variant(self._h, variant, _p3(rep_code3), code_bits, rm, addr(ml_pub), rows,
+                                                n, ld, ctypes.byref(ids), _p3(match3), mw_ld, _stream(stream)),
+                      "imc_compare_variant")
+
+    # -- imc_rotate_masks / imc_plain_ml (masks in plain)
+    def rotate_masks(self, masks, q, ids: imc_ids, out, stream=None):
+        return _check(lib().imc_rotate_masks(self._h, addr(masks), q, ctypes.byref(ids), addr(out), _stream(stream)),
+                      "imc_rotate_masks")
+
+    def plain_ml(self, row_masks, rows, db_masks, n, ml, ld, stream=None):
+        return _check(lib().imc_plain_ml(self._h, addr(row_masks), rows, addr(db_masks), n, addr(ml), ld,
+                                         _stream(stream)), "imc_plain_ml")
 
     # -- imc_compare_threshold
     def compare_threshold(self, rep_code3, rep_mask3, rows, n, ld, ids: imc_ids, match3, mw_ld, stream=None):

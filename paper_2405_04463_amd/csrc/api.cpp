@@ -187,7 +187,7 @@ imc_status dot_shares_impl(imc_ctx* c, int party, const void* qop, const uint32_
   if (st != IMC_OK) return st;
   const size_t rows = q * size_t(ids->r);
   if (rows == 0 || n == 0) return IMC_OK;
-  if (!qop || !db || !code_dot || !mask_dot) return IMC_EINVAL;
+  if (!qop || !db || !code_dot) return IMC_EINVAL;   // mask_dot NULL: code dot only
   if (!aligned(qop, 16) || !aligned(db, 256) || !aligned(code_dot, 2) || !aligned(mask_dot, 2)) return IMC_EINVAL;
   if (rows > c->max_rows) return IMC_ESHAPE;
   if (ld < n) return IMC_ESHAPE;
@@ -219,7 +219,7 @@ imc_status dot_shares_rows_impl(imc_ctx* c, int party, const void* qop, size_t q
                                 uint16_t* code_dot, uint16_t* mask_dot, size_t ld, imc_stream stream, bool galois) {
   if (!c || party < 0 || party > 2) return IMC_EINVAL;
   if (nrows == 0 || n == 0) return IMC_OK;
-  if (!qop || !rows || !db || !code_dot || !mask_dot || q == 0) return IMC_EINVAL;
+  if (!qop || !rows || !db || !code_dot || q == 0) return IMC_EINVAL;   // mask_dot NULL: code dot only
   if (!aligned(qop, 16) || !aligned(rows, 8) || !aligned(db, 256) || !aligned(code_dot, 2) || !aligned(mask_dot, 2))
     return IMC_EINVAL;
   if (first_entry_id % 64) return IMC_EINVAL;
@@ -356,14 +356,17 @@ imc_status imc_set_dot_tiles(imc_ctx* c, uint32_t flags) {
 imc_status imc_reshare(imc_ctx* c, const uint16_t* const add_code[3], const uint16_t* const add_mask[3], size_t rows,
                        size_t n, size_t ld, const imc_ids* ids, uint16_t* const msg[3], uint16_t* const rep_code[3],
                        uint16_t* const rep_mask[3], imc_stream stream) {
-  if (!c || !add_code || !add_mask || !msg || !rep_code || !rep_mask) return IMC_EINVAL;
+  if (!c || !add_code || !msg || !rep_code) return IMC_EINVAL;
+  if (add_mask && !rep_mask) return IMC_EINVAL;   // add_mask NULL: code shares only
   imc_status st = check_ids(ids);
   if (st != IMC_OK) return st;
   if (rows % size_t(ids->r)) return IMC_ESHAPE;
   if (ld < n) return IMC_ESHAPE;
   if (rows == 0 || n == 0) return IMC_OK;
-  for (int p = 0; p < 3; ++p)
-    if (!add_code[p] || !add_mask[p] || !msg[p] || !rep_code[p] || !rep_mask[p]) return IMC_EINVAL;
+  for (int p = 0; p < 3; ++p) {
+    if (!add_code[p] || !msg[p] || !rep_code[p]) return IMC_EINVAL;
+    if (add_mask && (!add_mask[p] || !rep_mask[p])) return IMC_EINVAL;
+  }
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;
   return dev_status(
@@ -387,6 +390,57 @@ imc_status imc_compare_threshold(imc_ctx* c, const uint16_t* const rep_code[3], 
   if (!g.ok) return IMC_EDEVICE;
   return dev_status(imc::launch_compare(c->party, rep_code, rep_mask, rows, n, ld, *ids, match, mw_ld,
                                         hipStream_t(stream)));
+}
+
+imc_status imc_compare_variant(imc_ctx* c, int variant, const void* const rep_code[3], int code_bits,
+                               const void* const rep_mask[3], const uint16_t* ml_pub, size_t rows, size_t n,
+                               size_t ld, const imc_ids* ids, uint64_t* const match[3], size_t mw_ld,
+                               imc_stream stream) {
+  if (!c || !rep_code || !match) return IMC_EINVAL;
+  if (variant < IMC_CMP_PLAIN_MASK || variant > IMC_CMP_CONST32) return IMC_EINVAL;
+  if (code_bits != 16 && !(code_bits == 32 && variant == IMC_CMP_CONST32)) return IMC_EINVAL;
+  imc_status st = check_ids(ids);
+  if (st != IMC_OK) return st;
+  if (rows % size_t(ids->r)) return IMC_ESHAPE;
+  if (ld < n || mw_ld < (n + 63) / 64) return IMC_ESHAPE;
+  if (rows == 0 || n == 0) return IMC_OK;
+  const size_t cw = code_bits / 8, mwid = variant == IMC_CMP_CONST32 ? 4 : 2;
+  for (int p = 0; p < 3; ++p) {
+    if (!rep_code[p] || !match[p]) return IMC_EINVAL;
+    if (!aligned(rep_code[p], cw) || !aligned(match[p], 8)) return IMC_EINVAL;
+    if (variant != IMC_CMP_PLAIN_MASK && (!rep_mask || !rep_mask[p] || !aligned(rep_mask[p], mwid)))
+      return IMC_EINVAL;
+  }
+  if (variant == IMC_CMP_PLAIN_MASK && (!ml_pub || !aligned(ml_pub, 2))) return IMC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  return dev_status(imc::launch_compare_variant(variant, c->party, rep_code, code_bits == 32,
+                                                variant == IMC_CMP_PLAIN_MASK ? nullptr : rep_mask, ml_pub, rows, n,
+                                                ld, *ids, match, mw_ld, hipStream_t(stream)));
+}
+
+imc_status imc_rotate_masks(imc_ctx* c, const uint64_t* masks, size_t q, const imc_ids* ids, uint64_t* out,
+                            imc_stream stream) {
+  if (!c) return IMC_EINVAL;
+  imc_status st = check_ids(ids);
+  if (st != IMC_OK) return st;
+  if (q == 0) return IMC_OK;
+  if (!masks || !out || !aligned(masks, 8) || !aligned(out, 8)) return IMC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  return dev_status(imc::launch_rotate_masks(masks, q, *ids, out, hipStream_t(stream)));
+}
+
+imc_status imc_plain_ml(imc_ctx* c, const uint64_t* row_masks, size_t rows, const uint64_t* db_masks, size_t n,
+                        uint16_t* ml, size_t ld, imc_stream stream) {
+  if (!c) return IMC_EINVAL;
+  if (ld < n) return IMC_ESHAPE;
+  if (rows == 0 || n == 0) return IMC_OK;
+  if (!row_masks || !db_masks || !ml) return IMC_EINVAL;
+  if (!aligned(row_masks, 8) || !aligned(db_masks, 8) || !aligned(ml, 2)) return IMC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  return dev_status(imc::launch_plain_ml(row_masks, rows, db_masks, n, ml, ld, hipStream_t(stream)));
 }
 
 imc_status imc_or_tree(imc_ctx* c, const uint64_t* const match[3], size_t q, size_t nw, size_t mw_ld,

@@ -234,14 +234,11 @@ __global__ void __launch_bounds__(256) compare_kernel(CmpArgs a) {
     for (int ii = 0; ii < 4; ++ii) {
       const int i = 4 * blk + ii;
       const uint64_t y0 = i < 16 ? x[0][i] : 0, y1 = i < 16 ? x[1][i] : 0, y2 = i < 16 ? x[2][i] : 0;
+      if (i > 17) break;
       bx_step(b, 2 * ii, i, 17, y0, y1, y2, cprev, carry, r);
       if (i == 16) bit16 = r;
+      if (i == 17) bit17 = r;   // bit 17 has no gates (its carry out is not needed)
     }
-  }
-  {  // step 17: no gates (the carry out of bit 17 is not needed)
-    Blk3 dummy;
-    bx_step(dummy, 0, 17, 17, 0, 0, 0, cprev, carry, r);
-    bit17 = r;
   }
 
   // BitInject bit 17 into Z_2^15 and bit 16 into Z_2^16 (tape blocks 13..24).
@@ -292,6 +289,272 @@ __global__ void __launch_bounds__(256) compare_kernel(CmpArgs a) {
       if (i >= 16) { y0 = U[0][i - 16]; y1 = U[1][i - 16]; y2 = U[2][i - 16]; }
       bx_step(b, 2 * ii, i, 31, y0, y1, y2, cprev, carry, r);
     }
+  }
+
+  const uint64_t keep = nval == 64 ? ~0ull : ((1ull << nval) - 1ull);
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    const int pm = (p + 2) % 3;
+    a.match[p][row * a.mw_ld + w] = r.c[p] & keep;
+    a.match[p][a.match_plane + row * a.mw_ld + w] = r.c[pm] & keep;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Comparison variants (Sec. 4.3 Alg. 2 and Sec. 4.3.1: masks in plain;
+// Sec. 5.1-5.2: lifting versus a dot product in the larger ring; the
+// settings of the comparison benchmark, Sec. 6.2).  The threshold 1 - 2*3/8
+// is 1/4 exactly; every variant decides 4 dot > ml.
+//
+//   kCmpPlain    ml public (u16 per comparison), code dot over Z_2^16:
+//                MSB_16(floor(ml/4) - dot), BitExtract m = 15 on tape
+//                words 0..29 (blocks 0..3): 29 AND gates.
+//   kCmpLift18   ml shared over Z_2^16 and lifted to Z_2^18 (bits 17 and
+//                16 of x0 + x1 + x2 by BitExtract m = 17 on words 0..33,
+//                injected into Z_2^1 and Z_2^2); y = ml - 4 dot over Z_2^18,
+//                MSB by BitExtract m = 17 on words 40..73 (blocks 5..9).
+//                Inject values: key_0 c0 word 80 (A), words 88..89 (B);
+//                key_2 c2 80, w0 81, w1 82 (A), c2 88..89, w0 90..91,
+//                w1 92..93 (B) -- blocks 10 and 11.  66 AND gates.
+//   kCmpConst32  ml shared over Z_2^32 (a dot product in the larger ring),
+//                the code dot over Z_2^16 or Z_2^32: y = 2^14 ml - 2^16 dot
+//                over Z_2^32, MSB by BitExtract m = 31 on words 0..61
+//                (blocks 0..7): 61 AND gates.
+// ---------------------------------------------------------------------------
+constexpr int kCmpPlain = 1, kCmpLift18 = 2, kCmpConst32 = 3;
+
+struct CmpVArgs {
+  Keys3 keys;
+  const void* code[3];        // rep_code[p] plane 0: u16, or u32 when code32
+  const void* mask[3];        // rep_mask[p] plane 0: u16 (Lift18) or u32 (Const32)
+  const uint16_t* ml_pub;     // [rows][ld] public ml (Plain)
+  uint64_t* match[3];         // [2][rows][mw_ld]
+  uint64_t ld, mw_ld, n, nw, rows, match_plane;
+  uint64_t qid_base, first_entry;
+  int32_t r;
+  int32_t vec;                // 16-byte loads allowed (ld % 8 == 0, 16-byte aligned rows)
+  int8_t rot[IMC_MAX_ROT_DEV];
+};
+
+// BitExtract over bits 0..M of y0 + y1 + y2 given as NB planes per component
+// (higher planes are zero); FA gate of bit i on tape word W0 + 2i, ripple
+// gate on W0 + 2i + 1 (W0 a multiple of 8).  Returns the sharing of bit M.
+template <int M, int W0, int NB>
+__device__ __forceinline__ B3 bit_extract_msb(const Keys3& keys, uint64_t stream, uint64_t base,
+                                              const uint64_t (&y)[3][NB]) {
+  static_assert(W0 % 8 == 0, "gate words start a block");
+  B3 cprev{{0, 0, 0}}, carry{{0, 0, 0}}, r{{0, 0, 0}};
+#pragma unroll
+  for (int blk = 0; blk < (M + 4) / 4; ++blk) {
+    Blk3 b;
+    gen3(b, keys, stream, after(base + W0 / 8 + blk, carry.c[0] ^ cprev.c[1]));
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int i = 4 * blk + ii;
+      if (i > M) break;
+      const uint64_t y0 = i < NB ? y[0][i] : 0, y1 = i < NB ? y[1][i] : 0, y2 = i < NB ? y[2][i] : 0;
+      bx_step(b, 2 * ii, i, M, y0, y1, y2, cprev, carry, r);
+    }
+  }
+  return r;
+}
+
+// BitInject of x into Z_2^K from tape words given per bit (see bit_inject).
+template <int K>
+__device__ __forceinline__ void inject_words(const B3& x, const uint64_t (&c0)[K], const uint64_t (&c2)[K],
+                                             const uint64_t (&w0)[K], const uint64_t (&w1)[K], uint64_t out[3][K]) {
+  const uint64_t u = x.c[0] ^ x.c[2], ch = x.c[1];
+  uint64_t bA0 = 0, bA1 = 0, bB0 = 0, bB1 = 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint64_t v0 = (j == 0) ? u : 0, v1 = (j == 0) ? ~u : 0;
+    const uint64_t d0 = v0 ^ c0[j] ^ bA0;
+    bA0 = (~v0 & c0[j]) | (~(v0 ^ c0[j]) & bA0);
+    const uint64_t m0 = d0 ^ c2[j] ^ bB0;
+    bB0 = (~d0 & c2[j]) | (~(d0 ^ c2[j]) & bB0);
+    const uint64_t d1 = v1 ^ c0[j] ^ bA1;
+    bA1 = (~v1 & c0[j]) | (~(v1 ^ c0[j]) & bA1);
+    const uint64_t m1 = d1 ^ c2[j] ^ bB1;
+    bB1 = (~d1 & c2[j]) | (~(d1 ^ c2[j]) & bB1);
+    const uint64_t k0 = w0[j] ^ m0, k1 = w1[j] ^ m1;          // party 0 -> party 1
+    const uint64_t wc = (ch & w1[j]) | (~ch & w0[j]);         // party 2 -> party 1
+    out[0][j] = c0[j];
+    out[1][j] = wc ^ ((ch & k1) | (~ch & k0));                // party 1 -> party 2
+    out[2][j] = c2[j];
+  }
+}
+
+// a -= b over NB bit planes (mod 2^NB).
+template <int NB>
+__device__ __forceinline__ void sub_planes(uint64_t (&a)[NB], const uint64_t (&b)[NB]) {
+  uint64_t br = 0;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const uint64_t x = a[j], y = b[j];
+    a[j] = x ^ y ^ br;
+    br = (~x & y) | (~(x ^ y) & br);
+  }
+}
+
+template <int V, bool C32>
+__global__ void __launch_bounds__(256) compare_variant_kernel(CmpVArgs a) {
+  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= a.rows * a.nw) return;
+  const uint64_t row = t / a.nw, w = t % a.nw;
+  const uint64_t col0 = w * 64;
+  const int nval = int(min<uint64_t>(64, a.n - col0));
+  const bool vec_ok = a.vec != 0;
+  const uint64_t qid = a.qid_base + row / uint64_t(a.r);
+  const int rot = a.rot[row % uint64_t(a.r)];
+  const uint32_t dom = V == kCmpPlain ? kDomCmpPlain : V == kCmpLift18 ? kDomCmpLift18 : kDomCmpConst32;
+  const uint64_t stream = row_stream(dom, qid, rot);
+  const uint64_t base = ((a.first_entry >> 6) + w) * kTapeBlocksPerGroup;
+  B3 r;
+
+  if constexpr (V == kCmpPlain) {
+    // y_0 = floor(ml/4) - d_0, y_p = -d_p (mod 2^16): the public term enters component 0
+    uint32_t M[32];
+    load64(a.ml_pub + row * a.ld, col0, nval, vec_ok, M);
+    uint64_t y[3][16];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      uint32_t W[32];
+      load64(static_cast<const uint16_t*>(a.code[p]) + row * a.ld, col0, nval, vec_ok, W);
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        const uint32_t tl = p == 0 ? ((M[i] & 0xFFFFu) >> 2) : 0u, th = p == 0 ? (M[i] >> 18) : 0u;
+        const uint32_t lo = (tl - (W[i] & 0xFFFFu)) & 0xFFFFu, hi = (th - (W[i] >> 16)) & 0xFFFFu;
+        W[i] = lo | (hi << 16);
+      }
+      to_planes(W, y[p]);
+    }
+    r = bit_extract_msb<15, 0, 16>(a.keys, stream, base, y);
+  } else if constexpr (V == kCmpLift18) {
+    uint64_t x[3][16];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      uint32_t W[32];
+      load64(static_cast<const uint16_t*>(a.mask[p]) + row * a.ld, col0, nval, vec_ok, W);
+      to_planes(W, x[p]);
+    }
+    // Lift: bits 16 and 17 of S = x0 + x1 + x2 (BitExtract m = 17, words 0..33)
+    B3 bit16{{0, 0, 0}}, bit17{{0, 0, 0}};
+    {
+      B3 cprev{{0, 0, 0}}, carry{{0, 0, 0}}, rr{{0, 0, 0}};
+#pragma unroll
+      for (int blk = 0; blk < 5; ++blk) {
+        Blk3 b;
+        gen3(b, a.keys, stream, after(base + blk, carry.c[0] ^ cprev.c[1]));
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int i = 4 * blk + ii;
+          if (i > 17) break;
+          const uint64_t y0 = i < 16 ? x[0][i] : 0, y1 = i < 16 ? x[1][i] : 0, y2 = i < 16 ? x[2][i] : 0;
+          bx_step(b, 2 * ii, i, 17, y0, y1, y2, cprev, carry, rr);
+          if (i == 16) bit16 = rr;
+          if (i == 17) bit17 = rr;
+        }
+      }
+    }
+    // Inject bit 17 into Z_2^1 and bit 16 into Z_2^2 (blocks 10, 11)
+    uint64_t A[3][1], B[3][2];
+    {
+      uint32_t blk[4][16];
+      const Key* const ks[4] = {&a.keys.k[0], &a.keys.k[0], &a.keys.k[2], &a.keys.k[2]};
+      const uint64_t st[4] = {stream, stream, stream, stream};
+      const uint64_t dep = bit16.c[0] ^ bit17.c[1];
+      const uint64_t ps[4] = {after(base + 10, dep), after(base + 11, dep), after(base + 10, dep),
+                              after(base + 11, dep)};
+      chacha12_n<4>(ks, st, ps, blk);
+      const uint64_t c0a[1] = {word64(blk[0], 0)}, c2a[1] = {word64(blk[2], 0)};
+      const uint64_t w0a[1] = {word64(blk[2], 1)}, w1a[1] = {word64(blk[2], 2)};
+      const uint64_t c0b[2] = {word64(blk[1], 0), word64(blk[1], 1)};
+      const uint64_t c2b[2] = {word64(blk[3], 0), word64(blk[3], 1)};
+      const uint64_t w0b[2] = {word64(blk[3], 2), word64(blk[3], 3)};
+      const uint64_t w1b[2] = {word64(blk[3], 4), word64(blk[3], 5)};
+      inject_words<1>(bit17, c0a, c2a, w0a, w1a, A);
+      inject_words<2>(bit16, c0b, c2b, w0b, w1b, B);
+    }
+    // y_p = x_p - 2^17 A_p - 2^16 B_p - 4 d_p (mod 2^18)
+    uint64_t y[3][18];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      uint32_t W[32];
+      uint64_t d[16];
+      load64(static_cast<const uint16_t*>(a.code[p]) + row * a.ld, col0, nval, vec_ok, W);
+      to_planes(W, d);
+      uint64_t s[18];
+#pragma unroll
+      for (int j = 0; j < 18; ++j) {
+        y[p][j] = j < 16 ? x[p][j] : 0;
+        s[j] = j >= 2 ? d[j - 2] : 0;
+      }
+      sub_planes<18>(y[p], s);
+#pragma unroll
+      for (int j = 0; j < 18; ++j) s[j] = j == 16 ? B[p][0] : j == 17 ? (B[p][1] ^ A[p][0]) : 0;
+      // 2^16 B + 2^17 A has bit 16 = B0 and bit 17 = B1 ^ A0 (mod 2^18)
+      sub_planes<18>(y[p], s);
+    }
+    r = bit_extract_msb<17, 40, 18>(a.keys, stream, base, y);
+  } else {
+    // y_p = 2^14 x_p - 2^16 d_p = (x_p - 4 d_p) 2^14 (mod 2^32): bits 0..13
+    // are zero, bits 14..31 are t = (x_p - 4 d_p) mod 2^18.  Four columns at
+    // a time: t's low 16 bits packed for the transpose, bits 16, 17 gathered
+    // into their planes directly.
+    uint64_t y[3][32];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const uint32_t* xr = static_cast<const uint32_t*>(a.mask[p]) + row * a.ld + col0;
+      const uint32_t* dr32 = static_cast<const uint32_t*>(a.code[p]) + row * a.ld + col0;
+      const uint16_t* dr16 = static_cast<const uint16_t*>(a.code[p]) + row * a.ld + col0;
+      uint32_t Wl[32];
+      uint64_t h16 = 0, h17 = 0;
+      auto put = [&](int g, const uint32_t (&xv)[4], const uint32_t (&dv)[4]) {
+        uint32_t tv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          tv[k] = xv[k] - (dv[k] << 2);
+          h16 |= uint64_t((tv[k] >> 16) & 1u) << (4 * g + k);
+          h17 |= uint64_t((tv[k] >> 17) & 1u) << (4 * g + k);
+        }
+        Wl[2 * g] = (tv[0] & 0xFFFFu) | (tv[1] << 16);
+        Wl[2 * g + 1] = (tv[2] & 0xFFFFu) | (tv[3] << 16);
+      };
+      if (vec_ok && nval == 64) {
+#pragma unroll
+        for (int g = 0; g < 16; ++g) {
+          const uint4 v = reinterpret_cast<const uint4*>(xr)[g];
+          const uint32_t xv[4] = {v.x, v.y, v.z, v.w};
+          uint32_t dv[4];
+          if constexpr (C32) {
+            const uint4 d = reinterpret_cast<const uint4*>(dr32)[g];
+            dv[0] = d.x; dv[1] = d.y; dv[2] = d.z; dv[3] = d.w;
+          } else {
+            const uint2 d = reinterpret_cast<const uint2*>(dr16)[g];
+            dv[0] = d.x & 0xFFFFu; dv[1] = d.x >> 16; dv[2] = d.y & 0xFFFFu; dv[3] = d.y >> 16;
+          }
+          put(g, xv, dv);
+        }
+      } else {
+#pragma unroll
+        for (int g = 0; g < 16; ++g) {
+          uint32_t xv[4], dv[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int c = 4 * g + k;
+            xv[k] = c < nval ? xr[c] : 0u;
+            if constexpr (C32) dv[k] = c < nval ? dr32[c] : 0u;
+            else dv[k] = c < nval ? uint32_t(dr16[c]) : 0u;
+          }
+          put(g, xv, dv);
+        }
+      }
+      uint64_t tp[16];
+      to_planes(Wl, tp);
+#pragma unroll
+      for (int j = 0; j < 32; ++j) y[p][j] = j < 14 ? 0 : j < 30 ? tp[j - 14] : j == 30 ? h16 : h17;
+    }
+    r = bit_extract_msb<31, 0, 32>(a.keys, stream, base, y);
   }
 
   const uint64_t keep = nval == 64 ? ~0ull : ((1ull << nval) - 1ull);
@@ -359,11 +622,12 @@ __global__ void __launch_bounds__(256) reshare_kernel(ReshareArgs a) {
   const int nval = int(min<uint64_t>(16, a.n - col0));
   const uint64_t off = row * a.ld + col0;
   const bool vec = (a.ld % 8) == 0;
+  const bool with_mask = a.add_mask[0] != nullptr;   // no mask dot when masks are public
   uint16_t zc[3][16], zm[3][16];
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
     ld16(a.add_code[p] + off, nval, vec, zc[p]);
-    ld16(a.add_mask[p] + off, nval, vec, zm[p]);
+    if (with_mask) ld16(a.add_mask[p] + off, nval, vec, zm[p]);
   }
   uint32_t F[3][16];
   {
@@ -385,9 +649,10 @@ __global__ void __launch_bounds__(256) reshare_kernel(ReshareArgs a) {
   for (int p = 0; p < 3; ++p) {
     const int pm = (p + 2) % 3;
     st16(a.msg[p] + off, nval, vec, oc[p]);              // party p -> party p+1
-    st16(a.msg[p] + a.plane + off, nval, vec, om[p]);
     st16(a.rep_code[p] + off, nval, vec, oc[p]);
     st16(a.rep_code[p] + a.plane + off, nval, vec, oc[pm]);   // received from party p-1
+    if (!with_mask) continue;
+    st16(a.msg[p] + a.plane + off, nval, vec, om[p]);
     st16(a.rep_mask[p] + off, nval, vec, om[p]);
     st16(a.rep_mask[p] + a.plane + off, nval, vec, om[pm]);
   }
@@ -577,10 +842,10 @@ hipError_t launch_reshare(const Keys3& keys, const uint16_t* const add_code[3], 
   a.keys = keys;
   for (int p = 0; p < 3; ++p) {
     a.add_code[p] = add_code[p];
-    a.add_mask[p] = add_mask[p];
+    a.add_mask[p] = add_mask ? add_mask[p] : nullptr;
     a.msg[p] = msg[p];
     a.rep_code[p] = rep_code[p];
-    a.rep_mask[p] = rep_mask[p];
+    a.rep_mask[p] = add_mask ? rep_mask[p] : nullptr;
   }
   a.ld = ld;
   a.n = n;
@@ -619,6 +884,46 @@ hipError_t launch_compare(const Keys3& keys, const uint16_t* const rep_code[3], 
   fill_rot(a.rot, ids);
   const uint64_t threads = rows * a.nw;
   hipLaunchKernelGGL(compare_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_compare_variant(int variant, const Keys3& keys, const void* const rep_code[3], bool code32,
+                                  const void* const rep_mask[3], const uint16_t* ml_pub, uint64_t rows, uint64_t n,
+                                  uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3], uint64_t mw_ld,
+                                  hipStream_t s) {
+  if (rows == 0 || n == 0) return hipSuccess;
+  CmpVArgs a;
+  a.keys = keys;
+  for (int p = 0; p < 3; ++p) {
+    a.code[p] = rep_code[p];
+    a.mask[p] = rep_mask ? rep_mask[p] : nullptr;
+    a.match[p] = match[p];
+  }
+  a.ml_pub = ml_pub;
+  a.ld = ld;
+  a.mw_ld = mw_ld;
+  a.n = n;
+  a.nw = (n + 63) / 64;
+  a.rows = rows;
+  a.match_plane = rows * mw_ld;
+  a.qid_base = ids.query_id_base;
+  a.first_entry = ids.first_entry_id;
+  a.r = ids.r;
+  bool vec = (ld % 8) == 0 && (reinterpret_cast<uintptr_t>(ml_pub) % 16) == 0;
+  for (int p = 0; p < 3; ++p)
+    vec = vec && (reinterpret_cast<uintptr_t>(a.code[p]) % 16) == 0 && (reinterpret_cast<uintptr_t>(a.mask[p]) % 16) == 0;
+  a.vec = vec ? 1 : 0;
+  fill_rot(a.rot, ids);
+  const dim3 grid(unsigned((rows * a.nw + 255) / 256)), block(256);
+  switch (variant) {
+    case kCmpPlain: hipLaunchKernelGGL((compare_variant_kernel<kCmpPlain, false>), grid, block, 0, s, a); break;
+    case kCmpLift18: hipLaunchKernelGGL((compare_variant_kernel<kCmpLift18, false>), grid, block, 0, s, a); break;
+    case kCmpConst32:
+      if (code32) hipLaunchKernelGGL((compare_variant_kernel<kCmpConst32, true>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((compare_variant_kernel<kCmpConst32, false>), grid, block, 0, s, a);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -36,12 +36,13 @@ constexpr int kKGalois = kCodeBits;                                           //
 // PRF domains: high byte of the 64-bit stream id.
 constexpr uint32_t kDomShareDb = 1, kDomShareQuery = 2, kDomReshare = 3, kDomCmp = 4, kDomOr = 5;
 constexpr uint32_t kDomGaloisDb = 6, kDomGaloisQuery = 7, kDomOrPairs = 8;
+constexpr uint32_t kDomCmpPlain = 9, kDomCmpLift18 = 10, kDomCmpConst32 = 11;
+constexpr uint32_t kDomShare32Db = 12, kDomShare32Query = 13, kDomReshare32 = 14;
 
-// Per 64-entry group, each key's tape holds u64 words (8 per ChaCha block):
-// words 0..32 = AND gates 0..32 (Lift), words 40..100 = AND gates 33..93 (MSB),
-// words 104.. = BitInject values; 32 blocks reserved per group.
+// Per 64-entry group, each key's tape holds u64 words (8 per ChaCha block),
+// 32 blocks reserved per group.  The comparison kernels document which words
+// each of their AND gates and BitInject values take.
 constexpr int kTapeBlocksPerGroup = 32;
-constexpr int kTapeCA = 104, kTapeCB = 119, kTapeW0A = 136, kTapeW0B = 151, kTapeW1A = 168, kTapeW1B = 183;
 
 // MFMA operand and accumulator vectors.
 typedef int v4i __attribute__((ext_vector_type(4)));

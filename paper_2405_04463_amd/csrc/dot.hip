@@ -310,7 +310,7 @@ static hipError_t launch_dot_cfg(DotArgs d, uint32_t rows, uint64_t n, hipStream
       d.persistent = 1;
     }
   }
-  const dim3 grid(blocks, 1, 2);
+  const dim3 grid(blocks, 1, d.out[1] ? 2 : 1);   // z: code, mask (no mask dot when masks are public)
   const size_t lds = 3 * size_t(C::kStageBytes);
   auto kern = dot_kernel<K, WM, WN, WAVES_M, WAVES_N, NSETS>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),

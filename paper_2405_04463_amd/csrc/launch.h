@@ -45,6 +45,14 @@ hipError_t launch_reshare(const Keys3& keys, const uint16_t* const add_code[3], 
 hipError_t launch_compare(const Keys3& keys, const uint16_t* const rep_code[3], const uint16_t* const rep_mask[3],
                           uint64_t rows, uint64_t n, uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3],
                           uint64_t mw_ld, hipStream_t s);
+hipError_t launch_compare_variant(int variant, const Keys3& keys, const void* const rep_code[3], bool code32,
+                                  const void* const rep_mask[3], const uint16_t* ml_pub, uint64_t rows, uint64_t n,
+                                  uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3], uint64_t mw_ld,
+                                  hipStream_t s);
+hipError_t launch_rotate_masks(const uint64_t* masks, uint64_t q, const imc_ids_dev& ids, uint64_t* out,
+                               hipStream_t s);
+hipError_t launch_plain_ml(const uint64_t* row_masks, uint64_t rows, const uint64_t* db_masks, uint64_t n,
+                           uint16_t* ml, uint64_t ld, hipStream_t s);
 size_t or_tree_ws_bytes(uint64_t q, uint64_t r, uint64_t nw);
 hipError_t launch_or_tree(const Keys3& keys, const uint64_t* const match[3], uint64_t q, uint64_t nw, uint64_t mw_ld,
                           const imc_ids_dev& ids, void* ws, uint8_t* const dup[3], hipStream_t s);

@@ -3,6 +3,10 @@
 Allocation and sequencing only; all arithmetic is in the library's kernels:
   share_db / share_query -> dot_shares (each party) -> reshare ->
   compare_threshold -> or_tree -> open
+
+Comparison settings (Sec. 6.2): "mpclift" (default, Alg. 3 with ml lifted to
+Z_2^32), "lift18" (ml lifted to Z_2^18 only) and "plain" (Alg. 2: masks
+public, ml computed in plain by every party, only the code dot is shared).
 """
 from __future__ import annotations
 
@@ -10,8 +14,11 @@ from dataclasses import dataclass
 
 import torch
 
-from . import (OPEN_U8_XOR, OPEN_U16_ADD, OPEN_U64_XOR, Context, db_bytes, galois_db_bytes, galois_query_op_bytes,
-               galois_query_raw_bytes, make_ids, or_tree_ws_bytes, query_op_bytes, query_raw_bytes)
+from . import (CMP_LIFT18, CMP_PLAIN_MASK, OPEN_U8_XOR, OPEN_U16_ADD, OPEN_U64_XOR, Context, db_bytes,
+               galois_db_bytes, galois_query_op_bytes, galois_query_raw_bytes, make_ids, or_tree_ws_bytes,
+               query_op_bytes, query_raw_bytes)
+
+COMPARE_SETTINGS = ("mpclift", "lift18", "plain")
 
 ROW_BYTES = 102400
 
@@ -82,37 +89,60 @@ class CheckBuffers:
     match: list
     dup: list
     ws: torch.Tensor
+    compare: str = "mpclift"
+    ml_pub: torch.Tensor | None = None       # "plain": public ml [rows, ld]
+    row_masks: torch.Tensor | None = None    # "plain": rotated query masks [rows, 200]
 
 
-def alloc_check(q: int, r: int, n: int, device=0) -> CheckBuffers:
+def alloc_check(q: int, r: int, n: int, device=0, compare: str = "mpclift") -> CheckBuffers:
+    if compare not in COMPARE_SETTINGS:
+        raise ValueError(compare)
     d = _dev(device)
     rows = q * r
     ld = ((n + 63) // 64) * 64
     nw = ld // 64
+    plain = compare == "plain"
     u16 = lambda *s: torch.empty(*s, dtype=torch.int16, device=d)  # noqa: E731
     return CheckBuffers(
         rows=rows, n=n, ld=ld, nw=nw,
         dot_code=[u16(rows, ld) for _ in range(3)],
-        dot_mask=[u16(rows, ld) for _ in range(3)],
+        dot_mask=None if plain else [u16(rows, ld) for _ in range(3)],
         msg=[u16(2, rows, ld) for _ in range(3)],
         rep_code=[u16(2, rows, ld) for _ in range(3)],
-        rep_mask=[u16(2, rows, ld) for _ in range(3)],
+        rep_mask=None if plain else [u16(2, rows, ld) for _ in range(3)],
         match=[torch.empty(2, rows, nw, dtype=torch.int64, device=d) for _ in range(3)],
         dup=[torch.empty(2, q, dtype=torch.uint8, device=d) for _ in range(3)],
         ws=torch.empty(max(8, or_tree_ws_bytes(q, r, nw)), dtype=torch.uint8, device=d),
+        compare=compare,
+        ml_pub=u16(rows, ld) if plain else None,
+        row_masks=torch.empty(rows, 200, dtype=torch.int64, device=d) if plain else None,
     )
 
 
 def run_check(ctx: Context, qs: SharedQueries, rot, db: SharedDB, first_entry: int, n: int, buf: CheckBuffers,
-              or_tree: bool = True, stream=None):
-    """Alg. 3 for queries qs at rotations rot against entries first_entry..+n."""
+              or_tree: bool = True, stream=None, query_masks=None, db_masks=None):
+    """Alg. 3 (Alg. 2 for buf.compare == "plain") for queries qs at rotations
+    rot against entries first_entry..+n.  "plain" needs the public masks:
+    query_masks [q, 200] and db_masks [>= first_entry + n, 200] (device int64)."""
     assert qs.galois == db.galois
     ids = make_ids(qs.qid_base, rot, first_entry)
+    plain = buf.compare == "plain"
     for p in range(3):
-        ctx.dot_shares(p, qs.op[p], qs.q, ids, db.regions[p], db.capacity, n, buf.dot_code[p], buf.dot_mask[p],
-                       buf.ld, stream, galois=db.galois)
+        ctx.dot_shares(p, qs.op[p], qs.q, ids, db.regions[p], db.capacity, n, buf.dot_code[p],
+                       None if plain else buf.dot_mask[p], buf.ld, stream, galois=db.galois)
+    if plain:
+        assert query_masks is not None and db_masks is not None and db_masks.shape[0] >= first_entry + n
+        ctx.rotate_masks(query_masks, qs.q, ids, buf.row_masks, stream)
+        ctx.plain_ml(buf.row_masks, buf.rows, db_masks[first_entry:], n, buf.ml_pub, buf.ld, stream)
     ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, n, buf.ld, ids, buf.msg, buf.rep_code, buf.rep_mask, stream)
-    ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, n, buf.ld, ids, buf.match, buf.nw, stream)
+    if plain:
+        ctx.compare_variant(CMP_PLAIN_MASK, buf.rep_code, 16, None, buf.ml_pub, buf.rows, n, buf.ld, ids, buf.match,
+                            buf.nw, stream)
+    elif buf.compare == "lift18":
+        ctx.compare_variant(CMP_LIFT18, buf.rep_code, 16, buf.rep_mask, None, buf.rows, n, buf.ld, ids, buf.match,
+                            buf.nw, stream)
+    else:
+        ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, n, buf.ld, ids, buf.match, buf.nw, stream)
     if or_tree:
         nw = (n + 63) // 64
         ctx.or_tree(buf.match, qs.q, nw, buf.nw, ids, buf.ws, buf.ws.numel(), buf.dup, stream)
