@@ -5,7 +5,11 @@ GPU) for 64 queries x 31 rotations (1,984 rows) against a database of
 300,000 entries per party, inputs resident in HBM.  One step = every party's
 dot products, resharing, the MPCLift comparison, the OR-tree and opening the
 per-query result.  `--workload party` times one party's dot products for 32
-queries x 31 rotations against 1,000,000 entries instead.
+queries x 31 rotations against 1,000,000 entries instead; `batched` and
+`serve` run uneven batches and the continuous-batching service; `compare`
+times the comparison settings of Sec. 6.2 side by side.  `--compare` picks
+the comparison setting of the full workload (MPCLift, Lift to Z_2^18 only, or
+masks in plain).
 
 Prints one JSON line (see the keys below).  Only N = 1 GPU is supported.
 """
@@ -67,19 +71,31 @@ def keys():
     return dealer, party
 
 
-def enroll_db(ctx, db, seed, n, chunk=32768):
+def enroll_db(ctx, db, seed, n, chunk=32768, keep_masks=False, db32=None):
+    """Share entries 0..n-1 into db (and into the Z_2^32 regions db32); with
+    keep_masks also return the packed masks on the device ([n, 200] int64:
+    the public masks of the setting with masks in plain)."""
     import torch
 
     import workload as wl
 
+    masks = torch.empty(n, 200, dtype=torch.int64, device="cuda") if keep_masks else None
     for s in range(0, n, chunk):
         m = min(chunk, n - s)
         c, k = wl.gen_codes(seed, s, m)
-        db.enroll(torch.from_numpy(c.view(np.int64)).cuda(), torch.from_numpy(k.view(np.int64)).cuda(), s)
+        cd = torch.from_numpy(c.view(np.int64)).cuda()
+        kd = torch.from_numpy(k.view(np.int64)).cuda()
+        if db is not None:
+            db.enroll(cd, kd, s)
+        if db32 is not None:
+            db32.enroll(cd, kd, s)
+        if masks is not None:
+            masks[s:s + m] = kd
     torch.cuda.synchronize()
+    return masks
 
 
-def cpu_baseline(w, qc, qm, sample_q=4, sample_n=8192, galois=False):
+def cpu_baseline(w, qc, qm, sample_q=4, sample_n=8192, galois=False, compare="mpclift"):
     """The oracle's step (local dots of all parties, reshare, compare, OR-tree)
     on a bounded sample of the same workload; shares made before timing."""
     import oracle as orc
@@ -95,6 +111,10 @@ def cpu_baseline(w, qc, qm, sample_q=4, sample_n=8192, galois=False):
         qsh = orc.share(dealer, orc.DOM_SHARE_QUERY, qc[:sample_q], qm[:sample_q], 0)
         dsh = orc.share(dealer, orc.DOM_SHARE_DB, dc, dm, 0)
         local_dot = orc.local_dot
+    q32 = d32 = None
+    if compare in ("constlift", "nolift"):
+        q32 = orc.share32(dealer, orc.DOM_SHARE32_QUERY, qc[:sample_q], qm[:sample_q], 0)
+        d32 = orc.share32(dealer, orc.DOM_SHARE32_DB, dc, dm, 0)
     t0 = time.perf_counter()
     zc, zm = [], []
     for p in range(3):
@@ -102,13 +122,25 @@ def cpu_baseline(w, qc, qm, sample_q=4, sample_n=8192, galois=False):
         zc.append(c)
         zm.append(m)
     rc, rm = orc.reshare(party, np.stack(zc), np.stack(zm), sample_q, w.rot, 0, 0)
-    match = orc.compare(party, rc, rm, sample_q, w.rot, 0, 0)
+    if q32 is not None:
+        z32 = [orc.local_dot32(p, q32, w.rot, d32) for p in range(3)]
+        rc32, rm32 = orc.reshare32(party, np.stack([z[0] for z in z32]) if compare == "nolift" else None,
+                                   np.stack([z[1] for z in z32]), sample_q, w.rot, 0, 0)
+        match = orc.compare_variant(party, orc.CMPV_CONST32, rc32 if compare == "nolift" else rc, rm32, None,
+                                    sample_q, w.rot, 0, 0)
+    elif compare == "plain":
+        _, ml, _, _ = orc.plain(qc[:sample_q], qm[:sample_q], w.rot, dc, dm)   # public ml
+        match = orc.compare_variant(party, orc.CMPV_PLAIN, rc, None, ml, sample_q, w.rot, 0, 0)
+    elif compare == "lift18":
+        match = orc.compare_variant(party, orc.CMPV_LIFT18, rc, rm, None, sample_q, w.rot, 0, 0)
+    else:
+        match = orc.compare(party, rc, rm, sample_q, w.rot, 0, 0)
     orc.or_tree(party, match, sample_q, len(w.rot), 0)
     dt = time.perf_counter() - t0
     ncmp = sample_q * len(w.rot) * sample_n
     return {"value": ncmp / dt, "unit": "comparisons/s", "cores": orc.threads(), "kind": "oracle",
-            "sample": f"oracle step (3 parties' local dots, reshare, compare, OR-tree) on {sample_q} queries x "
-                      f"{len(w.rot)} rotations x {sample_n} entries = {ncmp} comparisons, {dt:.1f} s"}
+            "sample": f"oracle step (3 parties' local dots, reshare, {compare} compare, OR-tree) on {sample_q} "
+                      f"queries x {len(w.rot)} rotations x {sample_n} entries = {ncmp} comparisons, {dt:.1f} s"}
 
 
 def verify(ctx, buf, w, qc, qm, n_sample=1024):
@@ -146,23 +178,32 @@ def run_full(args):
 
     import paper_2405_04463_amd as imc
     import workload as wl
-    from paper_2405_04463_amd.pipeline import SharedDB, SharedQueries, alloc_check, open_dup, run_check
+    from paper_2405_04463_amd.pipeline import (VECS32, SharedDB, SharedDB32, SharedQueries, SharedQueries32,
+                                               alloc_check, open_dup, run_check)
 
     w = wl.full_protocol(n_db=args.n_db, n_q=args.n_q)
     dealer, party = keys()
     galois = args.scheme == "galois"
+    plain = args.compare == "plain"
+    v32 = VECS32.get(args.compare, ())
+    code16 = 0 not in v32
     ctx = imc.Context(imc.Keys(dealer, party), max_rows=w.rows, dot_tiles=args.dot_tiles)
-    nbytes = imc.galois_db_bytes(w.n_db) if galois else imc.db_bytes(w.n_db)
-    log(f"enrolling {w.n_db} entries x 3 parties ({3 * nbytes / 1e9:.1f} GB, {args.scheme} shares)")
-    db = SharedDB(ctx, w.n_db, galois=galois)
-    enroll_db(ctx, db, w.seed, w.n_db)
+    nbytes = (imc.galois_db_bytes(w.n_db) if galois else imc.db_bytes(w.n_db)) if code16 else 0
+    nbytes += len(v32) * imc.db32_bytes(w.n_db)
+    log(f"enrolling {w.n_db} entries x 3 parties ({3 * nbytes / 1e9:.1f} GB, {args.scheme} shares"
+        + (f", Z_2^32 vectors {v32}" if v32 else "") + ")")
+    db = SharedDB(ctx, w.n_db if code16 else 32, galois=galois)
+    db32 = SharedDB32(ctx, w.n_db, vecs=v32) if v32 else None
+    db_masks = enroll_db(ctx, db if code16 else None, w.seed, w.n_db, keep_masks=plain, db32=db32)
     qc, qm = wl.make_queries(w)
-    qs = SharedQueries(ctx, torch.from_numpy(qc.view(np.int64)).cuda(), torch.from_numpy(qm.view(np.int64)).cuda(), 0,
-                       galois=galois)
-    buf = alloc_check(w.n_q, len(w.rot), w.n_db)
+    q_codes = torch.from_numpy(qc.view(np.int64)).cuda()
+    q_masks = torch.from_numpy(qm.view(np.int64)).cuda()
+    qs = SharedQueries(ctx, q_codes, q_masks, 0, galois=galois)
+    qs32 = SharedQueries32(ctx, q_codes, q_masks, 0, vecs=v32) if v32 else None
+    buf = alloc_check(w.n_q, len(w.rot), w.n_db, compare=args.compare)
     torch.cuda.synchronize()
-    log("first step + verification against the oracle")
-    run_check(ctx, qs, w.rot, db, 0, w.n_db, buf)
+    log(f"first step + verification against the oracle ({args.compare} comparison)")
+    run_check(ctx, qs, w.rot, db, 0, w.n_db, buf, query_masks=q_masks, db_masks=db_masks, qs32=qs32, db32=db32)
     torch.cuda.synchronize()
     ver = verify(ctx, buf, w, qc, qm)
     log(f"verification: {ver}")
@@ -174,13 +215,35 @@ def run_full(args):
         for p in range(3):
             if events is not None:
                 events[p][0].record(stream)
-            ctx.dot_shares(p, qs.op[p], qs.q, ids, db.regions[p], db.capacity, w.n_db, buf.dot_code[p],
-                           buf.dot_mask[p], buf.ld, stream, galois=galois)
+            if code16:
+                ctx.dot_shares(p, qs.op[p], qs.q, ids, db.regions[p], db.capacity, w.n_db, buf.dot_code[p],
+                               buf.dot_mask[p] if buf.dot_mask is not None else None, buf.ld, stream, galois=galois)
+            for v in v32:
+                ctx.dot32_shares(p, qs32.op[v][p], qs.q, ids, db32.regions[v][p], db32.capacity, w.n_db,
+                                 buf.dot32[v][p], buf.ld, stream)
             if events is not None:
                 events[p][1].record(stream)
-        ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, w.n_db, buf.ld, ids, buf.msg, buf.rep_code, buf.rep_mask,
-                    stream)
-        ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, w.n_db, buf.ld, ids, buf.match, buf.nw, stream)
+        if plain:   # masks public: every party computes ml itself
+            ctx.rotate_masks(q_masks, qs.q, ids, buf.row_masks, stream)
+            ctx.plain_ml(buf.row_masks, buf.rows, db_masks, w.n_db, buf.ml_pub, buf.ld, stream)
+        if code16:
+            ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, w.n_db, buf.ld, ids, buf.msg, buf.rep_code,
+                        buf.rep_mask, stream)
+        for v in v32:
+            ctx.reshare32(v, buf.dot32[v], buf.rows, w.n_db, buf.ld, ids, buf.msg32[v], buf.rep32[v], stream)
+        if plain:
+            ctx.compare_variant(imc.CMP_PLAIN_MASK, buf.rep_code, 16, None, buf.ml_pub, buf.rows, w.n_db, buf.ld,
+                                ids, buf.match, buf.nw, stream)
+        elif args.compare == "lift18":
+            ctx.compare_variant(imc.CMP_LIFT18, buf.rep_code, 16, buf.rep_mask, None, buf.rows, w.n_db, buf.ld,
+                                ids, buf.match, buf.nw, stream)
+        elif v32:
+            code, bits = (buf.rep32[0], 32) if 0 in v32 else (buf.rep_code, 16)
+            ctx.compare_variant(imc.CMP_CONST32, code, bits, buf.rep32[1], None, buf.rows, w.n_db, buf.ld, ids,
+                                buf.match, buf.nw, stream)
+        else:
+            ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, w.n_db, buf.ld, ids, buf.match, buf.nw,
+                                  stream)
         ctx.or_tree(buf.match, qs.q, buf.nw, buf.nw, ids, buf.ws, buf.ws.numel(), buf.dup, stream)
         open_dup(ctx, buf, qs.q, check=0, stream=stream)
 
@@ -205,10 +268,15 @@ def run_full(args):
     ncmp = w.rows * w.n_db
     ms = total / args.steps * 1e3
     dot_avg_s = float(np.mean(dot_ms)) / 1e3
-    ops = ncmp * (OPS_PER_CMP_PARTY // 2 if galois else OPS_PER_CMP_PARTY)
+    # per party: 3 limb products per Z_2^16 vector, 10 per Z_2^32 vector (a
+    # vector is 25,600 k x 2 ops per product); masks in plain: code dot only
+    n16 = 0 if not code16 else (1 if (plain or v32) else 2)
+    prods = 3 * n16 + 10 * len(v32)
+    vec_frac = prods / 6.0
+    ops = int(ncmp * (OPS_PER_CMP_PARTY // 2 if galois else OPS_PER_CMP_PARTY) * vec_frac)
     achieved = ops / dot_avg_s / 1e12
-    traffic = None if galois else dot_traffic(w.rows, w.n_db, args.dot_tiles)
-    entry_bytes = DB_BYTES_PER_ENTRY_PARTY // 2 if galois else DB_BYTES_PER_ENTRY_PARTY
+    traffic = None if (galois or plain or v32) else dot_traffic(w.rows, w.n_db, args.dot_tiles)
+    entry_bytes = int((DB_BYTES_PER_ENTRY_PARTY // 2 if galois else DB_BYTES_PER_ENTRY_PARTY) * (n16 + 2 * len(v32)) / 2)
     alg_bytes = w.n_db * entry_bytes + 2 * 2 * w.rows * w.n_db   # DB region read + u16 outputs
     res = {
         "metric": "shared iris comparisons/sec on 1 MI355X (bit-exact); p50/p99 query latency",
@@ -218,8 +286,13 @@ def run_full(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
         "config": {"workload": f"3-party protocol on one GPU: DB {w.n_db} entries per party, {w.n_q} queries x "
                                f"{len(w.rot)} rotations ({w.rows} rows)"
-                               + (", dot products on Galois-ring Shamir shares" if galois else ""),
-                   "rows": w.rows, "db_entries": w.n_db, "parties": 3, "sharing": args.scheme},
+                               + (", dot products on Galois-ring Shamir shares" if galois else "")
+                               + {"mpclift": "", "lift18": ", ml lifted to Z_2^18 only",
+                                  "plain": ", masks in plain (public ml, code dot only)",
+                                  "constlift": ", ml by a dot product over Z_2^32 (ConstLift)",
+                                  "nolift": ", both dot products over Z_2^32 (NoLift)"}[args.compare],
+                   "rows": w.rows, "db_entries": w.n_db, "parties": 3, "sharing": args.scheme,
+                   "comparison": args.compare},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                        "note": "one batch of all queries per step; per-query latency = step latency"},
         "roofline": {"bound": "mfma", "kernel": "dot_shares (one party, i8 MFMA over byte limbs)",
@@ -231,6 +304,88 @@ def run_full(args):
         "verification": ver,
     }
     return res, (w, qc, qm)
+
+
+# AND gates and bits sent by party 0 per comparison, per setting (Sec. 6.2).
+COMPARE_COUNTS = {"mpclift": (94, 156), "lift18": (66, 72), "plain": (29, 29), "constlift": (61, 61),
+                  "nolift": (61, 61)}
+
+
+def run_compare(args):
+    """The comparison settings side by side (Sec. 6.2, Table 3): each setting's
+    comparison kernel over the same rows x entries of replicated components
+    resident in HBM, then the OR-tree over one setting's output.  Component
+    values are random (the kernels' work does not depend on them; their
+    results are checked against the oracle by the test-suite)."""
+    import torch
+
+    import paper_2405_04463_amd as imc
+
+    dealer, party = keys()
+    rot = list(range(-15, 16))
+    q, n = args.n_q, args.n_db
+    rows = q * len(rot)
+    ld = ((n + 63) // 64) * 64
+    nw = ld // 64
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=rows)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+
+    def rnd(dtype, lo, hi, shape):
+        return torch.randint(lo, hi, shape, dtype=dtype, device="cuda", generator=g)
+
+    log(f"components for {rows} rows x {n} entries")
+    code = [rnd(torch.int16, -32768, 32768, (2, rows, ld)) for _ in range(3)]
+    mask = [rnd(torch.int16, -32768, 32768, (2, rows, ld)) for _ in range(3)]
+    code32 = [rnd(torch.int32, -2**31, 2**31 - 1, (2, rows, ld)) for _ in range(3)]
+    mask32 = [rnd(torch.int32, -2**31, 2**31 - 1, (2, rows, ld)) for _ in range(3)]
+    ml_pub = rnd(torch.int16, 0, 12801, (rows, ld))
+    match = [torch.empty(2, rows, nw, dtype=torch.int64, device="cuda") for _ in range(3)]
+    dup = [torch.empty(2, q, dtype=torch.uint8, device="cuda") for _ in range(3)]
+    ws = torch.empty(max(8, imc.or_tree_ws_bytes(q, len(rot), nw)), dtype=torch.uint8, device="cuda")
+    ids = imc.make_ids(0, rot, 0)
+    stream = torch.cuda.current_stream()
+    calls = {
+        "mpclift": lambda: ctx.compare_threshold(code, mask, rows, n, ld, ids, match, nw, stream),
+        "lift18": lambda: ctx.compare_variant(imc.CMP_LIFT18, code, 16, mask, None, rows, n, ld, ids, match, nw,
+                                              stream),
+        "plain": lambda: ctx.compare_variant(imc.CMP_PLAIN_MASK, code, 16, None, ml_pub, rows, n, ld, ids, match, nw,
+                                             stream),
+        "constlift": lambda: ctx.compare_variant(imc.CMP_CONST32, code, 16, mask32, None, rows, n, ld, ids, match,
+                                                 nw, stream),
+        "nolift": lambda: ctx.compare_variant(imc.CMP_CONST32, code32, 32, mask32, None, rows, n, ld, ids, match,
+                                              nw, stream),
+        "or_tree": lambda: ctx.or_tree(match, q, nw, nw, ids, ws, ws.numel(), dup, stream),
+    }
+    out = {}
+    ncmp = rows * n
+    for name, fn in calls.items():
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        out[name] = {"ms": ms, "elements_per_s": ncmp / (ms / 1e3)}
+        if name in COMPARE_COUNTS:
+            ands, bits = COMPARE_COUNTS[name]
+            out[name].update(and_gates=ands, bits_sent_party0=bits, kb_per_party_per_100k=bits * 100_000 / 8e3)
+        log(f"{name}: {ms:.3f} ms per call, {ncmp / (ms / 1e3):.3e} elements/s")
+    res = {
+        "metric": "shared iris comparisons/sec on 1 MI355X (bit-exact); p50/p99 query latency",
+        "value": out["mpclift"]["elements_per_s"], "unit": "comparisons/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": out["mpclift"]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
+        "config": {"workload": f"comparison kernels alone (3 parties on one GPU): {q} queries x {len(rot)} "
+                               f"rotations ({rows} rows) x {n} entries of reshared components per call",
+                   "rows": rows, "db_entries": n},
+        "settings": out,
+    }
+    return res, (None, None, None)
 
 
 def run_party(args):
@@ -439,7 +594,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["full", "party", "batched", "serve", "copy-probe"], default="full")
+    ap.add_argument("--workload", choices=["full", "party", "batched", "serve", "compare", "copy-probe"],
+                    default="full")
     ap.add_argument("--n-batches", type=int, default=200)
     ap.add_argument("--chunk", type=int, default=65536)
     ap.add_argument("--slots", type=int, default=64)
@@ -451,6 +607,8 @@ def main():
     ap.add_argument("--dot-tiles", type=int, default=0, help="dot kernel tile configuration (IMC_DOT_TILES_*)")
     ap.add_argument("--scheme", choices=["replicated", "galois"], default="replicated",
                     help="sharing of the dot-product operands (full, batched and serve workloads)")
+    ap.add_argument("--compare", choices=["mpclift", "lift18", "plain", "constlift", "nolift"], default="mpclift",
+                    help="comparison setting of the full workload (Sec. 6.2)")
     args = ap.parse_args()
     if args.workload == "copy-probe":
         run_copy_probe(args)
@@ -470,12 +628,18 @@ def main():
     elif args.workload == "batched":
         args.n_db = args.n_db or 1_000_000
         res, (w, qc, qm) = run_batched(args)
+    elif args.workload == "compare":
+        args.n_db = args.n_db or 300_000
+        args.n_q = args.n_q or 64
+        res, (w, qc, qm) = run_compare(args)
     else:
         args.n_db = args.n_db or 600_000
         res, (w, qc, qm) = run_serve(args)
     if not args.no_cpu_baseline and w is not None:
         log("timing the oracle on a bounded sample")
-        res["cpu_baseline"] = cpu_baseline(w, qc, qm, galois=args.workload == "full" and args.scheme == "galois")
+        full = args.workload == "full"
+        res["cpu_baseline"] = cpu_baseline(w, qc, qm, galois=full and args.scheme == "galois",
+                                           compare=args.compare if full else "mpclift")
     print(json.dumps(res), flush=True)
 
 

@@ -399,6 +399,59 @@ imc_status imc_galois_dot_shares_rows(imc_ctx* ctx, int party, const void* qop, 
 imc_status imc_galois_append_db(imc_ctx* ctx, const void* const qraw[3], size_t qi, void* const db[3],
                                 size_t db_capacity, uint64_t entry_id, imc_stream stream);
 
+/* ---------------------------------------------------------------------------
+ * Dot products over Z_2^32 (Sec. 5.1, "Lifting vs. Larger Dot-Product"): the
+ * ConstLift setting computes ml in the larger ring (no Lift in MPC), NoLift
+ * also the code dot; the comparison is then imc_compare_variant with
+ * IMC_CMP_CONST32.  One vector (vec 0 = masked code bits, 1 = mask bits) per
+ * region and operand.  A Z_2^32 value is stored as four balanced byte limbs
+ * v = b0 + 2^8 b1 + 2^16 b2 + 2^24 b3 (b_i signed bytes); a dot product takes
+ * the 10 limb products with i + j <= 3 (Sec. 6.1), accumulated exactly in
+ * i32 and combined mod 2^32.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of one party's Z_2^32 region of one vector for `capacity` entries
+ * (blocks of 32: [limb 4][k-chunk 1600][slot 32][16 B], k < 12800 holding
+ * x_p and k >= 12800 holding x_{p-1}; 102,400 B per entry), and of one
+ * party's Z_2^32 query operand of one vector for q queries ([q][limb 4][25600],
+ * k < 12800 holding x_p + x_{p-1}, k >= 12800 holding x_p). */
+size_t imc_db32_bytes(size_t capacity);
+size_t imc_query32_op_bytes(size_t q);
+
+/* Dealer sharing over Z_2^32 of vector vec of entries first_entry_id ..
+ * first_entry_id + n - 1 (codes, masks: device u64 [n][200]): x_0, x_1 from
+ * the dealer's PRF (ChaCha12, its own domain, keyed by vector, component and
+ * entry id; one block per 16 elements), x_2 = x - x_0 - x_1.  db[p]: region of
+ * imc_db32_bytes(db_capacity) bytes (alignment 256), NULL when not held.
+ * Errors: IMC_EINVAL (vec, null, unaligned), IMC_ESHAPE (first+n > capacity). */
+imc_status imc_share32_db(imc_ctx* ctx, int vec, const uint64_t* codes, const uint64_t* masks, size_t n,
+                          uint64_t first_entry_id, void* const db[3], size_t db_capacity, imc_stream stream);
+
+/* Query sharing over Z_2^32 of vector vec (own PRF domain, keyed by query
+ * id): qop[p] receives party p's operand of imc_query32_op_bytes(q) bytes
+ * (alignment 16).  Errors: IMC_EINVAL. */
+imc_status imc_share32_query(imc_ctx* ctx, int vec, const uint64_t* codes, const uint64_t* masks, size_t q,
+                             uint64_t query_id_base, void* const qop[3], imc_stream stream);
+
+/* Party-local dot products over Z_2^32 of one vector: for every row (query
+ * qi at rotation rot[ri]) and entry e,
+ *   dot = sum_k (x_p + x_{p-1})_k y_{p,k} + (x_p)_k y_{p-1,k}  mod 2^32,
+ * party p's additive share (before re-randomisation).  qop, db: party p's
+ * operand and region of the same vector; dot: device u32 [q*ids->r][ld].
+ * Errors: IMC_EINVAL (party, rotations, first_entry_id % 64, null,
+ * unaligned), IMC_ESHAPE (ld < n, first+n > capacity). */
+imc_status imc_dot32_shares(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_ids* ids, const void* db,
+                            size_t db_capacity, size_t n, uint32_t* dot, size_t ld, imc_stream stream);
+
+/* Resharing over Z_2^32 of one vector (App. C): party p adds F(key_p) -
+ * F(key_{p-1}) (ChaCha12 at (query id, rotation), block entry/8, word
+ * 2 (entry % 8) + vec) and sends the result to party p+1.  add[p]: u32
+ * [rows][ld] additive shares; msg[p]: device u32 [rows][ld] (party p's
+ * message); rep[p]: device u32 [2][rows][ld] (own share, the one received
+ * from party p-1).  Errors as imc_reshare, IMC_EINVAL for vec. */
+imc_status imc_reshare32(imc_ctx* ctx, int vec, const uint32_t* const add[3], size_t rows, size_t n, size_t ld,
+                         const imc_ids* ids, uint32_t* const msg[3], uint32_t* const rep[3], imc_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,8 @@ EXPORTS = [
     "imc_set_dot_tiles", "imc_galois_db_bytes", "imc_galois_query_op_bytes", "imc_galois_query_raw_bytes",
     "imc_galois_share_db", "imc_galois_share_query", "imc_galois_dot_shares", "imc_galois_dot_shares_rows",
     "imc_galois_append_db", "imc_mask_in_batch", "imc_or_bits", "imc_dot_shares_gather",
-    "imc_galois_dot_shares_gather", "imc_compare_variant", "imc_rotate_masks", "imc_plain_ml",
+    "imc_galois_dot_shares_gather", "imc_compare_variant", "imc_rotate_masks", "imc_plain_ml", "imc_db32_bytes",
+    "imc_query32_op_bytes", "imc_share32_db", "imc_share32_query", "imc_dot32_shares", "imc_reshare32",
 ]
 
 (DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW, DOT_TILES_ROTATION,
@@ -85,7 +86,7 @@ def lib():
         L.imc_strerror.argtypes = [st]
         L.imc_strerror.restype = ctypes.c_char_p
         for f in ("imc_db_bytes", "imc_query_op_bytes", "imc_query_raw_bytes", "imc_galois_db_bytes",
-                  "imc_galois_query_op_bytes", "imc_galois_query_raw_bytes"):
+                  "imc_galois_query_op_bytes", "imc_galois_query_raw_bytes", "imc_db32_bytes", "imc_query32_op_bytes"):
             getattr(L, f).argtypes = [sz]
             getattr(L, f).restype = sz
         L.imc_or_tree_ws_bytes.argtypes = [sz, sz, sz]
@@ -115,6 +116,10 @@ def lib():
                                           ctypes.POINTER(imc_ids), _P3, sz, _VP]
         L.imc_rotate_masks.argtypes = [_VP, _VP, sz, ctypes.POINTER(imc_ids), _VP, _VP]
         L.imc_plain_ml.argtypes = [_VP, _VP, sz, _VP, sz, _VP, sz, _VP]
+        L.imc_share32_db.argtypes = [_VP, ctypes.c_int, _VP, _VP, sz, ctypes.c_uint64, _P3, sz, _VP]
+        L.imc_share32_query.argtypes = [_VP, ctypes.c_int, _VP, _VP, sz, ctypes.c_uint64, _P3, _VP]
+        L.imc_dot32_shares.argtypes = [_VP, ctypes.c_int, _VP, sz, ctypes.POINTER(imc_ids), _VP, sz, sz, _VP, sz, _VP]
+        L.imc_reshare32.argtypes = [_VP, ctypes.c_int, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _P3, _P3, _VP]
         for f in EXPORTS:
             if f not in ("imc_destroy", "imc_strerror") and not f.endswith("_bytes"):
                 getattr(L, f).restype = st
@@ -191,6 +196,14 @@ def galois_query_op_bytes(q: int) -> int:
 
 def galois_query_raw_bytes(q: int) -> int:
     return lib().imc_galois_query_raw_bytes(q)
+
+
+def db32_bytes(capacity: int) -> int:
+    return lib().imc_db32_bytes(capacity)
+
+
+def query32_op_bytes(q: int) -> int:
+    return lib().imc_query32_op_bytes(q)
 
 
 def or_tree_ws_bytes(q: int, r: int, nw: int) -> int:
@@ -288,6 +301,23 @@ class Context:
         return _check(lib().imc_compare_variant(self._h, variant, _p3(rep_code3), code_bits, rm, addr(ml_pub), rows,
                                                 n, ld, ctypes.byref(ids), _p3(match3), mw_ld, _stream(stream)),
                       "imc_compare_variant")
+
+    # -- Z_2^32 sharing, dot products and resharing of one vector (vec 0 code, 1 mask)
+    def share32_db(self, vec, codes, masks, n, first_entry_id, db3, capacity, stream=None):
+        return _check(lib().imc_share32_db(self._h, vec, addr(codes), addr(masks), n, first_entry_id, _p3(db3),
+                                           capacity, _stream(stream)), "imc_share32_db")
+
+    def share32_query(self, vec, codes, masks, q, query_id_base, qop3, stream=None):
+        return _check(lib().imc_share32_query(self._h, vec, addr(codes), addr(masks), q, query_id_base, _p3(qop3),
+                                              _stream(stream)), "imc_share32_query")
+
+    def dot32_shares(self, party, qop, q, ids: imc_ids, db, capacity, n, dot, ld, stream=None):
+        return _check(lib().imc_dot32_shares(self._h, party, addr(qop), q, ctypes.byref(ids), addr(db), capacity, n,
+                                             addr(dot), ld, _stream(stream)), "imc_dot32_shares")
+
+    def reshare32(self, vec, add3, rows, n, ld, ids: imc_ids, msg3, rep3, stream=None):
+        return _check(lib().imc_reshare32(self._h, vec, _p3(add3), rows, n, ld, ctypes.byref(ids), _p3(msg3),
+                                          _p3(rep3), _stream(stream)), "imc_reshare32")
 
     # -- imc_rotate_masks / imc_plain_ml (masks in plain)
     def rotate_masks(self, masks, q, ids: imc_ids, out, stream=None):

@@ -91,6 +91,8 @@ size_t imc_galois_db_bytes(size_t capacity) { return blocks_for(capacity) * imc:
 size_t imc_galois_query_op_bytes(size_t q) { return q * imc::Geo<imc::kKGalois>::kQopRowBytes; }
 size_t imc_galois_query_raw_bytes(size_t q) { return q * 2 * imc::kCodeBits * sizeof(uint16_t); }
 size_t imc_or_tree_ws_bytes(size_t q, size_t r, size_t nw) { return imc::or_tree_ws_bytes(q, r, nw); }
+size_t imc_db32_bytes(size_t capacity) { return imc::db32_bytes(capacity); }
+size_t imc_query32_op_bytes(size_t q) { return imc::query32_op_bytes(q); }
 
 imc_status imc_create(const imc_params* p, int device, imc_ctx** out) {
   if (!p || !out) return IMC_EINVAL;
@@ -441,6 +443,75 @@ imc_status imc_plain_ml(imc_ctx* c, const uint64_t* row_masks, size_t rows, cons
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;
   return dev_status(imc::launch_plain_ml(row_masks, rows, db_masks, n, ml, ld, hipStream_t(stream)));
+}
+
+imc_status imc_share32_db(imc_ctx* c, int vec, const uint64_t* codes, const uint64_t* masks, size_t n,
+                          uint64_t first, void* const db[3], size_t capacity, imc_stream stream) {
+  if (!c || !db || (vec != 0 && vec != 1)) return IMC_EINVAL;
+  if (n && (!codes || !masks)) return IMC_EINVAL;
+  int held = 0;
+  for (int p = 0; p < 3; ++p) {
+    if (db[p] && !aligned(db[p], 256)) return IMC_EINVAL;
+    held += db[p] != nullptr;
+  }
+  if (!held) return IMC_EINVAL;
+  if (!aligned(codes, 8) || !aligned(masks, 8)) return IMC_EINVAL;
+  if (first > capacity || n > capacity - first) return IMC_ESHAPE;
+  if (first + n > (1ull << 48)) return IMC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  uint8_t* d[3] = {static_cast<uint8_t*>(db[0]), static_cast<uint8_t*>(db[1]), static_cast<uint8_t*>(db[2])};
+  return dev_status(imc::launch_share32_db(c->dealer, vec, codes, masks, n, first, d, hipStream_t(stream)));
+}
+
+imc_status imc_share32_query(imc_ctx* c, int vec, const uint64_t* codes, const uint64_t* masks, size_t q,
+                             uint64_t qid_base, void* const qop[3], imc_stream stream) {
+  if (!c || !qop || (vec != 0 && vec != 1)) return IMC_EINVAL;
+  if (q && (!codes || !masks)) return IMC_EINVAL;
+  if (!aligned(codes, 8) || !aligned(masks, 8)) return IMC_EINVAL;
+  for (int p = 0; p < 3; ++p)
+    if (!qop[p] || !aligned(qop[p], 16)) return IMC_EINVAL;
+  if (qid_base + q > (1ull << 48)) return IMC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  int8_t* op[3] = {static_cast<int8_t*>(qop[0]), static_cast<int8_t*>(qop[1]), static_cast<int8_t*>(qop[2])};
+  return dev_status(imc::launch_share32_query(c->dealer, vec, codes, masks, q, qid_base, op, hipStream_t(stream)));
+}
+
+imc_status imc_dot32_shares(imc_ctx* c, int party, const void* qop, size_t q, const imc_ids* ids, const void* db,
+                            size_t capacity, size_t n, uint32_t* dot, size_t ld, imc_stream stream) {
+  if (!c || party < 0 || party > 2) return IMC_EINVAL;
+  imc_status st = check_ids(ids);
+  if (st != IMC_OK) return st;
+  const size_t rows = q * size_t(ids->r);
+  if (rows == 0 || n == 0) return IMC_OK;
+  if (!qop || !db || !dot) return IMC_EINVAL;
+  if (!aligned(qop, 16) || !aligned(db, 256) || !aligned(dot, 4)) return IMC_EINVAL;
+  if (rows > 0xFFFFFFFFull) return IMC_ESHAPE;
+  if (ld < n) return IMC_ESHAPE;
+  if (ids->first_entry_id > capacity || n > capacity - ids->first_entry_id) return IMC_ESHAPE;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  return dev_status(imc::launch_dot32(static_cast<const int8_t*>(qop), uint32_t(q), uint32_t(ids->r), ids->rot,
+                                      static_cast<const int8_t*>(db), ids->first_entry_id, n, dot, ld,
+                                      hipStream_t(stream)));
+}
+
+imc_status imc_reshare32(imc_ctx* c, int vec, const uint32_t* const add[3], size_t rows, size_t n, size_t ld,
+                         const imc_ids* ids, uint32_t* const msg[3], uint32_t* const rep[3], imc_stream stream) {
+  if (!c || !add || !msg || !rep || (vec != 0 && vec != 1)) return IMC_EINVAL;
+  imc_status st = check_ids(ids);
+  if (st != IMC_OK) return st;
+  if (rows % size_t(ids->r)) return IMC_ESHAPE;
+  if (ld < n) return IMC_ESHAPE;
+  if (rows == 0 || n == 0) return IMC_OK;
+  for (int p = 0; p < 3; ++p) {
+    if (!add[p] || !msg[p] || !rep[p]) return IMC_EINVAL;
+    if (!aligned(add[p], 4) || !aligned(msg[p], 4) || !aligned(rep[p], 4)) return IMC_EINVAL;
+  }
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  return dev_status(imc::launch_reshare32(c->party, vec, add, rows, n, ld, *ids, msg, rep, hipStream_t(stream)));
 }
 
 imc_status imc_or_tree(imc_ctx* c, const uint64_t* const match[3], size_t q, size_t nw, size_t mw_ld,

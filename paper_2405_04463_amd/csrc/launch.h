@@ -53,6 +53,17 @@ hipError_t launch_rotate_masks(const uint64_t* masks, uint64_t q, const imc_ids_
                                hipStream_t s);
 hipError_t launch_plain_ml(const uint64_t* row_masks, uint64_t rows, const uint64_t* db_masks, uint64_t n,
                            uint16_t* ml, uint64_t ld, hipStream_t s);
+hipError_t launch_share32_db(const Key& dk, int vec, const uint64_t* codes, const uint64_t* masks, uint64_t n,
+                             uint64_t first, uint8_t* const db[3], hipStream_t s);
+hipError_t launch_share32_query(const Key& dk, int vec, const uint64_t* codes, const uint64_t* masks, uint64_t q,
+                                uint64_t qid_base, int8_t* const op[3], hipStream_t s);
+hipError_t launch_dot32(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+                        uint64_t first_entry, uint64_t n, uint32_t* out, uint64_t ld, hipStream_t s);
+hipError_t launch_reshare32(const Keys3& keys, int vec, const uint32_t* const add[3], uint64_t rows, uint64_t n,
+                            uint64_t ld, const imc_ids_dev& ids, uint32_t* const msg[3], uint32_t* const rep[3],
+                            hipStream_t s);
+size_t db32_bytes(uint64_t capacity);
+size_t query32_op_bytes(uint64_t q);
 size_t or_tree_ws_bytes(uint64_t q, uint64_t r, uint64_t nw);
 hipError_t launch_or_tree(const Keys3& keys, const uint64_t* const match[3], uint64_t q, uint64_t nw, uint64_t mw_ld,
                           const imc_ids_dev& ids, void* ws, uint8_t* const dup[3], hipStream_t s);

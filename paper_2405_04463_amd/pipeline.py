@@ -5,8 +5,10 @@ Allocation and sequencing only; all arithmetic is in the library's kernels:
   compare_threshold -> or_tree -> open
 
 Comparison settings (Sec. 6.2): "mpclift" (default, Alg. 3 with ml lifted to
-Z_2^32), "lift18" (ml lifted to Z_2^18 only) and "plain" (Alg. 2: masks
-public, ml computed in plain by every party, only the code dot is shared).
+Z_2^32), "lift18" (ml lifted to Z_2^18 only), "plain" (Alg. 2: masks public,
+ml computed in plain by every party, only the code dot is shared),
+"constlift" (ml by a dot product over Z_2^32, no Lift) and "nolift" (both dot
+products over Z_2^32).
 """
 from __future__ import annotations
 
@@ -14,11 +16,12 @@ from dataclasses import dataclass
 
 import torch
 
-from . import (CMP_LIFT18, CMP_PLAIN_MASK, OPEN_U8_XOR, OPEN_U16_ADD, OPEN_U64_XOR, Context, db_bytes,
-               galois_db_bytes, galois_query_op_bytes, galois_query_raw_bytes, make_ids, or_tree_ws_bytes,
-               query_op_bytes, query_raw_bytes)
+from . import (CMP_CONST32, CMP_LIFT18, CMP_PLAIN_MASK, OPEN_U8_XOR, OPEN_U16_ADD, OPEN_U64_XOR, Context, db32_bytes,
+               db_bytes, galois_db_bytes, galois_query_op_bytes, galois_query_raw_bytes, make_ids, or_tree_ws_bytes,
+               query32_op_bytes, query_op_bytes, query_raw_bytes)
 
-COMPARE_SETTINGS = ("mpclift", "lift18", "plain")
+COMPARE_SETTINGS = ("mpclift", "lift18", "plain", "constlift", "nolift")
+VECS32 = {"constlift": (1,), "nolift": (0, 1)}   # vectors whose dot products run over Z_2^32
 
 ROW_BYTES = 102400
 
@@ -75,6 +78,35 @@ class SharedQueries:
         ctx.share_query(codes, masks, self.q, query_id_base, self.op, self.raw, stream, galois=galois)
 
 
+class SharedDB32:
+    """Z_2^32 regions of the given vectors (0 code, 1 mask) for the three
+    parties: regions[vec][p]."""
+
+    def __init__(self, ctx: Context, capacity: int, vecs=(1,), device=0):
+        self.ctx = ctx
+        self.capacity = capacity
+        self.vecs = tuple(vecs)
+        self.regions = {v: [torch.empty(db32_bytes(capacity), dtype=torch.uint8, device=_dev(device))
+                            for _ in range(3)] for v in self.vecs}
+
+    def enroll(self, codes, masks, first: int, stream=None):
+        for v in self.vecs:
+            self.ctx.share32_db(v, codes, masks, codes.shape[0], first, self.regions[v], self.capacity, stream)
+
+
+class SharedQueries32:
+    """Z_2^32 query operands of the given vectors: op[vec][p]."""
+
+    def __init__(self, ctx: Context, codes, masks, query_id_base: int, vecs=(1,), device=0, stream=None):
+        self.q = codes.shape[0]
+        self.qid_base = query_id_base
+        self.vecs = tuple(vecs)
+        self.op = {v: [torch.empty(max(16, query32_op_bytes(self.q)), dtype=torch.uint8, device=_dev(device))
+                       for _ in range(3)] for v in self.vecs}
+        for v in self.vecs:
+            ctx.share32_query(v, codes, masks, self.q, query_id_base, self.op[v], stream)
+
+
 @dataclass
 class CheckBuffers:
     rows: int
@@ -92,6 +124,9 @@ class CheckBuffers:
     compare: str = "mpclift"
     ml_pub: torch.Tensor | None = None       # "plain": public ml [rows, ld]
     row_masks: torch.Tensor | None = None    # "plain": rotated query masks [rows, 200]
+    dot32: dict | None = None                # Z_2^32 settings: vec -> 3 x u32 [rows, ld]
+    msg32: dict | None = None                # vec -> 3 x u32 [rows, ld]
+    rep32: dict | None = None                # vec -> 3 x u32 [2, rows, ld]
 
 
 def alloc_check(q: int, r: int, n: int, device=0, compare: str = "mpclift") -> CheckBuffers:
@@ -102,14 +137,21 @@ def alloc_check(q: int, r: int, n: int, device=0, compare: str = "mpclift") -> C
     ld = ((n + 63) // 64) * 64
     nw = ld // 64
     plain = compare == "plain"
+    v32 = VECS32.get(compare, ())
     u16 = lambda *s: torch.empty(*s, dtype=torch.int16, device=d)  # noqa: E731
+    u32 = lambda *s: torch.empty(*s, dtype=torch.int32, device=d)  # noqa: E731
+    code16 = 0 not in v32
+    mask16 = not plain and 1 not in v32
     return CheckBuffers(
         rows=rows, n=n, ld=ld, nw=nw,
-        dot_code=[u16(rows, ld) for _ in range(3)],
-        dot_mask=None if plain else [u16(rows, ld) for _ in range(3)],
-        msg=[u16(2, rows, ld) for _ in range(3)],
-        rep_code=[u16(2, rows, ld) for _ in range(3)],
-        rep_mask=None if plain else [u16(2, rows, ld) for _ in range(3)],
+        dot_code=[u16(rows, ld) for _ in range(3)] if code16 else None,
+        dot_mask=[u16(rows, ld) for _ in range(3)] if mask16 else None,
+        msg=[u16(2, rows, ld) for _ in range(3)] if code16 else None,
+        rep_code=[u16(2, rows, ld) for _ in range(3)] if code16 else None,
+        rep_mask=[u16(2, rows, ld) for _ in range(3)] if mask16 else None,
+        dot32={v: [u32(rows, ld) for _ in range(3)] for v in v32} if v32 else None,
+        msg32={v: [u32(rows, ld) for _ in range(3)] for v in v32} if v32 else None,
+        rep32={v: [u32(2, rows, ld) for _ in range(3)] for v in v32} if v32 else None,
         match=[torch.empty(2, rows, nw, dtype=torch.int64, device=d) for _ in range(3)],
         dup=[torch.empty(2, q, dtype=torch.uint8, device=d) for _ in range(3)],
         ws=torch.empty(max(8, or_tree_ws_bytes(q, r, nw)), dtype=torch.uint8, device=d),
@@ -120,22 +162,38 @@ def alloc_check(q: int, r: int, n: int, device=0, compare: str = "mpclift") -> C
 
 
 def run_check(ctx: Context, qs: SharedQueries, rot, db: SharedDB, first_entry: int, n: int, buf: CheckBuffers,
-              or_tree: bool = True, stream=None, query_masks=None, db_masks=None):
+              or_tree: bool = True, stream=None, query_masks=None, db_masks=None, qs32=None, db32=None):
     """Alg. 3 (Alg. 2 for buf.compare == "plain") for queries qs at rotations
     rot against entries first_entry..+n.  "plain" needs the public masks:
-    query_masks [q, 200] and db_masks [>= first_entry + n, 200] (device int64)."""
-    assert qs.galois == db.galois
-    ids = make_ids(qs.qid_base, rot, first_entry)
+    query_masks [q, 200] and db_masks [>= first_entry + n, 200] (device int64);
+    "constlift" / "nolift" the Z_2^32 operands and regions qs32, db32 of their
+    vectors (qs and db then serve the code dot of "constlift" only)."""
+    ids = make_ids(qs.qid_base if qs is not None else qs32.qid_base, rot, first_entry)
     plain = buf.compare == "plain"
-    for p in range(3):
-        ctx.dot_shares(p, qs.op[p], qs.q, ids, db.regions[p], db.capacity, n, buf.dot_code[p],
-                       None if plain else buf.dot_mask[p], buf.ld, stream, galois=db.galois)
+    if buf.dot_code is not None:
+        assert qs.galois == db.galois
+        for p in range(3):
+            ctx.dot_shares(p, qs.op[p], qs.q, ids, db.regions[p], db.capacity, n, buf.dot_code[p],
+                           buf.dot_mask[p] if buf.dot_mask is not None else None, buf.ld, stream, galois=db.galois)
+    if buf.dot32:
+        for v, outs in buf.dot32.items():
+            for p in range(3):
+                ctx.dot32_shares(p, qs32.op[v][p], qs32.q, ids, db32.regions[v][p], db32.capacity, n, outs[p],
+                                 buf.ld, stream)
     if plain:
         assert query_masks is not None and db_masks is not None and db_masks.shape[0] >= first_entry + n
         ctx.rotate_masks(query_masks, qs.q, ids, buf.row_masks, stream)
         ctx.plain_ml(buf.row_masks, buf.rows, db_masks[first_entry:], n, buf.ml_pub, buf.ld, stream)
-    ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, n, buf.ld, ids, buf.msg, buf.rep_code, buf.rep_mask, stream)
-    if plain:
+    if buf.dot_code is not None:
+        ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, n, buf.ld, ids, buf.msg, buf.rep_code, buf.rep_mask, stream)
+    if buf.dot32:
+        for v in buf.dot32:
+            ctx.reshare32(v, buf.dot32[v], buf.rows, n, buf.ld, ids, buf.msg32[v], buf.rep32[v], stream)
+    if buf.compare in VECS32:
+        code, bits = (buf.rep32[0], 32) if 0 in buf.rep32 else (buf.rep_code, 16)
+        ctx.compare_variant(CMP_CONST32, code, bits, buf.rep32[1], None, buf.rows, n, buf.ld, ids, buf.match, buf.nw,
+                            stream)
+    elif plain:
         ctx.compare_variant(CMP_PLAIN_MASK, buf.rep_code, 16, None, buf.ml_pub, buf.rows, n, buf.ld, ids, buf.match,
                             buf.nw, stream)
     elif buf.compare == "lift18":
@@ -145,7 +203,8 @@ def run_check(ctx: Context, qs: SharedQueries, rot, db: SharedDB, first_entry: i
         ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, n, buf.ld, ids, buf.match, buf.nw, stream)
     if or_tree:
         nw = (n + 63) // 64
-        ctx.or_tree(buf.match, qs.q, nw, buf.nw, ids, buf.ws, buf.ws.numel(), buf.dup, stream)
+        q = qs.q if qs is not None else qs32.q
+        ctx.or_tree(buf.match, q, nw, buf.nw, ids, buf.ws, buf.ws.numel(), buf.dup, stream)
     return ids
 
 

@@ -142,10 +142,89 @@ def test_plain_ml_matches_oracle(ctx, imc, q, rot, n, first):
     assert np.all(got[:, n:] == 0xFFFF)          # nothing written past n
 
 
-@pytest.mark.parametrize("setting", ["plain", "lift18"])
+# --------------------------------------------------------------------------
+# Z_2^32 sharing, dot products and resharing (ConstLift / NoLift)
+# --------------------------------------------------------------------------
+def _limbs32(planes: np.ndarray) -> np.ndarray:
+    """[4, K] signed byte limbs -> u32 values sum_l b_l 2^(8l) mod 2^32."""
+    v = np.zeros(planes.shape[1], dtype=np.uint64)
+    for l_ in range(4):
+        v += (planes[l_].astype(np.int64) % (1 << 32)).astype(np.uint64) << np.uint64(8 * l_)
+    return (v % (1 << 32)).astype(np.uint32)
+
+
+@pytest.mark.parametrize("vec", [0, 1])
+def test_share32_layouts(ctx, imc, keys, vec):
+    dealer, _ = keys
+    n, first, cap, q = 40, 3, 64, 2
+    dc, dm = wl.gen_codes(71, first, n)
+    qc, qm = wl.gen_codes(71, 0, q, query=True)
+    ref = orc.share32(dealer, orc.DOM_SHARE32_DB, dc, dm, first)
+    qref = orc.share32(dealer, orc.DOM_SHARE32_QUERY, qc, qm, 30)
+    regions = [torch.zeros(imc.db32_bytes(cap), dtype=torch.uint8, device="cuda") for _ in range(3)]
+    ops = [torch.zeros(imc.query32_op_bytes(q), dtype=torch.uint8, device="cuda") for _ in range(3)]
+    ctx.share32_db(vec, dev64(dc), dev64(dm), n, first, regions, cap)
+    ctx.share32_query(vec, dev64(qc), dev64(qm), q, 30, ops)
+    torch.cuda.synchronize()
+    for p in range(3):
+        pm = (p + 2) % 3
+        h = regions[p].cpu().numpy()
+        for j in (0, 1, 28, 29, 39):
+            e = first + j
+            blk = h[(e // 32) * 3276800:(e // 32 + 1) * 3276800].reshape(4, 1600, 32, 16)
+            v = _limbs32(blk[:, :, e % 32, :].reshape(4, 25600).view(np.int8))
+            assert np.array_equal(v[:12800], ref[j, vec, p]) and np.array_equal(v[12800:], ref[j, vec, pm])
+        o = ops[p].cpu().numpy()
+        for qi in range(q):
+            v = _limbs32(o[qi * 102400:(qi + 1) * 102400].view(np.int8).reshape(4, 25600))
+            assert np.array_equal(v[:12800], qref[qi, vec, p] + qref[qi, vec, pm])
+            assert np.array_equal(v[12800:], qref[qi, vec, p])
+
+
+@pytest.mark.parametrize("q,rot,n,first", [
+    (3, list(range(-15, 16)), 130, 64),     # 93 rows: one row tile, ragged; three entry tiles, ragged
+    (5, [-3, 0, 9], 64, 0),                 # one entry tile exactly
+    (1, [7], 1, 0),                         # a single comparison
+])
+def test_dot32_and_reshare32_match_oracle(ctx, imc, keys, q, rot, n, first):
+    dealer, party = keys
+    dc, dm = wl.gen_codes(72, first, n)
+    qc, qm = wl.gen_codes(72, 0, q, query=True)
+    dsh = orc.share32(dealer, orc.DOM_SHARE32_DB, dc, dm, first)
+    qsh = orc.share32(dealer, orc.DOM_SHARE32_QUERY, qc, qm, 50)
+    rows, ld = q * len(rot), ((n + 63) // 64) * 64 + 4
+    ids = imc.make_ids(50, rot, first)
+    z = [orc.local_dot32(p, qsh, rot, dsh) for p in range(3)]
+    for vec in (0, 1):
+        regions = [torch.empty(imc.db32_bytes(first + n), dtype=torch.uint8, device="cuda") for _ in range(3)]
+        ops = [torch.empty(imc.query32_op_bytes(q), dtype=torch.uint8, device="cuda") for _ in range(3)]
+        ctx.share32_db(vec, dev64(dc), dev64(dm), n, first, regions, first + n)
+        ctx.share32_query(vec, dev64(qc), dev64(qm), q, 50, ops)
+        dots = [torch.full((rows, ld), -1, dtype=torch.int32, device="cuda") for _ in range(3)]
+        for p in range(3):
+            ctx.dot32_shares(p, ops[p], q, ids, regions[p], first + n, n, dots[p], ld)
+        msg = [torch.empty(rows, ld, dtype=torch.int32, device="cuda") for _ in range(3)]
+        rep = [torch.empty(2, rows, ld, dtype=torch.int32, device="cuda") for _ in range(3)]
+        ctx.reshare32(vec, dots, rows, n, ld, ids, msg, rep)
+        torch.cuda.synchronize()
+        zs = np.stack([z[p][vec] for p in range(3)])
+        rc, rm = orc.reshare32(party, zs if vec == 0 else None, zs if vec == 1 else None, q, rot, 50, first)
+        want = rc if vec == 0 else rm
+        for p in range(3):
+            pm = (p + 2) % 3
+            got = dots[p].cpu().numpy().view(np.uint32)
+            assert np.array_equal(got[:, :n], z[p][vec]), (vec, p)
+            assert np.all(got[:, n:] == 0xFFFFFFFF)
+            r_ = rep[p].cpu().numpy().view(np.uint32)
+            assert np.array_equal(r_[0, :, :n], want[p]) and np.array_equal(r_[1, :, :n], want[pm])
+            assert np.array_equal(msg[p].cpu().numpy().view(np.uint32)[:, :n], want[p])
+
+
+@pytest.mark.parametrize("setting", ["plain", "lift18", "constlift", "nolift"])
 def test_protocol_setting_matches_oracle(ctx, imc, keys, setting):
     """Every step on the GPU vs the oracle's protocol run in the same setting."""
-    from paper_2405_04463_amd.pipeline import SharedDB, SharedQueries, alloc_check, open_dup, open_match, run_check
+    from paper_2405_04463_amd.pipeline import (VECS32, SharedDB, SharedDB32, SharedQueries, SharedQueries32,
+                                               alloc_check, open_dup, open_match, run_check)
 
     dealer, party = keys
     n, q, rot, first = 200, 4, [-2, 0, 1, 5, 15], 64
@@ -160,7 +239,12 @@ def test_protocol_setting_matches_oracle(ctx, imc, keys, setting):
     buf = alloc_check(q, len(rot), n, compare=setting)
     db_masks = torch.zeros(first + n, 200, dtype=torch.int64, device="cuda")
     db_masks[first:] = dev64(dm)
-    run_check(ctx, qs, rot, db, first, n, buf, query_masks=dev64(qm), db_masks=db_masks)
+    qs32 = db32 = None
+    if setting in VECS32:
+        db32 = SharedDB32(ctx, first + n, vecs=VECS32[setting])
+        db32.enroll(dev64(dc), dev64(dm), first)
+        qs32 = SharedQueries32(ctx, dev64(qc), dev64(qm), 100, vecs=VECS32[setting])
+    run_check(ctx, qs, rot, db, first, n, buf, query_masks=dev64(qm), db_masks=db_masks, qs32=qs32, db32=db32)
     torch.cuda.synchronize()
 
     ref = orc.protocol(dealer, party, qc, qm, rot, dc, dm, qid_base=100, first_entry=first, compare_setting=setting)
@@ -170,10 +254,17 @@ def test_protocol_setting_matches_oracle(ctx, imc, keys, setting):
         assert np.array_equal(u16(buf.ml_pub)[:, :n], ml.astype(np.uint16))
     for p in range(3):
         pm = (p + 2) % 3
-        assert np.array_equal(u16(buf.rep_code[p])[0, :, :n], ref["rep_code"][p])
-        assert np.array_equal(u16(buf.rep_code[p])[1, :, :n], ref["rep_code"][pm])
-        if setting != "plain":
+        if setting != "nolift":
+            assert np.array_equal(u16(buf.rep_code[p])[0, :, :n], ref["rep_code"][p])
+            assert np.array_equal(u16(buf.rep_code[p])[1, :, :n], ref["rep_code"][pm])
+        if setting in ("mpclift", "lift18"):
             assert np.array_equal(u16(buf.rep_mask[p])[0, :, :n], ref["rep_mask"][p])
+        if setting in VECS32:
+            u32 = lambda t: t.cpu().numpy().view(np.uint32)  # noqa: E731
+            assert np.array_equal(u32(buf.rep32[1][p])[0, :, :n], ref["rep_mask32"][p])
+            assert np.array_equal(u32(buf.rep32[1][p])[1, :, :n], ref["rep_mask32"][pm])
+            if setting == "nolift":
+                assert np.array_equal(u32(buf.rep32[0][p])[0, :, :n], ref["rep_code32"][p])
         mh = buf.match[p].cpu().numpy().view(np.uint64)
         assert np.array_equal(mh[0, :, :nw], ref["match"][p]), f"match component {p}"
         assert np.array_equal(mh[1, :, :nw], ref["match"][pm])
