@@ -35,11 +35,11 @@ MFMA_I8_PEAK_TOPS = 5000.0      # MI355X dense int8, tera-ops/s (MAC = 2 ops)
 # WRITE_SIZE 1,048,580 KiB).  Valid only for the kernel sources it was taken on.
 DOT_TRAFFIC = {
     "sources": {"paper_2405_04463_amd/csrc/rot_dot.hip":
-                "8484bb95adf9305c1adba6300296d7761aa7d5e110e6159ffcb7fc53471c28e5",
+                "dbcce0661bcae6c9bef82f92052fe60ef3dac4f917e79de81f067770f188d2c3",
                 "paper_2405_04463_amd/csrc/device.h":
-                "01f9dd36d63565b5c861295fe075b1a5243fe589572217901aa318eb708a8a23"},
+                "8466481bb20ff366ed4d2cc1aee48cbc2f6e6a279bf900a6911792115338410d"},
     "rows": 1984, "n_db": 300_000,
-    "fetch_kib": 16_902_200.0, "write_kib": 2_329_190.0,
+    "fetch_kib": 16_902_800.0, "write_kib": 2_328_620.0,
     "fetch_scale": 1_048_576 / 524_302.0, "write_scale": 1_048_576 / 1_048_580.0,
 }
 
@@ -501,7 +501,11 @@ def run_batched(args):
 
 def run_serve(args):
     """Poisson arrivals into the continuous-batching service (3 parties on one
-    GPU, database resident, uniques appended) vs the plain per-query path."""
+    GPU, database resident, uniques appended) vs the plain per-query path.
+    With --party-local: one party's share of the service (its region of a
+    database growing from n_db towards 2,000,000 entries, its dot products),
+    the uniqueness decision for appends taken from the workload's planted
+    flags (the interactive part needs the other parties' GPUs)."""
     import torch
 
     import paper_2405_04463_amd as imc
@@ -513,12 +517,16 @@ def run_serve(args):
     rot = wl.ROT31
     ctx = imc.Context(imc.Keys(dealer, party), max_rows=args.slots * len(rot))
     galois = args.scheme == "galois"
-    cap = args.n_db + 20000
-    db = SharedDB(ctx, cap, galois=galois)
+    local = args.party_local
+    cap = max(2_000_000, args.n_db) if local else args.n_db + 20000
+    parties = (0,) if local else (0, 1, 2)
+    db = SharedDB(ctx, cap, galois=galois, parties=parties)
     nbytes = imc.galois_db_bytes(cap) if galois else imc.db_bytes(cap)
-    log(f"enrolling {args.n_db} entries x 3 parties ({3 * nbytes / 1e9:.1f} GB reserved, {args.scheme} shares)")
+    log(f"enrolling {args.n_db} entries x {len(parties)} part{'y' if local else 'ies'} "
+        f"({len(parties) * nbytes / 1e9:.1f} GB reserved, {args.scheme} shares)")
     enroll_db(ctx, db, 0x1A150005, args.n_db)
     db.n = args.n_db
+    planted_qids = set()
     rng = np.random.default_rng(5)
     out = {"lambda": {}}
     qid = 0
@@ -531,9 +539,11 @@ def run_serve(args):
                 e = int(rng.integers(0, args.n_db))
                 ec, em = wl.gen_codes(0x1A150005, e, 1)
                 qc[i], qm[i] = wl.plant(0x1A150005, qid + i, ec[0], em[0], int(rng.integers(-15, 16)), h=0.2)
+                planted_qids.add(qid + i)
         reqs = [Request(rid=i, qid=qid + i, code=qc[i], mask=qm[i], arrival=float(arr[i])) for i in range(n_req)]
         qid += n_req
-        srv = Server(ctx, db, rot, chunk=args.chunk, slots=args.slots)
+        decide = (lambda r: int(r.qid in planted_qids)) if local else None
+        srv = Server(ctx, db, rot, chunk=args.chunk, slots=args.slots, decide=decide)
         n0 = db.n
         log(f"serving lambda={lam}/s: {n_req} requests over {args.duration:.1f} s, DB {n0} entries")
         t0 = time.perf_counter()
@@ -554,7 +564,10 @@ def run_serve(args):
     ts = []
     for i in range(4):
         t0 = time.perf_counter()
-        plain_check(ctx, db, Request(rid=i, qid=qid + i, code=qc[i], mask=qm[i]), rot, cache)
+        if local:
+            plain_local_check(ctx, db, qc[i:i + 1], qm[i:i + 1], qid + i, rot, cache)
+        else:
+            plain_check(ctx, db, Request(rid=i, qid=qid + i, code=qc[i], mask=qm[i]), rot, cache)
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
     t_plain = float(np.median(ts[1:]))
@@ -567,12 +580,38 @@ def run_serve(args):
         "value": best, "unit": "comparisons/s", "n_gpus": 1, "steps": len(args.rates), "warmup": 0,
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16",
         "data": "synthetic",
-        "config": {"workload": f"continuous-batching service, 3 parties on one GPU, DB {args.n_db} entries per party "
-                               f"(+ appends), 31 rotations, Poisson arrivals {args.rates}/s for {args.duration} s",
-                   "chunk": args.chunk, "slots": args.slots, "sharing": args.scheme},
+        "config": {"workload": (f"continuous-batching service, party 0's share (its dot products) of a DB of "
+                                f"{args.n_db} entries (+ appends, capacity {cap}), appends decided by the planted "
+                                f"flags" if local else
+                                f"continuous-batching service, 3 parties on one GPU, DB {args.n_db} entries per party "
+                                f"(+ appends)") + f", 31 rotations, Poisson arrivals {args.rates}/s for "
+                                                  f"{args.duration} s",
+                   "chunk": args.chunk, "slots": args.slots, "sharing": args.scheme,
+                   "parties": len(parties)},
         "latency_ms": {"p50": out["lambda"][top]["p50_ms"], "p99": out["lambda"][top]["p99_ms"], "at_lambda": top},
         "serve": out,
     }, (None, None, None)
+
+
+def plain_local_check(ctx, db, qc, qm, qid, rot, cache):
+    """Party 0's plain per-query work: one query's dot products over the whole
+    database in one launch (no batching)."""
+    import torch
+
+    import paper_2405_04463_amd as imc
+    from paper_2405_04463_amd.pipeline import SharedQueries
+
+    n = db.n
+    ld = ((n + 63) // 64) * 64
+    if cache.get("ld") != ld:
+        cache.clear()
+        cache["ld"] = ld
+        cache["out"] = [torch.empty(len(rot), ld, dtype=torch.int16, device="cuda") for _ in range(2)]
+    qs = SharedQueries(ctx, torch.from_numpy(qc.view(np.int64)).cuda(), torch.from_numpy(qm.view(np.int64)).cuda(),
+                       qid, galois=db.galois)
+    ids = imc.make_ids(qid, rot, 0)
+    ctx.dot_shares(0, qs.op[0], 1, ids, db.regions[0], db.capacity, n, cache["out"][0], cache["out"][1], ld,
+                   galois=db.galois)
 
 
 def run_copy_probe(args):
@@ -607,6 +646,8 @@ def main():
     ap.add_argument("--dot-tiles", type=int, default=0, help="dot kernel tile configuration (IMC_DOT_TILES_*)")
     ap.add_argument("--scheme", choices=["replicated", "galois"], default="replicated",
                     help="sharing of the dot-product operands (full, batched and serve workloads)")
+    ap.add_argument("--party-local", action="store_true",
+                    help="serve workload: one party's share of the service (its DB region and dot products)")
     ap.add_argument("--compare", choices=["mpclift", "lift18", "plain", "constlift", "nolift"], default="mpclift",
                     help="comparison setting of the full workload (Sec. 6.2)")
     args = ap.parse_args()
@@ -633,7 +674,7 @@ def main():
         args.n_q = args.n_q or 64
         res, (w, qc, qm) = run_compare(args)
     else:
-        args.n_db = args.n_db or 600_000
+        args.n_db = args.n_db or (1_500_000 if args.party_local else 600_000)
         res, (w, qc, qm) = run_serve(args)
     if not args.no_cpu_baseline and w is not None:
         log("timing the oracle on a bounded sample")

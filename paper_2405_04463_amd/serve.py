@@ -22,6 +22,13 @@ is not implemented).
 
 Admission: a request needs a free slot (slots bound the rows of a tick) and
 its per-request buffers must fit in free HBM above a reserve.
+
+Party-local serving: when the database object holds one party's region
+only (the other regions None), the server does that party's share of the
+work -- its dot products over every chunk, with the same continuous batching,
+admission and appends -- and nothing that needs the other parties.  The
+uniqueness decision then comes from a caller-supplied `decide(request)`
+(a deployment receives it from the interactive part of the protocol).
 """
 from __future__ import annotations
 
@@ -56,17 +63,24 @@ class Request:
     dup: int = -1
     entry: int = -1           # database slot when appended
     dup_shares: np.ndarray | None = None   # [3] components of the result
+    dots: dict | None = None  # party-local serving with keep_shares: party -> (code, mask) [R, entries]
 
 
 class Server:
     def __init__(self, ctx: Context, db, rot, chunk: int = 65536, slots: int = 64, max_entries: int | None = None,
                  hbm_reserve: float = 0.01, append: bool = True, keep_shares: bool = False, device=0,
-                 gather: bool = True):
+                 gather: bool = True, decide=None):
         """hbm_reserve: fraction of the device's memory kept free by admission.
         gather: run each tick's dot products as one gathered uniform launch
         (`imc_dot_shares_gather`); otherwise through a row table
-        (`imc_dot_shares_rows`)."""
+        (`imc_dot_shares_rows`).  decide: request -> 0/1, the uniqueness
+        decision in party-local serving (required there, unused otherwise)."""
         self.gather = gather
+        self.parties = [p for p in range(3) if db.regions[p] is not None]
+        self.local = len(self.parties) < 3
+        if self.local and decide is None:
+            raise ValueError("party-local serving needs a decide(request) callback")
+        self.decide = decide
         assert chunk % 64 == 0
         self.ctx, self.db, self.rot = ctx, db, list(rot)
         self.galois = bool(getattr(db, "galois", False))
@@ -86,9 +100,9 @@ class Server:
         # slot-indexed query shares (operand row = slot)
         self.op = [torch.empty(slots * self.row_bytes, dtype=torch.uint8, device=d) for _ in range(3)]
         self.raw = [torch.empty(slots * self.raw_bytes // 2, dtype=torch.int16, device=d) for _ in range(3)]
-        # tick buffers: dot outputs of all slots' rows for one chunk
-        self.dot_code = [i16(rows, self.ld) for _ in range(3)]
-        self.dot_mask = [i16(rows, self.ld) for _ in range(3)]
+        # tick buffers: dot outputs of all slots' rows for one chunk (held parties)
+        self.dot_code = [i16(rows, self.ld) if p in self.parties else None for p in range(3)]
+        self.dot_mask = [i16(rows, self.ld) if p in self.parties else None for p in range(3)]
         # a small ring of row tables: the host fills one while earlier copies may
         # still be reading the others; a table is reused only after its copy ended
         self.ring = 4
@@ -96,10 +110,11 @@ class Server:
         self.rows_dev = [torch.empty(rows, 2, dtype=torch.int32, device=d) for _ in range(self.ring)]
         self.rows_ev = [None] * self.ring
         self.tick_ev = deque()          # the host runs at most two ticks ahead of the GPU
-        # per-slot buffers
-        self.msg = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(slots)]
-        self.rep_code = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(slots)]
-        self.rep_mask = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(slots)]
+        # per-slot buffers (the interactive steps; none in party-local serving)
+        nb = 0 if self.local else slots
+        self.msg = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(nb)]
+        self.rep_code = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(nb)]
+        self.rep_mask = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(nb)]
         self.match = [None] * slots     # [3] x [2, R, nw_full] int64, allocated on admission
         self.dup = [[torch.empty(2, 1, dtype=torch.uint8, device=d) for _ in range(3)] for _ in range(slots)]
         self.ws = torch.empty(max(8, or_tree_ws_bytes(1, self.R, self.nw_full)), dtype=torch.uint8, device=d)
@@ -120,7 +135,7 @@ class Server:
         return time.perf_counter() - self.t0
 
     def request_bytes(self) -> int:
-        return 3 * 2 * self.R * self.nw_full * 8
+        return 0 if self.local else 3 * 2 * self.R * self.nw_full * 8
 
     def n_chunks(self) -> int:
         return (self.db.n + self.chunk - 1) // self.chunk
@@ -152,8 +167,12 @@ class Server:
             m = torch.from_numpy(np.ascontiguousarray(req.mask).view(np.int64).reshape(1, 200)).to(self.dev)
             self.ctx.share_query(c, m, 1, req.qid, [o.data_ptr() + slot * self.row_bytes for o in self.op],
                                  [r.data_ptr() + slot * self.raw_bytes for r in self.raw], galois=self.galois)
-            self.match[slot] = [torch.zeros(2, self.R, self.nw_full, dtype=torch.int64, device=self.dev)
-                                for _ in range(3)]
+            if not self.local:
+                self.match[slot] = [torch.zeros(2, self.R, self.nw_full, dtype=torch.int64, device=self.dev)
+                                    for _ in range(3)]
+            elif self.keep_shares:   # test aid: the request's dot outputs over the whole database
+                req.dots = {p: [torch.zeros(self.R, req.snapshot, dtype=torch.int16, device=self.dev)
+                                for _ in range(2)] for p in self.parties}
             self.active[slot] = req
 
     # ------------------------------------------------------------------ tick
@@ -197,7 +216,7 @@ class Server:
         self.rows_ev[b] = torch.cuda.Event()
         self.rows_ev[b].record()
         ids_t = make_ids(0, self.rot, first)
-        for p in range(3):
+        for p in self.parties:
             if self.gather:
                 self.ctx.dot_shares_gather(p, self.op[p], self.rows_dev[b], k, ids_t, self.db.regions[p],
                                            self.db.capacity, n_max, self.dot_code[p], self.dot_mask[p], self.ld,
@@ -209,6 +228,16 @@ class Server:
         # per request: reshare and compare its rows into its match buffer
         for i, r in enumerate(reqs):
             n_j = min(self.chunk, r.snapshot - first)
+            if self.local:          # the party's share of the work ends with its dot products
+                if self.keep_shares:
+                    for p in self.parties:
+                        for v, src in enumerate((self.dot_code[p], self.dot_mask[p])):
+                            r.dots[p][v][:, first:first + n_j].copy_(src[i * self.R:(i + 1) * self.R, :n_j])
+                r.remaining.discard(j)
+                self.cmps += self.R * n_j
+                if not r.remaining:
+                    self._finish(r)
+                continue
             ids = make_ids(r.qid, self.rot, first)
             off = 2 * i * self.R * self.ld
             add_c = [self.dot_code[p].data_ptr() + off for p in range(3)]
@@ -232,6 +261,12 @@ class Server:
 
     def _finish(self, r: Request):
         s = r.slot
+        if self.local:
+            ev = torch.cuda.Event()
+            ev.record()
+            del self.active[s]
+            self.finishing.append((r, ev))
+            return
         ids = make_ids(r.qid, self.rot, 0)
         nw = (r.snapshot + 63) // 64
         self.ctx.or_tree(self.match[s], 1, nw, self.nw_full, ids, self.ws, self.ws.numel(), self.dup[s])
@@ -250,9 +285,9 @@ class Server:
             if not ev.query():
                 keep.append((r, ev))
                 continue
-            r.dup = int(self.open_host[r.slot].item())
+            r.dup = int(self.decide(r)) if self.local else int(self.open_host[r.slot].item())
             r.done_at = self.now()
-            if self.keep_shares:
+            if self.keep_shares and not self.local:
                 r.dup_shares = r.dup_shares.cpu().numpy()
                 r.match = [m.cpu().numpy() for m in self.match[r.slot]]
             if r.dup == 0 and self.append_uniques and self.db.n < self.max_entries:

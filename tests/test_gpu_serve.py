@@ -102,3 +102,37 @@ def test_unique_requests_are_appended(env, galois):
     z = Request(rid=9, qid=2009, code=e["qc"][5].copy(), mask=e["qm"][5].copy())
     done = _drive(srv, {0: [z]})
     assert done[9].dup == 1 and done[9].snapshot == N0 + 1 and db.n == N0 + 1
+
+
+def test_party_local_serving(env):
+    """One party's share of the work (its database region only): each
+    request's dot outputs over the whole database equal the oracle's party-0
+    local dots, alone and in a mix; the supplied decision drives appends."""
+    from paper_2405_04463_amd.pipeline import SharedDB
+    from paper_2405_04463_amd.serve import Server
+
+    e = env
+    db = SharedDB(e["ctx"], N0 + 16, parties=(0,))
+    d64 = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()  # noqa: E731
+    db.enroll(d64(e["dc"]), d64(e["dm"]), 0)
+    torch.cuda.synchronize()
+    decide = lambda r: 1 if r.rid in (0, 1) else 0   # noqa: E731  (planted: 0 and 1)
+    alone = _drive(Server(e["ctx"], db, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True, decide=decide),
+                   {0: [_req(e, 0, 3000)]})[0]
+    srv = Server(e["ctx"], db, ROT, chunk=CHUNK, slots=8, append=True, keep_shares=True, decide=decide)
+    done = _drive(srv, {0: [_req(e, i, 3000 + i) for i in (1, 2)], 2: [_req(e, 0, 3000)], 3: [_req(e, 6, 3006)]})
+    qsh = orc.share(e["dealer"], orc.DOM_SHARE_QUERY, e["qc"], e["qm"], 3000)
+    dsh = orc.share(e["dealer"], orc.DOM_SHARE_DB, e["dc"], e["dm"], 0)
+    for rid, r in done.items():
+        assert r.snapshot == N0 or rid == 6
+        n = r.snapshot
+        want_c, want_m = orc.local_dot(0, qsh[rid:rid + 1], ROT, dsh[:n]) if n == N0 else (None, None)
+        if want_c is None:
+            continue
+        assert np.array_equal(r.dots[0][0].cpu().numpy().view(np.uint16), want_c), rid
+        assert np.array_equal(r.dots[0][1].cpu().numpy().view(np.uint16), want_m), rid
+    assert np.array_equal(alone.dots[0][0].cpu().numpy(), done[0].dots[0][0].cpu().numpy())
+    # uniques (by the decision) were appended to the held region only
+    assert db.n == N0 + sum(1 for r in done.values() if r.dup == 0)
+    assert {r.dup for r in done.values()} == {0, 1}
+    assert db.regions[1] is None and db.regions[2] is None
