@@ -173,6 +173,31 @@ def verify(ctx, buf, w, qc, qm, n_sample=1024):
             "dup_true": int(dup.sum())}
 
 
+# ChaCha12 blocks per 64 comparisons of each comparison circuit (their PRF tapes)
+# and int32 ops per block (12 rounds x 4 quarter-rounds x 12 ops + 16 adds).
+CMP_BLOCKS_PER_64 = {"mpclift": 55, "lift18": 34, "plain": 12, "constlift": 24, "nolift": 24}
+CHACHA12_OPS = 12 * 4 * 12 + 16
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+
+
+def circuit_report(compare, ncmp, reshare_ms, compare_ms, plain, v32):
+    """The interactive steps of one batch: resharing against the HBM roof
+    (algorithmic bytes) and the comparison against the VALU roof (its PRF
+    work alone, a lower bound on its ops)."""
+    n16 = 0 if 0 in v32 else 1
+    n16 += 0 if (plain or 1 in v32) else 1                 # Z_2^16 vectors reshared
+    # per vector and comparison, 3 parties: read the additive share, write the
+    # message and both planes of the replicated share: 3 x (1 + 1 + 2) elements
+    per_vec16, per_vec32 = 3 * 4 * 2, 3 * 4 * 4
+    rb = ncmp * (n16 * per_vec16 + len(v32) * per_vec32)
+    ops = ncmp * CMP_BLOCKS_PER_64[compare] * CHACHA12_OPS / 64
+    return {"reshare_ms": reshare_ms, "reshare_bytes": rb, "reshare_gbs": rb / (reshare_ms / 1e3) / 1e9,
+            "reshare_hbm_frac": rb / (reshare_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "compare_ms": compare_ms, "compare_prf_ops": ops,
+            "compare_valu_tops": ops / (compare_ms / 1e3) / 1e12,
+            "compare_valu_frac": ops / (compare_ms / 1e3) / 1e12 / VALU_PEAK_TOPS}
+
+
 def run_full(args):
     import torch
 
@@ -226,11 +251,16 @@ def run_full(args):
         if plain:   # masks public: every party computes ml itself
             ctx.rotate_masks(q_masks, qs.q, ids, buf.row_masks, stream)
             ctx.plain_ml(buf.row_masks, buf.rows, db_masks, w.n_db, buf.ml_pub, buf.ld, stream)
+        if events is not None:
+            events[3][0].record(stream)
         if code16:
             ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, w.n_db, buf.ld, ids, buf.msg, buf.rep_code,
                         buf.rep_mask, stream)
         for v in v32:
             ctx.reshare32(v, buf.dot32[v], buf.rows, w.n_db, buf.ld, ids, buf.msg32[v], buf.rep32[v], stream)
+        if events is not None:
+            events[3][1].record(stream)
+            events[4][0].record(stream)
         if plain:
             ctx.compare_variant(imc.CMP_PLAIN_MASK, buf.rep_code, 16, None, buf.ml_pub, buf.rows, w.n_db, buf.ld,
                                 ids, buf.match, buf.nw, stream)
@@ -244,6 +274,8 @@ def run_full(args):
         else:
             ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, w.n_db, buf.ld, ids, buf.match, buf.nw,
                                   stream)
+        if events is not None:
+            events[4][1].record(stream)
         ctx.or_tree(buf.match, qs.q, buf.nw, buf.nw, ids, buf.ws, buf.ws.numel(), buf.dup, stream)
         open_dup(ctx, buf, qs.q, check=0, stream=stream)
 
@@ -257,14 +289,16 @@ def run_full(args):
     t0 = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
         step(ev)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
         evs.append(ev)
         log(f"step {i + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms")
     total = time.perf_counter() - t0
-    dot_ms = [a.elapsed_time(b) for ev in evs for a, b in ev]
+    dot_ms = [a.elapsed_time(b) for ev in evs for a, b in ev[:3]]
+    reshare_ms = float(np.mean([ev[3][0].elapsed_time(ev[3][1]) for ev in evs]))
+    compare_ms = float(np.mean([ev[4][0].elapsed_time(ev[4][1]) for ev in evs]))
     ncmp = w.rows * w.n_db
     ms = total / args.steps * 1e3
     dot_avg_s = float(np.mean(dot_ms)) / 1e3
@@ -301,6 +335,7 @@ def run_full(args):
                      "ops_per_launch": ops, "avg_launch_ms": dot_avg_s * 1e3,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "hbm_gbs": None if traffic is None else traffic / dot_avg_s / 1e9},
+        "circuit": circuit_report(args.compare, w.rows * w.n_db, reshare_ms, compare_ms, plain, v32),
         "verification": ver,
     }
     return res, (w, qc, qm)

@@ -259,3 +259,43 @@ def test_argument_errors(ctx, imc):
         with pytest.raises(imc.IMCError) as e:
             ctx.set_dot_tiles(bad)
         assert e.value.status == imc.IMC_EUNSUPPORTED
+
+
+def test_small_unrotated_configuration_all_components(ctx, imc, keys):
+    """1,000 entries, 16 queries, no rotation, 4 queries planted at HD 0.20:
+    every component of every step bit-exact against the oracle's protocol run,
+    and the opened duplicate flags are exactly the planted queries."""
+    from paper_2405_04463_amd.pipeline import SharedDB, SharedQueries, alloc_check, open_dup, open_match, run_check
+
+    dealer, party = keys
+    w = wl.small_plain()
+    dc, dm = wl.gen_codes(w.seed, 0, w.n_db)
+    qc, qm = wl.make_queries(w)
+    db = SharedDB(ctx, w.n_db)
+    db.enroll(dev64(dc), dev64(dm), 0)
+    qs = SharedQueries(ctx, dev64(qc), dev64(qm), 500)
+    buf = alloc_check(w.n_q, len(w.rot), w.n_db)
+    run_check(ctx, qs, w.rot, db, 0, w.n_db, buf)
+    torch.cuda.synchronize()
+    ref = orc.protocol(dealer, party, qc, qm, w.rot, dc, dm, qid_base=500, first_entry=0)
+    _, _, match, dup = orc.plain(qc, qm, w.rot, dc, dm)
+    n, nw = w.n_db, (w.n_db + 63) // 64
+    for p in range(3):
+        pm = (p + 2) % 3
+        assert np.array_equal(u16(buf.dot_code[p])[:, :n], ref["z_code"][p])
+        assert np.array_equal(u16(buf.dot_mask[p])[:, :n], ref["z_mask"][p])
+        assert np.array_equal(u16(buf.rep_code[p])[0, :, :n], ref["rep_code"][p])
+        assert np.array_equal(u16(buf.rep_mask[p])[1, :, :n], ref["rep_mask"][pm])
+        mh = buf.match[p].cpu().numpy().view(np.uint64)
+        assert np.array_equal(mh[0, :, :nw], ref["match"][p]) and np.array_equal(mh[1, :, :nw], ref["match"][pm])
+        dh = buf.dup[p].cpu().numpy()
+        assert np.array_equal(dh[0], ref["dup"][p]) and np.array_equal(dh[1], ref["dup"][pm])
+    mo, s = open_match(ctx, buf)
+    assert s == imc.IMC_OK
+    mo = mo.cpu().numpy().view(np.uint64)
+    bits = np.array([[(int(mo[r_, j // 64]) >> (j % 64)) & 1 for j in range(n)] for r_ in range(w.rows)])
+    assert np.array_equal(bits, match)
+    do, s = open_dup(ctx, buf, w.n_q)
+    assert s == imc.IMC_OK
+    assert sorted(np.nonzero(do.cpu().numpy())[0].tolist()) == sorted(qi for qi, _, _, _ in w.planted) == [1, 5, 9, 13]
+    assert np.array_equal(do.cpu().numpy(), dup)
