@@ -95,7 +95,7 @@ def enroll_db(ctx, db, seed, n, chunk=32768, keep_masks=False, db32=None):
     return masks
 
 
-def cpu_baseline(w, qc, qm, sample_q=4, sample_n=8192, galois=False, compare="mpclift"):
+def cpu_baseline(w, qc, qm, sample_q=4, sample_n=40960, galois=False, compare="mpclift"):
     """The oracle's step (local dots of all parties, reshare, compare, OR-tree)
     on a bounded sample of the same workload; shares made before timing."""
     import oracle as orc
@@ -578,7 +578,7 @@ def run_serve(args):
         reqs = [Request(rid=i, qid=qid + i, code=qc[i], mask=qm[i], arrival=float(arr[i])) for i in range(n_req)]
         qid += n_req
         decide = (lambda r: int(r.qid in planted_qids)) if local else None
-        srv = Server(ctx, db, rot, chunk=args.chunk, slots=args.slots, decide=decide)
+        srv = Server(ctx, db, rot, chunk=args.chunk, slots=args.slots, decide=decide, serial=not args.no_serial)
         n0 = db.n
         log(f"serving lambda={lam}/s: {n_req} requests over {args.duration:.1f} s, DB {n0} entries")
         t0 = time.perf_counter()
@@ -622,7 +622,7 @@ def run_serve(args):
                                 f"(+ appends)") + f", 31 rotations, Poisson arrivals {args.rates}/s for "
                                                   f"{args.duration} s",
                    "chunk": args.chunk, "slots": args.slots, "sharing": args.scheme,
-                   "parties": len(parties)},
+                   "parties": len(parties), "serial_uniqueness": not (args.no_serial or local)},
         "latency_ms": {"p50": out["lambda"][top]["p50_ms"], "p99": out["lambda"][top]["p99_ms"], "at_lambda": top},
         "serve": out,
     }, (None, None, None)
@@ -681,6 +681,8 @@ def main():
     ap.add_argument("--dot-tiles", type=int, default=0, help="dot kernel tile configuration (IMC_DOT_TILES_*)")
     ap.add_argument("--scheme", choices=["replicated", "galois"], default="replicated",
                     help="sharing of the dot-product operands (full, batched and serve workloads)")
+    ap.add_argument("--no-serial", action="store_true",
+                    help="serve workload: do not match requests with earlier requests still in flight")
     ap.add_argument("--party-local", action="store_true",
                     help="serve workload: one party's share of the service (its DB region and dot products)")
     ap.add_argument("--compare", choices=["mpclift", "lift18", "plain", "constlift", "nolift"], default="mpclift",

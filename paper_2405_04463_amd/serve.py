@@ -16,9 +16,16 @@ Unique requests (dup = 0) are appended to the database.
 Because every random value is addressed by (query id, rotation, entry, gate)
 and the OR-tree runs over the request's complete buffer, a request's shares
 and result are the same alone and in any mix, whatever chunk it starts at.
-A request checks the entries enrolled when it was admitted; requests in
-flight at the same time are not compared with each other (in-batch matching
-is not implemented).
+Serial uniqueness (Sec. 6.3: a batch is also matched against itself): a
+request must also match the unique requests admitted before it that were
+still in flight at its admission.  With `serial=True` (the default) a request
+whose pass over its snapshot is complete is finalised only after every
+earlier-admitted request has been decided and, if unique, appended; it is
+then compared with the entries appended since its admission (a short tail
+pass over [64-aligned snapshot, current size) into the same match buffer,
+recomputing identical words below the snapshot) before its OR-tree runs over
+the whole buffer.  Its shares and result then equal a plain check against the
+database as it stands after every earlier request, i.e. the serial order.
 
 Admission: a request needs a free slot (slots bound the rows of a tick) and
 its per-request buffers must fit in free HBM above a reserve.
@@ -64,23 +71,30 @@ class Request:
     entry: int = -1           # database slot when appended
     dup_shares: np.ndarray | None = None   # [3] components of the result
     dots: dict | None = None  # party-local serving with keep_shares: party -> (code, mask) [R, entries]
+    seq: int = -1             # admission order
+    checked: int = 0          # entries the final decision covers
 
 
 class Server:
     def __init__(self, ctx: Context, db, rot, chunk: int = 65536, slots: int = 64, max_entries: int | None = None,
                  hbm_reserve: float = 0.01, append: bool = True, keep_shares: bool = False, device=0,
-                 gather: bool = True, decide=None):
+                 gather: bool = True, decide=None, serial: bool = True):
         """hbm_reserve: fraction of the device's memory kept free by admission.
         gather: run each tick's dot products as one gathered uniform launch
         (`imc_dot_shares_gather`); otherwise through a row table
         (`imc_dot_shares_rows`).  decide: request -> 0/1, the uniqueness
-        decision in party-local serving (required there, unused otherwise)."""
+        decision in party-local serving (required there, unused otherwise).
+        serial: also match requests against earlier-admitted requests that were
+        in flight at their admission (see the module notes)."""
         self.gather = gather
         self.parties = [p for p in range(3) if db.regions[p] is not None]
         self.local = len(self.parties) < 3
         if self.local and decide is None:
             raise ValueError("party-local serving needs a decide(request) callback")
         self.decide = decide
+        self.serial = serial and not self.local
+        self.pending: list = []         # pass complete, waiting for every earlier request (serial)
+        self.seq = 0
         assert chunk % 64 == 0
         self.ctx, self.db, self.rot = ctx, db, list(rot)
         self.galois = bool(getattr(db, "galois", False))
@@ -160,6 +174,8 @@ class Server:
             req = self.queue.popleft()
             slot = self.free.pop()
             req.slot = slot
+            req.seq = self.seq
+            self.seq += 1
             req.snapshot = self.db.n
             req.remaining = set(range((req.snapshot + self.chunk - 1) // self.chunk))
             req.admitted_at = now
@@ -183,6 +199,7 @@ class Server:
         next tick)."""
         self._admit()
         self._poll()
+        self._finalize_ready()
         if not self.active:
             return False
         nch = self.n_chunks()
@@ -267,8 +284,66 @@ class Server:
             del self.active[s]
             self.finishing.append((r, ev))
             return
+        if self.serial:
+            del self.active[s]
+            self.pending.append(r)
+            self._finalize_ready()
+            return
+        self._finalize(r, r.snapshot)
+
+    def _finalize_ready(self):
+        """Finalise pending requests in admission order once every earlier
+        request has been decided (and appended if unique)."""
+        while self.pending:
+            r = min(self.pending, key=lambda x: x.seq)
+            if any(a.seq < r.seq for a in self.active.values()):
+                return
+            if self.finishing:
+                # earlier requests' results are on their way: wait for them now
+                # rather than a tick later, so a burst of finishing requests is
+                # decided in one go
+                for _, ev in self.finishing:
+                    ev.synchronize()
+                self._poll()
+                continue
+            self.pending.remove(r)
+            n_now = self.db.n
+            if n_now > r.snapshot:
+                self._tail_pass(r, n_now)
+            self._finalize(r, n_now)
+
+    def _tail_pass(self, r: Request, n_now: int):
+        """Compare r with the entries appended since its admission: entries
+        [64-aligned snapshot, n_now) into its match buffer."""
+        first = (r.snapshot // 64) * 64
+        s = r.slot
+        b = self.ticks % self.ring
+        if self.rows_ev[b] is not None:
+            self.rows_ev[b].synchronize()
+        self.rows_host[b].view(-1)[:1].fill_(s)
+        self.rows_dev[b].view(-1)[:1].copy_(self.rows_host[b].view(-1)[:1], non_blocking=True)
+        self.rows_ev[b] = torch.cuda.Event()
+        self.rows_ev[b].record()
+        self.ticks += 1
+        for f in range(first, n_now, self.chunk):
+            n_j = min(self.chunk, n_now - f)
+            ids = make_ids(r.qid, self.rot, f)
+            for p in range(3):
+                self.ctx.dot_shares_gather(p, self.op[p], self.rows_dev[b], 1, make_ids(0, self.rot, f),
+                                           self.db.regions[p], self.db.capacity, n_j, self.dot_code[p],
+                                           self.dot_mask[p], self.ld, galois=self.galois)
+            self.ctx.reshare(self.dot_code, self.dot_mask, self.R, n_j, self.ld, ids, self.msg[s], self.rep_code[s],
+                             self.rep_mask[s])
+            mw = [m.data_ptr() + 8 * (f // 64) for m in self.match[s]]
+            self.ctx.compare_threshold(self.rep_code[s], self.rep_mask[s], self.R, n_j, self.ld, ids, mw,
+                                       self.nw_full)
+            self.cmps += self.R * n_j
+
+    def _finalize(self, r: Request, n_checked: int):
+        s = r.slot
+        r.checked = n_checked
         ids = make_ids(r.qid, self.rot, 0)
-        nw = (r.snapshot + 63) // 64
+        nw = (n_checked + 63) // 64
         self.ctx.or_tree(self.match[s], 1, nw, self.nw_full, ids, self.ws, self.ws.numel(), self.dup[s])
         self.ctx.open(OPEN_U8_XOR, self.dup[s], 1, self.open_dev.data_ptr() + s, 0)
         self.open_host[s:s + 1].copy_(self.open_dev[s:s + 1], non_blocking=True)
@@ -276,7 +351,7 @@ class Server:
             r.dup_shares = torch.stack([d[0, 0] for d in self.dup[s]])
         ev = torch.cuda.Event()
         ev.record()
-        del self.active[s]
+        self.active.pop(s, None)
         self.finishing.append((r, ev))
 
     def _poll(self):
@@ -312,7 +387,7 @@ class Server:
                 raise TimeoutError("serving run exceeded its time limit")
             busy = self.tick()
             if not busy:
-                if self.finishing:
+                if self.finishing or self.pending:
                     torch.cuda.synchronize()
                 elif self.queue:
                     wait = self.queue[0].arrival - self.now()

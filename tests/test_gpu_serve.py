@@ -136,3 +136,36 @@ def test_party_local_serving(env):
     assert db.n == N0 + sum(1 for r in done.values() if r.dup == 0)
     assert {r.dup for r in done.values()} == {0, 1}
     assert db.regions[1] is None and db.regions[2] is None
+
+
+@pytest.mark.parametrize("galois", [False, True])
+def test_serial_uniqueness_of_requests_in_flight(env, galois):
+    """Two requests carrying the same iris, the second admitted while the
+    first is still in flight: the first is unique and appended, the second
+    is a duplicate of it (serial order), and its shares equal a plain check
+    against the database as it stood after the first request."""
+    from paper_2405_04463_amd.pipeline import SharedQueries, alloc_check, run_check
+    from paper_2405_04463_amd.serve import Request, Server
+
+    e = env
+    db = _db(e, galois=galois)
+    srv = Server(e["ctx"], db, ROT, chunk=CHUNK, slots=8, append=True, keep_shares=True)
+    a = _req(e, 5, 4005)
+    b = Request(rid=15, qid=4015, code=e["qc"][5].copy(), mask=e["qm"][5].copy())
+    c = _req(e, 6, 4006)
+    done = _drive(srv, {0: [a], 1: [b], 2: [c]})
+    assert done[5].dup == 0 and done[5].entry == N0 and done[5].checked == N0
+    assert done[15].snapshot == N0 and done[15].checked == N0 + 1
+    assert done[15].dup == 1 and done[15].entry == -1
+    assert done[6].dup == 0 and done[6].checked == N0 + 1 and done[6].entry == N0 + 1
+    assert db.n == N0 + 2
+    # b against the database after a's append, checked plainly
+    d64 = lambda x: torch.from_numpy(np.ascontiguousarray(x).view(np.int64).reshape(1, 200)).cuda()  # noqa: E731
+    qs = SharedQueries(e["ctx"], d64(e["qc"][5]), d64(e["qm"][5]), 4015, galois=galois)
+    buf = alloc_check(1, len(ROT), N0 + 1)
+    run_check(e["ctx"], qs, ROT, db, 0, N0 + 1, buf)
+    torch.cuda.synchronize()
+    nw = (N0 + 1 + 63) // 64
+    for p in range(3):
+        assert np.array_equal(done[15].match[p][:, :, :nw], buf.match[p].cpu().numpy()[:, :, :nw]), p
+        assert int(done[15].dup_shares[p]) == int(buf.dup[p].cpu().numpy()[0, 0]), p
