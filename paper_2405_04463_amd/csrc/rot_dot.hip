@@ -209,6 +209,9 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotA
     for (int uu = 0; uu < NSETS; ++uu) {
       const int k = k0 + uu;
       const int seg = k / kSegSteps, ts = k - seg * kSegSteps;
+      // interleave the next step's fragment reads with this step's MFMAs
+      // (the compiler's single-wave small-GEMM schedule; ~1.5 % faster here)
+      __builtin_amdgcn_iglp_opt(1);
       IMC_FRAGS(nalo, nahi, nblo, nbhi, min(k + 1, kSteps - 1))
 #pragma unroll
       for (int x = 0; x < WM; ++x)
