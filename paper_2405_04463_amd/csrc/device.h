@@ -33,6 +33,13 @@ struct Geo {
 };
 constexpr int kKGalois = kCodeBits;                                           // 12,800
 
+// One angular row of a query operand plane as the rotation-aware kernels keep
+// it in LDS: 800 bytes with 64 bytes of circular padding on both sides, so
+// that a row rotated by s (|s| <= 15, 4s bytes) is read in place.
+constexpr int kSegPad = 64;                       // >= 4 * 15 and a multiple of 16
+constexpr int kSegBytes = kRowLen + 2 * kSegPad;  // 928
+constexpr int kSegChunks = kSegBytes / 16;        // 58
+
 // PRF domains: high byte of the 64-bit stream id.
 constexpr uint32_t kDomShareDb = 1, kDomShareQuery = 2, kDomReshare = 3, kDomCmp = 4, kDomOr = 5;
 constexpr uint32_t kDomGaloisDb = 6, kDomGaloisQuery = 7, kDomOrPairs = 8;

@@ -246,6 +246,257 @@ __global__ void __launch_bounds__(256) dot32_kernel(Dot32Args args) {
 }
 
 // ---------------------------------------------------------------------------
+// Rotation-aware dot kernel over Z_2^32 (r >= 13 rotations per query).  A
+// row tile of kBM (query, rotation) rows holds only ceil(kBM / r) + 1
+// distinct queries, so the workgroup keeps each tile query's bytes of the
+// current 800-byte angular-row segment in LDS (four limb planes, circular
+// padding as in the Z_2^16 kernel) and every lane reads its rotated fragment
+// in place; the database tile streams through three LDS stages, one K-step
+// per stage.  Database data is loaded NSETS steps ahead into registers; the
+// next query segment is loaded during the current one and stored half-way
+// through it into the other of two A buffers.  A wave's tile of WM x WN
+// 32 x 32 blocks needs 64 WM WN accumulator registers (four limb sums), so
+// tiles stay small: two waves per SIMD at 32 x 64.
+// ---------------------------------------------------------------------------
+struct RotDot32Args {
+  const int8_t* qop;     // [q][limb 4][25600]
+  const int8_t* b;       // party's Z_2^32 region of the vector
+  uint32_t* out;
+  uint64_t ld;
+  uint32_t rows, q, r;
+  uint64_t b_block0, b_blocks, n;
+  uint32_t mt, nt;
+  uint32_t max_q;        // query slots per tile (LDS sizing)
+  int8_t rot[IMC_MAX_ROT_DEV];
+};
+
+template <int WM, int WN, int WAVES_M, int WAVES_N, int NSETS, int ACH>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot32_kernel(RotDot32Args args) {
+  constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N;
+  constexpr int kThreads = 64 * WAVES_M * WAVES_N;
+  constexpr int kBBlk = kBN / 32;
+  constexpr int kBChunks = kBBlk * kLimbs32 * 2 * 32;          // 16-byte chunks per K-step
+  constexpr int kBPerThread = kBChunks / kThreads;
+  constexpr int kBStage = kBChunks * 16;
+  constexpr int kSlotBytes = kLimbs32 * kSegBytes;              // one query's segment, four limbs
+  static_assert(kBChunks % kThreads == 0, "B chunks must divide evenly");
+  extern __shared__ __align__(16) int8_t lds[];
+  int8_t* bst = lds;                                            // 3 B stages
+  int8_t* ast = lds + 3 * kBStage;                              // 2 A segment buffers
+  const uint32_t abuf = args.max_q * kSlotBytes;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+  const uint32_t i = blockIdx.x, xcd = i & 7, s8 = i >> 3;
+  const uint32_t u = s8 % args.mt, t = (s8 / args.mt) * 8 + xcd;
+  if (t >= args.nt) return;
+
+  const uint32_t m0 = u * kBM;
+  const uint32_t q_lo = m0 / args.r;
+  const uint32_t last_row = min(m0 + kBM, args.rows) - 1;
+  const uint32_t nq = last_row / args.r - q_lo + 1;             // <= max_q
+
+  // byte offset of this lane's rotated fragment (limb 0) in an A buffer
+  int a_off[WM];
+#pragma unroll
+  for (int x = 0; x < WM; ++x) {
+    const uint32_t row = m0 + (wm * WM + x) * 32 + (lane & 31);
+    int slot = 0, sft = 0;
+    if (row < args.rows) {
+      slot = int(row / args.r - q_lo);
+      sft = 4 * args.rot[row % args.r];
+    }
+    a_off[x] = slot * kSlotBytes + kSegPad - sft + 16 * (lane >> 5);
+  }
+
+  // B chunk c of a stage = (block, limb, k-chunk of the step, slot) at byte 16 c
+  const int8_t* bsrc[kBPerThread];
+#pragma unroll
+  for (int j = 0; j < kBPerThread; ++j) {
+    const int c = tid + j * kThreads;
+    const int blk = c >> 8, rem = c & 255;
+    const int limb = rem >> 6, kcl = (rem >> 5) & 1, slot = rem & 31;
+    uint64_t cb = uint64_t(t) * kBBlk + blk;
+    cb = cb < args.b_blocks ? cb : args.b_blocks - 1;
+    bsrc[j] = args.b + size_t(args.b_block0 + cb) * kBlock32Bytes + size_t(limb) * kPlane32Bytes + size_t(kcl) * 512 +
+              slot * 16;
+  }
+  // A chunk c of a segment buffer = (query slot, limb, 16-byte piece)
+  const int a_chunks = int(nq) * kLimbs32 * kSegChunks;
+  const int8_t* asrc[ACH];
+  int adst[ACH];
+#pragma unroll
+  for (int j = 0; j < ACH; ++j) {
+    int c = tid + j * kThreads;
+    const bool ok = c < a_chunks;
+    c = ok ? c : 0;
+    const int qs = c / (kLimbs32 * kSegChunks), rem = c % (kLimbs32 * kSegChunks);
+    const int limb = rem / kSegChunks, piece = rem % kSegChunks;
+    const int src_off = ((piece * 16 - kSegPad) % kRowLen + kRowLen) % kRowLen;   // circular
+    asrc[j] = args.qop + size_t(q_lo + qs) * kQop32RowBytes + size_t(limb) * kK + src_off;
+    adst[j] = ok ? (qs * kSlotBytes + limb * kSegBytes + piece * 16) : -1;
+  }
+
+  v16i acc[4][WM][WN];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int x = 0; x < WM; ++x)
+#pragma unroll
+      for (int y = 0; y < WN; ++y)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[a][x][y][e] = 0;
+
+  constexpr int kSteps = kChunks / 2;         // 800 steps of 32 k
+  constexpr int kSegSteps = kRowLen / 32;     // 25 per segment
+  constexpr int kSegs = kSteps / kSegSteps;   // 32
+  static_assert(kSteps % NSETS == 0, "the K loop is unrolled by NSETS");
+  v4i rs[NSETS][kBPerThread];
+  v4i ra[ACH];
+
+#define IMC_BLOAD(R, KS)                                                              \
+  _Pragma("unroll") for (int c_ = 0; c_ < kBPerThread; ++c_)                          \
+      R[c_] = *reinterpret_cast<const v4i*>(bsrc[c_] + size_t(2 * (KS)) * 512);
+#define IMC_BSTORE(R, STAGE)                                                          \
+  _Pragma("unroll") for (int c_ = 0; c_ < kBPerThread; ++c_)                          \
+      *reinterpret_cast<v4i*>(bst + (STAGE) * kBStage + (tid + c_ * kThreads) * 16) = R[c_];
+#define IMC_ALOAD(SEG)                                                                \
+  _Pragma("unroll") for (int c_ = 0; c_ < ACH; ++c_)                                  \
+      ra[c_] = *reinterpret_cast<const v4i*>(asrc[c_] + size_t(SEG) * kRowLen);
+#define IMC_ASTORE(BUF)                                                               \
+  _Pragma("unroll") for (int c_ = 0; c_ < ACH; ++c_)                                  \
+      if (adst[c_] >= 0) *reinterpret_cast<v4i*>(ast + (BUF) * abuf + adst[c_]) = ra[c_];
+#define IMC_AFRAGS(FA, K)                                                             \
+  {                                                                                   \
+    const int kk_ = (K);                                                              \
+    const int seg_ = kk_ / kSegSteps, ts_ = kk_ - seg_ * kSegSteps;                   \
+    const int8_t* sa_ = ast + (seg_ & 1) * abuf + 32 * ts_;                           \
+    _Pragma("unroll") for (int x_ = 0; x_ < WM; ++x_)                                 \
+    _Pragma("unroll") for (int l_ = 0; l_ < kLimbs32; ++l_) {                         \
+      const int32_t* pa_ = reinterpret_cast<const int32_t*>(sa_ + a_off[x_] + l_ * kSegBytes); \
+      FA[x_][l_] = v4i{pa_[0], pa_[1], pa_[2], pa_[3]};                               \
+    }                                                                                 \
+  }
+#define IMC_BFRAGS(FB, Y, K)                                                          \
+  _Pragma("unroll") for (int l_ = 0; l_ < kLimbs32; ++l_)                             \
+    FB[l_] = *reinterpret_cast<const v4i*>(bst + ((K) % 3) * kBStage +                \
+                                           ((wn * WN + (Y)) * kLimbs32 + l_) * 1024 + lane * 16);
+
+  // prologue: A segment 0; B steps 0 and 1 in stages 0 and 1; steps 2.. in registers
+  IMC_ALOAD(0)
+  IMC_ASTORE(0)
+  {
+    v4i r0[kBPerThread];
+    IMC_BLOAD(r0, 0)
+    IMC_BSTORE(r0, 0)
+    IMC_BLOAD(r0, 1)
+    IMC_BSTORE(r0, 1)
+  }
+#pragma unroll
+  for (int set = 0; set < NSETS; ++set) { IMC_BLOAD(rs[set], set + 2) }
+  IMC_ALOAD(1)
+  __syncthreads();
+  // Query fragments are double-buffered (read one step ahead); database
+  // fragments of column block y are re-read for the next step right after
+  // the MFMAs of block y have been issued.
+  v4i fa[WM][kLimbs32], na[WM][kLimbs32], fb[WN][kLimbs32];
+  IMC_AFRAGS(fa, 0)
+#pragma unroll
+  for (int y = 0; y < WN; ++y) { IMC_BFRAGS(fb[y], y, 0) }
+
+  // Stage (k+2)%3 is overwritten at step k: it held step k-1, whose
+  // fragments were read during step k-2 and consumed before the barrier that
+  // ends step k-1.
+  for (int k0 = 0; k0 < kSteps; k0 += NSETS) {
+#pragma unroll
+    for (int uu = 0; uu < NSETS; ++uu) {
+      const int k = k0 + uu;
+      const int seg = k / kSegSteps, ts = k - seg * kSegSteps;
+      const int kn = min(k + 1, kSteps - 1);
+      IMC_AFRAGS(na, kn)
+#pragma unroll
+      for (int y = 0; y < WN; ++y) {
+#pragma unroll
+        for (int x = 0; x < WM; ++x)
+#pragma unroll
+          for (int ia = 0; ia < kLimbs32; ++ia)
+#pragma unroll
+            for (int jb = 0; ia + jb < kLimbs32; ++jb)
+              acc[ia + jb][x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[x][ia], fb[y][jb], acc[ia + jb][x][y],
+                                                                         0, 0, 0);
+        IMC_BFRAGS(fb[y], y, kn)
+      }
+      IMC_BSTORE(rs[uu], (k + 2) % 3)
+      if (ts == kSegSteps / 2 && seg + 1 < kSegs) {
+        IMC_ASTORE((seg + 1) & 1)
+        IMC_ALOAD(min(seg + 2, kSegs - 1))
+      }
+      __syncthreads();
+      IMC_BLOAD(rs[uu], min(k + 2 + NSETS, kSteps - 1))
+#pragma unroll
+      for (int x = 0; x < WM; ++x)
+#pragma unroll
+        for (int l = 0; l < kLimbs32; ++l) fa[x][l] = na[x][l];
+    }
+  }
+#undef IMC_AFRAGS
+#undef IMC_BFRAGS
+#undef IMC_BLOAD
+#undef IMC_BSTORE
+#undef IMC_ALOAD
+#undef IMC_ASTORE
+
+#pragma unroll
+  for (int x = 0; x < WM; ++x)
+#pragma unroll
+    for (int y = 0; y < WN; ++y) {
+      const uint64_t col = uint64_t(t) * kBN + (wn * WN + y) * 32 + (lane & 31);
+      if (col >= args.n) continue;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const uint32_t row = m0 + (wm * WM + x) * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (row < args.rows) {
+          const uint32_t z = uint32_t(acc[0][x][y][e]) + (uint32_t(acc[1][x][y][e]) << 8) +
+                             (uint32_t(acc[2][x][y][e]) << 16) + (uint32_t(acc[3][x][y][e]) << 24);
+          args.out[uint64_t(row) * args.ld + col] = z;
+        }
+      }
+    }
+}
+
+template <int WM, int WN, int WAVES_M, int WAVES_N, int NSETS, int ACH>
+static hipError_t launch_rot_dot32(const int8_t* qop, uint32_t q, uint32_t r, const int8_t* rot, const int8_t* b,
+                                   uint64_t first_entry, uint64_t n, uint32_t* out, uint64_t ld, hipStream_t s) {
+  constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N, kThreads = 64 * WAVES_M * WAVES_N;
+  RotDot32Args d;
+  d.qop = qop;
+  d.b = b;
+  d.out = out;
+  d.ld = ld;
+  d.rows = q * r;
+  d.q = q;
+  d.r = r;
+  d.b_block0 = first_entry / 32;
+  d.b_blocks = (n + 31) / 32;
+  d.n = n;
+  d.mt = (d.rows + kBM - 1) / kBM;
+  d.nt = uint32_t((n + kBN - 1) / kBN);
+  d.max_q = (kBM + r - 1) / r + 1;
+  if (int(d.max_q) * kLimbs32 * kSegChunks > ACH * kThreads) return hipErrorInvalidValue;
+  for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) d.rot[i] = i < int(r) ? rot[i] : 0;
+  const uint64_t groups = uint64_t((d.nt + 7) / 8) * 8 * d.mt;
+  if (groups > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  const size_t lds = 3 * size_t(kBN / 32) * kLimbs32 * 2 * 32 * 16 + 2 * size_t(d.max_q) * kLimbs32 * kSegBytes;
+  auto kern = rot_dot32_kernel<WM, WN, WAVES_M, WAVES_N, NSETS, ACH>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(unsigned(groups)), dim3(kThreads), lds, s, d);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Resharing over Z_2^32 (App. C): z_p + F(key_p) - F(key_{p-1}), stream
 // (DOM_RESHARE32, qid, rot), block entry >> 3, word 2 (entry & 7) + vec.
 // One thread: 8 consecutive entries of one row.
@@ -257,8 +508,31 @@ struct Reshare32Args {
   uint32_t* rep[3];     // [2][rows][ld]
   uint64_t ld, n, rows, plane, qid_base, first_entry;
   int32_t r, vec;
+  int32_t wide;         // every row offset 16-byte aligned: 8 values move as two 16-byte accesses
   int8_t rot[IMC_MAX_ROT_DEV];
 };
+
+__device__ __forceinline__ void ld8u32(const uint32_t* p, int nval, bool wide, uint32_t v[8]) {
+  if (wide && nval == 8) {
+    const uint4 x = reinterpret_cast<const uint4*>(p)[0], y = reinterpret_cast<const uint4*>(p)[1];
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = j < nval ? p[j] : 0u;
+  }
+}
+
+__device__ __forceinline__ void st8u32(uint32_t* p, int nval, bool wide, const uint32_t v[8]) {
+  if (wide && nval == 8) {
+    reinterpret_cast<uint4*>(p)[0] = make_uint4(v[0], v[1], v[2], v[3]);
+    reinterpret_cast<uint4*>(p)[1] = make_uint4(v[4], v[5], v[6], v[7]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < nval) p[j] = v[j];
+  }
+}
 
 __global__ void __launch_bounds__(256) reshare32_kernel(Reshare32Args a) {
   const uint64_t nc = (a.n + 7) / 8;
@@ -276,26 +550,26 @@ __global__ void __launch_bounds__(256) reshare32_kernel(Reshare32Args a) {
   }
   const int nval = int(min<uint64_t>(8, a.n - 8 * c));
   const uint64_t off = row * a.ld + 8 * c;
+  const bool wide = a.wide != 0;
   uint32_t z[3][8], G[3][8];
 #pragma unroll
-  for (int p = 0; p < 3; ++p)
+  for (int p = 0; p < 3; ++p) {
+    ld8u32(a.add[p] + off, nval, wide, z[p]);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      z[p][j] = j < nval ? a.add[p][off + j] : 0u;
-      G[p][j] = a.vec ? F[p][2 * j + 1] : F[p][2 * j];
-    }
+    for (int j = 0; j < 8; ++j) G[p][j] = a.vec ? F[p][2 * j + 1] : F[p][2 * j];
+  }
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
     const int pm = (p + 2) % 3;
+    uint32_t own[8], prev[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      if (j >= nval) continue;
-      const uint32_t own = z[p][j] + G[p][j] - G[pm][j];
-      const uint32_t prev = z[pm][j] + G[pm][j] - G[(pm + 2) % 3][j];
-      a.msg[p][off + j] = own;                 // party p -> party p+1
-      a.rep[p][off + j] = own;
-      a.rep[p][a.plane + off + j] = prev;      // received from party p-1
+      own[j] = z[p][j] + G[p][j] - G[pm][j];
+      prev[j] = z[pm][j] + G[pm][j] - G[(pm + 2) % 3][j];
     }
+    st8u32(a.msg[p] + off, nval, wide, own);                  // party p -> party p+1
+    st8u32(a.rep[p] + off, nval, wide, own);
+    st8u32(a.rep[p] + a.plane + off, nval, wide, prev);      // received from party p-1
   }
 }
 
@@ -324,6 +598,10 @@ hipError_t launch_dot32(const int8_t* qop, uint32_t q, uint32_t r, const int8_t*
                         uint64_t first_entry, uint64_t n, uint32_t* out, uint64_t ld, hipStream_t s) {
   const uint32_t rows = q * r;
   if (rows == 0 || n == 0) return hipSuccess;
+  // rotation-aware tiles of 128 x 128 (8 waves of 32 x 64) when the tile's
+  // queries fit the A staging (3 chunks per thread: r >= 26; 5: r >= 13)
+  if (r >= 26) return launch_rot_dot32<1, 2, 4, 2, 2, 3>(qop, q, r, rot, b, first_entry, n, out, ld, s);
+  if (r >= 13) return launch_rot_dot32<1, 2, 4, 2, 2, 5>(qop, q, r, rot, b, first_entry, n, out, ld, s);
   Dot32Args d;
   d.qop = qop;
   d.b = b;
@@ -362,6 +640,11 @@ hipError_t launch_reshare32(const Keys3& keys, int vec, const uint32_t* const ad
   a.first_entry = ids.first_entry_id;
   a.r = ids.r;
   a.vec = vec;
+  bool wide = ld % 4 == 0;
+  for (int p = 0; p < 3; ++p)
+    wide = wide && (reinterpret_cast<uintptr_t>(add[p]) | reinterpret_cast<uintptr_t>(msg[p]) |
+                    reinterpret_cast<uintptr_t>(rep[p])) % 16 == 0;
+  a.wide = wide ? 1 : 0;
   for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) a.rot[i] = i < ids.r ? ids.rot[i] : 0;
   const uint64_t threads = rows * ((n + 7) / 8);
   hipLaunchKernelGGL(reshare32_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, a);

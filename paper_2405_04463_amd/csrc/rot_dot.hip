@@ -34,10 +34,6 @@ struct RotDotArgs {
   int8_t rot[IMC_MAX_ROT_DEV];
 };
 
-constexpr int kSegPad = 64;                       // >= 4 * 15 and a multiple of 16
-constexpr int kSegBytes = kRowLen + 2 * kSegPad;  // 928
-constexpr int kSegChunks = kSegBytes / 16;        // 58
-
 // Waits and barriers with explicit counts (the kernels below keep copies and
 // reads in flight across them).
 template <int N>

@@ -119,80 +119,20 @@ def test_compare_variant_on_random_components(ctx, imc, keys, variant, rows_r, n
     assert np.array_equal(bits, (4 * dot > ml).astype(int))
 
 
-@pytest.mark.parametrize("q,rot,n,first", [
-    (3, list(range(-15, 16)), 300, 64),    # 93 rows: two row tiles; three entry tiles, ragged
-    (1, [0], 1, 0),
-    (2, [-7, 2], 129, 0),
+@pytest.mark.parametrize("q,rot,n,first,pad", [
+    (3, list(range(-15, 16)), 130, 64, 4),     # 93 rows: one row tile, ragged; three entry tiles, ragged
+    (10, list(range(-15, 16)), 300, 0, 4),     # 310 rows: three row tiles of the rotation-aware kernel
+    (9, list(range(-7, 8)), 257, 128, 3),      # 15 rotations (its larger query staging); row stride not 16-B aligned
+    (5, [-3, 0, 9], 64, 0, 4),                 # one entry tile exactly
+    (1, [7], 1, 0, 1),                         # a single comparison
 ])
-def test_plain_ml_matches_oracle(ctx, imc, q, rot, n, first):
-    dc, dm = wl.gen_codes(61, 0, first + n)
-    qc, qm = wl.gen_codes(61, 0, q, query=True)
-    _, ml, _, _ = orc.plain(qc, qm, rot, dc[first:], dm[first:])
-    rows = q * len(rot)
-    ld = ((n + 63) // 64) * 64 + 8
-    row_masks = torch.empty(rows, 200, dtype=torch.int64, device="cuda")
-    out = torch.full((rows, ld), -1, dtype=torch.int16, device="cuda")
-    ids = imc.make_ids(0, rot, first)
-    ctx.rotate_masks(dev64(qm), q, ids, row_masks)
-    dmd = dev64(dm)
-    ctx.plain_ml(row_masks, rows, dmd[first:], n, out, ld)
-    torch.cuda.synchronize()
-    got = u16(out)
-    assert np.array_equal(got[:, :n], ml.astype(np.uint16))
-    assert np.all(got[:, n:] == 0xFFFF)          # nothing written past n
-
-
-# --------------------------------------------------------------------------
-# Z_2^32 sharing, dot products and resharing (ConstLift / NoLift)
-# --------------------------------------------------------------------------
-def _limbs32(planes: np.ndarray) -> np.ndarray:
-    """[4, K] signed byte limbs -> u32 values sum_l b_l 2^(8l) mod 2^32."""
-    v = np.zeros(planes.shape[1], dtype=np.uint64)
-    for l_ in range(4):
-        v += (planes[l_].astype(np.int64) % (1 << 32)).astype(np.uint64) << np.uint64(8 * l_)
-    return (v % (1 << 32)).astype(np.uint32)
-
-
-@pytest.mark.parametrize("vec", [0, 1])
-def test_share32_layouts(ctx, imc, keys, vec):
-    dealer, _ = keys
-    n, first, cap, q = 40, 3, 64, 2
-    dc, dm = wl.gen_codes(71, first, n)
-    qc, qm = wl.gen_codes(71, 0, q, query=True)
-    ref = orc.share32(dealer, orc.DOM_SHARE32_DB, dc, dm, first)
-    qref = orc.share32(dealer, orc.DOM_SHARE32_QUERY, qc, qm, 30)
-    regions = [torch.zeros(imc.db32_bytes(cap), dtype=torch.uint8, device="cuda") for _ in range(3)]
-    ops = [torch.zeros(imc.query32_op_bytes(q), dtype=torch.uint8, device="cuda") for _ in range(3)]
-    ctx.share32_db(vec, dev64(dc), dev64(dm), n, first, regions, cap)
-    ctx.share32_query(vec, dev64(qc), dev64(qm), q, 30, ops)
-    torch.cuda.synchronize()
-    for p in range(3):
-        pm = (p + 2) % 3
-        h = regions[p].cpu().numpy()
-        for j in (0, 1, 28, 29, 39):
-            e = first + j
-            blk = h[(e // 32) * 3276800:(e // 32 + 1) * 3276800].reshape(4, 1600, 32, 16)
-            v = _limbs32(blk[:, :, e % 32, :].reshape(4, 25600).view(np.int8))
-            assert np.array_equal(v[:12800], ref[j, vec, p]) and np.array_equal(v[12800:], ref[j, vec, pm])
-        o = ops[p].cpu().numpy()
-        for qi in range(q):
-            v = _limbs32(o[qi * 102400:(qi + 1) * 102400].view(np.int8).reshape(4, 25600))
-            assert np.array_equal(v[:12800], qref[qi, vec, p] + qref[qi, vec, pm])
-            assert np.array_equal(v[12800:], qref[qi, vec, p])
-
-
-@pytest.mark.parametrize("q,rot,n,first", [
-    (3, list(range(-15, 16)), 130, 64),     # 93 rows: one row tile, ragged; three entry tiles, ragged
-    (5, [-3, 0, 9], 64, 0),                 # one entry tile exactly
-    (1, [7], 1, 0),                         # a single comparison
-])
-def test_dot32_and_reshare32_match_oracle(ctx, imc, keys, q, rot, n, first):
+def test_dot32_and_reshare32_match_oracle(ctx, imc, keys, q, rot, n, first, pad):
     dealer, party = keys
     dc, dm = wl.gen_codes(72, first, n)
     qc, qm = wl.gen_codes(72, 0, q, query=True)
     dsh = orc.share32(dealer, orc.DOM_SHARE32_DB, dc, dm, first)
     qsh = orc.share32(dealer, orc.DOM_SHARE32_QUERY, qc, qm, 50)
-    rows, ld = q * len(rot), ((n + 63) // 64) * 64 + 4
+    rows, ld = q * len(rot), ((n + 63) // 64) * 64 + pad
     ids = imc.make_ids(50, rot, first)
     z = [orc.local_dot32(p, qsh, rot, dsh) for p in range(3)]
     for vec in (0, 1):
