@@ -95,52 +95,94 @@ def enroll_db(ctx, db, seed, n, chunk=32768, keep_masks=False, db32=None):
     return masks
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, qc, qm, sample_q=4, sample_n=40960, galois=False, compare="mpclift"):
     """The oracle's step (local dots of all parties, reshare, compare, OR-tree)
-    on a bounded sample of the same workload; shares made before timing."""
+    on a bounded sample of the same workload on all host threads, plus the
+    same step and the plaintext check (popcounts) on one thread; shares are
+    made before timing."""
     import oracle as orc
     import workload as wl
 
     dealer, party = keys()
     dc, dm = wl.gen_codes(w.seed, 0, sample_n)
-    if galois:
-        qsh = orc.galois_share(dealer, orc.DOM_GALOIS_QUERY, qc[:sample_q], qm[:sample_q], 0)
-        dsh = orc.galois_share(dealer, orc.DOM_GALOIS_DB, dc, dm, 0)
-        local_dot = orc.galois_local_dot
-    else:
-        qsh = orc.share(dealer, orc.DOM_SHARE_QUERY, qc[:sample_q], qm[:sample_q], 0)
-        dsh = orc.share(dealer, orc.DOM_SHARE_DB, dc, dm, 0)
-        local_dot = orc.local_dot
-    q32 = d32 = None
-    if compare in ("constlift", "nolift"):
-        q32 = orc.share32(dealer, orc.DOM_SHARE32_QUERY, qc[:sample_q], qm[:sample_q], 0)
-        d32 = orc.share32(dealer, orc.DOM_SHARE32_DB, dc, dm, 0)
-    t0 = time.perf_counter()
-    zc, zm = [], []
-    for p in range(3):
-        c, m = local_dot(p, qsh, w.rot, dsh)
-        zc.append(c)
-        zm.append(m)
-    rc, rm = orc.reshare(party, np.stack(zc), np.stack(zm), sample_q, w.rot, 0, 0)
-    if q32 is not None:
-        z32 = [orc.local_dot32(p, q32, w.rot, d32) for p in range(3)]
-        rc32, rm32 = orc.reshare32(party, np.stack([z[0] for z in z32]) if compare == "nolift" else None,
-                                   np.stack([z[1] for z in z32]), sample_q, w.rot, 0, 0)
-        match = orc.compare_variant(party, orc.CMPV_CONST32, rc32 if compare == "nolift" else rc, rm32, None,
-                                    sample_q, w.rot, 0, 0)
-    elif compare == "plain":
-        _, ml, _, _ = orc.plain(qc[:sample_q], qm[:sample_q], w.rot, dc, dm)   # public ml
-        match = orc.compare_variant(party, orc.CMPV_PLAIN, rc, None, ml, sample_q, w.rot, 0, 0)
-    elif compare == "lift18":
-        match = orc.compare_variant(party, orc.CMPV_LIFT18, rc, rm, None, sample_q, w.rot, 0, 0)
-    else:
-        match = orc.compare(party, rc, rm, sample_q, w.rot, 0, 0)
-    orc.or_tree(party, match, sample_q, len(w.rot), 0)
-    dt = time.perf_counter() - t0
+
+    def shares(nq, n):
+        if galois:
+            qsh = orc.galois_share(dealer, orc.DOM_GALOIS_QUERY, qc[:nq], qm[:nq], 0)
+            dsh = orc.galois_share(dealer, orc.DOM_GALOIS_DB, dc[:n], dm[:n], 0)
+        else:
+            qsh = orc.share(dealer, orc.DOM_SHARE_QUERY, qc[:nq], qm[:nq], 0)
+            dsh = orc.share(dealer, orc.DOM_SHARE_DB, dc[:n], dm[:n], 0)
+        q32 = d32 = None
+        if compare in ("constlift", "nolift"):
+            q32 = orc.share32(dealer, orc.DOM_SHARE32_QUERY, qc[:nq], qm[:nq], 0)
+            d32 = orc.share32(dealer, orc.DOM_SHARE32_DB, dc[:n], dm[:n], 0)
+        return qsh, dsh, q32, d32
+
+    def step(nq, n, sh):
+        qsh, dsh, q32, d32 = sh
+        local_dot = orc.galois_local_dot if galois else orc.local_dot
+        t0 = time.perf_counter()
+        zc, zm = [], []
+        for p in range(3):
+            c, m = local_dot(p, qsh, w.rot, dsh)
+            zc.append(c)
+            zm.append(m)
+        rc, rm = orc.reshare(party, np.stack(zc), np.stack(zm), nq, w.rot, 0, 0)
+        if q32 is not None:
+            z32 = [orc.local_dot32(p, q32, w.rot, d32) for p in range(3)]
+            rc32, rm32 = orc.reshare32(party, np.stack([z[0] for z in z32]) if compare == "nolift" else None,
+                                       np.stack([z[1] for z in z32]), nq, w.rot, 0, 0)
+            match = orc.compare_variant(party, orc.CMPV_CONST32, rc32 if compare == "nolift" else rc, rm32, None,
+                                        nq, w.rot, 0, 0)
+        elif compare == "plain":
+            _, ml, _, _ = orc.plain(qc[:nq], qm[:nq], w.rot, dc[:n], dm[:n])   # public ml
+            match = orc.compare_variant(party, orc.CMPV_PLAIN, rc, None, ml, nq, w.rot, 0, 0)
+        elif compare == "lift18":
+            match = orc.compare_variant(party, orc.CMPV_LIFT18, rc, rm, None, nq, w.rot, 0, 0)
+        else:
+            match = orc.compare(party, rc, rm, nq, w.rot, 0, 0)
+        orc.or_tree(party, match, nq, len(w.rot), 0)
+        return time.perf_counter() - t0
+
+    def plain_rate(nq, n):
+        t0 = time.perf_counter()
+        orc.plain(qc[:nq], qm[:nq], w.rot, dc[:n], dm[:n])
+        return nq * len(w.rot) * n / (time.perf_counter() - t0)
+
+    dt = step(sample_q, sample_n, shares(sample_q, sample_n))
     ncmp = sample_q * len(w.rot) * sample_n
-    return {"value": ncmp / dt, "unit": "comparisons/s", "cores": orc.threads(), "kind": "oracle",
+    cores = orc.threads()
+    o1_all = plain_rate(sample_q, sample_n)
+    # one thread: one query of the sample against 1,024 entries
+    one_n = min(1024, sample_n)
+    sh1 = shares(1, one_n)
+    old = orc.set_threads(1)
+    try:
+        dt1 = step(1, one_n, sh1)
+        o1_one = plain_rate(1, one_n)
+    finally:
+        orc.set_threads(old)
+    n1 = len(w.rot) * one_n
+    return {"value": ncmp / dt, "unit": "comparisons/s", "cores": cores, "kind": "oracle",
             "sample": f"oracle step (3 parties' local dots, reshare, {compare} compare, OR-tree) on {sample_q} "
-                      f"queries x {len(w.rot)} rotations x {sample_n} entries = {ncmp} comparisons, {dt:.1f} s"}
+                      f"queries x {len(w.rot)} rotations x {sample_n} entries = {ncmp} comparisons, {dt:.1f} s",
+            "cpu_model": _cpu_model(),
+            "single_core": {"value": n1 / dt1, "sample": f"the same step on 1 query x {len(w.rot)} rotations x "
+                                                         f"{one_n} entries, one thread, {dt1:.1f} s"},
+            "plaintext_check": {"all_cores": o1_all, "single_core": o1_one, "unit": "comparisons/s",
+                                "note": "the oracle's plaintext definition (popcounts of masked XOR and AND)"}}
 
 
 def verify(ctx, buf, w, qc, qm, n_sample=1024):

@@ -54,6 +54,7 @@ def lib():
         _lib.orc_prf_u16.restype = ctypes.c_uint16
         _lib.orc_prf_u64.restype = ctypes.c_uint64
         _lib.orc_threads.restype = ctypes.c_int
+        _lib.orc_set_threads.restype = ctypes.c_int
         _lib.orc_compare.restype = ctypes.c_int
         _lib.orc_test_gr_inv.restype = ctypes.c_int
         _lib.orc_compare_variant.restype = ctypes.c_int
@@ -63,6 +64,11 @@ def lib():
 
 def threads() -> int:
     return lib().orc_threads()
+
+
+def set_threads(n: int) -> int:
+    """Thread count of later oracle calls; returns the previous count."""
+    return lib().orc_set_threads(ctypes.c_int(n))
 
 
 def chacha_block(key: bytes, rounds: int, words12_15) -> np.ndarray:

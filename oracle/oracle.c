@@ -1186,3 +1186,15 @@ int orc_threads(void) {
   return 1;
 #endif
 }
+
+/* Thread count of later calls (for timing on one core); returns the old one. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  const int old = omp_get_max_threads();
+  if (n > 0) omp_set_num_threads(n);
+  return old;
+#else
+  (void)n;
+  return 1;
+#endif
+}

@@ -399,3 +399,20 @@ def test_protocol_is_batch_independent(keys):
     part = orc.protocol(dealer, party, qc[2:3], qm[2:3], rot, dc[64:], dm[64:], qid_base=12, first_entry=64)
     assert np.array_equal(part["match"], full["match"][:, 6:9, 1:])
     assert np.array_equal(part["rep_code"], full["rep_code"][:, 6:9, 64:])
+
+
+def test_protocol_is_thread_count_independent(keys):
+    # The oracle's loops are split over host threads only by output element:
+    # one thread gives the same components as all of them.
+    dealer, party = keys
+    qc, qm, rot, dc, dm = _small_case(seed=23, n=70)
+    many = orc.protocol(dealer, party, qc, qm, rot, dc, dm, qid_base=10, first_entry=0)
+    old = orc.set_threads(1)
+    try:
+        assert orc.threads() == 1
+        one = orc.protocol(dealer, party, qc, qm, rot, dc, dm, qid_base=10, first_entry=0)
+    finally:
+        orc.set_threads(old)
+    assert orc.threads() == old
+    for k in ("match", "rep_code", "rep_mask", "dup"):
+        assert np.array_equal(one[k], many[k]), k
