@@ -1,0 +1,160 @@
+"""Parity at the full sizes of the measured workloads, in the launch
+configuration the benchmark times, on outputs the oracle computes one by one.
+
+* One party's dot products, 32 queries x 31 rotations (992 rows) against
+  1,000,000 entries (102.4 GB of shares): every row against every planted
+  entry, the first and last entries and 200 random ones, code and mask,
+  against the oracle's local dot of party 0.
+* The three-party protocol, 64 queries x 31 rotations against 300,000
+  entries per party: the resharing components and the shared match bits of
+  four 64-entry groups (the first, two random ones and the ragged last group
+  of 32 entries) against the oracle's protocol run on those entries; the
+  opened duplicate bit of every query against the OR of its opened match
+  bits over the whole database; every planted pair against the plaintext
+  decision.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+import workload as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def imc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_04463_amd as imc_mod
+
+    imc_mod.lib()
+    return imc_mod
+
+
+def dev64(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+
+
+def enroll(db, seed, n, chunk=65536):
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        c, k = wl.gen_codes(seed, s, m)
+        db.enroll(dev64(c), dev64(k), s)
+    torch.cuda.synchronize()
+
+
+def free():
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def test_party_dot_at_one_million_entries(imc, keys):
+    from paper_2405_04463_amd.pipeline import SharedDB, SharedQueries
+
+    dealer, party = keys
+    w = wl.party_local()
+    assert (w.n_db, w.n_q, len(w.rot)) == (1_000_000, 32, 31)
+    qc, qm = wl.make_queries(w)
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=w.rows)
+    try:
+        db = SharedDB(ctx, w.n_db, parties=(0,))
+        enroll(db, w.seed, w.n_db)
+        qs = SharedQueries(ctx, dev64(qc), dev64(qm), 0)
+        ld = ((w.n_db + 63) // 64) * 64
+        code = torch.empty(w.rows, ld, dtype=torch.int16, device="cuda")
+        mask = torch.empty_like(code)
+        ids = imc.make_ids(0, w.rot, 0)
+        ctx.dot_shares(0, qs.op[0], qs.q, ids, db.regions[0], db.capacity, w.n_db, code, mask, ld)
+        torch.cuda.synchronize()
+
+        rng = np.random.default_rng(11)
+        ents = sorted({0, w.n_db - 1} | {e for _, e, _, _ in w.planted} |
+                      set(int(x) for x in rng.choice(w.n_db, 200, replace=False)))
+        idx = torch.tensor(ents, dtype=torch.int64, device="cuda")
+        got_c = code.index_select(1, idx).cpu().numpy().view(np.uint16)
+        got_m = mask.index_select(1, idx).cpu().numpy().view(np.uint16)
+        del code, mask, db, qs
+        free()
+
+        qsh = orc.share(dealer, orc.DOM_SHARE_QUERY, qc, qm, 0)
+        dsh = []
+        for e in ents:
+            c, k = wl.gen_codes(w.seed, e, 1)
+            dsh.append(orc.share(dealer, orc.DOM_SHARE_DB, c, k, e))
+        want_c, want_m = orc.local_dot(0, qsh, w.rot, np.concatenate(dsh))
+        assert np.array_equal(got_c, want_c)
+        assert np.array_equal(got_m, want_m)
+    finally:
+        ctx.close()
+        free()
+
+
+def test_three_party_protocol_at_300k_entries(imc, keys):
+    from paper_2405_04463_amd.pipeline import SharedDB, SharedQueries, alloc_check, open_dup, open_match, run_check
+
+    dealer, party = keys
+    w = wl.full_protocol()
+    assert (w.n_db, w.n_q, len(w.rot)) == (300_000, 64, 31)
+    n, r = w.n_db, len(w.rot)
+    qc, qm = wl.make_queries(w)
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=w.rows)
+    try:
+        db = SharedDB(ctx, n)
+        enroll(db, w.seed, n)
+        qs = SharedQueries(ctx, dev64(qc), dev64(qm), 0)
+        buf = alloc_check(w.n_q, r, n)
+        run_check(ctx, qs, w.rot, db, 0, n, buf)
+        mo, s1 = open_match(ctx, buf, check=1)
+        do, s2 = open_dup(ctx, buf, w.n_q, check=1)
+        torch.cuda.synchronize()
+        assert s1 == imc.IMC_OK and s2 == imc.IMC_OK
+
+        ngroups = (n + 63) // 64
+        assert n % 64 == 32                                   # the last group is ragged
+        rng = np.random.default_rng(12)
+        groups = sorted({0, ngroups - 1} | set(int(x) for x in rng.choice(ngroups - 1, 2, replace=False)))
+        got = {}
+        for g in groups:
+            a, b = 64 * g, min(64 * g + 64, n)
+            got[g] = [(buf.rep_code[p][:, :, a:b].cpu().numpy().view(np.uint16),
+                       buf.rep_mask[p][:, :, a:b].cpu().numpy().view(np.uint16),
+                       buf.match[p][:, :, g].cpu().numpy().view(np.uint64)) for p in range(3)]
+        mo = mo.cpu().numpy().view(np.uint64)
+        dup = do.cpu().numpy()
+        del buf, db, qs
+        free()
+
+        for g in groups:
+            a, b = 64 * g, min(64 * g + 64, n)
+            dc, dm = wl.gen_codes(w.seed, a, b - a)
+            ref = orc.protocol(dealer, party, qc, qm, w.rot, dc, dm, qid_base=0, first_entry=a)
+            for p in range(3):
+                pm = (p + 2) % 3
+                rc, rmk, mt = got[g][p]
+                assert np.array_equal(rc[0], ref["rep_code"][p]) and np.array_equal(rc[1], ref["rep_code"][pm]), g
+                assert np.array_equal(rmk[0], ref["rep_mask"][p]) and np.array_equal(rmk[1], ref["rep_mask"][pm]), g
+                assert np.array_equal(mt[0], ref["match"][p][:, 0]) and np.array_equal(mt[1], ref["match"][pm][:, 0]), g
+            # the opened words of the group are the plaintext decision
+            _, _, match, _ = orc.plain(qc, qm, w.rot, dc, dm)
+            bits = (mo[:, g][:, None] >> np.arange(b - a, dtype=np.uint64)) & np.uint64(1)
+            assert np.array_equal(bits.astype(np.uint8), match), g
+
+        # dup[q] is the OR of q's opened match bits over every rotation and entry
+        real = mo.copy()
+        real[:, -1] &= np.uint64((1 << (n % 64)) - 1)
+        any_row = (real != 0).any(axis=1)
+        assert np.array_equal(dup.astype(bool), any_row.reshape(w.n_q, r).any(axis=1))
+        # each planted pair opens its plaintext decision
+        for qi, e, s, _ in w.planted:
+            ec, em = wl.gen_codes(w.seed, e, 1)
+            _, _, m1, _ = orc.plain(qc[qi:qi + 1], qm[qi:qi + 1], w.rot, ec, em)
+            for ri in range(r):
+                assert (int(mo[qi * r + ri, e // 64]) >> (e % 64)) & 1 == int(m1[ri, 0]), (qi, e, ri)
+            if m1.any():
+                assert dup[qi] == 1
+        assert dup.sum() > 0
+    finally:
+        ctx.close()
+        free()
