@@ -12,6 +12,7 @@ configuration the benchmark times, on outputs the oracle computes one by one.
   opened duplicate bit of every query against the OR of its opened match
   bits over the whole database; every planted pair against the plaintext
   decision.
+* The batched step of 200 uneven batches against 1,000,000 entries.
 """
 import numpy as np
 import pytest
@@ -155,6 +156,56 @@ def test_three_party_protocol_at_300k_entries(imc, keys):
             if m1.any():
                 assert dup[qi] == 1
         assert dup.sum() > 0
+    finally:
+        ctx.close()
+        free()
+
+
+def test_batched_step_at_one_million_entries(imc, keys):
+    """200 uneven batches (1..64 queries, 1/15/31 rotations) against one
+    party's 1,000,000 entries in 65,536-entry chunks, the tile choice made by
+    the autotuner as in the benchmark: every row of every batch against 16
+    entries of the last (ragged) chunk, including its first and last."""
+    from paper_2405_04463_amd.batch import BatchedStep, BatchSet, uneven_batches
+    from paper_2405_04463_amd.pipeline import SharedDB
+
+    dealer, party = keys
+    seed, n, chunk = 0x1A150004, 1_000_000, 65536
+    batches = uneven_batches(200, seed=seed)
+    nq = sum(b.q for b in batches)
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=sum(b.rows for b in batches))
+    try:
+        db = SharedDB(ctx, n, parties=(0,))
+        enroll(db, seed, n)
+        qc, qm = wl.gen_codes(seed, 0, nq, query=True)
+        bs = BatchSet(ctx, batches, dev64(qc), dev64(qm))
+        st = BatchedStep(ctx, bs, db, 0, n, chunk=chunk, parties=(0,))
+        st.autotune(probe_n=16384)
+        st.run()
+        torch.cuda.synchronize()
+        c0 = (n - 1) // chunk * chunk                         # first entry of the last chunk
+        rng = np.random.default_rng(13)
+        cols = sorted({0, n - 1 - c0} | set(int(x) for x in rng.choice(n - c0, 14, replace=False)))
+        idx = torch.tensor(cols, dtype=torch.int64, device="cuda")
+        got_c = st.dot_code[0].index_select(1, idx).cpu().numpy().view(np.uint16)
+        got_m = st.dot_mask[0].index_select(1, idx).cpu().numpy().view(np.uint16)
+        rbase = list(bs.rbase)
+        del st, bs, db
+        free()
+
+        dsh = []
+        for j in cols:
+            c, k = wl.gen_codes(seed, c0 + j, 1)
+            dsh.append(orc.share(dealer, orc.DOM_SHARE_DB, c, k, c0 + j))
+        dsh = np.concatenate(dsh)
+        q0 = 0
+        for bi, b in enumerate(batches):
+            qsh = orc.share(dealer, orc.DOM_SHARE_QUERY, qc[q0:q0 + b.q], qm[q0:q0 + b.q], b.qid_base)
+            rc, rm = orc.local_dot(0, qsh, b.rot, dsh)
+            r0 = rbase[bi]
+            assert np.array_equal(got_c[r0:r0 + b.rows], rc), bi
+            assert np.array_equal(got_m[r0:r0 + b.rows], rm), bi
+            q0 += b.q
     finally:
         ctx.close()
         free()
