@@ -13,6 +13,7 @@ configuration the benchmark times, on outputs the oracle computes one by one.
   bits over the whole database; every planted pair against the plaintext
   decision.
 * The batched step of 200 uneven batches against 1,000,000 entries.
+* Party-local serving over 1,500,000 entries of a 2,000,000-entry region.
 """
 import numpy as np
 import pytest
@@ -206,6 +207,80 @@ def test_batched_step_at_one_million_entries(imc, keys):
             assert np.array_equal(got_c[r0:r0 + b.rows], rc), bi
             assert np.array_equal(got_m[r0:r0 + b.rows], rm), bi
             q0 += b.q
+    finally:
+        ctx.close()
+        free()
+
+
+def _drive(srv, reqs_at_tick):
+    """Submit requests at given ticks and tick until all are done."""
+    total = len(srv.done) + sum(len(v) for v in reqs_at_tick.values())
+    t = 0
+    while len(srv.done) < total:
+        for r in reqs_at_tick.get(t, []):
+            srv.submit(r)
+        if not srv.tick():
+            torch.cuda.synchronize()
+        t += 1
+        assert t < 5000, srv.state()
+    torch.cuda.synchronize()
+    return {r.rid: r for r in srv.done}
+
+
+def test_party_local_serving_at_1_5M_entries(imc, keys):
+    """One party's share of the service over a region of 2,000,000 entries
+    holding 1,500,000 (204.8 GB allocated), 31 rotations, 65,536-entry chunks
+    (the last one ragged): each request's dot outputs over the whole
+    database, on the planted, first, last and 100 random entries, equal the
+    oracle's party-0 local dots; a request gives the same outputs alone and
+    joining a mix mid-cycle; the decided uniques are appended."""
+    from paper_2405_04463_amd.pipeline import SharedDB
+    from paper_2405_04463_amd.serve import Request, Server
+
+    dealer, party = keys
+    seed, n0, cap, chunk = 0x1A150005, 1_500_000, 2_000_000, 65536
+    assert n0 % chunk != 0
+    rot = wl.ROT31
+    qc, qm = wl.gen_codes(seed, 0, 4, query=True)
+    planted = {0: (1_234_567, 5, 0.20), 1: (n0 - 1, -9, 0.25)}
+    for qi, (e, s, h) in planted.items():
+        ec, em = wl.gen_codes(seed, e, 1)
+        qc[qi], qm[qi] = wl.plant(seed, qi, ec[0], em[0], s, h=h)
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=64 * len(rot))
+    try:
+        db = SharedDB(ctx, cap, parties=(0,))
+        enroll(db, seed, n0)
+        req = lambda i: Request(rid=i, qid=7000 + i, code=qc[i].copy(), mask=qm[i].copy())   # noqa: E731
+        decide = lambda r: 1 if r.rid in planted else 0                                        # noqa: E731
+        alone = _drive(Server(ctx, db, rot, chunk=chunk, slots=64, append=False, keep_shares=True, decide=decide),
+                       {0: [req(0)]})[0]
+        srv = Server(ctx, db, rot, chunk=chunk, slots=64, append=True, keep_shares=True, decide=decide)
+        done = _drive(srv, {0: [req(1), req(2)], 3: [req(0)], 7: [req(3)]})
+        assert torch.equal(alone.dots[0][0], done[0].dots[0][0]) and torch.equal(alone.dots[0][1], done[0].dots[0][1])
+        rng = np.random.default_rng(14)
+        ents = sorted({0, n0 - 1} | {e for e, _, _ in planted.values()} |
+                      set(int(x) for x in rng.choice(n0, 100, replace=False)))
+        idx = torch.tensor(ents, dtype=torch.int64, device="cuda")
+        got = {}
+        for rid, r in done.items():
+            assert r.snapshot == n0, rid
+            got[rid] = (r.dots[0][0].index_select(1, idx).cpu().numpy().view(np.uint16),
+                        r.dots[0][1].index_select(1, idx).cpu().numpy().view(np.uint16))
+        assert db.n == n0 + sum(1 for r in done.values() if r.dup == 0)
+        assert sorted(r.dup for r in done.values()) == [0, 0, 1, 1]
+        del alone, srv, done, db
+        free()
+
+        qsh = orc.share(dealer, orc.DOM_SHARE_QUERY, qc, qm, 7000)
+        dsh = []
+        for e in ents:
+            c, k = wl.gen_codes(seed, e, 1)
+            dsh.append(orc.share(dealer, orc.DOM_SHARE_DB, c, k, e))
+        dsh = np.concatenate(dsh)
+        for rid, (gc, gm) in got.items():
+            want_c, want_m = orc.local_dot(0, qsh[rid:rid + 1], rot, dsh)
+            assert np.array_equal(gc, want_c), rid
+            assert np.array_equal(gm, want_m), rid
     finally:
         ctx.close()
         free()
