@@ -215,6 +215,27 @@ def verify(ctx, buf, w, qc, qm, n_sample=1024):
             "dup_true": int(dup.sum())}
 
 
+def verify_in_batch(ctx, buf, bb, w, qc, qm):
+    """The opened final decision of every query against the opened database
+    decision OR the plaintext decision over the batch's earlier queries."""
+    import torch
+
+    import oracle as orc
+    import paper_2405_04463_amd as imc
+    from paper_2405_04463_amd.pipeline import open_dup
+
+    db_dup, s1 = open_dup(ctx, buf, w.n_q, check=1)
+    final = torch.empty(w.n_q, dtype=torch.uint8, device="cuda")
+    s2 = ctx.open(imc.OPEN_U8_XOR, bb.final, w.n_q, final, 1)
+    torch.cuda.synchronize()
+    batch = np.array([0] + [int(orc.plain(qc[i:i + 1], qm[i:i + 1], w.rot, qc[:i], qm[:i])[3][0])
+                            for i in range(1, w.n_q)], dtype=np.uint8)
+    want = db_dup.cpu().numpy() | batch
+    got = final.cpu().numpy()
+    return {"bit_exact": bool(np.array_equal(got, want)) and s1 == 0 and s2 == 0,
+            "batch_duplicates": int(batch.sum()), "final_true": int(got.sum())}
+
+
 # ChaCha12 blocks per 64 comparisons of each comparison circuit (their PRF tapes)
 # and int32 ops per block (12 rounds x 4 quarter-rounds x 12 ops + 16 adds).
 CMP_BLOCKS_PER_64 = {"mpclift": 55, "lift18": 34, "plain": 12, "constlift": 24, "nolift": 24}
@@ -246,9 +267,12 @@ def run_full(args):
     import paper_2405_04463_amd as imc
     import workload as wl
     from paper_2405_04463_amd.pipeline import (VECS32, SharedDB, SharedDB32, SharedQueries, SharedQueries32,
-                                               alloc_check, open_dup, run_check)
+                                               alloc_check, open_dup, run_check, run_in_batch)
 
     w = wl.full_protocol(n_db=args.n_db, n_q=args.n_q)
+    in_batch = args.in_batch
+    if in_batch and (args.compare != "mpclift" or w.n_q < 16):
+        raise SystemExit("--in-batch runs with the MPCLift comparison and at least 16 queries")
     dealer, party = keys()
     galois = args.scheme == "galois"
     plain = args.compare == "plain"
@@ -263,6 +287,8 @@ def run_full(args):
     db32 = SharedDB32(ctx, w.n_db, vecs=v32) if v32 else None
     db_masks = enroll_db(ctx, db if code16 else None, w.seed, w.n_db, keep_masks=plain, db32=db32)
     qc, qm = wl.make_queries(w)
+    if in_batch:
+        wl.plant_in_batch(w, qc, qm)
     q_codes = torch.from_numpy(qc.view(np.int64)).cuda()
     q_masks = torch.from_numpy(qm.view(np.int64)).cuda()
     qs = SharedQueries(ctx, q_codes, q_masks, 0, galois=galois)
@@ -274,6 +300,12 @@ def run_full(args):
     torch.cuda.synchronize()
     ver = verify(ctx, buf, w, qc, qm)
     log(f"verification: {ver}")
+    bb = None
+    if in_batch:
+        bb = run_in_batch(ctx, qs, w.rot, buf)
+        ver["in_batch"] = verify_in_batch(ctx, buf, bb, w, qc, qm)
+        log(f"in-batch verification: {ver['in_batch']}")
+    final_out = torch.empty(w.n_q, dtype=torch.uint8, device="cuda")
 
     stream = torch.cuda.current_stream()
     ids = imc.make_ids(0, w.rot, 0)
@@ -319,7 +351,15 @@ def run_full(args):
         if events is not None:
             events[4][1].record(stream)
         ctx.or_tree(buf.match, qs.q, buf.nw, buf.nw, ids, buf.ws, buf.ws.numel(), buf.dup, stream)
-        open_dup(ctx, buf, qs.q, check=0, stream=stream)
+        if in_batch:
+            if events is not None:
+                events[5][0].record(stream)
+            run_in_batch(ctx, qs, w.rot, buf, stream, reuse=bb)
+            if events is not None:
+                events[5][1].record(stream)
+            ctx.open(imc.OPEN_U8_XOR, bb.final, qs.q, final_out, 0, stream)
+        else:
+            open_dup(ctx, buf, qs.q, check=0, stream=stream)
 
     for i in range(args.warmup):
         step()
@@ -331,7 +371,7 @@ def run_full(args):
     t0 = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(6)]
         step(ev)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
@@ -380,6 +420,14 @@ def run_full(args):
         "circuit": circuit_report(args.compare, w.rows * w.n_db, reshare_ms, compare_ms, plain, v32),
         "verification": ver,
     }
+    if in_batch:
+        res["config"]["workload"] += (f", plus in-batch matching (each query against the batch's earlier "
+                                      f"queries: {w.rows} x {w.n_q} more comparisons)")
+        res["config"]["in_batch"] = True
+        res["in_batch"] = {"ms_per_step": float(np.mean([ev[5][0].elapsed_time(ev[5][1]) for ev in evs])),
+                           "comparisons": w.rows * w.n_q,
+                           "note": "batch appended as entries, dots, reshare, compare, triangle mask, OR-tree, "
+                                   "OR with the database decision; inside the timed step"}
     return res, (w, qc, qm)
 
 
@@ -729,6 +777,8 @@ def main():
                     help="serve workload: one party's share of the service (its DB region and dot products)")
     ap.add_argument("--compare", choices=["mpclift", "lift18", "plain", "constlift", "nolift"], default="mpclift",
                     help="comparison setting of the full workload (Sec. 6.2)")
+    ap.add_argument("--in-batch", action="store_true",
+                    help="full workload: also match each query against the batch's earlier queries (Sec. 6.3)")
     args = ap.parse_args()
     if args.workload == "copy-probe":
         run_copy_probe(args)

@@ -235,17 +235,24 @@ BATCH_ENTRY_BASE = 1 << 47
 BATCH_OR_QID_OFFSET = 1 << 46
 
 
-def run_in_batch(ctx: Context, qs: SharedQueries, rot, buf_db: CheckBuffers, stream=None):
+def run_in_batch(ctx: Context, qs: SharedQueries, rot, buf_db: CheckBuffers, stream=None, reuse=None):
     """Query qi of the batch is also compared with queries j < qi.  buf_db
     holds the database check of the same queries (its dup); returns the
-    buffers of the batch part, whose `final` holds dup_db OR dup_batch."""
+    buffers of the batch part, whose `final` holds dup_db OR dup_batch.
+    reuse: the buffers a previous call on a batch of the same shape returned
+    (nothing is allocated then)."""
     assert qs.raw is not None and 0 < qs.q <= 64
     q, r = qs.q, len(rot)
-    region = SharedDB(ctx, 64, galois=qs.galois, device=buf_db.dup[0].device)
+    if reuse is not None:
+        assert reuse.rows == q * r and reuse.region.galois == qs.galois
+        region, buf, final = reuse.region, reuse, reuse.final
+    else:
+        region = SharedDB(ctx, 64, galois=qs.galois, device=buf_db.dup[0].device)
+        buf = alloc_check(q, r, q, device=buf_db.dup[0].device)
+        final = [torch.empty(2, q, dtype=torch.uint8, device=buf_db.dup[0].device) for _ in range(3)]
     for j in range(q):
         ctx.append_db(qs.raw, j, region.regions, region.capacity, j, stream, galois=qs.galois)
     region.n = q
-    buf = alloc_check(q, r, q, device=buf_db.dup[0].device)
     ids0 = make_ids(qs.qid_base, rot, 0)
     for p in range(3):
         ctx.dot_shares(p, qs.op[p], q, ids0, region.regions[p], region.capacity, q, buf.dot_code[p],
@@ -256,7 +263,6 @@ def run_in_batch(ctx: Context, qs: SharedQueries, rot, buf_db: CheckBuffers, str
     ctx.mask_in_batch(buf.match, q, r, buf.nw, 0, stream)
     ids_or = make_ids(qs.qid_base + BATCH_OR_QID_OFFSET, rot, BATCH_ENTRY_BASE)
     ctx.or_tree(buf.match, q, 1, buf.nw, ids_or, buf.ws, buf.ws.numel(), buf.dup, stream)
-    final = [torch.empty(2, q, dtype=torch.uint8, device=buf_db.dup[0].device) for _ in range(3)]
     ctx.or_bits(buf_db.dup, buf.dup, q, qs.qid_base, final, stream)
     buf.final = final
     buf.region = region

@@ -202,6 +202,21 @@ def party_local(n_db: int = 1_000_000, n_q: int = 32, seed: int = 0x1A150002) ->
     return w
 
 
+def plant_in_batch(w: Workload, qc: np.ndarray, qm: np.ndarray,
+                   pairs=((9, 4, 3, 0.20), (11, 2, -5, 0.30), (13, 12, 0, 0.42), (15, 14, 7, "eq"))):
+    """Make query i of the batch a near-duplicate of the earlier query j (at
+    rotation s, with fractional HD h or an exact-threshold case): the
+    duplicates that only in-batch matching finds.  Modifies qc, qm in place."""
+    for i, j, s, hx in pairs:
+        assert j < i < qc.shape[0]
+        if isinstance(hx, str):
+            c, m = plant(w.seed, i, qc[j], qm[j], s, exact=hx)
+        else:
+            c, m = plant(w.seed, i, qc[j], qm[j], s, h=hx)
+        qc[i], qm[i] = c, m
+    return qc, qm
+
+
 def make_queries(w: Workload, db_lookup=None):
     """Packed (codes, masks) [n_q, 200] for a workload.  ``db_lookup(e)``
     returns the packed (code, mask) of entry e (default: regenerate it)."""
