@@ -55,6 +55,11 @@ def test_in_batch_matches_oracle_and_plaintext(imc, keys, galois):
         for name, got in (("dup_batch", bb.dup[p]), ("dup", bb.final[p])):
             g = got.cpu().numpy()
             assert np.array_equal(g[0], ref[name][p]) and np.array_equal(g[1], ref[name][pm]), (name, p)
+    # a second run on the same buffers (nothing allocated) gives the same components
+    first = [t.clone() for t in bb.final]
+    again = run_in_batch(ctx, qs, rot, buf, reuse=bb)
+    torch.cuda.synchronize()
+    assert again is bb and all(torch.equal(a, b) for a, b in zip(first, bb.final))
     opened = np.bitwise_xor.reduce(np.stack([bb.final[p][0].cpu().numpy() for p in range(3)]), axis=0)
     want = [bool(orc.plain(qc[i:i + 1], qm[i:i + 1], rot, np.concatenate([dc, qc[:i]]),
                            np.concatenate([dm, qm[:i]]))[3][0]) for i in range(6)]
