@@ -65,14 +65,19 @@ __device__ __forceinline__ void limb_rows(const uint32_t v[16], uint4 out[4]) {
 }
 
 // Database: party p's region of vector vec, entry e in block e/32 slot e%32,
-// k-chunk g holds x_p[16g..], k-chunk 800 + g holds x_{p-1}[16g..].
+// k-chunk g holds x_p[16g..], k-chunk 800 + g holds x_{p-1}[16g..].  Thread
+// layout: 32 consecutive entries (one block) per 32 lanes, then g, so that a
+// wave's stores of one limb plane and k-chunk are 512 contiguous bytes.
 __global__ void __launch_bounds__(256) share32_db_kernel(Key dk, int vec, const uint64_t* codes, const uint64_t* masks,
                                                          uint64_t n, uint64_t first, uint8_t* d0, uint8_t* d1,
                                                          uint8_t* d2) {
+  constexpr uint32_t kGroups = kCodeBits / 16;   // 800
   const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= n * (kCodeBits / 16)) return;
-  const uint64_t j = t / (kCodeBits / 16);
-  const int g = int(t % (kCodeBits / 16));
+  const uint64_t chunk = t / (32 * kGroups);
+  const uint32_t within = uint32_t(t % (32 * kGroups));
+  const int g = int(within / 32);
+  const uint64_t j = chunk * 32 + within % 32;
+  if (j >= n) return;
   const uint64_t e = first + j;
   uint32_t c[3][16];
   share16x32(dk, kDomShare32Db, vec, e, codes + j * kWords, masks + j * kWords, g, c);
@@ -578,7 +583,7 @@ __global__ void __launch_bounds__(256) reshare32_kernel(Reshare32Args a) {
 // ---------------------------------------------------------------------------
 hipError_t launch_share32_db(const Key& dk, int vec, const uint64_t* codes, const uint64_t* masks, uint64_t n,
                              uint64_t first, uint8_t* const db[3], hipStream_t s) {
-  const uint64_t threads = n * (kCodeBits / 16);
+  const uint64_t threads = (n + 31) / 32 * 32 * (kCodeBits / 16);
   if (threads == 0) return hipSuccess;
   hipLaunchKernelGGL(share32_db_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, dk, vec, codes, masks,
                      n, first, db[0], db[1], db[2]);
