@@ -1,0 +1,64 @@
+"""Host-side logic of the benchmark, without a GPU: the one-GPU guard, the
+HBM-traffic figure's validity check, the comparison counts it reports, and
+the CPU baseline's fields on a tiny sample."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+import workload as wl  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr and r.stdout == ""
+
+
+def test_dot_traffic_only_for_the_measured_kernel_and_workload():
+    t = bench.dot_traffic(1984, 300_000, 0)
+    assert t is not None
+    # the stored passes: FETCH_SIZE scaled x2 (copy calibration), WRITE_SIZE x1
+    assert 43e9 < t < 44e9
+    assert bench.dot_traffic(1984, 300_001, 0) is None
+    assert bench.dot_traffic(992, 300_000, 0) is None
+    assert bench.dot_traffic(1984, 300_000, 1) is None       # an expanded tile configuration
+
+
+def test_reported_op_counts():
+    # 2 vectors x 25,600 k x 3 limb products x 2 ops per comparison and party
+    assert bench.OPS_PER_CMP_PARTY == 307_200
+    assert bench.DB_BYTES_PER_ENTRY_PARTY == 102_400
+    # ChaCha12: 12 rounds x 4 quarter-rounds x 12 int ops + 16 final adds
+    assert bench.CHACHA12_OPS == 592
+    assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
+
+
+def test_cpu_baseline_fields_on_a_tiny_sample():
+    w = wl.full_protocol(n_db=1024, n_q=2)
+    qc, qm = wl.make_queries(w)
+    r = bench.cpu_baseline(w, qc, qm, sample_q=1, sample_n=64)
+    assert r["kind"] == "oracle" and r["unit"] == "comparisons/s" and r["cores"] >= 1
+    assert r["value"] > 0 and "1 queries x 31 rotations x 64 entries" in r["sample"]
+    assert r["single_core"]["value"] > 0 and r["plaintext_check"]["single_core"] > 0
+    assert isinstance(r["cpu_model"], str)
+    import oracle as orc
+
+    assert orc.threads() == r["cores"]          # the single-thread timing restored the thread count
+
+
+def test_in_batch_planting_targets_earlier_queries():
+    import oracle as orc
+
+    w = wl.full_protocol(n_db=1024, n_q=16)
+    qc, qm = wl.make_queries(w)
+    wl.plant_in_batch(w, qc, qm)
+    dups = [int(orc.plain(qc[i:i + 1], qm[i:i + 1], w.rot, qc[:i], qm[:i])[3][0]) for i in (9, 11, 13, 15)]
+    assert dups == [1, 1, 0, 0]                # HD 0.20 and 0.30 match; 0.42 and the exact threshold do not
+    assert np.array_equal(wl.make_queries(w)[0][:9], qc[:9])
