@@ -88,6 +88,35 @@ def test_same_alone_in_mix_and_plain(env, galois, gather):
     assert mixed[1].dup == 1
 
 
+def test_admission_waits_for_free_hbm(env):
+    """Admission needs free HBM above the reserve: with the whole device
+    reserved nothing is admitted and the queue waits; once memory is
+    available again the queued requests run and give the plaintext decisions."""
+    from paper_2405_04463_amd.serve import Server
+
+    e = env
+    db = _db(e)
+    srv = Server(e["ctx"], db, ROT, chunk=CHUNK, slots=8, append=False, hbm_reserve=1.0)
+    for i in (0, 2):
+        srv.submit(_req(e, i, 4000 + i))
+    for _ in range(3):
+        assert srv.tick() is False
+    st = srv.state()
+    assert st["queued"] == 2 and st["active"] == 0 and st["done"] == 0
+    srv.hbm_reserve = 0
+    t = 0
+    while len(srv.done) < 2:
+        if not srv.tick():
+            torch.cuda.synchronize()
+        t += 1
+        assert t < 1000, srv.state()
+    torch.cuda.synchronize()
+    for r in srv.done:
+        _, _, _, dup = orc.plain(e["qc"][r.rid:r.rid + 1], e["qm"][r.rid:r.rid + 1], ROT, e["dc"], e["dm"])
+        assert r.dup == int(dup[0]), r.rid
+    assert sorted(r.dup for r in srv.done) == [0, 1]
+
+
 @pytest.mark.parametrize("galois", [False, True])
 def test_unique_requests_are_appended(env, galois):
     from paper_2405_04463_amd.serve import Request, Server
