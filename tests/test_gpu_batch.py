@@ -115,3 +115,28 @@ def test_graph_replay_matches_eager(env, mode, tiles):
         st.run_plain()           # eager work between replays
         torch.cuda.synchronize()
     e["ctx"].set_dot_tiles(imc.DOT_TILES_AUTO)
+
+
+def test_autotune_keeps_the_fastest_and_outputs_are_unchanged(env):
+    """The autotuner times every (mode, tile configuration) candidate on a
+    probe slice and keeps the fastest; whichever it keeps, the outputs are the
+    ones of the default configuration."""
+    from paper_2405_04463_amd.batch import BatchedStep
+    from paper_2405_04463_amd.tune import CANDIDATES_ROWS, CANDIDATES_UNIFORM
+
+    e = env
+    imc = e["imc"]
+    n = e["n"]
+    e["ctx"].set_dot_tiles(imc.DOT_TILES_AUTO)
+    ref = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], n, parties=(0,))
+    ref.run()
+    torch.cuda.synchronize()
+    want = (_u16(ref.dot_code[0])[:, :n].copy(), _u16(ref.dot_mask[0])[:, :n].copy())
+    st = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], n, parties=(0,))
+    mode, flags, times = st.autotune(probe_n=128, reps=1)
+    assert set(times) == {("rows", c) for c in CANDIDATES_ROWS} | {("grouped", c) for c in CANDIDATES_UNIFORM}
+    assert times[(mode, flags)] == min(times.values()) and st.mode == mode
+    st.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(_u16(st.dot_code[0])[:, :n], want[0]) and np.array_equal(_u16(st.dot_mask[0])[:, :n], want[1])
+    e["ctx"].set_dot_tiles(imc.DOT_TILES_AUTO)
