@@ -35,12 +35,12 @@ MFMA_I8_PEAK_TOPS = 5000.0      # MI355X dense int8, tera-ops/s (MAC = 2 ops)
 # WRITE_SIZE 1,048,580 KiB).  Valid only for the kernel sources it was taken on.
 DOT_TRAFFIC = {
     "sources": {"paper_2405_04463_amd/csrc/rot_dot.hip":
-                "af0e6016bbe4d9ae5ac7eedcff516e0085806d30b9229b2d1c0830599ac4c99c",
+                "e75a201cfa54fafc6fc870a62c6f6b3a24d4b482e979e7f8efbd867f4d60f89b",
                 "paper_2405_04463_amd/csrc/device.h":
                 "4c1a3b4ab4b31d959d8bad5a27477516a04872568ad8d0abc29b0de3c59b9f10"},
     "rows": 1984, "n_db": 300_000,
-    "fetch_kib": 20_015_500.0, "write_kib": 2_325_730.0,
-    "fetch_scale": 1_048_576 / 524_302.0, "write_scale": 1_048_576 / 1_048_580.0,
+    "fetch_kib": 19_850_300.0, "write_kib": 2_325_560.0,
+    "fetch_scale": 1_048_576 / 524_303.0, "write_scale": 1_048_576 / 1_048_580.0,
 }
 
 HBM_PEAK_GBS = 8000.0

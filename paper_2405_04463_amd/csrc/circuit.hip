@@ -856,6 +856,7 @@ hipError_t launch_reshare(const Keys3& keys, const uint16_t* const add_code[3], 
   a.r = ids.r;
   fill_rot(a.rot, ids);
   const uint64_t threads = rows * ((n + 15) / 16);
+  if (!fits_grid(threads, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(reshare_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -883,6 +884,7 @@ hipError_t launch_compare(const Keys3& keys, const uint16_t* const rep_code[3], 
   a.r = ids.r;
   fill_rot(a.rot, ids);
   const uint64_t threads = rows * a.nw;
+  if (!fits_grid(threads, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(compare_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -914,6 +916,7 @@ hipError_t launch_compare_variant(int variant, const Keys3& keys, const void* co
     vec = vec && (reinterpret_cast<uintptr_t>(a.code[p]) % 16) == 0 && (reinterpret_cast<uintptr_t>(a.mask[p]) % 16) == 0;
   a.vec = vec ? 1 : 0;
   fill_rot(a.rot, ids);
+  if (!fits_grid(rows * a.nw, 256)) return hipErrorInvalidValue;
   const dim3 grid(unsigned((rows * a.nw + 255) / 256)), block(256);
   switch (variant) {
     case kCmpPlain: hipLaunchKernelGGL((compare_variant_kernel<kCmpPlain, false>), grid, block, 0, s, a); break;
@@ -959,6 +962,7 @@ hipError_t launch_or_tree(const Keys3& keys, const uint64_t* const match[3], uin
     a.first = cur < 0;
     const uint64_t half = (len + 1) / 2;
     const uint64_t threads = q * ((half + 7) / 8);
+    if (!fits_grid(threads, 256)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(or_level_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -980,6 +984,7 @@ hipError_t launch_or_tree(const Keys3& keys, const uint64_t* const match[3], uin
   f.r = ids.r;
   f.level = level;
   f.first = cur < 0;
+  if (!fits_grid(q, 64)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(or_final_kernel, dim3(unsigned((q + 63) / 64)), dim3(64), 0, s, f);
   return hipGetLastError();
 }
@@ -989,6 +994,7 @@ __global__ void zero_counter_kernel(unsigned long long* c) { *c = 0ull; }
 hipError_t launch_open(int kind, const void* const rep[3], uint64_t count, void* out, int check,
                        unsigned long long* bad, hipStream_t s) {
   if (count == 0) return hipSuccess;
+  if (!fits_grid(count, 256)) return hipErrorInvalidValue;
   if (check) hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, bad);
   const dim3 grid(unsigned((count + 255) / 256)), block(256);
   switch (kind) {
@@ -1016,6 +1022,7 @@ hipError_t launch_mask_in_batch(uint64_t* const match[3], uint64_t q, uint32_t r
                                 hipStream_t s) {
   const uint64_t rows = q * r;
   if (rows == 0) return hipSuccess;
+  if (!fits_grid(rows, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(mask_in_batch_kernel, dim3(unsigned((rows + 255) / 256)), dim3(256), 0, s, match[0], match[1],
                      match[2], q, r, mw_ld, word);
   return hipGetLastError();
@@ -1033,6 +1040,7 @@ hipError_t launch_or_bits(const Keys3& keys, const uint8_t* const x[3], const ui
   }
   a.count = count;
   a.id = id;
+  if (!fits_grid(count, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(or_bits_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }

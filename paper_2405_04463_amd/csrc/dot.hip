@@ -284,6 +284,7 @@ hipError_t launch_expand(const int8_t* qop, const uint32_t* qidx, uint32_t q, ui
   for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) rr.s[i] = i < int(r) ? rot[i] : 0;
   const uint64_t chunks = galois ? Geo<kKGalois>::kChunks : Geo<kK>::kChunks;
   const uint64_t total = uint64_t(rows_pad) * kPlanes * chunks;
+  if (!fits_grid(total, 256)) return hipErrorInvalidValue;
   const dim3 grid(unsigned((total + 255) / 256));
   if (galois)
     hipLaunchKernelGGL(expand_kernel<kKGalois>, grid, dim3(256), 0, s, qop, qidx, q, r, rr, rows_pad, a);
@@ -298,6 +299,7 @@ static hipError_t launch_dot_cfg(DotArgs d, uint32_t rows, uint64_t n, hipStream
   d.mt = (rows + C::kBM - 1) / C::kBM;
   d.nt = uint32_t((n + C::kBN - 1) / C::kBN);
   const uint32_t ntg = (d.nt + 7) / 8;
+  if (uint64_t(ntg) * 8 * d.mt > 0x7FFFFFFFull) return hipErrorInvalidValue;
   uint32_t blocks = ntg * 8 * d.mt;
   d.persistent = 0;
   if (persistent) {
@@ -324,6 +326,7 @@ hipError_t launch_expand_rows(const int8_t* qop, uint32_t q, const imc_row* rows
                               uint32_t rows_pad, hipStream_t s, bool galois) {
   const uint64_t chunks = galois ? Geo<kKGalois>::kChunks : Geo<kK>::kChunks;
   const uint64_t total = uint64_t(rows_pad) * kPlanes * chunks;
+  if (!fits_grid(total, 256)) return hipErrorInvalidValue;
   const dim3 grid(unsigned((total + 255) / 256));
   if (galois)
     hipLaunchKernelGGL(expand_rows_kernel<kKGalois>, grid, dim3(256), 0, s, qop, q, rows, nrows, rows_pad, a);

@@ -585,6 +585,7 @@ hipError_t launch_share32_db(const Key& dk, int vec, const uint64_t* codes, cons
                              uint64_t first, uint8_t* const db[3], hipStream_t s) {
   const uint64_t threads = (n + 31) / 32 * 32 * (kCodeBits / 16);
   if (threads == 0) return hipSuccess;
+  if ((threads + 255) / 256 > 0x7FFFFFFFull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(share32_db_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, dk, vec, codes, masks,
                      n, first, db[0], db[1], db[2]);
   return hipGetLastError();
@@ -594,6 +595,7 @@ hipError_t launch_share32_query(const Key& dk, int vec, const uint64_t* codes, c
                                 uint64_t qid_base, int8_t* const op[3], hipStream_t s) {
   const uint64_t threads = q * (kCodeBits / 16);
   if (threads == 0) return hipSuccess;
+  if ((threads + 255) / 256 > 0x7FFFFFFFull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(share32_query_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, dk, vec, codes,
                      masks, q, qid_base, op[0], op[1], op[2]);
   return hipGetLastError();
@@ -652,6 +654,7 @@ hipError_t launch_reshare32(const Keys3& keys, int vec, const uint32_t* const ad
   a.wide = wide ? 1 : 0;
   for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) a.rot[i] = i < ids.r ? ids.rot[i] : 0;
   const uint64_t threads = rows * ((n + 7) / 8);
+  if ((threads + 255) / 256 > 0x7FFFFFFFull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(reshare32_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }

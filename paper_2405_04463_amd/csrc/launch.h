@@ -14,6 +14,9 @@ struct Key;
 struct Keys3;
 typedef imc_ids imc_ids_dev;
 
+// True when `threads` threads in workgroups of `block` fit the grid's x limit.
+inline bool fits_grid(uint64_t threads, uint64_t block) { return (threads + block - 1) / block <= 0x7FFFFFFFull; }
+
 hipError_t launch_share_db(const Key& dk, const uint64_t* codes, const uint64_t* masks, uint64_t n, uint64_t first,
                            uint8_t* const db[3], hipStream_t s);
 hipError_t launch_share_query(const Key& dk, const uint64_t* codes, const uint64_t* masks, uint64_t q,

@@ -116,6 +116,7 @@ hipError_t launch_rotate_masks(const uint64_t* masks, uint64_t q, const imc_ids_
   a.q = q;
   a.r = ids.r;
   for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) a.rot[i] = i < ids.r ? ids.rot[i] : 0;
+  if (!fits_grid(threads, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(rotate_masks_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -663,6 +663,7 @@ static hipError_t launch_rot_cfg(const int8_t* qop, const uint32_t* qidx, uint32
   if (int(d.max_q) * 2 * kSegChunks > ACH * kThreads) return hipErrorInvalidValue;
   for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) d.rot[i] = i < int(r) ? rot[i] : 0;
   const uint32_t ntg = (d.nt + 7) / 8;
+  if (uint64_t(ntg) * 8 * d.mt > 0x7FFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid(ntg * 8 * d.mt, 1, mask ? 2 : 1);   // z: code, mask
   const size_t lds = 3 * size_t(kBN / 32) * 2 * 2 * 32 * 16 + 2 * size_t(d.max_q) * 2 * kSegBytes;
   auto kern = rot_dot_kernel<K, WM, WN, WAVES_M, WAVES_N, NSETS, ACH>;
@@ -702,6 +703,7 @@ static hipError_t launch_rot_dma(const int8_t* qop, const uint32_t* qidx, uint32
   if (int(d.max_q) * 2 * kSegChunks > ACH * kThreads) return hipErrorInvalidValue;
   for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) d.rot[i] = i < int(r) ? rot[i] : 0;
   const uint32_t ntg = (d.nt + 7) / 8;
+  if (uint64_t(ntg) * 8 * d.mt > 0x7FFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid(ntg * 8 * d.mt, 1, mask ? 2 : 1);   // z: code, mask
   const size_t lds = size_t(S) * (kBN / 32) * 2 * 2 * 32 * 16 + 2 * size_t(ACH) * kThreads * 16;
   auto kern = rot_dot_dma_kernel<K, WM, WN, WAVES_M, WAVES_N, S, ACH>;
@@ -740,6 +742,7 @@ static hipError_t launch_rot_gb(const int8_t* qop, const uint32_t* qidx, uint32_
   if (int(d.max_q) * 2 * kSegChunks > ACH * kThreads) return hipErrorInvalidValue;
   for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) d.rot[i] = i < int(r) ? rot[i] : 0;
   const uint32_t ntg = (d.nt + 7) / 8;
+  if (uint64_t(ntg) * 8 * d.mt > 0x7FFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid(ntg * 8 * d.mt, 1, mask ? 2 : 1);   // z: code, mask
   const size_t lds = 2 * size_t(d.max_q) * 2 * kSegBytes;
   auto kern = rot_dot_gb_kernel<K, WM, WN, WAVES_M, WAVES_N, D, ACH>;

@@ -297,6 +297,7 @@ hipError_t launch_galois_share_db(const Key& dk, const uint64_t* codes, const ui
   if (n == 0) return hipSuccess;
   uint64_t threads = ((n + 31) / 32) * 32 * 800;
   DbOut o{{db[0], db[1], db[2]}};
+  if (!fits_grid(threads, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(galois_share_db_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, dk, codes, masks,
                      n, first, o);
   return hipGetLastError();
@@ -307,6 +308,7 @@ hipError_t launch_galois_share_query(const Key& dk, const uint64_t* codes, const
   if (q == 0) return hipSuccess;
   uint64_t threads = q * 800;
   QOut o{{op[0], op[1], op[2]}, {raw ? raw[0] : nullptr, raw ? raw[1] : nullptr, raw ? raw[2] : nullptr}};
+  if (!fits_grid(threads, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(galois_share_query_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, dk, codes,
                      masks, q, qid_base, o);
   return hipGetLastError();
@@ -325,6 +327,7 @@ hipError_t launch_share_db(const Key& dk, const uint64_t* codes, const uint64_t*
   if (n == 0) return hipSuccess;
   uint64_t threads = ((n + 31) / 32) * 32 * 800;
   DbOut o{{db[0], db[1], db[2]}};
+  if (!fits_grid(threads, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(share_db_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, dk, codes, masks, n,
                      first, o);
   return hipGetLastError();
@@ -335,6 +338,7 @@ hipError_t launch_share_query(const Key& dk, const uint64_t* codes, const uint64
   if (q == 0) return hipSuccess;
   uint64_t threads = q * 800;
   QOut o{{op[0], op[1], op[2]}, {raw ? raw[0] : nullptr, raw ? raw[1] : nullptr, raw ? raw[2] : nullptr}};
+  if (!fits_grid(threads, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(share_query_kernel, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, dk, codes, masks, q,
                      qid_base, o);
   return hipGetLastError();
