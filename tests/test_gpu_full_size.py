@@ -14,6 +14,8 @@ configuration the benchmark times, on outputs the oracle computes one by one.
   decision.
 * The batched step of 200 uneven batches against 1,000,000 entries.
 * Party-local serving over 1,500,000 entries of a 2,000,000-entry region.
+* The comparison settings (public masks, Lift to Z_2^18, ConstLift, NoLift)
+  at 64 queries x 31 rotations against 300,000 entries.
 """
 import numpy as np
 import pytest
@@ -281,6 +283,108 @@ def test_party_local_serving_at_1_5M_entries(imc, keys):
             want_c, want_m = orc.local_dot(0, qsh[rid:rid + 1], rot, dsh)
             assert np.array_equal(gc, want_c), rid
             assert np.array_equal(gm, want_m), rid
+    finally:
+        ctx.close()
+        free()
+
+
+@pytest.mark.parametrize("setting", ["plain", "lift18", "constlift", "nolift"])
+def test_comparison_settings_at_300k_entries(imc, keys, setting):
+    """The other comparison settings of the full protocol at 64 queries x 31
+    rotations against 300,000 entries per party, as the benchmark runs them:
+    the components of the compared values (public ml, reshared Z_2^16 or
+    Z_2^32 shares) and of the match bits on four sampled 64-entry groups
+    (the ragged last one among them) against the oracle's protocol in the
+    same setting, the opened bits of those groups against the plaintext
+    decision, and every query's opened duplicate bit against the OR of its
+    opened match bits."""
+    from paper_2405_04463_amd.pipeline import (VECS32, SharedDB, SharedDB32, SharedQueries, SharedQueries32,
+                                               alloc_check, open_dup, open_match, run_check)
+
+    dealer, party = keys
+    w = wl.full_protocol()
+    n, r = w.n_db, len(w.rot)
+    qc, qm = wl.make_queries(w)
+    v32 = VECS32.get(setting, ())
+    code16, plain = 0 not in v32, setting == "plain"
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=w.rows)
+    try:
+        db = SharedDB(ctx, n) if code16 else None
+        db32 = SharedDB32(ctx, n, vecs=v32) if v32 else None
+        db_masks = torch.empty(n, 200, dtype=torch.int64, device="cuda") if plain else None
+        for s in range(0, n, 65536):
+            m = min(65536, n - s)
+            c, k = wl.gen_codes(w.seed, s, m)
+            cd, kd = dev64(c), dev64(k)
+            if db is not None:
+                db.enroll(cd, kd, s)
+            if db32 is not None:
+                db32.enroll(cd, kd, s)
+            if db_masks is not None:
+                db_masks[s:s + m] = kd
+        q_codes, q_masks = dev64(qc), dev64(qm)
+        qs = SharedQueries(ctx, q_codes, q_masks, 0) if code16 else None
+        qs32 = SharedQueries32(ctx, q_codes, q_masks, 0, vecs=v32) if v32 else None
+        buf = alloc_check(w.n_q, r, n, compare=setting)
+        run_check(ctx, qs, w.rot, db, 0, n, buf, query_masks=q_masks, db_masks=db_masks, qs32=qs32, db32=db32)
+        mo, s1 = open_match(ctx, buf, check=1)
+        do, s2 = open_dup(ctx, buf, w.n_q, check=1)
+        torch.cuda.synchronize()
+        assert s1 == imc.IMC_OK and s2 == imc.IMC_OK
+
+        ngroups = (n + 63) // 64
+        rng = np.random.default_rng(15)
+        groups = sorted({0, ngroups - 1} | set(int(x) for x in rng.choice(ngroups - 1, 2, replace=False)))
+        u16 = lambda t: t.cpu().numpy().view(np.uint16)   # noqa: E731
+        u32 = lambda t: t.cpu().numpy().view(np.uint32)   # noqa: E731
+        got = {}
+        for g in groups:
+            a, b = 64 * g, min(64 * g + 64, n)
+            got[g] = {"match": [buf.match[p][:, :, g].cpu().numpy().view(np.uint64) for p in range(3)]}
+            if code16:
+                got[g]["rep_code"] = [u16(buf.rep_code[p][:, :, a:b]) for p in range(3)]
+            if setting == "lift18":
+                got[g]["rep_mask"] = [u16(buf.rep_mask[p][:, :, a:b]) for p in range(3)]
+            if plain:
+                got[g]["ml_pub"] = u16(buf.ml_pub[:, a:b])
+            for v in v32:
+                got[g]["rep32_%d" % v] = [u32(buf.rep32[v][p][:, :, a:b]) for p in range(3)]
+        mo = mo.cpu().numpy().view(np.uint64)
+        dup = do.cpu().numpy()
+        del buf, db, db32, db_masks, qs, qs32
+        free()
+
+        for g in groups:
+            a, b = 64 * g, min(64 * g + 64, n)
+            dc, dm = wl.gen_codes(w.seed, a, b - a)
+            ref = orc.protocol(dealer, party, qc, qm, w.rot, dc, dm, qid_base=0, first_entry=a,
+                               compare_setting=setting)
+            _, ml, match, _ = orc.plain(qc, qm, w.rot, dc, dm)
+            if plain:
+                assert np.array_equal(got[g]["ml_pub"], ml.astype(np.uint16)), g
+            for p in range(3):
+                pm = (p + 2) % 3
+                mt = got[g]["match"][p]
+                assert np.array_equal(mt[0], ref["match"][p][:, 0]) and np.array_equal(mt[1], ref["match"][pm][:, 0])
+                pairs = []
+                if code16:
+                    pairs.append(("rep_code", "rep_code"))
+                if setting == "lift18":
+                    pairs.append(("rep_mask", "rep_mask"))
+                if 1 in v32:
+                    pairs.append(("rep32_1", "rep_mask32"))
+                if 0 in v32:
+                    pairs.append(("rep32_0", "rep_code32"))
+                for gk, rk in pairs:
+                    x = got[g][gk][p]
+                    assert np.array_equal(x[0], ref[rk][p]) and np.array_equal(x[1], ref[rk][pm]), (g, gk, p)
+            bits = (mo[:, g][:, None] >> np.arange(b - a, dtype=np.uint64)) & np.uint64(1)
+            assert np.array_equal(bits.astype(np.uint8), match), g
+
+        real = mo.copy()
+        real[:, -1] &= np.uint64((1 << (n % 64)) - 1)
+        assert np.array_equal(dup.astype(bool), (real != 0).any(axis=1).reshape(w.n_q, r).any(axis=1))
+        assert dup.sum() > 0
     finally:
         ctx.close()
         free()
