@@ -95,7 +95,10 @@ def test_party_dot_at_one_million_entries(imc, keys):
         free()
 
 
-def test_three_party_protocol_at_300k_entries(imc, keys):
+@pytest.mark.parametrize("galois", [False, True])
+def test_three_party_protocol_at_300k_entries(imc, keys, galois):
+    """galois: the dot products on Galois-ring Shamir shares (the rest of the
+    protocol unchanged)."""
     from paper_2405_04463_amd.pipeline import SharedDB, SharedQueries, alloc_check, open_dup, open_match, run_check
 
     dealer, party = keys
@@ -105,9 +108,9 @@ def test_three_party_protocol_at_300k_entries(imc, keys):
     qc, qm = wl.make_queries(w)
     ctx = imc.Context(imc.Keys(dealer, party), max_rows=w.rows)
     try:
-        db = SharedDB(ctx, n)
+        db = SharedDB(ctx, n, galois=galois)
         enroll(db, w.seed, n)
-        qs = SharedQueries(ctx, dev64(qc), dev64(qm), 0)
+        qs = SharedQueries(ctx, dev64(qc), dev64(qm), 0, galois=galois)
         buf = alloc_check(w.n_q, r, n)
         run_check(ctx, qs, w.rot, db, 0, n, buf)
         mo, s1 = open_match(ctx, buf, check=1)
@@ -133,7 +136,8 @@ def test_three_party_protocol_at_300k_entries(imc, keys):
         for g in groups:
             a, b = 64 * g, min(64 * g + 64, n)
             dc, dm = wl.gen_codes(w.seed, a, b - a)
-            ref = orc.protocol(dealer, party, qc, qm, w.rot, dc, dm, qid_base=0, first_entry=a)
+            ref = orc.protocol(dealer, party, qc, qm, w.rot, dc, dm, qid_base=0, first_entry=a,
+                               **({"scheme": "galois"} if galois else {}))
             for p in range(3):
                 pm = (p + 2) % 3
                 rc, rmk, mt = got[g][p]
