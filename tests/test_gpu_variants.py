@@ -125,6 +125,7 @@ def test_compare_variant_on_random_components(ctx, imc, keys, variant, rows_r, n
     (9, list(range(-7, 8)), 257, 128, 3),      # 15 rotations (its larger query staging); row stride not 16-B aligned
     (5, [-3, 0, 9], 64, 0, 4),                 # one entry tile exactly
     (1, [7], 1, 0, 1),                         # a single comparison
+    (2, list(range(-15, 16)), 1, 192, 2),      # one entry against the rotation-aware kernel's tiles
 ])
 def test_dot32_and_reshare32_match_oracle(ctx, imc, keys, q, rot, n, first, pad):
     dealer, party = keys
