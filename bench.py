@@ -185,9 +185,15 @@ def cpu_baseline(w, qc, qm, sample_q=4, sample_n=40960, galois=False, compare="m
                                 "note": "the oracle's plaintext definition (popcounts of masked XOR and AND)"}}
 
 
-def verify(ctx, buf, w, qc, qm, n_sample=1024):
-    """Opened match bits vs the plaintext oracle on every planted entry plus a
-    random sample of entries (all rows)."""
+def verify(ctx, buf, w, qc, qm, party_keys):
+    """Every opened value of the step against the plaintext oracle (Alg. 1)
+    and the duplicate-bit components against the oracle's OR-tree (Sec. 4.2)
+    over the GPU's own match-bit components: each opened one is re-decided
+    on its pair and must be a match; the opened ones must be exactly the
+    plaintext matches of the planted pairs (all rotations), every other pair
+    being a random code ~25 standard deviations above the threshold; and
+    every opened duplicate bit must equal the plaintext one (0 for a query
+    without a planted match)."""
     import oracle as orc
     import workload as wl
     from paper_2405_04463_amd.pipeline import open_dup, open_match
@@ -195,24 +201,36 @@ def verify(ctx, buf, w, qc, qm, n_sample=1024):
     mo, s1 = open_match(ctx, buf, check=1)
     do, s2 = open_dup(ctx, buf, w.n_q, check=1)
     mo = mo.cpu().numpy().view(np.uint64)
-    rng = np.random.default_rng(5)
-    ents = sorted(set([e for _, e, _, _ in w.planted] + list(rng.choice(w.n_db, n_sample, replace=False))))
+    dup = do.cpu().numpy()
+    r, n = len(w.rot), buf.n
+    ones = []
+    for row, word in zip(*[x.tolist() for x in np.nonzero(mo)]):
+        v = int(mo[row, word])
+        while v:
+            low = v & -v
+            ones.append((row, 64 * word + low.bit_length() - 1))
+            v ^= low
+    ents = sorted({c for _, c in ones if c < n} | {e for _, e, _, _ in w.planted})
     dc = np.empty((len(ents), 200), np.uint64)
     dm = np.empty_like(dc)
     for i, e in enumerate(ents):
         c, m = wl.gen_codes(w.seed, e, 1)
         dc[i], dm[i] = c[0], m[0]
     _, _, match, _ = orc.plain(qc, qm, w.rot, dc, dm)
-    got = np.stack([(mo[:, e // 64] >> np.uint64(e % 64)) & np.uint64(1) for e in ents], axis=1).astype(np.uint8)
-    ok = bool(np.array_equal(got, match)) and s1 == 0 and s2 == 0
-    # every planted query that matches its entry must open dup = 1
-    dup = do.cpu().numpy()
-    planted_rows = {(qi, e): (match[qi * len(w.rot) + w.rot.index(s), ents.index(e)]) for qi, e, s, _ in w.planted}
-    for (qi, e), m in planted_rows.items():
-        if m:
-            ok = ok and bool(dup[qi] == 1)
-    return {"bit_exact": bool(ok), "pairs_checked": int(match.size), "matches_in_sample": int(match.sum()),
-            "dup_true": int(dup.sum())}
+    col = {e: i for i, e in enumerate(ents)}
+    want = {(qi * r + ri, e) for qi, e, _, _ in w.planted for ri in range(r) if match[qi * r + ri, col[e]]}
+    rejected = sum(1 for row, c in ones if c >= n or not match[row, col[c]])
+    want_dup = np.zeros(w.n_q, np.uint8)
+    for row, _ in want:
+        want_dup[row // r] = 1
+    comps = np.stack([buf.match[p][0].cpu().numpy().view(np.uint64)[:, :(n + 63) // 64] for p in range(3)])
+    ref, _ = orc.or_tree(party_keys, comps, w.n_q, r, 0)
+    or_ok = all(np.array_equal(buf.dup[p][0].cpu().numpy(), ref[p]) for p in range(3))
+    ok = (rejected == 0 and set(ones) == want and np.array_equal(dup, want_dup) and or_ok
+          and s1 == 0 and s2 == 0)
+    return {"bit_exact": bool(ok), "opened_bits": int(mo.shape[0]) * n,
+            "opened_ones": len(ones), "ones_rejected_by_plaintext": rejected, "planted_matches": len(want),
+            "dup_true": int(dup.sum()), "dup_expected": int(want_dup.sum()), "or_tree_components_equal": or_ok}
 
 
 def verify_in_batch(ctx, buf, bb, w, qc, qm):
@@ -298,7 +316,7 @@ def run_full(args):
     log(f"first step + verification against the oracle ({args.compare} comparison)")
     run_check(ctx, qs, w.rot, db, 0, w.n_db, buf, query_masks=q_masks, db_masks=db_masks, qs32=qs32, db32=db32)
     torch.cuda.synchronize()
-    ver = verify(ctx, buf, w, qc, qm)
+    ver = verify(ctx, buf, w, qc, qm, party)
     log(f"verification: {ver}")
     bb = None
     if in_batch:
@@ -778,7 +796,7 @@ def main():
     ap.add_argument("--compare", choices=["mpclift", "lift18", "plain", "constlift", "nolift"], default="mpclift",
                     help="comparison setting of the full workload (Sec. 6.2)")
     ap.add_argument("--in-batch", action="store_true",
-                    help="full workload: also match each query against the batch's earlier queries (Sec. 6.3)")
+                    help="full workload: also match each query against the batch's earlier queries (Sec. 6.4)")
     args = ap.parse_args()
     if args.workload == "copy-probe":
         run_copy_probe(args)

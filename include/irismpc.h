@@ -308,7 +308,7 @@ imc_status imc_open(imc_ctx* ctx, int kind, const void* const rep[3], size_t cou
 imc_status imc_append_db(imc_ctx* ctx, const void* const qraw[3], size_t qi, void* const db[3],
                          size_t db_capacity, uint64_t entry_id, imc_stream stream);
 
-/* In-batch matching (Sec. 6.3: the queries of a batch are also matched with
+/* In-batch matching (Sec. 6.4: the queries of a batch are also matched with
  * each other).  The batch's queries are compared as entries (their raw
  * shares appended to a region with imc_append_db, compared under entry ids
  * distinct from the database's) and query qi may only match the earlier

@@ -40,7 +40,9 @@ def build_lib() -> str:
 
 
 def _p(a):
-    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+    # data_as keeps a reference to the array, so a temporary (a contiguous
+    # copy made in the argument list) lives until the call returns
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
 
 def lib():

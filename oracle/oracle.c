@@ -587,6 +587,8 @@ void orc_or_tree(const uint8_t* keys, const uint64_t* match, int nq, int r, long
                  uint64_t qid_base, uint8_t* dup, long* and_words) {
   long rows = (long)nq * r;
   long tot = 0;
+  /* queries are independent trees: one per thread */
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : tot)
   for (int qi = 0; qi < nq; ++qi) {
     uint64_t st = ((uint64_t)DOM_OR << 56) | ((qid_base + (uint64_t)qi) & 0xFFFFFFFFFFFFull);
     long len = (long)r * nw;
@@ -623,7 +625,7 @@ void orc_or_tree(const uint8_t* keys, const uint64_t* match, int nq, int r, long
 }
 
 /* ------------------------------------------------------------------ */
-/* In-batch matching and combining decisions [Sec. 6.3: the queries of a */
+/* In-batch matching and combining decisions [Sec. 6.4: the queries of a */
 /* batch are also matched with each other; a person's query covers both  */
 /* eyes].  Query i of a batch is compared with the earlier queries j < i  */
 /* only: the shared match bits of columns j >= i are replaced by public   */

@@ -222,16 +222,23 @@ class BatchedStep:
         self.graph.replay()
 
 
+def centred_rotations(r: int) -> list[int]:
+    """The r rotation offsets of a query (Sec. 3: small circular shifts of the
+    angular axis), centred on 0: 1 -> [0], 15 -> [-7..7], 31 -> [-15..15]."""
+    if r < 1 or r > 31 or r % 2 == 0:
+        raise ValueError(f"rotation count {r}: an odd number in 1..31 is centred")
+    h = (r - 1) // 2
+    return list(range(-h, h + 1))
+
+
 def uneven_batches(n_batches: int, seed: int, qmax: int = 64, rot_counts=(1, 15, 31), qid0: int = 0):
     """Batch sizes uniform in 1..qmax, rotation counts drawn from rot_counts
     (centred offsets), consecutive query ids."""
-    from workload import rotations
-
     rng = np.random.default_rng(seed)
     out, qid = [], qid0
     for _ in range(n_batches):
         q = int(rng.integers(1, qmax + 1))
         r = int(rng.choice(rot_counts))
-        out.append(Batch(q, rotations(r), qid))
+        out.append(Batch(q, centred_rotations(r), qid))
         qid += q
     return out

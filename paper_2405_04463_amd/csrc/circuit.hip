@@ -752,7 +752,7 @@ __global__ void __launch_bounds__(64) or_final_kernel(OrFinalArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// In-batch matching (Sec. 6.3): query qi of a batch is compared with the
+// In-batch matching (Sec. 6.4): query qi of a batch is compared with the
 // earlier queries j < qi only.  The shared match bits of columns j >= qi in
 // word `word` of every row qi*r + ri become public zeros: every component of
 // both planes is cleared.

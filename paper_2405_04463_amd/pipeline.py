@@ -228,7 +228,7 @@ def open_dots(ctx: Context, buf: CheckBuffers, check: int = 1, stream=None):
     return outc, outm, (s1, s2)
 
 
-# In-batch matching (Sec. 6.3): the batch's queries are compared with each
+# In-batch matching (Sec. 6.4): the batch's queries are compared with each
 # other as entries, under entry ids distinct from the database's and an
 # OR-tree query-id offset distinct from the database tree's.
 BATCH_ENTRY_BASE = 1 << 47

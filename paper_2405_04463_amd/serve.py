@@ -16,7 +16,7 @@ Unique requests (dup = 0) are appended to the database.
 Because every random value is addressed by (query id, rotation, entry, gate)
 and the OR-tree runs over the request's complete buffer, a request's shares
 and result are the same alone and in any mix, whatever chunk it starts at.
-Serial uniqueness (Sec. 6.3: a batch is also matched against itself): a
+Serial uniqueness (Sec. 6.4: a batch is also matched against itself): a
 request must also match the unique requests admitted before it that were
 still in flight at its admission.  With `serial=True` (the default) a request
 whose pass over its snapshot is complete is finalised only after every

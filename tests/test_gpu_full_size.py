@@ -9,13 +9,17 @@ configuration the benchmark times, on outputs the oracle computes one by one.
   entries per party: the resharing components and the shared match bits of
   four 64-entry groups (the first, two random ones and the ragged last group
   of 32 entries) against the oracle's protocol run on those entries; the
-  opened duplicate bit of every query against the OR of its opened match
-  bits over the whole database; every planted pair against the plaintext
-  decision.
+  match-bit components of 32 more groups against the oracle's comparison of
+  the GPU's reshared components; the duplicate-bit components of every query
+  against the oracle's OR-tree over the GPU's match-bit components of the
+  whole database; every opened one re-decided by the plaintext check, the
+  opened ones equal to the plaintext matches of the planted pairs and every
+  opened duplicate bit equal to the plaintext one (tests/fullcheck.py).
 * The batched step of 200 uneven batches against 1,000,000 entries.
 * Party-local serving over 1,500,000 entries of a 2,000,000-entry region.
 * The comparison settings (public masks, Lift to Z_2^18, ConstLift, NoLift)
-  at 64 queries x 31 rotations against 300,000 entries.
+  at 64 queries x 31 rotations against 300,000 entries, with the same
+  OR-tree and opened-bit checks.
 """
 import numpy as np
 import pytest
@@ -98,7 +102,12 @@ def test_party_dot_at_one_million_entries(imc, keys):
 @pytest.mark.parametrize("galois", [False, True])
 def test_three_party_protocol_at_300k_entries(imc, keys, galois):
     """galois: the dot products on Galois-ring Shamir shares (the rest of the
-    protocol unchanged)."""
+    protocol unchanged).  Share-level parity on four groups from sharing on;
+    the comparison on the GPU's own reshared components of 32 more groups;
+    every opened bit and duplicate against the plaintext decision; the
+    duplicate-bit components against the oracle's OR-tree on the GPU's
+    match-bit components of the whole database."""
+    from fullcheck import check_every_opened_bit, check_or_tree_components
     from paper_2405_04463_amd.pipeline import SharedDB, SharedQueries, alloc_check, open_dup, open_match, run_check
 
     dealer, party = keys
@@ -122,17 +131,23 @@ def test_three_party_protocol_at_300k_entries(imc, keys, galois):
         assert n % 64 == 32                                   # the last group is ragged
         rng = np.random.default_rng(12)
         groups = sorted({0, ngroups - 1} | set(int(x) for x in rng.choice(ngroups - 1, 2, replace=False)))
+        more = sorted(set(int(x) for x in rng.choice(ngroups - 1, 40, replace=False)) - set(groups))[:32]
+        u16 = lambda t: t.cpu().numpy().view(np.uint16)   # noqa: E731
         got = {}
-        for g in groups:
+        for g in groups + more:
             a, b = 64 * g, min(64 * g + 64, n)
-            got[g] = [(buf.rep_code[p][:, :, a:b].cpu().numpy().view(np.uint16),
-                       buf.rep_mask[p][:, :, a:b].cpu().numpy().view(np.uint16),
-                       buf.match[p][:, :, g].cpu().numpy().view(np.uint64)) for p in range(3)]
+            got[g] = [(u16(buf.rep_code[p][:, :, a:b]), u16(buf.rep_mask[p][:, :, a:b])) for p in range(3)]
+        match_own = np.stack([buf.match[p][0].cpu().numpy().view(np.uint64) for p in range(3)])
+        match_prev = [buf.match[p][1].cpu().numpy().view(np.uint64) for p in range(3)]
+        dup_planes = [buf.dup[p].cpu().numpy() for p in range(3)]
         mo = mo.cpu().numpy().view(np.uint64)
         dup = do.cpu().numpy()
         del buf, db, qs
         free()
+        for p in range(3):   # replicated: party p's second plane is component p-1
+            assert np.array_equal(match_prev[p], match_own[(p + 2) % 3]), p
 
+        # share level from the dealer's sharing on
         for g in groups:
             a, b = 64 * g, min(64 * g + 64, n)
             dc, dm = wl.gen_codes(w.seed, a, b - a)
@@ -140,29 +155,29 @@ def test_three_party_protocol_at_300k_entries(imc, keys, galois):
                                **({"scheme": "galois"} if galois else {}))
             for p in range(3):
                 pm = (p + 2) % 3
-                rc, rmk, mt = got[g][p]
+                rc, rmk = got[g][p]
                 assert np.array_equal(rc[0], ref["rep_code"][p]) and np.array_equal(rc[1], ref["rep_code"][pm]), g
                 assert np.array_equal(rmk[0], ref["rep_mask"][p]) and np.array_equal(rmk[1], ref["rep_mask"][pm]), g
-                assert np.array_equal(mt[0], ref["match"][p][:, 0]) and np.array_equal(mt[1], ref["match"][pm][:, 0]), g
-            # the opened words of the group are the plaintext decision
+                assert np.array_equal(match_own[p][:, g], ref["match"][p][:, 0]), g
             _, _, match, _ = orc.plain(qc, qm, w.rot, dc, dm)
             bits = (mo[:, g][:, None] >> np.arange(b - a, dtype=np.uint64)) & np.uint64(1)
             assert np.array_equal(bits.astype(np.uint8), match), g
 
-        # dup[q] is the OR of q's opened match bits over every rotation and entry
-        real = mo.copy()
-        real[:, -1] &= np.uint64((1 << (n % 64)) - 1)
-        any_row = (real != 0).any(axis=1)
-        assert np.array_equal(dup.astype(bool), any_row.reshape(w.n_q, r).any(axis=1))
-        # each planted pair opens its plaintext decision
-        for qi, e, s, _ in w.planted:
-            ec, em = wl.gen_codes(w.seed, e, 1)
-            _, _, m1, _ = orc.plain(qc[qi:qi + 1], qm[qi:qi + 1], w.rot, ec, em)
-            for ri in range(r):
-                assert (int(mo[qi * r + ri, e // 64]) >> (e % 64)) & 1 == int(m1[ri, 0]), (qi, e, ri)
-            if m1.any():
-                assert dup[qi] == 1
-        assert dup.sum() > 0
+        # the comparison on the GPU's reshared components, 32 more groups
+        for g in more:
+            a = 64 * g
+            d = np.stack([got[g][p][0][0] for p in range(3)])
+            x = np.stack([got[g][p][1][0] for p in range(3)])
+            for p in range(3):
+                pm = (p + 2) % 3
+                assert np.array_equal(got[g][p][0][1], d[pm]) and np.array_equal(got[g][p][1][1], x[pm]), g
+            ref = orc.compare(party, d, x, w.n_q, w.rot, 0, a)
+            for p in range(3):
+                assert np.array_equal(match_own[p][:, g], ref[p][:, 0]), (g, p)
+
+        check_or_tree_components(party, match_own, dup_planes, w.n_q, r)
+        nones, ndup = check_every_opened_bit(mo, dup, w, qc, qm, n)
+        assert nones > 0 and ndup > 0
     finally:
         ctx.close()
         free()
@@ -300,8 +315,10 @@ def test_comparison_settings_at_300k_entries(imc, keys, setting):
     Z_2^32 shares) and of the match bits on four sampled 64-entry groups
     (the ragged last one among them) against the oracle's protocol in the
     same setting, the opened bits of those groups against the plaintext
-    decision, and every query's opened duplicate bit against the OR of its
-    opened match bits."""
+    decision, the duplicate-bit components against the oracle's OR-tree over
+    the GPU's match-bit components, and every opened bit and duplicate bit
+    against the plaintext decision."""
+    from fullcheck import check_every_opened_bit, check_or_tree_components
     from paper_2405_04463_amd.pipeline import (VECS32, SharedDB, SharedDB32, SharedQueries, SharedQueries32,
                                                alloc_check, open_dup, open_match, run_check)
 
@@ -353,6 +370,8 @@ def test_comparison_settings_at_300k_entries(imc, keys, setting):
                 got[g]["ml_pub"] = u16(buf.ml_pub[:, a:b])
             for v in v32:
                 got[g]["rep32_%d" % v] = [u32(buf.rep32[v][p][:, :, a:b]) for p in range(3)]
+        match_own = np.stack([buf.match[p][0].cpu().numpy().view(np.uint64) for p in range(3)])
+        dup_planes = [buf.dup[p].cpu().numpy() for p in range(3)]
         mo = mo.cpu().numpy().view(np.uint64)
         dup = do.cpu().numpy()
         del buf, db, db32, db_masks, qs, qs32
@@ -385,10 +404,9 @@ def test_comparison_settings_at_300k_entries(imc, keys, setting):
             bits = (mo[:, g][:, None] >> np.arange(b - a, dtype=np.uint64)) & np.uint64(1)
             assert np.array_equal(bits.astype(np.uint8), match), g
 
-        real = mo.copy()
-        real[:, -1] &= np.uint64((1 << (n % 64)) - 1)
-        assert np.array_equal(dup.astype(bool), (real != 0).any(axis=1).reshape(w.n_q, r).any(axis=1))
-        assert dup.sum() > 0
+        check_or_tree_components(party, match_own, dup_planes, w.n_q, r)
+        nones, ndup = check_every_opened_bit(mo, dup, w, qc, qm, n)
+        assert nones > 0 and ndup > 0
     finally:
         ctx.close()
         free()

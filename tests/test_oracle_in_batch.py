@@ -1,4 +1,4 @@
-"""Pins of the oracle's in-batch matching and decision combining (Sec. 6.3:
+"""Pins of the oracle's in-batch matching and decision combining (Sec. 6.4:
 the queries of a batch are matched with each other as well as with the
 database; a person's query covers both eyes).
 
