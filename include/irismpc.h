@@ -113,8 +113,11 @@ typedef struct imc_ids {
 
 /* Create a context on HIP device `device`.  Copies the keys, allocates the
  * internal scratch (rotated query operands for params->max_rows rows, about
- * 102,400 B per row, and a few counters).  Errors: IMC_EINVAL (null),
- * IMC_EUNSUPPORTED (code_bits, thr_a, flags), IMC_ENOMEM, IMC_EDEVICE. */
+ * 102,400 B per row, and a few counters) and, the first time on a device,
+ * looks up the device address of the static array that
+ * imc_dot_shares_rows_noalloc uses.  Errors: IMC_EINVAL (null),
+ * IMC_EUNSUPPORTED (code_bits, thr_a, flags; device index >= 64),
+ * IMC_ENOMEM, IMC_EDEVICE. */
 imc_status imc_create(const imc_params* params, int device, imc_ctx** out);
 
 /* Release the context and its scratch (synchronises the device).  NULL is a no-op. */
@@ -187,6 +190,26 @@ imc_status imc_dot_shares(imc_ctx* ctx, int party, const void* qop, size_t q, co
 imc_status imc_dot_shares_rows(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_row* rows,
                                size_t nrows, const void* db, size_t db_capacity, uint64_t first_entry_id,
                                size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld, imc_stream stream);
+
+/* Largest nrows of imc_dot_shares_rows_noalloc. */
+#define IMC_NOALLOC_MAX_ROWS 512
+
+/* For callers that cannot allocate device memory when they call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * imc_dot_shares_rows with the expanded rotated rows kept in a device array
+ * that the library holds statically (IMC_NOALLOC_MAX_ROWS rows, 52,428,800 B,
+ * on every GPU the library runs on, until the process ends) instead of the
+ * context's scratch.  The call allocates nothing; every byte of the array
+ * that the dot kernel reads is written by the same call first.  Arguments,
+ * results and errors are those of imc_dot_shares_rows, except that nrows is
+ * limited by IMC_NOALLOC_MAX_ROWS instead of the context's max_rows (more:
+ * IMC_ESHAPE).  All calls on one GPU share that GPU's array: calls that may
+ * overlap on one GPU (different streams, host threads or contexts) race and
+ * must be serialised by the caller. */
+imc_status imc_dot_shares_rows_noalloc(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_row* rows,
+                                       size_t nrows, const void* db, size_t db_capacity, uint64_t first_entry_id,
+                                       size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
+                                       imc_stream stream);
 
 /* imc_dot_shares over gathered queries: query i of the call (i < q) is row
  * qidx[i] of qop (qidx: DEVICE array of q u32; rows may repeat or come in any

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libirismpc.so")
 IMC_OK, IMC_EINVAL, IMC_ESHAPE, IMC_ENOMEM, IMC_EDEVICE, IMC_ECORRUPT, IMC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 OPEN_U8_XOR, OPEN_U64_XOR, OPEN_U16_ADD, OPEN_U32_ADD = 0, 1, 2, 3
 CODE_BITS, CODE_WORDS, MAX_ROT, ENTRY_BYTES = 12800, 200, 32, 102400
+NOALLOC_MAX_ROWS = 512   # rows of one imc_dot_shares_rows_noalloc call
 
 EXPORTS = [
     "imc_create", "imc_destroy", "imc_strerror", "imc_db_bytes", "imc_query_op_bytes", "imc_query_raw_bytes",
@@ -28,6 +29,7 @@ EXPORTS = [
     "imc_galois_append_db", "imc_mask_in_batch", "imc_or_bits", "imc_dot_shares_gather",
     "imc_galois_dot_shares_gather", "imc_compare_variant", "imc_rotate_masks", "imc_plain_ml", "imc_db32_bytes",
     "imc_query32_op_bytes", "imc_share32_db", "imc_share32_query", "imc_dot32_shares", "imc_reshare32",
+    "imc_dot_shares_rows_noalloc",
 ]
 
 (DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW, DOT_TILES_ROTATION,
@@ -106,6 +108,7 @@ def lib():
         L.imc_galois_share_query.argtypes = L.imc_share_query.argtypes
         L.imc_galois_dot_shares.argtypes = L.imc_dot_shares.argtypes
         L.imc_galois_dot_shares_rows.argtypes = L.imc_dot_shares_rows.argtypes
+        L.imc_dot_shares_rows_noalloc.argtypes = L.imc_dot_shares_rows.argtypes
         L.imc_galois_append_db.argtypes = L.imc_append_db.argtypes
         L.imc_mask_in_batch.argtypes = [_VP, _P3, sz, sz, sz, sz, _VP]
         L.imc_dot_shares_gather.argtypes = [_VP, ctypes.c_int, _VP, _VP, sz, ctypes.POINTER(imc_ids), _VP, sz, sz, _VP,
@@ -282,6 +285,13 @@ class Context:
         f = "imc_galois_dot_shares_rows" if galois else "imc_dot_shares_rows"
         return _check(getattr(lib(), f)(self._h, party, addr(qop), q, addr(rows), nrows, addr(db), capacity,
                                         first_entry_id, n, addr(code_dot), addr(mask_dot), ld, _stream(stream)), f)
+
+    # -- imc_dot_shares_rows_noalloc (expanded rows in the library's static device array)
+    def dot_shares_rows_noalloc(self, party, qop, q, rows, nrows, db, capacity, first_entry_id, n, code_dot, mask_dot,
+                                ld, stream=None):
+        return _check(lib().imc_dot_shares_rows_noalloc(self._h, party, addr(qop), q, addr(rows), nrows, addr(db),
+                                                        capacity, first_entry_id, n, addr(code_dot), addr(mask_dot),
+                                                        ld, _stream(stream)), "imc_dot_shares_rows_noalloc")
 
     # -- imc_set_dot_tiles
     def set_dot_tiles(self, flags: int):

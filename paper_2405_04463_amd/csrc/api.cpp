@@ -3,8 +3,10 @@
 // here, before anything is enqueued.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/irismpc.h"
@@ -22,7 +24,29 @@ struct imc_ctx {
   unsigned long long* bad;        // open-check counter
 };
 
+// Device array behind imc_dot_shares_rows_noalloc: the expanded rotated query
+// rows of one call (IMC_NOALLOC_MAX_ROWS rows in blocks of 32).  Each GPU the
+// library runs on holds its own copy until the process ends.  In host code
+// the name is only a handle for hipGetSymbolAddress: kernels and copies take
+// the per-device address resolved at context creation.
+static __device__ __align__(256) int8_t scratch[(IMC_NOALLOC_MAX_ROWS / 32) * imc::kBlockBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+std::atomic<int8_t*> g_scratch[kMaxDevices];   // address of `scratch` on each device, null until resolved
+
+// Resolve `scratch` on `device`, which must be the current device.  Once per device.
+imc_status resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return IMC_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device].load(std::memory_order_acquire)) return IMC_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return IMC_EDEVICE;
+  g_scratch[device].store(static_cast<int8_t*>(ptr), std::memory_order_release);
+  return IMC_OK;
+}
 
 imc::Key load_key(const uint8_t* b) {
   imc::Key k;
@@ -122,6 +146,13 @@ imc_status imc_create(const imc_params* p, int device, imc_ctx** out) {
     delete c;
     return IMC_ENOMEM;
   }
+  const imc_status rs = resolve_scratch(device);   // the device is current (guard above)
+  if (rs != IMC_OK) {
+    (void)hipFree(c->rot_op);
+    (void)hipFree(c->bad);
+    delete c;
+    return rs;
+  }
   *out = c;
   return IMC_OK;
 }
@@ -216,28 +247,36 @@ imc_status dot_shares_impl(imc_ctx* c, int party, const void* qop, const uint32_
   return dev_status(e);
 }
 
+// `a` receives the expanded rows (room for max_rows rows); a null `a` means the
+// static array of the current device (imc_dot_shares_rows_noalloc).
 imc_status dot_shares_rows_impl(imc_ctx* c, int party, const void* qop, size_t q, const imc_row* rows, size_t nrows,
                                 const void* db, size_t capacity, uint64_t first_entry_id, size_t n,
-                                uint16_t* code_dot, uint16_t* mask_dot, size_t ld, imc_stream stream, bool galois) {
+                                uint16_t* code_dot, uint16_t* mask_dot, size_t ld, imc_stream stream, bool galois,
+                                int8_t* a, size_t max_rows) {
   if (!c || party < 0 || party > 2) return IMC_EINVAL;
   if (nrows == 0 || n == 0) return IMC_OK;
   if (!qop || !rows || !db || !code_dot || q == 0) return IMC_EINVAL;   // mask_dot NULL: code dot only
   if (!aligned(qop, 16) || !aligned(rows, 8) || !aligned(db, 256) || !aligned(code_dot, 2) || !aligned(mask_dot, 2))
     return IMC_EINVAL;
   if (first_entry_id % 64) return IMC_EINVAL;
-  if (nrows > c->max_rows) return IMC_ESHAPE;
+  if (nrows > max_rows) return IMC_ESHAPE;
   if (ld < n) return IMC_ESHAPE;
   if (first_entry_id > capacity || n > capacity - first_entry_id) return IMC_ESHAPE;
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;
+  if (!a) {
+    a = g_scratch[c->device].load(std::memory_order_acquire);   // resolved by imc_create
+    if (!a) return IMC_EDEVICE;
+  }
+  // every row the dot kernel reads (padding rows as zeros) is written here first
   const uint32_t rows_pad = uint32_t(blocks_for(nrows) * 32);
-  hipError_t e = imc::launch_expand_rows(static_cast<const int8_t*>(qop), uint32_t(q), rows, uint32_t(nrows), c->rot_op,
+  hipError_t e = imc::launch_expand_rows(static_cast<const int8_t*>(qop), uint32_t(q), rows, uint32_t(nrows), a,
                                          rows_pad, hipStream_t(stream), galois);
   if (e != hipSuccess) return IMC_EDEVICE;
   int v = c->dot_variant;
   if ((v & 0xF) == IMC_DOT_TILES_AUTO || (v & 0xF) >= IMC_DOT_TILES_ROTATION)
     v = (v & ~0xF) | IMC_DOT_TILES_EXPANDED_256x128;
-  e = imc::launch_dot(c->rot_op, uint32_t(nrows), rows_pad / 32, static_cast<const int8_t*>(db), first_entry_id, n,
+  e = imc::launch_dot(a, uint32_t(nrows), rows_pad / 32, static_cast<const int8_t*>(db), first_entry_id, n,
                       code_dot, mask_dot, ld, hipStream_t(stream), v, galois);
   return dev_status(e);
 }
@@ -305,15 +344,24 @@ imc_status imc_galois_dot_shares_gather(imc_ctx* c, int party, const void* qop, 
 imc_status imc_dot_shares_rows(imc_ctx* c, int party, const void* qop, size_t q, const imc_row* rows, size_t nrows,
                                const void* db, size_t capacity, uint64_t first_entry_id, size_t n, uint16_t* code_dot,
                                uint16_t* mask_dot, size_t ld, imc_stream stream) {
+  if (!c) return IMC_EINVAL;
   return dot_shares_rows_impl(c, party, qop, q, rows, nrows, db, capacity, first_entry_id, n, code_dot, mask_dot, ld,
-                              stream, false);
+                              stream, false, c->rot_op, c->max_rows);
+}
+imc_status imc_dot_shares_rows_noalloc(imc_ctx* c, int party, const void* qop, size_t q, const imc_row* rows,
+                                       size_t nrows, const void* db, size_t capacity, uint64_t first_entry_id,
+                                       size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
+                                       imc_stream stream) {
+  return dot_shares_rows_impl(c, party, qop, q, rows, nrows, db, capacity, first_entry_id, n, code_dot, mask_dot, ld,
+                              stream, false, nullptr, IMC_NOALLOC_MAX_ROWS);
 }
 imc_status imc_galois_dot_shares_rows(imc_ctx* c, int party, const void* qop, size_t q, const imc_row* rows,
                                       size_t nrows, const void* db, size_t capacity, uint64_t first_entry_id,
                                       size_t n, uint16_t* code_dot, uint16_t* mask_dot, size_t ld,
                                       imc_stream stream) {
+  if (!c) return IMC_EINVAL;
   return dot_shares_rows_impl(c, party, qop, q, rows, nrows, db, capacity, first_entry_id, n, code_dot, mask_dot, ld,
-                              stream, true);
+                              stream, true, c->rot_op, c->max_rows);
 }
 imc_status imc_append_db(imc_ctx* c, const void* const qraw[3], size_t qi, void* const db[3], size_t capacity,
                          uint64_t entry_id, imc_stream stream) {
