@@ -61,6 +61,7 @@ def lib():
         _lib.orc_test_gr_inv.restype = ctypes.c_int
         _lib.orc_compare_variant.restype = ctypes.c_int
         _lib.orc_test_compare_variant.restype = ctypes.c_int
+        _lib.orc_msg_count.restype = ctypes.c_int
     return _lib
 
 
@@ -140,33 +141,44 @@ def reshare(keys: bytes, z_code, z_mask, nq, rot, qid_base, first_entry):
     return oc, om
 
 
-def compare(keys: bytes, d_comp, x_comp, nq, rot, qid_base, first_entry, want_aux=False):
+def msg_count(variant: int = 0) -> int:
+    """Messages (bits sent by the three parties) per comparison of a setting:
+    0 = MPCLift, else CMPV_*."""
+    return lib().orc_msg_count(ctypes.c_int(variant))
+
+
+def compare(keys: bytes, d_comp, x_comp, nq, rot, qid_base, first_entry, want_aux=False, want_msg=False):
     """Components of the match bits [3, rows, nw] (u64) from components of the
     code dot and ml [3, rows, n].  With want_aux also returns lifted-ml and y
-    components [3, rows, n] (u32) and counts (AND gates, bits sent by 0,1,2)."""
+    components [3, rows, n] (u32) and counts (AND gates, bits sent by 0,1,2).
+    With want_msg the last item returned is the message log
+    [msg_count(0), rows, nw] (u64, bit o of word w = column 64 w + o)."""
     _, rows, n = d_comp.shape
     nw = (n + 63) // 64
     match = np.zeros((3, rows, nw), dtype=np.uint64)
     ml = np.zeros((3, rows, n), dtype=np.uint32) if want_aux else None
     y = np.zeros((3, rows, n), dtype=np.uint32) if want_aux else None
+    msg = np.zeros((msg_count(0), rows, nw), dtype=np.uint64) if want_msg else None
     counts = np.zeros(4, dtype=np.int64)
     rc = lib().orc_compare(ctypes.c_char_p(bytes(keys)), _p(np.ascontiguousarray(d_comp)),
                            _p(np.ascontiguousarray(x_comp)), ctypes.c_int(nq), _p(_rot(rot)),
                            ctypes.c_int(len(rot)), ctypes.c_long(n), ctypes.c_uint64(qid_base),
-                           ctypes.c_uint64(first_entry), _p(match), _p(ml), _p(y), _p(counts))
+                           ctypes.c_uint64(first_entry), _p(match), _p(ml), _p(y), _p(counts), _p(msg))
     if rc != 0:
         raise ValueError("first_entry must be a multiple of 64")
-    if want_aux:
-        return match, ml, y, counts
-    return match
+    out = (match, ml, y, counts) if want_aux else (match,)
+    if want_msg:
+        out = out + (msg,)
+    return out if len(out) > 1 else match
 
 
 def compare_variant(keys: bytes, variant: int, d_comp, x_comp, ml_pub, nq, rot, qid_base, first_entry,
-                    want_aux=False):
+                    want_aux=False, want_msg=False):
     """Comparison variant (CMPV_*) over [3, rows, n] components: d_comp the
     code dot (u16 or u32), x_comp ml (u16 for LIFT18, u32 for CONST32, None
     for PLAIN), ml_pub [rows, n] the public ml (PLAIN).  Returns the match
-    components [3, rows, nw]; with want_aux also y components and counts."""
+    components [3, rows, nw]; with want_aux also y components and counts;
+    with want_msg the message log [msg_count(variant), rows, nw] last."""
     _, rows, n = d_comp.shape
     nw = (n + 63) // 64
     d32 = np.ascontiguousarray(d_comp.astype(np.uint32))
@@ -174,16 +186,18 @@ def compare_variant(keys: bytes, variant: int, d_comp, x_comp, ml_pub, nq, rot, 
     mlp = None if ml_pub is None else np.ascontiguousarray(np.asarray(ml_pub, dtype=np.int32))
     match = np.zeros((3, rows, nw), dtype=np.uint64)
     y = np.zeros((3, rows, n), dtype=np.uint32) if want_aux else None
+    msg = np.zeros((msg_count(variant), rows, nw), dtype=np.uint64) if want_msg else None
     counts = np.zeros(4, dtype=np.int64)
     rc = lib().orc_compare_variant(ctypes.c_int(variant), ctypes.c_char_p(bytes(keys)), _p(d32), _p(x32), _p(mlp),
                                    ctypes.c_int(nq), _p(_rot(rot)), ctypes.c_int(len(rot)), ctypes.c_long(n),
                                    ctypes.c_uint64(qid_base), ctypes.c_uint64(first_entry), _p(match), _p(y),
-                                   _p(counts))
+                                   _p(counts), _p(msg))
     if rc != 0:
         raise ValueError("bad variant or first_entry not a multiple of 64")
-    if want_aux:
-        return match, y, counts
-    return match
+    out = (match, y, counts) if want_aux else (match,)
+    if want_msg:
+        out = out + (msg,)
+    return out if len(out) > 1 else match
 
 
 def share32(dealer_key: bytes, dom: int, codes, masks, first_id: int):

@@ -105,6 +105,12 @@
 #define TAPE_W0_B 168
 #define TAPE_W1_B 184
 #define TAPE_WORDS 200       /* 25 ChaCha blocks per key per 64-entry group */
+/* Message log of one MPCLift comparison (see ccount): 94 AND gates x 3
+ * senders, then the two BitInjects (4 x 15 and 4 x 16 bits): 406 messages,
+ * the bits the three parties send (156 + 125 + 125). */
+#define MSG_INJ_A (3 * (2 * LIFT_M - 1 + 2 * MSB_M - 1))   /* 282 */
+#define MSG_INJ_B (MSG_INJ_A + 4 * INJ_A_K)                   /* 342 */
+#define MSG_MPCLIFT (MSG_INJ_B + 4 * INJ_B_K)                 /* 406 */
 #define TAPE_BLOCKS_PER_GROUP 32
 
 /* ------------------------------------------------------------------ */
@@ -356,8 +362,14 @@ typedef struct {
   uint32_t c0[2], c2[2], w0[2], w1[2];   /* [0] = inject A (Z_2^15), [1] = inject B (Z_2^16) */
 } crand;
 
-/* Communication and gate accounting. */
-typedef struct { long and_gates; long bits_sent[3]; } ccount;
+/* Communication and gate accounting.  msg (optional) logs every message of
+ * one comparison, one bit per message, in the order the protocol sends them:
+ * AND gate g (numbered in evaluation order) from party p at msg[3 g + p];
+ * then, per BitInject (first the one of the higher bit), the 3OT messages
+ * k0 and k1 (party 0 -> 1), w_c (party 2 -> 1) and c1 (party 1 -> 2), k bits
+ * each, bit j of k0 at base + j, of k1 at base + k + j, of w_c at
+ * base + 2k + j, of c1 at base + 3k + j.  The log changes no arithmetic. */
+typedef struct { long and_gates; long bits_sent[3]; uint8_t* msg; } ccount;
 
 static bsh bxor(bsh a, bsh b) {
   bsh z;
@@ -368,23 +380,28 @@ static bsh bxor(bsh a, bsh b) {
 static bsh bsh_zero(void) { bsh z = {{0, 0, 0}, 0}; return z; }
 
 /* ABY3 AND [App. C]: z_p = x_p y_p ^ x_{p-1} y_p ^ x_p y_{p-1} ^ r_p with the
- * zero share r_p = F(key_p) ^ F(key_{p-1}); z_p is sent to party p+1. */
-static bsh band(bsh x, bsh y, const uint8_t* f, ccount* cnt) {
+ * zero share r_p = F(key_p) ^ F(key_{p-1}); z_p is sent to party p+1.  g is
+ * the gate's number in evaluation order (its messages' place in the log). */
+static bsh band(bsh x, bsh y, const uint8_t* f, int g, ccount* cnt) {
   bsh z;
   for (int p = 0; p < 3; ++p) {
     int pm = (p + 2) % 3;
     z.c[p] = (uint8_t)((x.c[p] & y.c[p]) ^ (x.c[pm] & y.c[p]) ^ (x.c[p] & y.c[pm]) ^ f[p] ^ f[pm]);
   }
   z.depth = (x.depth > y.depth ? x.depth : y.depth) + 1;
-  if (cnt) { cnt->and_gates++; for (int p = 0; p < 3; ++p) cnt->bits_sent[p]++; }
+  if (cnt) {
+    cnt->and_gates++;
+    for (int p = 0; p < 3; ++p) cnt->bits_sent[p]++;
+    if (cnt->msg) for (int p = 0; p < 3; ++p) cnt->msg[3 * g + p] = z.c[p];
+  }
   return z;
 }
 
 /* FA [App. D]: t1 = a^c, t2 = b^c, s = t1^b, o = t1 t2 ^ c.  Returns s; o via out. */
-static bsh full_adder(bsh a, bsh b, bsh c, const uint8_t* f, bsh* carry, ccount* cnt) {
+static bsh full_adder(bsh a, bsh b, bsh c, const uint8_t* f, int g, bsh* carry, ccount* cnt) {
   bsh t1 = bxor(a, c), t2 = bxor(b, c);
   bsh s = bxor(t1, b);
-  if (carry) *carry = bxor(band(t1, t2, f, cnt), c);
+  if (carry) *carry = bxor(band(t1, t2, f, g, cnt), c);
   return s;
 }
 
@@ -394,8 +411,12 @@ static bsh full_adder(bsh a, bsh b, bsh c, const uint8_t* f, bsh* carry, ccount*
  * bits 0..m (carry of bit m unused), then BinAdd((c[m-1..0], 0), s[m..0]).
  * Randomness: the FA-layer gate of bit i (i < m) uses tape word w0 + 2i, the
  * ripple gate producing the carry into bit i+1 (1 <= i < m) word w0 + 2i + 1.
+ * Gate numbers (message log order) run bit by bit, a bit's FA-layer gate
+ * before its ripple gate: the FA gate of bit i is g0 + 2i - 1 (g0 for
+ * i = 0), the ripple gate of bit i is g0 + 2i; 2m - 1 gates in all.
  * Returns r[0..m]. */
-static void bit_extract(const uint32_t x[3], int m, int w0, int d0, const crand* rnd, bsh* r, ccount* cnt) {
+static void bit_extract(const uint32_t x[3], int m, int w0, int g0, int d0, const crand* rnd, bsh* r,
+                        ccount* cnt) {
   bsh s[33], c[33];
   for (int i = 0; i < 33; ++i) s[i] = c[i] = bsh_zero();
   for (int i = 0; i <= m; ++i) {
@@ -404,7 +425,7 @@ static void bit_extract(const uint32_t x[3], int m, int w0, int d0, const crand*
     a.c[0] = (uint8_t)((x[0] >> i) & 1u);   /* InpLocal(x_1[i], party 1) */
     b.c[1] = (uint8_t)((x[1] >> i) & 1u);   /* InpLocal(x_2[i], party 2) */
     cc.c[2] = (uint8_t)((x[2] >> i) & 1u);  /* InpLocal(x_3[i], party 3) */
-    s[i] = full_adder(a, b, cc, rnd->g[w0 + 2 * i], i < m ? &c[i] : NULL, cnt);
+    s[i] = full_adder(a, b, cc, rnd->g[w0 + 2 * i], g0 + (i == 0 ? 0 : 2 * i - 1), i < m ? &c[i] : NULL, cnt);
   }
   /* BinAdd: A[0] = 0 (public), A[i] = c[i-1]; B[i] = s[i]. */
   bsh carry = bsh_zero();   /* carry into bit 1 is A[0] AND B[0] = 0 (public) */
@@ -414,7 +435,7 @@ static void bit_extract(const uint32_t x[3], int m, int w0, int d0, const crand*
     r[i] = bxor(bxor(A, B), carry);
     if (i < m) {
       bsh t1 = bxor(A, carry), t2 = bxor(B, carry);
-      carry = bxor(band(t1, t2, rnd->g[w0 + 2 * i + 1], cnt), carry);
+      carry = bxor(band(t1, t2, rnd->g[w0 + 2 * i + 1], g0 + 2 * i, cnt), carry);
     }
   }
 }
@@ -422,11 +443,21 @@ static void bit_extract(const uint32_t x[3], int m, int w0, int d0, const crand*
 /* 3OT [App. D]: sender party 0 holds (m0, m1), receiver party 1 and helper
  * party 2 hold the choice bit ch; pads w0, w1 come from key_2 (held by
  * parties 0 and 2).  Returns m_ch at the receiver. */
-static uint32_t three_ot(uint32_t m0, uint32_t m1, int ch, uint32_t w0, uint32_t w1, int k, ccount* cnt) {
+static uint32_t three_ot(uint32_t m0, uint32_t m1, int ch, uint32_t w0, uint32_t w1, int k, int mbase,
+                         ccount* cnt) {
   uint32_t mask = (k == 32) ? 0xFFFFFFFFu : ((1u << k) - 1u);
   uint32_t k0 = (w0 ^ m0) & mask, k1 = (w1 ^ m1) & mask;   /* party 0 -> party 1 */
   uint32_t wc = (ch ? w1 : w0) & mask;                      /* party 2 -> party 1 */
-  if (cnt) { cnt->bits_sent[0] += 2 * k; cnt->bits_sent[2] += k; }
+  if (cnt) {
+    cnt->bits_sent[0] += 2 * k;
+    cnt->bits_sent[2] += k;
+    if (cnt->msg)
+      for (int j = 0; j < k; ++j) {
+        cnt->msg[mbase + j] = (uint8_t)((k0 >> j) & 1u);
+        cnt->msg[mbase + k + j] = (uint8_t)((k1 >> j) & 1u);
+        cnt->msg[mbase + 2 * k + j] = (uint8_t)((wc >> j) & 1u);
+      }
+  }
   return (wc ^ (ch ? k1 : k0)) & mask;
 }
 
@@ -434,14 +465,18 @@ static uint32_t three_ot(uint32_t m0, uint32_t m1, int ch, uint32_t w0, uint32_t
  * (key_2, parties 0,2) are random; party 0 forms m_t = (t ^ x0 ^ x2) - c0 - c2
  * for t in {0,1}; the 3OT with choice x1 gives party 1 c1 = m_{x1}, which it
  * sends to party 2.  Output components (c0, c1, c2) mod 2^k. */
-static void bit_inject(bsh x, int k, uint32_t c0, uint32_t c2, uint32_t w0, uint32_t w1,
+static void bit_inject(bsh x, int k, uint32_t c0, uint32_t c2, uint32_t w0, uint32_t w1, int mbase,
                        uint32_t out[3], ccount* cnt) {
   uint32_t mask = (k == 32) ? 0xFFFFFFFFu : ((1u << k) - 1u);
   c0 &= mask; c2 &= mask;
   uint32_t m[2];
   for (int t = 0; t < 2; ++t) m[t] = ((uint32_t)(t ^ x.c[0] ^ x.c[2]) - c0 - c2) & mask;
-  uint32_t c1 = three_ot(m[0], m[1], x.c[1], w0, w1, k, cnt);
-  if (cnt) cnt->bits_sent[1] += k;   /* party 1 -> party 2 */
+  uint32_t c1 = three_ot(m[0], m[1], x.c[1], w0, w1, k, mbase, cnt);
+  if (cnt) {
+    cnt->bits_sent[1] += k;   /* party 1 -> party 2 */
+    if (cnt->msg)
+      for (int j = 0; j < k; ++j) cnt->msg[mbase + 3 * k + j] = (uint8_t)((c1 >> j) & 1u);
+  }
   out[0] = c0; out[1] = c1; out[2] = c2;
 }
 
@@ -454,12 +489,12 @@ static bsh compare_one(const uint16_t d[3], const uint16_t x[3], const crand* rn
   /* Lift [App. D]: InpLocal each component into Z_2^32 and add. */
   uint32_t S[3] = {x[0], x[1], x[2]};
   bsh r[33];
-  bit_extract(S, LIFT_M, LIFT_W0, 0, rnd, r, cnt);
+  bit_extract(S, LIFT_M, LIFT_W0, 0, 0, rnd, r, cnt);
   bsh a = r[17], b = r[16];
   int d_inj = (a.depth > b.depth ? a.depth : b.depth) + 2;   /* 3OT round + c1 forwarding round */
   uint32_t A[3], B[3];
-  bit_inject(a, INJ_A_K, rnd->c0[0], rnd->c2[0], rnd->w0[0], rnd->w1[0], A, cnt);
-  bit_inject(b, INJ_B_K, rnd->c0[1], rnd->c2[1], rnd->w0[1], rnd->w1[1], B, cnt);
+  bit_inject(a, INJ_A_K, rnd->c0[0], rnd->c2[0], rnd->w0[0], rnd->w1[0], MSG_INJ_A, A, cnt);
+  bit_inject(b, INJ_B_K, rnd->c0[1], rnd->c2[1], rnd->w0[1], rnd->w1[1], MSG_INJ_B, B, cnt);
   uint32_t ml[3], y[3];
   for (int p = 0; p < 3; ++p) {
     uint32_t a17 = A[p] << 17;        /* ConstLift([a]_{2^15}, 2^17) */
@@ -470,7 +505,7 @@ static bsh compare_one(const uint16_t d[3], const uint16_t x[3], const crand* rn
     if (ml_lift) ml_lift[p] = ml[p];
     if (y_out) y_out[p] = y[p];
   }
-  bit_extract(y, MSB_M, MSB_W0, d_inj, rnd, r, cnt);
+  bit_extract(y, MSB_M, MSB_W0, 2 * LIFT_M - 1, d_inj, rnd, r, cnt);
   return r[31];
 }
 
@@ -501,12 +536,14 @@ static void gather_rand(const uint64_t tape[3][TAPE_WORDS], int o, crand* rnd) {
  * and of ml.  match: [3][rows][nw] u64 components of the match bits, bit o of
  * word w = entry column 64w + o; bits at columns >= n are public zeros.
  * Optional (NULL to skip): ml_out [3][rows][n] u32 components of lifted ml;
- * y_out likewise; counts[4] = {AND gates, bits sent by party 0, 1, 2}.
+ * y_out likewise; counts[4] = {AND gates, bits sent by party 0, 1, 2};
+ * msg_out [406][rows][nw] u64: every message of every comparison (the log
+ * order of ccount), bit o of word w = the comparison at column 64w + o.
  * Randomness: stream (DOM_CMP, qid, rot), group G = entry>>6 at block
  * position G*32 + t/8.  first_entry must be a multiple of 64. */
 int orc_compare(const uint8_t* keys, const uint16_t* d_comp, const uint16_t* x_comp,
                 int nq, const int* rot, int r, long n, uint64_t qid_base, uint64_t first_entry,
-                uint64_t* match, uint32_t* ml_out, uint32_t* y_out, long* counts) {
+                uint64_t* match, uint32_t* ml_out, uint32_t* y_out, long* counts, uint64_t* msg_out) {
   if (first_entry % 64) return -1;
   long rows = (long)nq * r;
   long nw = (n + 63) / 64;
@@ -515,7 +552,7 @@ int orc_compare(const uint8_t* keys, const uint16_t* d_comp, const uint16_t* x_c
   for (long row = 0; row < rows; ++row) {
     uint64_t qid = qid_base + (uint64_t)(row / r);
     uint64_t st = row_stream(DOM_CMP, qid, rot[row % r]);
-    ccount cnt = {0, {0, 0, 0}};
+    ccount cnt = {0, {0, 0, 0}, NULL};
     static __thread uint64_t tape[3][TAPE_WORDS];
     for (long w = 0; w < nw; ++w) {
       uint64_t G = (first_entry >> 6) + (uint64_t)w;
@@ -538,12 +575,16 @@ int orc_compare(const uint8_t* keys, const uint16_t* d_comp, const uint16_t* x_c
         crand rnd;
         gather_rand(tape, o, &rnd);
         uint32_t mlv[3], yv[3];
+        uint8_t msg[MSG_MPCLIFT];
+        cnt.msg = msg_out ? msg : NULL;
         bsh mb = compare_one(d, x, &rnd, mlv, yv, &cnt);
         for (int p = 0; p < 3; ++p) {
           mw[p] |= (uint64_t)mb.c[p] << o;
           if (ml_out) ml_out[((size_t)p * rows + row) * n + j] = mlv[p];
           if (y_out) y_out[((size_t)p * rows + row) * n + j] = yv[p];
         }
+        if (msg_out)
+          for (int m = 0; m < MSG_MPCLIFT; ++m) msg_out[((size_t)m * rows + row) * nw + w] |= (uint64_t)msg[m] << o;
       }
       for (int p = 0; p < 3; ++p) match[((size_t)p * rows + row) * nw + w] = mw[p];
     }
@@ -658,7 +699,7 @@ void orc_or_bits(const uint8_t* keys, const uint8_t* a, const uint8_t* b, long c
       y.c[p] = b[(size_t)p * count + i];
     }
     x.depth = y.depth = 0;
-    bsh z = band(x, y, f, NULL);
+    bsh z = band(x, y, f, 0, NULL);
     for (int p = 0; p < 3; ++p) out[(size_t)p * count + i] = (uint8_t)(x.c[p] ^ y.c[p] ^ z.c[p]);
   }
 }
@@ -849,6 +890,14 @@ static uint32_t cmpv_dom(int v) {
 /* Tape blocks per key a variant reads. */
 static int cmpv_blocks(int v) { return v == CMPV_PLAIN ? 4 : v == CMPV_LIFT18 ? 12 : 8; }
 
+/* Messages per comparison (the bits the three parties send, in the log
+ * order of ccount): MPCLift (v = 0) 406; PLAIN 29 AND gates = 87; LIFT18
+ * 33 + 33 AND gates and BitInjects of 1 and 2 bits = 198 + 12; CONST32 61
+ * AND gates = 183.  LIFT18 logs its injects after all 66 gates. */
+int orc_msg_count(int v) {
+  return v == 0 ? MSG_MPCLIFT : v == CMPV_PLAIN ? 87 : v == CMPV_LIFT18 ? 210 : v == CMPV_CONST32 ? 183 : -1;
+}
+
 /* One comparison.  d: code-dot components (Z_2^16 for PLAIN and LIFT18;
  * Z_2^16 or Z_2^32 for CONST32); x: ml components (Z_2^16 for LIFT18,
  * Z_2^32 for CONST32; unused for PLAIN); ml_pub: public ml (PLAIN).
@@ -862,28 +911,28 @@ static bsh compare_variant_one(int v, const uint32_t d[3], const uint32_t x[3], 
     /* public minus shared: the constant enters component 0 only */
     uint32_t t = ml_pub / 4u;
     for (int p = 0; p < 3; ++p) y[p] = ((p == 0 ? t : 0u) - d[p]) & 0xFFFFu;
-    bit_extract(y, 15, 0, 0, rnd, r, cnt);
+    bit_extract(y, 15, 0, 0, 0, rnd, r, cnt);
     if (y_out) for (int p = 0; p < 3; ++p) y_out[p] = y[p];
     return r[15];
   }
   if (v == CMPV_LIFT18) {
     uint32_t S[3] = {x[0] & 0xFFFFu, x[1] & 0xFFFFu, x[2] & 0xFFFFu};
-    bit_extract(S, 17, 0, 0, rnd, r, cnt);
+    bit_extract(S, 17, 0, 0, 0, rnd, r, cnt);
     bsh hi = r[17], lo = r[16];
     int d_inj = (hi.depth > lo.depth ? hi.depth : lo.depth) + 2;
     uint32_t A[3], B[3];
-    bit_inject(hi, 1, rnd->c0[0], rnd->c2[0], rnd->w0[0], rnd->w1[0], A, cnt);
-    bit_inject(lo, 2, rnd->c0[1], rnd->c2[1], rnd->w0[1], rnd->w1[1], B, cnt);
+    bit_inject(hi, 1, rnd->c0[0], rnd->c2[0], rnd->w0[0], rnd->w1[0], 3 * 66, A, cnt);
+    bit_inject(lo, 2, rnd->c0[1], rnd->c2[1], rnd->w0[1], rnd->w1[1], 3 * 66 + 4, B, cnt);
     for (int p = 0; p < 3; ++p) {
       uint32_t ml = S[p] - (A[p] << 17) - (B[p] << 16);     /* [ml]_{2^18} */
       y[p] = (ml - ((d[p] & 0xFFFFu) << 2)) & 0x3FFFFu;     /* a [ml] - b [dot], a = 1, b = 4 */
     }
-    bit_extract(y, 17, 40, d_inj, rnd, r, cnt);
+    bit_extract(y, 17, 40, 33, d_inj, rnd, r, cnt);
     if (y_out) for (int p = 0; p < 3; ++p) y_out[p] = y[p];
     return r[17];
   }
   for (int p = 0; p < 3; ++p) y[p] = (x[p] << 14) - (d[p] << 16);   /* a = 2^14, b = 2^16 over Z_2^32 */
-  bit_extract(y, 31, 0, 0, rnd, r, cnt);
+  bit_extract(y, 31, 0, 0, 0, rnd, r, cnt);
   if (y_out) for (int p = 0; p < 3; ++p) y_out[p] = y[p];
   return r[31];
 }
@@ -911,21 +960,24 @@ static void gather_rand_variant(int v, const uint64_t tape[3][TAPE_WORDS], int o
  * components (x_comp unused for PLAIN); ml_pub: [rows][n] public ml (PLAIN
  * only).  match: [3][rows][nw] u64 components as in orc_compare; y_out
  * (optional) [3][rows][n] u32; counts[4] = {AND gates, bits sent by party
- * 0, 1, 2}.  first_entry must be a multiple of 64. */
+ * 0, 1, 2}; msg_out (optional) [orc_msg_count(v)][rows][nw] u64, the
+ * message log as in orc_compare.  first_entry must be a multiple of 64. */
 int orc_compare_variant(int v, const uint8_t* keys, const uint32_t* d_comp, const uint32_t* x_comp,
                         const int32_t* ml_pub, int nq, const int* rot, int r, long n, uint64_t qid_base,
-                        uint64_t first_entry, uint64_t* match, uint32_t* y_out, long* counts) {
+                        uint64_t first_entry, uint64_t* match, uint32_t* y_out, long* counts,
+                        uint64_t* msg_out) {
   if (first_entry % 64) return -1;
   if (v < CMPV_PLAIN || v > CMPV_CONST32) return -2;
   long rows = (long)nq * r;
   long nw = (n + 63) / 64;
   int nblk = cmpv_blocks(v);
+  const int nmsg = orc_msg_count(v);
   long tot_and = 0, tot_bits[3] = {0, 0, 0};
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : tot_and)
   for (long row = 0; row < rows; ++row) {
     uint64_t qid = qid_base + (uint64_t)(row / r);
     uint64_t st = row_stream(cmpv_dom(v), qid, rot[row % r]);
-    ccount cnt = {0, {0, 0, 0}};
+    ccount cnt = {0, {0, 0, 0}, NULL};
     static __thread uint64_t tape[3][TAPE_WORDS];
     for (long w = 0; w < nw; ++w) {
       uint64_t G = (first_entry >> 6) + (uint64_t)w;
@@ -950,11 +1002,15 @@ int orc_compare_variant(int v, const uint8_t* keys, const uint32_t* d_comp, cons
         crand rnd;
         gather_rand_variant(v, tape, o, &rnd);
         uint32_t yv[3];
+        uint8_t msg[MSG_MPCLIFT];
+        cnt.msg = msg_out ? msg : NULL;
         bsh mb = compare_variant_one(v, d, x, mlp, &rnd, yv, &cnt);
         for (int p = 0; p < 3; ++p) {
           mw[p] |= (uint64_t)mb.c[p] << o;
           if (y_out) y_out[((size_t)p * rows + row) * n + j] = yv[p];
         }
+        if (msg_out)
+          for (int m = 0; m < nmsg; ++m) msg_out[((size_t)m * rows + row) * nw + w] |= (uint64_t)msg[m] << o;
       }
       for (int p = 0; p < 3; ++p) match[((size_t)p * rows + row) * nw + w] = mw[p];
     }
@@ -1100,9 +1156,9 @@ long orc_test_bit_extract(int k, int m, uint32_t x0, uint32_t x1, uint32_t x2, u
   uint32_t mask = (k == 32) ? 0xFFFFFFFFu : ((1u << k) - 1u);
   uint32_t x[3] = {x0 & mask, x1 & mask, x2 & mask};
   crand rnd; uint64_t s = seed; random_crand(&s, &rnd);
-  ccount cnt = {0, {0, 0, 0}};
+  ccount cnt = {0, {0, 0, 0}, NULL};
   bsh r[33];
-  bit_extract(x, m, 0, 0, &rnd, r, &cnt);
+  bit_extract(x, m, 0, 0, 0, &rnd, r, &cnt);
   for (int i = 0; i <= m; ++i) {
     out_bits[i] = r[i].c[0] ^ r[i].c[1] ^ r[i].c[2];
     if (out_depth) out_depth[i] = r[i].depth;
@@ -1115,7 +1171,7 @@ long orc_test_bit_extract(int k, int m, uint32_t x0, uint32_t x1, uint32_t x2, u
 void orc_test_and(const uint8_t* x, const uint8_t* y, const uint8_t* f, uint8_t* z) {
   bsh a = bsh_zero(), b = bsh_zero();
   for (int p = 0; p < 3; ++p) { a.c[p] = x[p]; b.c[p] = y[p]; }
-  bsh c = band(a, b, f, NULL);
+  bsh c = band(a, b, f, 0, NULL);
   for (int p = 0; p < 3; ++p) z[p] = c.c[p];
 }
 
@@ -1124,7 +1180,7 @@ void orc_test_fa(const uint8_t* a, const uint8_t* b, const uint8_t* c, const uin
                  uint8_t* s, uint8_t* o) {
   bsh A = bsh_zero(), B = bsh_zero(), C = bsh_zero(), O = bsh_zero();
   for (int p = 0; p < 3; ++p) { A.c[p] = a[p]; B.c[p] = b[p]; C.c[p] = c[p]; }
-  bsh S = full_adder(A, B, C, f, &O, NULL);
+  bsh S = full_adder(A, B, C, f, 0, &O, NULL);
   for (int p = 0; p < 3; ++p) { s[p] = S.c[p]; o[p] = O.c[p]; }
 }
 
@@ -1134,8 +1190,8 @@ void orc_test_bit_inject(const uint8_t* x, int k, uint32_t c0, uint32_t c2, uint
                          uint32_t* out, long* bits_sent) {
   bsh b = bsh_zero();
   for (int p = 0; p < 3; ++p) b.c[p] = x[p];
-  ccount cnt = {0, {0, 0, 0}};
-  bit_inject(b, k, c0, c2, w0, w1, out, &cnt);
+  ccount cnt = {0, {0, 0, 0}, NULL};
+  bit_inject(b, k, c0, c2, w0, w1, 0, out, &cnt);
   if (bits_sent) for (int p = 0; p < 3; ++p) bits_sent[p] = cnt.bits_sent[p];
 }
 
@@ -1144,7 +1200,7 @@ void orc_test_bit_inject(const uint8_t* x, int k, uint32_t c0, uint32_t c2, uint
 int orc_test_compare_one(const uint16_t* d, const uint16_t* x, uint64_t seed,
                          uint32_t* ml_open, uint32_t* y_open, long* counts, int* depth) {
   crand rnd; uint64_t s = seed; random_crand(&s, &rnd);
-  ccount cnt = {0, {0, 0, 0}};
+  ccount cnt = {0, {0, 0, 0}, NULL};
   uint32_t ml[3], y[3];
   bsh mb = compare_one(d, x, &rnd, ml, y, &cnt);
   if (depth) *depth = mb.depth;
@@ -1160,7 +1216,7 @@ int orc_test_compare_one(const uint16_t* d, const uint16_t* x, uint64_t seed,
 int orc_test_compare_variant(int v, const uint32_t* d, const uint32_t* x, uint32_t ml_pub, uint64_t seed,
                              uint32_t* y_open, long* counts, int* depth) {
   crand rnd; uint64_t s = seed; random_crand(&s, &rnd);
-  ccount cnt = {0, {0, 0, 0}};
+  ccount cnt = {0, {0, 0, 0}, NULL};
   uint32_t y[3];
   bsh mb = compare_variant_one(v, d, x, ml_pub, &rnd, y, &cnt);
   if (depth) *depth = mb.depth;
