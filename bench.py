@@ -261,10 +261,19 @@ CHACHA12_OPS = 12 * 4 * 12 + 16
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12     # int32 lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 
 
-def circuit_report(compare, ncmp, reshare_ms, compare_ms, plain, v32):
+# Bits each party sends per comparison, per setting (the oracle's message
+# counts): AND-gate messages plus the 3OT roles of the BitInjects.
+MSG_BITS = {"mpclift": (156, 125, 125), "lift18": (72, 69, 69), "plain": (29, 29, 29), "constlift": (61, 61, 61),
+            "nolift": (61, 61, 61)}
+
+
+def circuit_report(compare, ncmp, reshare_ms, compare_ms, plain, v32, net="registers", other_ms=None):
     """The interactive steps of one batch: resharing against the HBM roof
     (algorithmic bytes) and the comparison against the VALU roof (its PRF
-    work alone, a lower bound on its ops)."""
+    work alone, a lower bound on its ops).  net: how the step's comparison
+    passed its messages ("buffers": parties apart, every message stored and
+    loaded through device memory; "registers": the three parties of a
+    comparison in one lane); other_ms: the comparison in the other mode."""
     n16 = 0 if 0 in v32 else 1
     n16 += 0 if (plain or 1 in v32) else 1                 # Z_2^16 vectors reshared
     # per vector and comparison, 3 parties: read the additive share, write the
@@ -272,11 +281,23 @@ def circuit_report(compare, ncmp, reshare_ms, compare_ms, plain, v32):
     per_vec16, per_vec32 = 3 * 4 * 2, 3 * 4 * 4
     rb = ncmp * (n16 * per_vec16 + len(v32) * per_vec32)
     ops = ncmp * CMP_BLOCKS_PER_64[compare] * CHACHA12_OPS / 64
-    return {"reshare_ms": reshare_ms, "reshare_bytes": rb, "reshare_gbs": rb / (reshare_ms / 1e3) / 1e9,
-            "reshare_hbm_frac": rb / (reshare_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-            "compare_ms": compare_ms, "compare_prf_ops": ops,
-            "compare_valu_tops": ops / (compare_ms / 1e3) / 1e12,
-            "compare_valu_frac": ops / (compare_ms / 1e3) / 1e12 / VALU_PEAK_TOPS}
+    bits = MSG_BITS[compare]
+    # the buffered network runs each party's two keys: 2 of the 3 PRF blocks
+    # per tape position per party, i.e. twice the register simulation's PRF work
+    ops_net = ops * (2 if net == "buffers" else 1)
+    r = {"reshare_ms": reshare_ms, "reshare_bytes": rb, "reshare_gbs": rb / (reshare_ms / 1e3) / 1e9,
+         "reshare_hbm_frac": rb / (reshare_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+         "compare_net": net, "compare_ms": compare_ms, "compare_prf_ops": ops_net,
+         "compare_valu_tops": ops_net / (compare_ms / 1e3) / 1e12,
+         "compare_valu_frac": ops_net / (compare_ms / 1e3) / 1e12 / VALU_PEAK_TOPS,
+         "message_bits_per_comparison": {"party0": bits[0], "party1": bits[1], "party2": bits[2]}}
+    if net == "buffers":
+        mb = ncmp * sum(bits) / 8
+        r["message_bytes"] = mb
+        r["message_gbs"] = 2 * mb / (compare_ms / 1e3) / 1e9      # each message stored once and loaded once
+    if other_ms is not None:
+        r["compare_ms_" + ("registers" if net == "buffers" else "buffers")] = other_ms
+    return r
 
 
 def run_full(args):
@@ -311,7 +332,7 @@ def run_full(args):
     q_masks = torch.from_numpy(qm.view(np.int64)).cuda()
     qs = SharedQueries(ctx, q_codes, q_masks, 0, galois=galois)
     qs32 = SharedQueries32(ctx, q_codes, q_masks, 0, vecs=v32) if v32 else None
-    buf = alloc_check(w.n_q, len(w.rot), w.n_db, compare=args.compare)
+    buf = alloc_check(w.n_q, len(w.rot), w.n_db, compare=args.compare, net=args.net)
     torch.cuda.synchronize()
     log(f"first step + verification against the oracle ({args.compare} comparison)")
     run_check(ctx, qs, w.rot, db, 0, w.n_db, buf, query_masks=q_masks, db_masks=db_masks, qs32=qs32, db32=db32)
@@ -327,6 +348,22 @@ def run_full(args):
 
     stream = torch.cuda.current_stream()
     ids = imc.make_ids(0, w.rot, 0)
+
+    def compare(net):
+        """The step's comparison; net: its message buffer (None: messages in registers)."""
+        if plain:
+            ctx.compare_variant(imc.CMP_PLAIN_MASK, buf.rep_code, 16, None, buf.ml_pub, buf.rows, w.n_db, buf.ld,
+                                ids, buf.match, buf.nw, stream, msg_ws=net)
+        elif args.compare == "lift18":
+            ctx.compare_variant(imc.CMP_LIFT18, buf.rep_code, 16, buf.rep_mask, None, buf.rows, w.n_db, buf.ld,
+                                ids, buf.match, buf.nw, stream, msg_ws=net)
+        elif v32:
+            code, bits = (buf.rep32[0], 32) if 0 in v32 else (buf.rep_code, 16)
+            ctx.compare_variant(imc.CMP_CONST32, code, bits, buf.rep32[1], None, buf.rows, w.n_db, buf.ld, ids,
+                                buf.match, buf.nw, stream, msg_ws=net)
+        else:
+            ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, w.n_db, buf.ld, ids, buf.match, buf.nw,
+                                  stream, msg_ws=net)
 
     def step(events=None):
         for p in range(3):
@@ -353,19 +390,7 @@ def run_full(args):
         if events is not None:
             events[3][1].record(stream)
             events[4][0].record(stream)
-        if plain:
-            ctx.compare_variant(imc.CMP_PLAIN_MASK, buf.rep_code, 16, None, buf.ml_pub, buf.rows, w.n_db, buf.ld,
-                                ids, buf.match, buf.nw, stream)
-        elif args.compare == "lift18":
-            ctx.compare_variant(imc.CMP_LIFT18, buf.rep_code, 16, buf.rep_mask, None, buf.rows, w.n_db, buf.ld,
-                                ids, buf.match, buf.nw, stream)
-        elif v32:
-            code, bits = (buf.rep32[0], 32) if 0 in v32 else (buf.rep_code, 16)
-            ctx.compare_variant(imc.CMP_CONST32, code, bits, buf.rep32[1], None, buf.rows, w.n_db, buf.ld, ids,
-                                buf.match, buf.nw, stream)
-        else:
-            ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, w.n_db, buf.ld, ids, buf.match, buf.nw,
-                                  stream)
+        compare(buf.net)
         if events is not None:
             events[4][1].record(stream)
         ctx.or_tree(buf.match, qs.q, buf.nw, buf.nw, ids, buf.ws, buf.ws.numel(), buf.dup, stream)
@@ -396,6 +421,19 @@ def run_full(args):
         evs.append(ev)
         log(f"step {i + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms")
     total = time.perf_counter() - t0
+    # the comparison in the other network mode, outside the timed steps (the
+    # register simulation when the step passes messages through the buffer)
+    other_ms = None
+    if buf.net is not None:
+        ts = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            compare(None)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        other_ms = float(np.mean(ts))     # (the same match components as the step's)
     dot_ms = [a.elapsed_time(b) for ev in evs for a, b in ev[:3]]
     reshare_ms = float(np.mean([ev[3][0].elapsed_time(ev[3][1]) for ev in evs]))
     compare_ms = float(np.mean([ev[4][0].elapsed_time(ev[4][1]) for ev in evs]))
@@ -435,7 +473,8 @@ def run_full(args):
                      "ops_per_launch": ops, "avg_launch_ms": dot_avg_s * 1e3,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "hbm_gbs": None if traffic is None else traffic / dot_avg_s / 1e9},
-        "circuit": circuit_report(args.compare, w.rows * w.n_db, reshare_ms, compare_ms, plain, v32),
+        "circuit": circuit_report(args.compare, w.rows * w.n_db, reshare_ms, compare_ms, plain, v32, args.net,
+                                  other_ms),
         "verification": ver,
     }
     if in_batch:
@@ -500,6 +539,19 @@ def run_compare(args):
                                               nw, stream),
         "or_tree": lambda: ctx.or_tree(match, q, nw, nw, ids, ws, ws.numel(), dup, stream),
     }
+    # the same settings with the parties apart and their messages through a device buffer
+    net = torch.empty(imc.compare_msg_bytes(0, rows, nw) // 8, dtype=torch.int64, device="cuda")
+    calls.update({
+        "mpclift_buffers": lambda: ctx.compare_threshold(code, mask, rows, n, ld, ids, match, nw, stream, msg_ws=net),
+        "lift18_buffers": lambda: ctx.compare_variant(imc.CMP_LIFT18, code, 16, mask, None, rows, n, ld, ids, match,
+                                                      nw, stream, msg_ws=net),
+        "plain_buffers": lambda: ctx.compare_variant(imc.CMP_PLAIN_MASK, code, 16, None, ml_pub, rows, n, ld, ids,
+                                                     match, nw, stream, msg_ws=net),
+        "constlift_buffers": lambda: ctx.compare_variant(imc.CMP_CONST32, code, 16, mask32, None, rows, n, ld, ids,
+                                                         match, nw, stream, msg_ws=net),
+        "nolift_buffers": lambda: ctx.compare_variant(imc.CMP_CONST32, code32, 32, mask32, None, rows, n, ld, ids,
+                                                      match, nw, stream, msg_ws=net),
+    })
     out = {}
     ncmp = rows * n
     for name, fn in calls.items():
@@ -514,17 +566,21 @@ def run_compare(args):
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / args.steps
         out[name] = {"ms": ms, "elements_per_s": ncmp / (ms / 1e3)}
-        if name in COMPARE_COUNTS:
-            ands, bits = COMPARE_COUNTS[name]
-            out[name].update(and_gates=ands, bits_sent_party0=bits, kb_per_party_per_100k=bits * 100_000 / 8e3)
+        setting = name.split("_")[0]
+        if setting in COMPARE_COUNTS:
+            ands, bits = COMPARE_COUNTS[setting]
+            out[name].update(and_gates=ands, bits_sent_party0=bits, kb_per_party_per_100k=bits * 100_000 / 8e3,
+                             messages="device buffer, parties apart" if name.endswith("_buffers")
+                             else "registers, three parties per lane")
         log(f"{name}: {ms:.3f} ms per call, {ncmp / (ms / 1e3):.3e} elements/s")
     res = {
         "metric": "shared iris comparisons/sec on 1 MI355X (bit-exact); p50/p99 query latency",
-        "value": out["mpclift"]["elements_per_s"], "unit": "comparisons/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": out["mpclift"]["ms"],
+        "value": out["mpclift_buffers"]["elements_per_s"], "unit": "comparisons/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": out["mpclift_buffers"]["ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16", "data": "synthetic",
-        "config": {"workload": f"comparison kernels alone (3 parties on one GPU): {q} queries x {len(rot)} "
-                               f"rotations ({rows} rows) x {n} entries of reshared components per call",
+        "config": {"workload": f"comparison kernels alone (3 parties on one GPU, messages through a device "
+                               f"buffer): {q} queries x {len(rot)} rotations ({rows} rows) x {n} entries of "
+                               f"reshared components per call",
                    "rows": rows, "db_entries": n},
         "settings": out,
     }
@@ -795,6 +851,9 @@ def main():
                     help="serve workload: one party's share of the service (its DB region and dot products)")
     ap.add_argument("--compare", choices=["mpclift", "lift18", "plain", "constlift", "nolift"], default="mpclift",
                     help="comparison setting of the full workload (Sec. 6.2)")
+    ap.add_argument("--net", choices=["buffers", "registers"], default="buffers",
+                    help="comparison messages: through a device buffer with the parties apart (default), or held "
+                         "in registers with the three parties of a comparison in one lane")
     ap.add_argument("--in-batch", action="store_true",
                     help="full workload: also match each query against the batch's earlier queries (Sec. 6.4)")
     args = ap.parse_args()

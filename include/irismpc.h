@@ -234,7 +234,7 @@ imc_status imc_set_dot_tiles(imc_ctx* ctx, uint32_t flags);
  * received from party p-1.  rows must equal q * ids->r for some q.
  * add_mask may be NULL (masks in plain: no mask dot); then only the code
  * shares are reshared, rep_mask is ignored and the mask plane of msg[p] is
- * left untouched. */
+ * left untouched.  When ld % 8 == 0 every plane must be 16-byte aligned. */
 imc_status imc_reshare(imc_ctx* ctx, const uint16_t* const add_code[3], const uint16_t* const add_mask[3],
                        size_t rows, size_t n, size_t ld, const imc_ids* ids, uint16_t* const msg[3],
                        uint16_t* const rep_code[3], uint16_t* const rep_mask[3], imc_stream stream);
@@ -243,16 +243,40 @@ imc_status imc_reshare(imc_ctx* ctx, const uint16_t* const add_code[3], const ui
  * Sec. 5.2; App. D Lift, BitExtract, BitInject, 3OT, ConstLift):
  *   [ml'] = Lift([ml]_{2^16}) to Z_2^32, y = 2^14 [ml'] - ConstLift([dot], 2^16),
  *   [match] = MSB(y)   (match <=> hd/ml < 3/8 <=> 4 dot > ml).
- * rep_code[p], rep_mask[p]: as produced by imc_reshare ([2][rows][ld]).
+ * rep_code[p], rep_mask[p]: as produced by imc_reshare ([2][rows][ld]; all
+ * 16-byte aligned when ld % 8 == 0).
  * match[p]: device u64 [2][rows][mw_ld] (mw_ld >= ceil(n/64)): plane 0 = party
  * p's own component, plane 1 = component p-1; bit o of word w is column
  * 64w + o; bits at columns >= n are public zeros.  All 3 x 94 AND gates per
- * comparison and both BitInjects run; one GPU lane evaluates 64 comparisons
- * bit-sliced.  ids->first_entry_id must be a multiple of 64. */
+ * comparison and both BitInjects run, 64 comparisons bit-sliced per lane.
+ * ids->first_entry_id must be a multiple of 64.
+ * msg_ws: the network between the parties (Sec. 6.4 keeps it on the GPU):
+ * device u64 [406][rows][mw_ld], msg_ws_bytes >= imc_compare_msg_bytes(0,
+ * rows, mw_ld), alignment 8.  Then the three parties run as three waves of
+ * a workgroup, each holding its own view only (components p and p-1, keys p
+ * and p-1), and every message is stored by its sender into its plane and
+ * loaded by its receiver after a workgroup barrier, one barrier per round
+ * (50 rounds).  Plane order (the oracle's message log): AND gate g
+ * (numbered bit by bit, a bit's FA-layer gate before its ripple gate; gates
+ * 0..32 the Lift, 33..93 the MSB) sent by party p at plane 3g + p; then
+ * the BitInject of bit 17 (Z_2^15) at planes 282.. and of bit 16 (Z_2^16)
+ * at 342..: k0, k1 (party 0 -> 1), w_c (party 2 -> 1), c1 (party 1 -> 2),
+ * k planes each.  Column bits >= n of a plane are unspecified.  On return
+ * the buffer holds every message of the call (406 bits per comparison:
+ * 156 sent by party 0, 125 by party 1, 125 by party 2).
+ * msg_ws NULL: the same arithmetic with the three parties of a comparison in
+ * one lane, messages held in registers (a faster simulation; identical
+ * outputs).
+ * Errors: IMC_EINVAL (null, unaligned), IMC_ESHAPE (sizes, msg_ws_bytes). */
 imc_status imc_compare_threshold(imc_ctx* ctx, const uint16_t* const rep_code[3],
                                  const uint16_t* const rep_mask[3], size_t rows, size_t n, size_t ld,
-                                 const imc_ids* ids, uint64_t* const match[3], size_t mw_ld,
-                                 imc_stream stream);
+                                 const imc_ids* ids, void* msg_ws, size_t msg_ws_bytes,
+                                 uint64_t* const match[3], size_t mw_ld, imc_stream stream);
+
+/* Bytes of the message buffer of a comparison call: variant 0 = MPCLift
+ * (imc_compare_threshold, 406 planes), IMC_CMP_PLAIN_MASK 87,
+ * IMC_CMP_LIFT18 210, IMC_CMP_CONST32 183 planes of rows x mw_ld u64. */
+size_t imc_compare_msg_bytes(int variant, size_t rows, size_t mw_ld);
 
 /* Other settings of the threshold comparison (Sec. 4.3 Alg. 2 and Sec. 4.3.1;
  * Sec. 5.1-5.2; the settings compared in Sec. 6.2).  The threshold 1 - 2*3/8
@@ -275,14 +299,19 @@ imc_status imc_compare_threshold(imc_ctx* ctx, const uint16_t* const rep_code[3]
  * 16) or u32 (code_bits 32, IMC_CMP_CONST32 only).  match[p], ids, the output
  * layout and the first_entry_id alignment are as imc_compare_threshold.  Each
  * setting draws its randomness from its own PRF domain.
+ * msg_ws, msg_ws_bytes: as imc_compare_threshold (NULL: messages held in
+ * registers), imc_compare_msg_bytes(variant, rows, mw_ld) bytes: Plain AND
+ * gates 0..28 (87 planes); Lift18 gates 0..32 (Lift) and 33..65 (MSB), then
+ * the BitInjects of bit 17 (Z_2^1) at planes 198.. and bit 16 (Z_2^2) at
+ * 202.. (210 planes); Const32 gates 0..60 (183 planes).
  * Errors: IMC_EINVAL (null, unaligned, unknown variant, code_bits), IMC_ESHAPE. */
 #define IMC_CMP_PLAIN_MASK 1
 #define IMC_CMP_LIFT18 2
 #define IMC_CMP_CONST32 3
 imc_status imc_compare_variant(imc_ctx* ctx, int variant, const void* const rep_code[3], int code_bits,
                                const void* const rep_mask[3], const uint16_t* ml_pub, size_t rows, size_t n,
-                               size_t ld, const imc_ids* ids, uint64_t* const match[3], size_t mw_ld,
-                               imc_stream stream);
+                               size_t ld, const imc_ids* ids, void* msg_ws, size_t msg_ws_bytes,
+                               uint64_t* const match[3], size_t mw_ld, imc_stream stream);
 
 /* Public mask overlap for the setting with masks in plain (Sec. 4.3 Alg. 2:
  * the masks travel in plain, so every party computes ml = |m' AND M| for

@@ -29,7 +29,7 @@ EXPORTS = [
     "imc_galois_append_db", "imc_mask_in_batch", "imc_or_bits", "imc_dot_shares_gather",
     "imc_galois_dot_shares_gather", "imc_compare_variant", "imc_rotate_masks", "imc_plain_ml", "imc_db32_bytes",
     "imc_query32_op_bytes", "imc_share32_db", "imc_share32_query", "imc_dot32_shares", "imc_reshare32",
-    "imc_dot_shares_rows_noalloc",
+    "imc_dot_shares_rows_noalloc", "imc_compare_msg_bytes",
 ]
 
 (DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW, DOT_TILES_ROTATION,
@@ -97,7 +97,9 @@ def lib():
         L.imc_share_query.argtypes = [_VP, _VP, _VP, sz, ctypes.c_uint64, _P3, _VP, _VP]
         L.imc_dot_shares.argtypes = [_VP, ctypes.c_int, _VP, sz, ctypes.POINTER(imc_ids), _VP, sz, sz, _VP, _VP, sz, _VP]
         L.imc_reshare.argtypes = [_VP, _P3, _VP, sz, sz, sz, ctypes.POINTER(imc_ids), _P3, _P3, _VP, _VP]
-        L.imc_compare_threshold.argtypes = [_VP, _P3, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _P3, sz, _VP]
+        L.imc_compare_threshold.argtypes = [_VP, _P3, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, sz, _P3, sz, _VP]
+        L.imc_compare_msg_bytes.argtypes = [ctypes.c_int, sz, sz]
+        L.imc_compare_msg_bytes.restype = sz
         L.imc_or_tree.argtypes = [_VP, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, sz, _P3, _VP]
         L.imc_open.argtypes = [_VP, ctypes.c_int, _P3, sz, _VP, ctypes.c_int, _VP]
         L.imc_append_db.argtypes = [_VP, _P3, sz, _P3, sz, ctypes.c_uint64, _VP]
@@ -116,7 +118,7 @@ def lib():
         L.imc_galois_dot_shares_gather.argtypes = L.imc_dot_shares_gather.argtypes
         L.imc_or_bits.argtypes = [_VP, _P3, _P3, sz, ctypes.c_uint64, _P3, _VP]
         L.imc_compare_variant.argtypes = [_VP, ctypes.c_int, _P3, ctypes.c_int, _VP, _VP, sz, sz, sz,
-                                          ctypes.POINTER(imc_ids), _P3, sz, _VP]
+                                          ctypes.POINTER(imc_ids), _VP, sz, _P3, sz, _VP]
         L.imc_rotate_masks.argtypes = [_VP, _VP, sz, ctypes.POINTER(imc_ids), _VP, _VP]
         L.imc_plain_ml.argtypes = [_VP, _VP, sz, _VP, sz, _VP, sz, _VP]
         L.imc_share32_db.argtypes = [_VP, ctypes.c_int, _VP, _VP, sz, ctypes.c_uint64, _P3, sz, _VP]
@@ -213,6 +215,11 @@ def or_tree_ws_bytes(q: int, r: int, nw: int) -> int:
     return lib().imc_or_tree_ws_bytes(q, r, nw)
 
 
+def compare_msg_bytes(variant: int, rows: int, mw_ld: int) -> int:
+    """Bytes of a comparison call's message buffer (variant 0 = MPCLift)."""
+    return lib().imc_compare_msg_bytes(variant, rows, mw_ld)
+
+
 @dataclass
 class Keys:
     dealer: bytes
@@ -304,13 +311,15 @@ class Context:
         return _check(lib().imc_reshare(self._h, _p3(add_code3), am, rows, n, ld, ctypes.byref(ids),
                                         _p3(msg3), _p3(rep_code3), rm, _stream(stream)), "imc_reshare")
 
-    # -- imc_compare_variant (variant CMP_*; rep_mask3 None for CMP_PLAIN_MASK)
+    # -- imc_compare_variant (variant CMP_*; rep_mask3 None for CMP_PLAIN_MASK; msg_ws: message buffer
+    #    of compare_msg_bytes(variant, rows, mw_ld) bytes, None: messages held in registers)
     def compare_variant(self, variant, rep_code3, code_bits, rep_mask3, ml_pub, rows, n, ld, ids: imc_ids, match3,
-                        mw_ld, stream=None):
+                        mw_ld, stream=None, msg_ws=None):
         rm = ctypes.cast(_p3(rep_mask3), _VP) if rep_mask3 is not None else None
+        mb = msg_ws.numel() * msg_ws.element_size() if msg_ws is not None else 0
         return _check(lib().imc_compare_variant(self._h, variant, _p3(rep_code3), code_bits, rm, addr(ml_pub), rows,
-                                                n, ld, ctypes.byref(ids), _p3(match3), mw_ld, _stream(stream)),
-                      "imc_compare_variant")
+                                                n, ld, ctypes.byref(ids), addr(msg_ws), mb, _p3(match3), mw_ld,
+                                                _stream(stream)), "imc_compare_variant")
 
     # -- Z_2^32 sharing, dot products and resharing of one vector (vec 0 code, 1 mask)
     def share32_db(self, vec, codes, masks, n, first_entry_id, db3, capacity, stream=None):
@@ -338,11 +347,14 @@ class Context:
         return _check(lib().imc_plain_ml(self._h, addr(row_masks), rows, addr(db_masks), n, addr(ml), ld,
                                          _stream(stream)), "imc_plain_ml")
 
-    # -- imc_compare_threshold
-    def compare_threshold(self, rep_code3, rep_mask3, rows, n, ld, ids: imc_ids, match3, mw_ld, stream=None):
+    # -- imc_compare_threshold (msg_ws: device tensor of compare_msg_bytes(0, rows, mw_ld) bytes, the
+    #    message buffer between the parties; None: messages held in registers)
+    def compare_threshold(self, rep_code3, rep_mask3, rows, n, ld, ids: imc_ids, match3, mw_ld, stream=None,
+                          msg_ws=None):
+        mb = msg_ws.numel() * msg_ws.element_size() if msg_ws is not None else 0
         return _check(lib().imc_compare_threshold(self._h, _p3(rep_code3), _p3(rep_mask3), rows, n, ld,
-                                                  ctypes.byref(ids), _p3(match3), mw_ld, _stream(stream)),
-                      "imc_compare_threshold")
+                                                  ctypes.byref(ids), addr(msg_ws), mb, _p3(match3), mw_ld,
+                                                  _stream(stream)), "imc_compare_threshold")
 
     # -- imc_or_tree
     def or_tree(self, match3, q, nw, mw_ld, ids: imc_ids, ws, ws_bytes, dup3, stream=None):

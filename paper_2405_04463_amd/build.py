@@ -9,7 +9,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libirismpc.so")
-SOURCES = ["api.cpp", "share.hip", "dot.hip", "rot_dot.hip", "circuit.hip", "plain_ml.hip", "dot32.hip"]
+SOURCES = ["api.cpp", "share.hip", "dot.hip", "rot_dot.hip", "circuit.hip", "circuit_msg.hip", "plain_ml.hip",
+           "dot32.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed-FP32 instructions

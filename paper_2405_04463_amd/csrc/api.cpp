@@ -413,9 +413,13 @@ imc_status imc_reshare(imc_ctx* c, const uint16_t* const add_code[3], const uint
   if (rows % size_t(ids->r)) return IMC_ESHAPE;
   if (ld < n) return IMC_ESHAPE;
   if (rows == 0 || n == 0) return IMC_OK;
+  // 16-byte vector accesses are taken when ld % 8 == 0: every plane must then be 16-byte aligned
+  const size_t va = ld % 8 == 0 ? 16 : 2;
   for (int p = 0; p < 3; ++p) {
     if (!add_code[p] || !msg[p] || !rep_code[p]) return IMC_EINVAL;
     if (add_mask && (!add_mask[p] || !rep_mask[p])) return IMC_EINVAL;
+    if (!aligned(add_code[p], va) || !aligned(msg[p], va) || !aligned(rep_code[p], va)) return IMC_EINVAL;
+    if (add_mask && (!aligned(add_mask[p], va) || !aligned(rep_mask[p], va))) return IMC_EINVAL;
   }
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;
@@ -423,29 +427,45 @@ imc_status imc_reshare(imc_ctx* c, const uint16_t* const add_code[3], const uint
       imc::launch_reshare(c->party, add_code, add_mask, rows, n, ld, *ids, msg, rep_code, rep_mask, hipStream_t(stream)));
 }
 
+size_t imc_compare_msg_bytes(int variant, size_t rows, size_t mw_ld) {
+  return imc::compare_msg_planes(variant) * rows * mw_ld * sizeof(uint64_t);
+}
+
 imc_status imc_compare_threshold(imc_ctx* c, const uint16_t* const rep_code[3], const uint16_t* const rep_mask[3],
-                                 size_t rows, size_t n, size_t ld, const imc_ids* ids, uint64_t* const match[3],
-                                 size_t mw_ld, imc_stream stream) {
+                                 size_t rows, size_t n, size_t ld, const imc_ids* ids, void* msg_ws,
+                                 size_t msg_ws_bytes, uint64_t* const match[3], size_t mw_ld, imc_stream stream) {
   if (!c || !rep_code || !rep_mask || !match) return IMC_EINVAL;
   imc_status st = check_ids(ids);
   if (st != IMC_OK) return st;
   if (rows % size_t(ids->r)) return IMC_ESHAPE;
   if (ld < n || mw_ld < (n + 63) / 64) return IMC_ESHAPE;
   if (rows == 0 || n == 0) return IMC_OK;
+  // 16-byte vector accesses are taken when ld % 8 == 0: every plane must then be 16-byte aligned
+  const size_t va = ld % 8 == 0 ? 16 : 2;
   for (int p = 0; p < 3; ++p) {
     if (!rep_code[p] || !rep_mask[p] || !match[p]) return IMC_EINVAL;
-    if (!aligned(rep_code[p], 2) || !aligned(rep_mask[p], 2) || !aligned(match[p], 8)) return IMC_EINVAL;
+    if (!aligned(rep_code[p], va) || !aligned(rep_mask[p], va) || !aligned(match[p], 8)) return IMC_EINVAL;
+  }
+  if (msg_ws) {
+    if (!aligned(msg_ws, 8)) return IMC_EINVAL;
+    if (msg_ws_bytes < imc_compare_msg_bytes(0, rows, mw_ld)) return IMC_ESHAPE;
   }
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;
+  if (msg_ws) {
+    const void* code[3] = {rep_code[0], rep_code[1], rep_code[2]};
+    const void* mask[3] = {rep_mask[0], rep_mask[1], rep_mask[2]};
+    return dev_status(imc::launch_compare_msg(0, c->party, code, false, mask, nullptr, rows, n, ld, *ids, match,
+                                              mw_ld, static_cast<uint64_t*>(msg_ws), hipStream_t(stream)));
+  }
   return dev_status(imc::launch_compare(c->party, rep_code, rep_mask, rows, n, ld, *ids, match, mw_ld,
                                         hipStream_t(stream)));
 }
 
 imc_status imc_compare_variant(imc_ctx* c, int variant, const void* const rep_code[3], int code_bits,
                                const void* const rep_mask[3], const uint16_t* ml_pub, size_t rows, size_t n,
-                               size_t ld, const imc_ids* ids, uint64_t* const match[3], size_t mw_ld,
-                               imc_stream stream) {
+                               size_t ld, const imc_ids* ids, void* msg_ws, size_t msg_ws_bytes,
+                               uint64_t* const match[3], size_t mw_ld, imc_stream stream) {
   if (!c || !rep_code || !match) return IMC_EINVAL;
   if (variant < IMC_CMP_PLAIN_MASK || variant > IMC_CMP_CONST32) return IMC_EINVAL;
   if (code_bits != 16 && !(code_bits == 32 && variant == IMC_CMP_CONST32)) return IMC_EINVAL;
@@ -462,8 +482,17 @@ imc_status imc_compare_variant(imc_ctx* c, int variant, const void* const rep_co
       return IMC_EINVAL;
   }
   if (variant == IMC_CMP_PLAIN_MASK && (!ml_pub || !aligned(ml_pub, 2))) return IMC_EINVAL;
+  if (msg_ws) {
+    if (!aligned(msg_ws, 8)) return IMC_EINVAL;
+    if (msg_ws_bytes < imc_compare_msg_bytes(variant, rows, mw_ld)) return IMC_ESHAPE;
+  }
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;
+  if (msg_ws)
+    return dev_status(imc::launch_compare_msg(variant, c->party, rep_code, code_bits == 32,
+                                              variant == IMC_CMP_PLAIN_MASK ? nullptr : rep_mask, ml_pub, rows, n,
+                                              ld, *ids, match, mw_ld, static_cast<uint64_t*>(msg_ws),
+                                              hipStream_t(stream)));
   return dev_status(imc::launch_compare_variant(variant, c->party, rep_code, code_bits == 32,
                                                 variant == IMC_CMP_PLAIN_MASK ? nullptr : rep_mask, ml_pub, rows, n,
                                                 ld, *ids, match, mw_ld, hipStream_t(stream)));

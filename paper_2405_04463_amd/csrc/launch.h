@@ -52,6 +52,11 @@ hipError_t launch_compare_variant(int variant, const Keys3& keys, const void* co
                                   const void* const rep_mask[3], const uint16_t* ml_pub, uint64_t rows, uint64_t n,
                                   uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3], uint64_t mw_ld,
                                   hipStream_t s);
+size_t compare_msg_planes(int variant);
+hipError_t launch_compare_msg(int variant, const Keys3& keys, const void* const rep_code[3], bool code32,
+                              const void* const rep_mask[3], const uint16_t* ml_pub, uint64_t rows, uint64_t n,
+                              uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3], uint64_t mw_ld,
+                              uint64_t* msg, hipStream_t s);
 hipError_t launch_rotate_masks(const uint64_t* masks, uint64_t q, const imc_ids_dev& ids, uint64_t* out,
                                hipStream_t s);
 hipError_t launch_plain_ml(const uint64_t* row_masks, uint64_t rows, const uint64_t* db_masks, uint64_t n,

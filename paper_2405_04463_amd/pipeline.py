@@ -2,7 +2,7 @@
 
 Allocation and sequencing only; all arithmetic is in the library's kernels:
   share_db / share_query -> dot_shares (each party) -> reshare ->
-  compare_threshold -> or_tree -> open
+  compare_threshold (messages through a device buffer) -> or_tree -> open
 
 Comparison settings (Sec. 6.2): "mpclift" (default, Alg. 3 with ml lifted to
 Z_2^32), "lift18" (ml lifted to Z_2^18 only), "plain" (Alg. 2: masks public,
@@ -16,9 +16,9 @@ from dataclasses import dataclass
 
 import torch
 
-from . import (CMP_CONST32, CMP_LIFT18, CMP_PLAIN_MASK, OPEN_U8_XOR, OPEN_U16_ADD, OPEN_U64_XOR, Context, db32_bytes,
-               db_bytes, galois_db_bytes, galois_query_op_bytes, galois_query_raw_bytes, make_ids, or_tree_ws_bytes,
-               query32_op_bytes, query_op_bytes, query_raw_bytes)
+from . import (CMP_CONST32, CMP_LIFT18, CMP_PLAIN_MASK, OPEN_U8_XOR, OPEN_U16_ADD, OPEN_U64_XOR, Context,
+               compare_msg_bytes, db32_bytes, db_bytes, galois_db_bytes, galois_query_op_bytes, galois_query_raw_bytes,
+               make_ids, or_tree_ws_bytes, query32_op_bytes, query_op_bytes, query_raw_bytes)
 
 COMPARE_SETTINGS = ("mpclift", "lift18", "plain", "constlift", "nolift")
 VECS32 = {"constlift": (1,), "nolift": (0, 1)}   # vectors whose dot products run over Z_2^32
@@ -127,11 +127,23 @@ class CheckBuffers:
     dot32: dict | None = None                # Z_2^32 settings: vec -> 3 x u32 [rows, ld]
     msg32: dict | None = None                # vec -> 3 x u32 [rows, ld]
     rep32: dict | None = None                # vec -> 3 x u32 [2, rows, ld]
+    net: torch.Tensor | None = None          # the comparison's message buffer (None: messages in registers)
 
 
-def alloc_check(q: int, r: int, n: int, device=0, compare: str = "mpclift") -> CheckBuffers:
+# Message-buffer layout of each comparison setting (imc_compare_msg_bytes's variant).
+NET_VARIANT = {"mpclift": 0, "plain": CMP_PLAIN_MASK, "lift18": CMP_LIFT18, "constlift": CMP_CONST32,
+               "nolift": CMP_CONST32}
+
+
+def alloc_check(q: int, r: int, n: int, device=0, compare: str = "mpclift", net: str = "buffers") -> CheckBuffers:
+    """Buffers of one check.  net = "buffers": the comparison's parties run
+    apart and pass every message through a device buffer (406 bits per
+    comparison for MPCLift); "registers": the faster simulation that holds
+    all three parties of a comparison in one lane."""
     if compare not in COMPARE_SETTINGS:
         raise ValueError(compare)
+    if net not in ("buffers", "registers"):
+        raise ValueError(net)
     d = _dev(device)
     rows = q * r
     ld = ((n + 63) // 64) * 64
@@ -158,6 +170,8 @@ def alloc_check(q: int, r: int, n: int, device=0, compare: str = "mpclift") -> C
         compare=compare,
         ml_pub=u16(rows, ld) if plain else None,
         row_masks=torch.empty(rows, 200, dtype=torch.int64, device=d) if plain else None,
+        net=(torch.empty(compare_msg_bytes(NET_VARIANT[compare], rows, nw) // 8, dtype=torch.int64, device=d)
+             if net == "buffers" else None),
     )
 
 
@@ -192,15 +206,16 @@ def run_check(ctx: Context, qs: SharedQueries, rot, db: SharedDB, first_entry: i
     if buf.compare in VECS32:
         code, bits = (buf.rep32[0], 32) if 0 in buf.rep32 else (buf.rep_code, 16)
         ctx.compare_variant(CMP_CONST32, code, bits, buf.rep32[1], None, buf.rows, n, buf.ld, ids, buf.match, buf.nw,
-                            stream)
+                            stream, msg_ws=buf.net)
     elif plain:
         ctx.compare_variant(CMP_PLAIN_MASK, buf.rep_code, 16, None, buf.ml_pub, buf.rows, n, buf.ld, ids, buf.match,
-                            buf.nw, stream)
+                            buf.nw, stream, msg_ws=buf.net)
     elif buf.compare == "lift18":
         ctx.compare_variant(CMP_LIFT18, buf.rep_code, 16, buf.rep_mask, None, buf.rows, n, buf.ld, ids, buf.match,
-                            buf.nw, stream)
+                            buf.nw, stream, msg_ws=buf.net)
     else:
-        ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, n, buf.ld, ids, buf.match, buf.nw, stream)
+        ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, n, buf.ld, ids, buf.match, buf.nw, stream,
+                              msg_ws=buf.net)
     if or_tree:
         nw = (n + 63) // 64
         q = qs.q if qs is not None else qs32.q
@@ -259,7 +274,8 @@ def run_in_batch(ctx: Context, qs: SharedQueries, rot, buf_db: CheckBuffers, str
                        buf.dot_mask[p], buf.ld, stream, galois=qs.galois)
     ids = make_ids(qs.qid_base, rot, BATCH_ENTRY_BASE)
     ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, q, buf.ld, ids, buf.msg, buf.rep_code, buf.rep_mask, stream)
-    ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, q, buf.ld, ids, buf.match, buf.nw, stream)
+    ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, q, buf.ld, ids, buf.match, buf.nw, stream,
+                          msg_ws=buf.net)
     ctx.mask_in_batch(buf.match, q, r, buf.nw, 0, stream)
     ids_or = make_ids(qs.qid_base + BATCH_OR_QID_OFFSET, rot, BATCH_ENTRY_BASE)
     ctx.or_tree(buf.match, q, 1, buf.nw, ids_or, buf.ws, buf.ws.numel(), buf.dup, stream)

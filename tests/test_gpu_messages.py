@@ -1,0 +1,163 @@
+"""The comparison with the parties run apart and every message passed through
+a device buffer (imc_compare_threshold / imc_compare_variant with msg_ws),
+against the oracle's message log, bit for bit: every AND-gate message of
+every party and every 3OT message, plus the match components; the same calls
+with the messages held in registers must give the same components.
+
+Inputs are random replicated components uploaded from the host (every value
+of the rings, not only reachable dot products), over ragged 64-entry words,
+with and without the 16-byte load path."""
+import numpy as np
+import pytest
+
+import oracle as orc
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def imc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_04463_amd as imc_mod
+
+    imc_mod.lib()
+    return imc_mod
+
+
+@pytest.fixture(scope="module")
+def ctx(imc, keys):
+    dealer, party = keys
+    c = imc.Context(imc.Keys(dealer, party), max_rows=512)
+    yield c
+    c.close()
+
+
+def _rep_dev(comps: np.ndarray, ld: int):
+    """[3, rows, n] components -> per party device [2, rows, ld] (own, previous)."""
+    _, rows, n = comps.shape
+    dt = comps.dtype
+    out = []
+    for p in range(3):
+        h = np.zeros((2, rows, ld), dtype=dt)
+        h[0, :, :n] = comps[p]
+        h[1, :, :n] = comps[(p + 2) % 3]
+        out.append(torch.from_numpy(h.view(np.int16 if dt == np.uint16 else np.int32)).cuda())
+    return out
+
+
+def _split(rng, v, bits):
+    mod = 1 << bits
+    c = rng.integers(0, mod, (3,) + v.shape, dtype=np.uint64)
+    c[2] = (v.astype(np.int64) - c[0].astype(np.int64) - c[1].astype(np.int64)) % mod
+    return c.astype(np.uint32 if bits == 32 else np.uint16)
+
+
+def _check_components(match, want, nw):
+    for p in range(3):
+        got = match[p].cpu().numpy().view(np.uint64)[:, :, :nw]
+        assert np.array_equal(got[0], want[p]), p
+        assert np.array_equal(got[1], want[(p + 2) % 3]), p
+
+
+def _check_log(msg, want_log, rows, n, mw_ld):
+    nmsg, _, nw = want_log.shape
+    got = msg.cpu().numpy().view(np.uint64).reshape(nmsg, rows, mw_ld)[:, :, :nw].copy()
+    if n % 64:
+        got[:, :, nw - 1] &= np.uint64((1 << (n % 64)) - 1)     # columns past n are unspecified
+    bad = np.argwhere(got != want_log)
+    assert bad.size == 0, f"{len(bad)} message words differ, first (plane, row, word) {bad[:3].tolist()}"
+
+
+SHAPES = [
+    ((2, [-3, 0, 5]), 150, 192, 64),      # vector loads, three words, the last ragged
+    ((1, [1, 4]), 130, 130, 0),           # ld not a multiple of 8: element-wise loads
+    ((3, [2]), 64, 64, 128),              # exactly one word per row
+    ((1, [0]), 1, 8, 0),                  # a single comparison
+]
+
+
+@pytest.mark.parametrize("rows_r,n,ld,first", SHAPES)
+def test_mpclift_messages_equal_the_oracle_log(ctx, imc, keys, rows_r, n, ld, first):
+    _, party = keys
+    nq, rot = rows_r
+    rows = nq * len(rot)
+    rng = np.random.default_rng(n * 1000 + ld)
+    d = rng.integers(0, 1 << 16, (3, rows, n), dtype=np.uint64).astype(np.uint16)
+    x = rng.integers(0, 1 << 16, (3, rows, n), dtype=np.uint64).astype(np.uint16)
+    want, want_log = orc.compare(party, d, x, nq, rot, 21, first, want_msg=True)
+    nw = (n + 63) // 64
+    mw_ld = nw + 1
+    rep_code, rep_mask = _rep_dev(d, ld), _rep_dev(x, ld)
+    ids = imc.make_ids(21, rot, first)
+    nbytes = imc.compare_msg_bytes(0, rows, mw_ld)
+    assert nbytes == 406 * rows * mw_ld * 8
+    msg = torch.full((nbytes // 8,), -1, dtype=torch.int64, device="cuda")
+    match = [torch.full((2, rows, mw_ld), -1, dtype=torch.int64, device="cuda") for _ in range(3)]
+    ctx.compare_threshold(rep_code, rep_mask, rows, n, ld, ids, match, mw_ld, msg_ws=msg)
+    torch.cuda.synchronize()
+    _check_components(match, want, nw)
+    _check_log(msg, want_log, rows, n, mw_ld)
+    # the register simulation gives the same components
+    match2 = [torch.full((2, rows, mw_ld), -1, dtype=torch.int64, device="cuda") for _ in range(3)]
+    ctx.compare_threshold(rep_code, rep_mask, rows, n, ld, ids, match2, mw_ld)
+    torch.cuda.synchronize()
+    _check_components(match2, want, nw)
+
+
+@pytest.mark.parametrize("variant", ["plain", "lift18", "const32", "nolift"])
+@pytest.mark.parametrize("rows_r,n,ld,first", SHAPES[:2])
+def test_variant_messages_equal_the_oracle_log(ctx, imc, keys, variant, rows_r, n, ld, first):
+    _, party = keys
+    nq, rot = rows_r
+    rows = nq * len(rot)
+    rng = np.random.default_rng(sum(map(ord, variant)) + n)
+    ml = rng.integers(0, 12801, (rows, n)).astype(np.int64)
+    dot = rng.integers(-12800, 12801, (rows, n)).astype(np.int64)
+    code_bits = 32 if variant == "nolift" else 16
+    mask_bits = 32 if variant in ("const32", "nolift") else 16
+    d = _split(rng, dot, code_bits)
+    x = _split(rng, ml, mask_bits)
+    v = {"plain": orc.CMPV_PLAIN, "lift18": orc.CMPV_LIFT18}.get(variant, orc.CMPV_CONST32)
+    want, want_log = orc.compare_variant(party, v, d, None if variant == "plain" else x,
+                                         ml if variant == "plain" else None, nq, rot, 8, first, want_msg=True)
+    nw = (n + 63) // 64
+    mw_ld = nw + 1
+    rep_code = _rep_dev(d, ld)
+    rep_mask = None if variant == "plain" else _rep_dev(x, ld)
+    ml_pub = None
+    if variant == "plain":
+        h = np.zeros((rows, ld), dtype=np.uint16)
+        h[:, :n] = ml
+        ml_pub = torch.from_numpy(h.view(np.int16)).cuda()
+    cv = {"plain": imc.CMP_PLAIN_MASK, "lift18": imc.CMP_LIFT18}.get(variant, imc.CMP_CONST32)
+    nbytes = imc.compare_msg_bytes(cv, rows, mw_ld)
+    assert nbytes == orc.msg_count(v) * rows * mw_ld * 8
+    msg = torch.full((nbytes // 8,), -1, dtype=torch.int64, device="cuda")
+    match = [torch.full((2, rows, mw_ld), -1, dtype=torch.int64, device="cuda") for _ in range(3)]
+    ids = imc.make_ids(8, rot, first)
+    ctx.compare_variant(cv, rep_code, code_bits, rep_mask, ml_pub, rows, n, ld, ids, match, mw_ld, msg_ws=msg)
+    torch.cuda.synchronize()
+    _check_components(match, want, nw)
+    _check_log(msg, want_log, rows, n, mw_ld)
+
+
+def test_message_buffer_argument_errors(ctx, imc):
+    rows, n, ld, rot = 2, 64, 64, [0, 1]
+    rep = [torch.zeros(2, rows, ld, dtype=torch.int16, device="cuda") for _ in range(3)]
+    match = [torch.zeros(2, rows, 1, dtype=torch.int64, device="cuda") for _ in range(3)]
+    ids = imc.make_ids(0, rot, 0)
+    small = torch.zeros(imc.compare_msg_bytes(0, rows, 1) // 8 - 1, dtype=torch.int64, device="cuda")
+    with pytest.raises(imc.IMCError) as e:
+        ctx.compare_threshold(rep, rep, rows, n, ld, ids, match, 1, msg_ws=small)
+    assert e.value.status == imc.IMC_ESHAPE
+    odd = torch.zeros(imc.compare_msg_bytes(0, rows, 1) + 8, dtype=torch.uint8, device="cuda")[1:]
+    with pytest.raises(imc.IMCError) as e:
+        ctx.compare_threshold(rep, rep, rows, n, ld, ids, match, 1, msg_ws=odd)
+    assert e.value.status == imc.IMC_EINVAL
+    # planes that are not 16-byte aligned while ld % 8 == 0 (16-byte loads)
+    shifted = [torch.zeros(2 * rows * ld + 8, dtype=torch.int16, device="cuda")[1:] for _ in range(3)]
+    with pytest.raises(imc.IMCError) as e:
+        ctx.compare_threshold(shifted, shifted, rows, n, ld, ids, match, 1)
+    assert e.value.status == imc.IMC_EINVAL
