@@ -235,23 +235,44 @@ def verify(ctx, buf, w, qc, qm, party_keys):
 
 def verify_in_batch(ctx, buf, bb, w, qc, qm):
     """The opened final decision of every query against the opened database
-    decision OR the plaintext decision over the batch's earlier queries."""
+    decision OR the plaintext decision over the queries of earlier groups
+    (w.group = 2: the eyes of earlier persons); with two eyes, also every
+    opened person decision against the OR of its eyes' expected decisions."""
     import torch
 
     import oracle as orc
     import paper_2405_04463_amd as imc
     from paper_2405_04463_amd.pipeline import open_dup
 
+    g = w.group
     db_dup, s1 = open_dup(ctx, buf, w.n_q, check=1)
     final = torch.empty(w.n_q, dtype=torch.uint8, device="cuda")
     s2 = ctx.open(imc.OPEN_U8_XOR, bb.final, w.n_q, final, 1)
     torch.cuda.synchronize()
-    batch = np.array([0] + [int(orc.plain(qc[i:i + 1], qm[i:i + 1], w.rot, qc[:i], qm[:i])[3][0])
-                            for i in range(1, w.n_q)], dtype=np.uint8)
+    batch = np.zeros(w.n_q, dtype=np.uint8)
+    for i in range(g, w.n_q):
+        k = g * (i // g)
+        batch[i] = orc.plain(qc[i:i + 1], qm[i:i + 1], w.rot, qc[:k], qm[:k])[3][0]
     want = db_dup.cpu().numpy() | batch
     got = final.cpu().numpy()
-    return {"bit_exact": bool(np.array_equal(got, want)) and s1 == 0 and s2 == 0,
-            "batch_duplicates": int(batch.sum()), "final_true": int(got.sum())}
+    res = {"bit_exact": bool(np.array_equal(got, want)) and s1 == 0 and s2 == 0,
+           "batch_duplicates": int(batch.sum()), "final_true": int(got.sum())}
+    if g == 2:
+        persons = torch.empty(w.n_q // 2, dtype=torch.uint8, device="cuda")
+        s3 = ctx.open(imc.OPEN_U8_XOR, bb.person, w.n_q // 2, persons, 1)
+        torch.cuda.synchronize()
+        pw = want[0::2] | want[1::2]
+        pg = persons.cpu().numpy()
+        res["persons_bit_exact"] = bool(np.array_equal(pg, pw)) and s3 == 0
+        res["bit_exact"] = res["bit_exact"] and res["persons_bit_exact"]
+        res["persons"] = int(pg.size)
+        res["persons_duplicate"] = int(pg.sum())
+        # the patterns of the workload: eyes the database holds, eyes that
+        # only in-batch matching finds, and a person's own eyes never meeting
+        res["persons_by_left_eye_only"] = int(((want[0::2] == 1) & (want[1::2] == 0)).sum())
+        res["persons_by_right_eye_only"] = int(((want[0::2] == 0) & (want[1::2] == 1)).sum())
+        res["persons_by_both_eyes"] = int(((want[0::2] == 1) & (want[1::2] == 1)).sum())
+    return res
 
 
 # ChaCha12 blocks per 64 comparisons of each comparison circuit (their PRF tapes)
@@ -308,10 +329,13 @@ def run_full(args):
     from paper_2405_04463_amd.pipeline import (VECS32, SharedDB, SharedDB32, SharedQueries, SharedQueries32,
                                                alloc_check, open_dup, run_check, run_in_batch)
 
-    w = wl.full_protocol(n_db=args.n_db, n_q=args.n_q)
-    in_batch = args.in_batch
+    if args.two_eyes:
+        w = wl.two_eyes(n_db=args.n_db, persons=(args.n_q or 64) // 2)
+    else:
+        w = wl.full_protocol(n_db=args.n_db, n_q=args.n_q)
+    in_batch = args.in_batch or args.two_eyes
     if in_batch and (args.compare != "mpclift" or w.n_q < 16):
-        raise SystemExit("--in-batch runs with the MPCLift comparison and at least 16 queries")
+        raise SystemExit("--in-batch and --two-eyes run with the MPCLift comparison and at least 16 queries")
     dealer, party = keys()
     galois = args.scheme == "galois"
     plain = args.compare == "plain"
@@ -326,7 +350,9 @@ def run_full(args):
     db32 = SharedDB32(ctx, w.n_db, vecs=v32) if v32 else None
     db_masks = enroll_db(ctx, db if code16 else None, w.seed, w.n_db, keep_masks=plain, db32=db32)
     qc, qm = wl.make_queries(w)
-    if in_batch:
+    if args.two_eyes:
+        wl.plant_in_batch(w, qc, qm, w.batch_pairs)
+    elif in_batch:
         wl.plant_in_batch(w, qc, qm)
     q_codes = torch.from_numpy(qc.view(np.int64)).cuda()
     q_masks = torch.from_numpy(qm.view(np.int64)).cuda()
@@ -341,7 +367,7 @@ def run_full(args):
     log(f"verification: {ver}")
     bb = None
     if in_batch:
-        bb = run_in_batch(ctx, qs, w.rot, buf)
+        bb = run_in_batch(ctx, qs, w.rot, buf, group=w.group)
         ver["in_batch"] = verify_in_batch(ctx, buf, bb, w, qc, qm)
         log(f"in-batch verification: {ver['in_batch']}")
     final_out = torch.empty(w.n_q, dtype=torch.uint8, device="cuda")
@@ -397,10 +423,13 @@ def run_full(args):
         if in_batch:
             if events is not None:
                 events[5][0].record(stream)
-            run_in_batch(ctx, qs, w.rot, buf, stream, reuse=bb)
+            run_in_batch(ctx, qs, w.rot, buf, stream, reuse=bb, group=w.group)
             if events is not None:
                 events[5][1].record(stream)
-            ctx.open(imc.OPEN_U8_XOR, bb.final, qs.q, final_out, 0, stream)
+            if w.group == 2:
+                ctx.open(imc.OPEN_U8_XOR, bb.person, qs.q // 2, final_out, 0, stream)
+            else:
+                ctx.open(imc.OPEN_U8_XOR, bb.final, qs.q, final_out, 0, stream)
         else:
             open_dup(ctx, buf, qs.q, check=0, stream=stream)
 
@@ -477,14 +506,24 @@ def run_full(args):
                                   other_ms),
         "verification": ver,
     }
-    if in_batch:
+    if args.two_eyes:
+        res["config"]["workload"] = (f"3-party protocol on one GPU: DB {w.n_db} entries per party, "
+                                     f"{w.n_q // 2} persons x 2 eyes x {len(w.rot)} rotations ({w.rows} rows), "
+                                     f"in-batch matching of each eye against the eyes of earlier persons "
+                                     f"({w.rows} x {w.n_q} more comparisons), a person a duplicate if "
+                                     f"either eye is")
+        res["config"]["persons"] = w.n_q // 2
+        res["config"]["in_batch"] = True
+    elif in_batch:
         res["config"]["workload"] += (f", plus in-batch matching (each query against the batch's earlier "
                                       f"queries: {w.rows} x {w.n_q} more comparisons)")
         res["config"]["in_batch"] = True
         res["in_batch"] = {"ms_per_step": float(np.mean([ev[5][0].elapsed_time(ev[5][1]) for ev in evs])),
                            "comparisons": w.rows * w.n_q,
                            "note": "batch appended as entries, dots, reshare, compare, triangle mask, OR-tree, "
-                                   "OR with the database decision; inside the timed step"}
+                                   "OR with the database decision"
+                                   + (", OR of each person's two eyes" if w.group == 2 else "")
+                                   + "; inside the timed step"}
     return res, (w, qc, qm)
 
 
@@ -854,6 +893,9 @@ def main():
     ap.add_argument("--net", choices=["buffers", "registers"], default="buffers",
                     help="comparison messages: through a device buffer with the parties apart (default), or held "
                          "in registers with the three parties of a comparison in one lane")
+    ap.add_argument("--two-eyes", action="store_true",
+                    help="full workload as persons of two eyes (queries 2k, 2k+1), with in-batch matching over "
+                         "earlier persons and one decision per person")
     ap.add_argument("--in-batch", action="store_true",
                     help="full workload: also match each query against the batch's earlier queries (Sec. 6.4)")
     args = ap.parse_args()
@@ -862,7 +904,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the protocol's three parties are simulated on it "
-              "(multi-GPU party transport is not part of this build)", file=sys.stderr)
+              "(multi-GPU party transport is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "full":
         args.n_db = args.n_db or 300_000

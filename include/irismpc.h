@@ -363,14 +363,16 @@ imc_status imc_append_db(imc_ctx* ctx, const void* const qraw[3], size_t qi, voi
 /* In-batch matching (Sec. 6.4: the queries of a batch are also matched with
  * each other).  The batch's queries are compared as entries (their raw
  * shares appended to a region with imc_append_db, compared under entry ids
- * distinct from the database's) and query qi may only match the earlier
- * queries j < qi: this call turns the shared match bits of columns j >= qi in
- * word `word` of every row qi*r + ri into public zeros (all components of both
- * planes of match[p], [2][q*r][mw_ld], are cleared).  q <= 64 (one word of
- * columns).  Errors: IMC_EINVAL (null, unaligned, q > 64, r outside 1..32),
+ * distinct from the database's) and query qi may only match the queries of
+ * earlier groups, a group being `group` consecutive queries (1: each query
+ * alone; 2: a person's two eyes, Sec. 6.4 / Table 4): this call turns the
+ * shared match bits of columns j >= group * floor(qi / group) in word `word`
+ * of every row qi*r + ri into public zeros (all components of both planes of
+ * match[p], [2][q*r][mw_ld], are cleared).  q <= 64 (one word of columns).
+ * Errors: IMC_EINVAL (null, unaligned, q > 64, r outside 1..32, group 0),
  * IMC_ESHAPE (word >= mw_ld). */
 imc_status imc_mask_in_batch(imc_ctx* ctx, uint64_t* const match[3], size_t q, size_t r, size_t mw_ld, size_t word,
-                             imc_stream stream);
+                             size_t group, imc_stream stream);
 
 /* Shared OR of two bit sharings (Sec. 4.2's x OR y = x ^ y ^ (x AND y), one
  * AND gate per element): combines two decisions, e.g. a query's database and
@@ -380,6 +382,15 @@ imc_status imc_mask_in_batch(imc_ctx* ctx, uint64_t* const match[3], size_t q, s
  * a distinct id per combination.  Errors: IMC_EINVAL (null). */
 imc_status imc_or_bits(imc_ctx* ctx, const uint8_t* const a[3], const uint8_t* const b[3], size_t count,
                        uint64_t id, uint8_t* const out[3], imc_stream stream);
+
+/* A person's decision from the decisions of its two eyes (Sec. 6.4: a
+ * person is a duplicate if either eye is): out element i = in element 2i OR
+ * in element 2i+1, one AND gate per person, with the randomness and results
+ * of imc_or_bits on a = the even elements, b = the odd ones.  in[p]: device
+ * u8 [2][2*count] (own component, then component p-1; 0/1), out[p]: device
+ * u8 [2][count].  Errors: IMC_EINVAL (null). */
+imc_status imc_or_pairs(imc_ctx* ctx, const uint8_t* const in[3], size_t count, uint64_t id, uint8_t* const out[3],
+                        imc_stream stream);
 
 /* ---------------------------------------------------------------------------
  * Galois-ring Shamir form of the dot products (Sec. 4.3.2, "Optimized

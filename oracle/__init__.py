@@ -358,11 +358,12 @@ def t_gr_inv(a):
     return out if ok else None
 
 
-def mask_in_batch(match, q: int, r: int, word: int):
-    """Clear shared match bits of columns j >= qi in `word` of rows qi*r+ri (copy)."""
+def mask_in_batch(match, q: int, r: int, word: int, group: int = 1):
+    """Clear shared match bits of columns j with j//group >= qi//group in
+    `word` of rows qi*r+ri (copy): a query meets only earlier groups."""
     out = np.ascontiguousarray(match, dtype=np.uint64).copy()
     lib().orc_mask_in_batch(_p(out), ctypes.c_int(q), ctypes.c_int(r), ctypes.c_long(out.shape[-1]),
-                            ctypes.c_long(word))
+                            ctypes.c_long(word), ctypes.c_int(group))
     return out
 
 
@@ -376,14 +377,23 @@ def or_bits(keys: bytes, a, b, id_: int):
     return out
 
 
+def or_pairs(keys: bytes, x, id_: int):
+    """A person's decision from its eyes' decisions [Sec. 6.4]: element i of
+    the result is element 2i OR element 2i+1 of x ([3, 2*count])."""
+    x = np.asarray(x, dtype=np.uint8)
+    return or_bits(keys, x[:, 0::2], x[:, 1::2], id_)
+
+
 BATCH_ENTRY_BASE = 1 << 47    # entry ids of in-batch columns (distinct randomness from database entries)
+PERSON_OR_BASE = 1 << 47      # OR-gate stream ids of the per-person combination
 
 
-def protocol_in_batch(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_base=0, scheme="aby3"):
+def protocol_in_batch(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_base=0, scheme="aby3", group=1):
     """Protocol run where each query is also compared with the earlier queries
     of its batch: database part as `protocol`; batch part with the queries'
-    own shares as entries (ids BATCH_ENTRY_BASE + j), columns j >= qi cleared,
-    its OR-tree, then one OR gate per query combining both decisions."""
+    own shares as entries (ids BATCH_ENTRY_BASE + j), the columns of its own
+    and later groups cleared (group=2: a person's two eyes never meet), its
+    OR-tree, then one OR gate per query combining both decisions."""
     q, r = qc.shape[0], len(rot)
     res = protocol(dealer_key, keys, qc, qm, rot, dc, dm, qid_base=qid_base, first_entry=0, scheme=scheme)
     qsh = res["qsh"]
@@ -395,10 +405,12 @@ def protocol_in_batch(dealer_key: bytes, keys: bytes, qc, qm, rot, dc, dm, qid_b
         zm.append(m)
     rc, rm = reshare(keys, np.stack(zc), np.stack(zm), q, rot, qid_base, BATCH_ENTRY_BASE)
     bm = compare(keys, rc, rm, q, rot, qid_base, BATCH_ENTRY_BASE)
-    bm = mask_in_batch(bm, q, r, 0)
+    bm = mask_in_batch(bm, q, r, 0, group)
     dup_b, _ = or_tree(keys, bm, q, r, qid_base + (1 << 46))
     dup = or_bits(keys, res["dup"], dup_b, qid_base)
     res.update(batch_match=bm, dup_db=res["dup"], dup_batch=dup_b, dup=dup)
+    if group == 2:     # person k = eyes 2k, 2k+1: duplicate if either eye is
+        res["person"] = or_pairs(keys, dup, PERSON_OR_BASE | qid_base)
     return res
 
 

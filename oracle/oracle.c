@@ -668,21 +668,24 @@ void orc_or_tree(const uint8_t* keys, const uint64_t* match, int nq, int r, long
 /* ------------------------------------------------------------------ */
 /* In-batch matching and combining decisions [Sec. 6.4: the queries of a */
 /* batch are also matched with each other; a person's query covers both  */
-/* eyes].  Query i of a batch is compared with the earlier queries j < i  */
-/* only: the shared match bits of columns j >= i are replaced by public   */
-/* zeros (every component cleared).  Two shared decisions are combined    */
-/* with one OR gate, x OR y = x ^ y ^ (x AND y).                          */
+/* eyes].  Query i of a batch is compared with the queries of earlier     */
+/* groups only (a group: one query, or the two eyes of one person): the   */
+/* other shared match bits are replaced by public zeros (every component  */
+/* cleared).  Two shared decisions are combined with one OR gate,        */
+/* x OR y = x ^ y ^ (x AND y).                                            */
 /* ------------------------------------------------------------------ */
 
-/* match: [3][q*r][nw] components; clears bits j >= qi of word `word` in
- * every row qi*r + ri. */
-void orc_mask_in_batch(uint64_t* match, int q, int r, long nw, long word) {
+/* match: [3][q*r][nw] components.  Queries come in groups of `group`
+ * consecutive queries (1: every query alone; 2: the two eyes of a person);
+ * query qi is compared with the queries of earlier groups only, so bit j of
+ * word `word` in every row qi*r + ri survives iff j/group < qi/group. */
+void orc_mask_in_batch(uint64_t* match, int q, int r, long nw, long word, int group) {
   long rows = (long)q * r;
   for (int p = 0; p < 3; ++p)
     for (long row = 0; row < rows; ++row) {
       int qi = (int)(row / r);
-      uint64_t keep = qi >= 64 ? ~0ull : ((1ull << qi) - 1);   /* columns j < qi */
-      match[((size_t)p * rows + row) * nw + word] &= keep;
+      for (int j = 0; j < 64; ++j)
+        if (j / group >= qi / group) match[((size_t)p * rows + row) * nw + word] &= ~(1ull << j);
     }
 }
 

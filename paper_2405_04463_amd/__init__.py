@@ -29,7 +29,7 @@ EXPORTS = [
     "imc_galois_append_db", "imc_mask_in_batch", "imc_or_bits", "imc_dot_shares_gather",
     "imc_galois_dot_shares_gather", "imc_compare_variant", "imc_rotate_masks", "imc_plain_ml", "imc_db32_bytes",
     "imc_query32_op_bytes", "imc_share32_db", "imc_share32_query", "imc_dot32_shares", "imc_reshare32",
-    "imc_dot_shares_rows_noalloc", "imc_compare_msg_bytes",
+    "imc_dot_shares_rows_noalloc", "imc_compare_msg_bytes", "imc_or_pairs",
 ]
 
 (DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW, DOT_TILES_ROTATION,
@@ -112,7 +112,8 @@ def lib():
         L.imc_galois_dot_shares_rows.argtypes = L.imc_dot_shares_rows.argtypes
         L.imc_dot_shares_rows_noalloc.argtypes = L.imc_dot_shares_rows.argtypes
         L.imc_galois_append_db.argtypes = L.imc_append_db.argtypes
-        L.imc_mask_in_batch.argtypes = [_VP, _P3, sz, sz, sz, sz, _VP]
+        L.imc_mask_in_batch.argtypes = [_VP, _P3, sz, sz, sz, sz, sz, _VP]
+        L.imc_or_pairs.argtypes = [_VP, _P3, sz, ctypes.c_uint64, _P3, _VP]
         L.imc_dot_shares_gather.argtypes = [_VP, ctypes.c_int, _VP, _VP, sz, ctypes.POINTER(imc_ids), _VP, sz, sz, _VP,
                                             _VP, sz, _VP]
         L.imc_galois_dot_shares_gather.argtypes = L.imc_dot_shares_gather.argtypes
@@ -361,10 +362,14 @@ class Context:
         return _check(lib().imc_or_tree(self._h, _p3(match3), q, nw, mw_ld, ctypes.byref(ids), addr(ws), ws_bytes,
                                         _p3(dup3), _stream(stream)), "imc_or_tree")
 
-    # -- imc_mask_in_batch
-    def mask_in_batch(self, match3, q, r, mw_ld, word, stream=None):
-        return _check(lib().imc_mask_in_batch(self._h, _p3(match3), q, r, mw_ld, word, _stream(stream)),
+    # -- imc_mask_in_batch (group: consecutive queries that may not match each other, e.g. 2 eyes)
+    def mask_in_batch(self, match3, q, r, mw_ld, word, stream=None, group=1):
+        return _check(lib().imc_mask_in_batch(self._h, _p3(match3), q, r, mw_ld, word, group, _stream(stream)),
                       "imc_mask_in_batch")
+
+    # -- imc_or_pairs (element i of out = elements 2i OR 2i+1 of in)
+    def or_pairs(self, in3, count, id_, out3, stream=None):
+        return _check(lib().imc_or_pairs(self._h, _p3(in3), count, id_, _p3(out3), _stream(stream)), "imc_or_pairs")
 
     # -- imc_or_bits
     def or_bits(self, a3, b3, count, id_, out3, stream=None):

@@ -373,16 +373,27 @@ imc_status imc_galois_append_db(imc_ctx* c, const void* const qraw[3], size_t qi
 }
 
 imc_status imc_mask_in_batch(imc_ctx* c, uint64_t* const match[3], size_t q, size_t r, size_t mw_ld, size_t word,
-                             imc_stream stream) {
+                             size_t group, imc_stream stream) {
   if (!c || !match) return IMC_EINVAL;
   for (int p = 0; p < 3; ++p)
     if (!match[p] || !aligned(match[p], 8)) return IMC_EINVAL;
-  if (q > 64 || r < 1 || r > IMC_MAX_ROT) return IMC_EINVAL;
+  if (q > 64 || r < 1 || r > IMC_MAX_ROT || group < 1) return IMC_EINVAL;
   if (word >= mw_ld) return IMC_ESHAPE;
   if (q == 0) return IMC_OK;
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;
-  return dev_status(imc::launch_mask_in_batch(match, q, uint32_t(r), mw_ld, word, hipStream_t(stream)));
+  return dev_status(imc::launch_mask_in_batch(match, q, uint32_t(r), mw_ld, word, group, hipStream_t(stream)));
+}
+
+imc_status imc_or_pairs(imc_ctx* c, const uint8_t* const in[3], size_t count, uint64_t id, uint8_t* const out[3],
+                        imc_stream stream) {
+  if (!c || !in || !out) return IMC_EINVAL;
+  for (int p = 0; p < 3; ++p)
+    if (!in[p] || !out[p]) return IMC_EINVAL;
+  if (count == 0) return IMC_OK;
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  return dev_status(imc::launch_or_pairs(c->party, in, count, id, out, hipStream_t(stream)));
 }
 
 imc_status imc_or_bits(imc_ctx* c, const uint8_t* const a[3], const uint8_t* const b[3], size_t count, uint64_t id,

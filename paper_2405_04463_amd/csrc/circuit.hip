@@ -683,17 +683,18 @@ __global__ void __launch_bounds__(64) or_final_kernel(OrFinalArgs a) {
 
 // ---------------------------------------------------------------------------
 // In-batch matching (Sec. 6.4): query qi of a batch is compared with the
-// earlier queries j < qi only.  The shared match bits of columns j >= qi in
-// word `word` of every row qi*r + ri become public zeros: every component of
-// both planes is cleared.
+// queries of earlier groups only (groups of `group` consecutive queries, e.g.
+// a person's two eyes): the shared match bits of columns
+// j >= group * floor(qi / group) in word `word` of every row qi*r + ri become
+// public zeros (every component of both planes is cleared).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) mask_in_batch_kernel(uint64_t* m0, uint64_t* m1, uint64_t* m2, uint64_t q,
-                                                            uint32_t r, uint64_t mw_ld, uint64_t word) {
+                                                            uint32_t r, uint64_t mw_ld, uint64_t word, uint64_t group) {
   const uint64_t rows = q * r;
   const uint64_t row = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (row >= rows) return;
-  const uint64_t qi = row / r;
-  const uint64_t keep = qi >= 64 ? ~0ull : ((1ull << qi) - 1);
+  const uint64_t cut = (row / r) / group * group;   // first query of this query's group
+  const uint64_t keep = cut >= 64 ? ~0ull : ((1ull << cut) - 1);
   uint64_t* m[3] = {m0, m1, m2};
 #pragma unroll
   for (int p = 0; p < 3; ++p)
@@ -706,10 +707,10 @@ __global__ void __launch_bounds__(256) mask_in_batch_kernel(uint64_t* m0, uint64
 // (kDomOrPairs << 56 | id) from every key.  a, b, out: u8 [2][count].
 struct OrBitsArgs {
   Keys3 keys;
-  const uint8_t* a[3];
+  const uint8_t* a[3];       // element i at a[p][i * stride]
   const uint8_t* b[3];
   uint8_t* out[3];
-  uint64_t count, id;
+  uint64_t count, id, stride;
 };
 
 __global__ void __launch_bounds__(256) or_bits_kernel(OrBitsArgs a) {
@@ -728,8 +729,8 @@ __global__ void __launch_bounds__(256) or_bits_kernel(OrBitsArgs a) {
   B3 x, y;
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
-    x.c[p] = a.a[p][i] & 1u;
-    y.c[p] = a.b[p][i] & 1u;
+    x.c[p] = a.a[p][i * a.stride] & 1u;
+    y.c[p] = a.b[p][i * a.stride] & 1u;
   }
   const B3 z = bx(bx(x, y), band(x, y, f[0], f[1], f[2]));
 #pragma unroll
@@ -949,12 +950,12 @@ hipError_t launch_open(int kind, const void* const rep[3], uint64_t count, void*
 }
 
 hipError_t launch_mask_in_batch(uint64_t* const match[3], uint64_t q, uint32_t r, uint64_t mw_ld, uint64_t word,
-                                hipStream_t s) {
+                                uint64_t group, hipStream_t s) {
   const uint64_t rows = q * r;
   if (rows == 0) return hipSuccess;
   if (!fits_grid(rows, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(mask_in_batch_kernel, dim3(unsigned((rows + 255) / 256)), dim3(256), 0, s, match[0], match[1],
-                     match[2], q, r, mw_ld, word);
+                     match[2], q, r, mw_ld, word, group);
   return hipGetLastError();
 }
 
@@ -970,6 +971,25 @@ hipError_t launch_or_bits(const Keys3& keys, const uint8_t* const x[3], const ui
   }
   a.count = count;
   a.id = id;
+  a.stride = 1;
+  if (!fits_grid(count, 256)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(or_bits_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_or_pairs(const Keys3& keys, const uint8_t* const in[3], uint64_t count, uint64_t id,
+                           uint8_t* const out[3], hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  OrBitsArgs a;
+  a.keys = keys;
+  for (int p = 0; p < 3; ++p) {
+    a.a[p] = in[p];        // elements 2i
+    a.b[p] = in[p] + 1;    // elements 2i + 1
+    a.out[p] = out[p];
+  }
+  a.count = count;
+  a.id = id;
+  a.stride = 2;
   if (!fits_grid(count, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(or_bits_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();

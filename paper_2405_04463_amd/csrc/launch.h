@@ -76,7 +76,9 @@ size_t or_tree_ws_bytes(uint64_t q, uint64_t r, uint64_t nw);
 hipError_t launch_or_tree(const Keys3& keys, const uint64_t* const match[3], uint64_t q, uint64_t nw, uint64_t mw_ld,
                           const imc_ids_dev& ids, void* ws, uint8_t* const dup[3], hipStream_t s);
 hipError_t launch_mask_in_batch(uint64_t* const match[3], uint64_t q, uint32_t r, uint64_t mw_ld, uint64_t word,
-                                hipStream_t s);
+                                uint64_t group, hipStream_t s);
+hipError_t launch_or_pairs(const Keys3& keys, const uint8_t* const in[3], uint64_t count, uint64_t id,
+                           uint8_t* const out[3], hipStream_t s);
 hipError_t launch_or_bits(const Keys3& keys, const uint8_t* const x[3], const uint8_t* const y[3], uint64_t count,
                           uint64_t id, uint8_t* const out[3], hipStream_t s);
 hipError_t launch_open(int kind, const void* const rep[3], uint64_t count, void* out, int check,

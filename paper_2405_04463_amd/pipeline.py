@@ -128,6 +128,8 @@ class CheckBuffers:
     msg32: dict | None = None                # vec -> 3 x u32 [rows, ld]
     rep32: dict | None = None                # vec -> 3 x u32 [2, rows, ld]
     net: torch.Tensor | None = None          # the comparison's message buffer (None: messages in registers)
+    group: int = 1                           # in-batch part: queries per person
+    person: list | None = None               # in-batch part, 2 eyes: 3 x u8 [2, q/2] person decisions
 
 
 # Message-buffer layout of each comparison setting (imc_compare_msg_bytes's variant).
@@ -248,23 +250,32 @@ def open_dots(ctx: Context, buf: CheckBuffers, check: int = 1, stream=None):
 # OR-tree query-id offset distinct from the database tree's.
 BATCH_ENTRY_BASE = 1 << 47
 BATCH_OR_QID_OFFSET = 1 << 46
+# Both eyes (Sec. 6.4): queries 2k and 2k+1 are person k's left and right
+# eye; the person's decision is one more OR gate, under its own stream id.
+PERSON_OR_BASE = 1 << 47
 
 
-def run_in_batch(ctx: Context, qs: SharedQueries, rot, buf_db: CheckBuffers, stream=None, reuse=None):
-    """Query qi of the batch is also compared with queries j < qi.  buf_db
-    holds the database check of the same queries (its dup); returns the
-    buffers of the batch part, whose `final` holds dup_db OR dup_batch.
+def run_in_batch(ctx: Context, qs: SharedQueries, rot, buf_db: CheckBuffers, stream=None, reuse=None,
+                 group: int = 1):
+    """Query qi of the batch is also compared with the queries of earlier
+    groups (group=1: queries j < qi; group=2: the eyes of earlier persons).
+    buf_db holds the database check of the same queries (its dup); returns
+    the buffers of the batch part, whose `final` holds dup_db OR dup_batch
+    per query and, for group=2, `person` the OR of each person's two eyes.
     reuse: the buffers a previous call on a batch of the same shape returned
     (nothing is allocated then)."""
-    assert qs.raw is not None and 0 < qs.q <= 64
+    assert qs.raw is not None and 0 < qs.q <= 64 and group in (1, 2) and qs.q % group == 0
     q, r = qs.q, len(rot)
+    dev = buf_db.dup[0].device
     if reuse is not None:
-        assert reuse.rows == q * r and reuse.region.galois == qs.galois
+        assert reuse.rows == q * r and reuse.region.galois == qs.galois and reuse.group == group
         region, buf, final = reuse.region, reuse, reuse.final
     else:
-        region = SharedDB(ctx, 64, galois=qs.galois, device=buf_db.dup[0].device)
-        buf = alloc_check(q, r, q, device=buf_db.dup[0].device)
-        final = [torch.empty(2, q, dtype=torch.uint8, device=buf_db.dup[0].device) for _ in range(3)]
+        region = SharedDB(ctx, 64, galois=qs.galois, device=dev)
+        buf = alloc_check(q, r, q, device=dev)
+        final = [torch.empty(2, q, dtype=torch.uint8, device=dev) for _ in range(3)]
+        buf.group = group
+        buf.person = [torch.empty(2, q // 2, dtype=torch.uint8, device=dev) for _ in range(3)] if group == 2 else None
     for j in range(q):
         ctx.append_db(qs.raw, j, region.regions, region.capacity, j, stream, galois=qs.galois)
     region.n = q
@@ -276,10 +287,12 @@ def run_in_batch(ctx: Context, qs: SharedQueries, rot, buf_db: CheckBuffers, str
     ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, q, buf.ld, ids, buf.msg, buf.rep_code, buf.rep_mask, stream)
     ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, q, buf.ld, ids, buf.match, buf.nw, stream,
                           msg_ws=buf.net)
-    ctx.mask_in_batch(buf.match, q, r, buf.nw, 0, stream)
+    ctx.mask_in_batch(buf.match, q, r, buf.nw, 0, stream, group=group)
     ids_or = make_ids(qs.qid_base + BATCH_OR_QID_OFFSET, rot, BATCH_ENTRY_BASE)
     ctx.or_tree(buf.match, q, 1, buf.nw, ids_or, buf.ws, buf.ws.numel(), buf.dup, stream)
     ctx.or_bits(buf_db.dup, buf.dup, q, qs.qid_base, final, stream)
+    if group == 2:
+        ctx.or_pairs(final, q // 2, PERSON_OR_BASE | qs.qid_base, buf.person, stream)
     buf.final = final
     buf.region = region
     return buf

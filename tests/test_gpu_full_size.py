@@ -15,6 +15,12 @@ configuration the benchmark times, on outputs the oracle computes one by one.
   whole database; every opened one re-decided by the plaintext check, the
   opened ones equal to the plaintext matches of the planted pairs and every
   opened duplicate bit equal to the plaintext one (tests/fullcheck.py).
+* Both eyes at the deployed batch: 32 persons x 2 eyes x 31 rotations
+  against 300,000 entries, with in-batch matching over the eyes of earlier
+  persons: the database part as above (every opened bit, the OR-tree
+  components), the batch part's match, duplicate, combined and person
+  components against the oracle, and every opened person decision against
+  the plaintext OR over its two eyes.
 * The batched step of 200 uneven batches against 1,000,000 entries.
 * Party-local serving over 1,500,000 entries of a 2,000,000-entry region.
 * The comparison settings (public masks, Lift to Z_2^18, ConstLift, NoLift)
@@ -178,6 +184,77 @@ def test_three_party_protocol_at_300k_entries(imc, keys, galois):
         check_or_tree_components(party, match_own, dup_planes, w.n_q, r)
         nones, ndup = check_every_opened_bit(mo, dup, w, qc, qm, n)
         assert nones > 0 and ndup > 0
+    finally:
+        ctx.close()
+        free()
+
+
+def test_two_eyes_at_300k_entries(imc, keys):
+    """The deployed batch shape (Sec. 6.4): the person decisions of 32
+    persons, each eye checked against the database and the eyes of earlier
+    persons, in the configuration of the benchmark's two-eye step."""
+    from fullcheck import check_every_opened_bit, check_or_tree_components
+    from paper_2405_04463_amd.pipeline import (PERSON_OR_BASE, SharedDB, SharedQueries, alloc_check, open_dup,
+                                               open_match, run_check, run_in_batch)
+
+    dealer, party = keys
+    w = wl.two_eyes()
+    assert (w.n_db, w.n_q, len(w.rot), w.group) == (300_000, 64, 31, 2)
+    n, r = w.n_db, len(w.rot)
+    qc, qm = wl.make_queries(w)
+    wl.plant_in_batch(w, qc, qm, w.batch_pairs)
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=w.rows)
+    try:
+        db = SharedDB(ctx, n)
+        enroll(db, w.seed, n)
+        qs = SharedQueries(ctx, dev64(qc), dev64(qm), 0)
+        buf = alloc_check(w.n_q, r, n)
+        run_check(ctx, qs, w.rot, db, 0, n, buf)
+        bb = run_in_batch(ctx, qs, w.rot, buf, group=2)
+        mo, s1 = open_match(ctx, buf, check=1)
+        do, s2 = open_dup(ctx, buf, w.n_q, check=1)
+        persons = torch.empty(w.n_q // 2, dtype=torch.uint8, device="cuda")
+        s3 = ctx.open(imc.OPEN_U8_XOR, bb.person, w.n_q // 2, persons, 1)
+        torch.cuda.synchronize()
+        assert s1 == imc.IMC_OK and s2 == imc.IMC_OK and s3 == imc.IMC_OK
+        match_own = np.stack([buf.match[p][0].cpu().numpy().view(np.uint64) for p in range(3)])
+        dup_planes = [buf.dup[p].cpu().numpy() for p in range(3)]
+        host = lambda ts: [t.cpu().numpy() for t in ts]     # noqa: E731
+        bmatch = [m.view(np.uint64) for m in host(bb.match)]
+        bdup, bfinal, bperson = host(bb.dup), host(bb.final), host(bb.person)
+        mo = mo.cpu().numpy().view(np.uint64)
+        dup = do.cpu().numpy()
+        persons = persons.cpu().numpy()
+        del buf, bb, db, qs
+        free()
+
+        # the database part
+        check_or_tree_components(party, match_own, dup_planes, w.n_q, r)
+        nones, ndup = check_every_opened_bit(mo, dup, w, qc, qm, n)
+        assert nones > 0 and ndup > 0
+        # the batch part depends on the queries' shares alone: the oracle's run
+        # over a one-entry database gives its components
+        dc1, dm1 = wl.gen_codes(w.seed, 0, 1)
+        ref = orc.protocol_in_batch(dealer, party, qc, qm, w.rot, dc1, dm1, qid_base=0, group=2)
+        dup_db = np.stack([dup_planes[p][0] for p in range(3)])
+        final = orc.or_bits(party, dup_db, ref["dup_batch"], 0)
+        person = orc.or_pairs(party, final, PERSON_OR_BASE)
+        for p in range(3):
+            pm = (p + 2) % 3
+            assert np.array_equal(bmatch[p][0, :, :1], ref["batch_match"][p]), p
+            assert np.array_equal(bmatch[p][1, :, :1], ref["batch_match"][pm]), p
+            for name, got, want in (("dup_batch", bdup, ref["dup_batch"]), ("dup", bfinal, final),
+                                    ("person", bperson, person)):
+                assert np.array_equal(got[p][0], want[p]) and np.array_equal(got[p][1], want[pm]), (name, p)
+        # every opened person decision against the plaintext over both eyes
+        batch = np.zeros(w.n_q, dtype=np.uint8)
+        for i in range(2, w.n_q):
+            k = 2 * (i // 2)
+            batch[i] = orc.plain(qc[i:i + 1], qm[i:i + 1], w.rot, qc[:k], qm[:k])[3][0]
+        eyes = dup.astype(np.uint8) | batch
+        assert np.array_equal(persons, eyes[0::2] | eyes[1::2])
+        assert batch[[22, 39, 55]].all() and batch.sum() == 3       # the in-batch pairs that count
+        assert not batch[31] and not batch[62]                       # own left eye; exactly at the threshold
     finally:
         ctx.close()
         free()

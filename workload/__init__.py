@@ -156,6 +156,8 @@ class Workload:
     rot: list
     seed: int
     planted: list = field(default_factory=list)   # (query idx, entry, rot, h or exact)
+    batch_pairs: list = field(default_factory=list)   # (query i, query j, rot, h or exact): i from j
+    group: int = 1                                # queries per person (2: left and right eye)
 
     @property
     def rows(self) -> int:
@@ -202,13 +204,51 @@ def party_local(n_db: int = 1_000_000, n_q: int = 32, seed: int = 0x1A150002) ->
     return w
 
 
+def two_eyes(n_db: int = 300_000, persons: int = 32, seed: int = 0x1A150005) -> Workload:
+    """A batch of persons, each a query of both eyes (query 2k: left eye of
+    person k, 2k+1: right eye) x 31 rotations, with the patterns a person
+    decision has to get right.  Persons k = 4i: left eye planted against the
+    database (HD ~ U[0.15, 0.45]); 4i+1: right eye; 4i+2: both eyes (two
+    entries); 4i+3: neither, except person 3 (left eye exactly at the
+    threshold: no match) and person 7 (right eye one below: a match).
+    In-batch pairs (eye i made from eye j): a later person's eye from an
+    earlier person's (counts), an eye from a later person's (counts for the
+    later person only), a right eye from the same person's left eye (never
+    counts: a person's eyes are not matched with each other), and two
+    exact-threshold cases."""
+    n_q = 2 * persons
+    w = Workload(f"db{n_db}_persons{persons}_eyes2_r31", n_db, n_q, ROT31, seed, group=2)
+    rng = _rng(seed, 5, 0)
+
+    def entry():
+        return int(rng.integers(0, n_db)), int(rng.integers(-15, 16))
+
+    for k in range(persons):
+        eyes = {0: (0,), 1: (1,), 2: (0, 1), 3: ()}[k % 4]
+        for eye in eyes:
+            e, s = entry()
+            w.planted.append((2 * k + eye, e, s, float(rng.uniform(0.15, 0.45))))
+    for k, eye, ex in ((3, 0, "eq"), (7, 1, "lt")):
+        if k < persons:
+            e, s = entry()
+            w.planted.append((2 * k + eye, e, s, ex))
+    pairs = ((22, 6, 3, 0.20),      # person 11 left from person 3 left (earlier person)
+             (31, 30, 0, 0.10),     # person 15 right from its own left eye (not a duplicate)
+             (46, 55, -6, 0.25),    # person 23 left from person 27 right (counts for person 27)
+             (39, 14, -4, "lt"),    # person 19 right from person 7 left, one below the threshold
+             (62, 23, 9, "eq"))     # person 31 left from person 11 right, exactly at the threshold
+    w.batch_pairs = [p for p in pairs if max(p[0], p[1]) < n_q]
+    return w
+
+
 def plant_in_batch(w: Workload, qc: np.ndarray, qm: np.ndarray,
                    pairs=((9, 4, 3, 0.20), (11, 2, -5, 0.30), (13, 12, 0, 0.42), (15, 14, 7, "eq"))):
-    """Make query i of the batch a near-duplicate of the earlier query j (at
-    rotation s, with fractional HD h or an exact-threshold case): the
-    duplicates that only in-batch matching finds.  Modifies qc, qm in place."""
+    """Make query i of the batch a near-duplicate of query j (at rotation s,
+    with fractional HD h or an exact-threshold case): the duplicates that
+    only in-batch matching finds (for i if j is earlier, else for j).
+    Modifies qc, qm in place."""
     for i, j, s, hx in pairs:
-        assert j < i < qc.shape[0]
+        assert i != j and max(i, j) < qc.shape[0]
         if isinstance(hx, str):
             c, m = plant(w.seed, i, qc[j], qm[j], s, exact=hx)
         else:
