@@ -513,10 +513,10 @@ def run_full(args):
                                      f"({w.rows} x {w.n_q} more comparisons), a person a duplicate if "
                                      f"either eye is")
         res["config"]["persons"] = w.n_q // 2
-        res["config"]["in_batch"] = True
     elif in_batch:
         res["config"]["workload"] += (f", plus in-batch matching (each query against the batch's earlier "
                                       f"queries: {w.rows} x {w.n_q} more comparisons)")
+    if in_batch:
         res["config"]["in_batch"] = True
         res["in_batch"] = {"ms_per_step": float(np.mean([ev[5][0].elapsed_time(ev[5][1]) for ev in evs])),
                            "comparisons": w.rows * w.n_q,
