@@ -35,11 +35,11 @@ MFMA_I8_PEAK_TOPS = 5000.0      # MI355X dense int8, tera-ops/s (MAC = 2 ops)
 # WRITE_SIZE 1,048,580 KiB).  Valid only for the kernel sources it was taken on.
 DOT_TRAFFIC = {
     "sources": {"paper_2405_04463_amd/csrc/rot_dot.hip":
-                "e75a201cfa54fafc6fc870a62c6f6b3a24d4b482e979e7f8efbd867f4d60f89b",
+                "b9ec8787f36d1e50c3af5c71ab5c889b9b44b2b5e9c4c77b200bab57e322f5ed",
                 "paper_2405_04463_amd/csrc/device.h":
                 "4c1a3b4ab4b31d959d8bad5a27477516a04872568ad8d0abc29b0de3c59b9f10"},
     "rows": 1984, "n_db": 300_000,
-    "fetch_kib": 19_850_300.0, "write_kib": 2_325_560.0,
+    "fetch_kib": 16_895_078.0, "write_kib": 2_327_044.0,
     "fetch_scale": 1_048_576 / 524_303.0, "write_scale": 1_048_576 / 1_048_580.0,
 }
 
@@ -700,8 +700,14 @@ def run_batched(args):
     bs = BatchSet(ctx, batches, torch.from_numpy(qc.view(np.int64)).cuda(), torch.from_numpy(qm.view(np.int64)).cuda(),
                   galois=galois)
     st = BatchedStep(ctx, bs, db, 0, args.n_db, chunk=args.chunk, parties=(0,))
-    mode, best, times = st.autotune(probe_n=16384)
-    log(f"autotuned: mode {mode}, dot configuration {best}; probe ms {times}")
+    if args.batched_mode == "auto":
+        mode, best, times = st.autotune(probe_n=16384)
+        log(f"autotuned: mode {mode}, dot configuration {best}; probe ms {times}")
+    else:
+        mode, best = args.batched_mode, args.dot_tiles
+        st.mode = mode
+        ctx.set_dot_tiles(best)
+        log(f"mode {mode}, dot configuration {best} (no autotuning)")
     torch.cuda.empty_cache()
     st.run()
     torch.cuda.synchronize()
@@ -893,6 +899,8 @@ def main():
     ap.add_argument("--net", choices=["buffers", "registers"], default="buffers",
                     help="comparison messages: through a device buffer with the parties apart (default), or held "
                          "in registers with the three parties of a comparison in one lane")
+    ap.add_argument("--batched-mode", choices=["auto", "grouped", "fused", "rows"], default="auto",
+                    help="batched workload: the autotuner's choice, or one mode with the --dot-tiles configuration")
     ap.add_argument("--two-eyes", action="store_true",
                     help="full workload as persons of two eyes (queries 2k, 2k+1), with in-batch matching over "
                          "earlier persons and one decision per person")

@@ -77,8 +77,9 @@ typedef int imc_status;
                                             pass through LDS; two barriers per 25 K-steps);
                                             used when r >= 22, else as AUTO */
 #define IMC_DOT_TILES_MAX 7
-#define IMC_DOT_PERSISTENT 0x10          /* bit 4: expanded tilings run a persistent grid (one
-                                            workgroup per CU walking its XCD's tile sequence) */
+#define IMC_DOT_PERSISTENT 0x10          /* bit 4: expanded tilings and imc_dot_shares_groups run a
+                                            persistent grid (one workgroup per CU walking its
+                                            XCD's tile sequence) */
 
 /* Stream handle: a hipStream_t (NULL = the default stream). */
 typedef struct ihipStream_t* imc_stream;
@@ -220,6 +221,36 @@ imc_status imc_dot_shares_rows_noalloc(imc_ctx* ctx, int party, const void* qop,
 imc_status imc_dot_shares_gather(imc_ctx* ctx, int party, const void* qop, const uint32_t* qidx, size_t q,
                                  const imc_ids* ids, const void* db, size_t db_capacity, size_t n,
                                  uint16_t* code_dot, uint16_t* mask_dot, size_t ld, imc_stream stream);
+
+/* Query groups of one fused dot launch (imc_dot_shares_groups). */
+#define IMC_MAX_DOT_GROUPS 8
+
+typedef struct imc_dot_group {
+  const void* qop;             /* the group's unrotated query operand: q rows as written by
+                                  imc_share_query (16-byte aligned) */
+  uint64_t q;                  /* queries of the group (0: the group is skipped) */
+  int32_t r;                   /* rotations per query, 13..32 */
+  int8_t rot[IMC_MAX_ROT];     /* rotation offsets, each in [-15, 15] */
+  uint16_t* code_dot;          /* device u16 [q*r][ld]: row qi*r + ri, column e - first_entry_id */
+  uint16_t* mask_dot;          /* the same for the mask vector; NULL in every group or in none */
+} imc_dot_group;
+
+/* imc_dot_shares for several query groups at once (Alg. 3's inner products
+ * of uneven batches, Sec. 6.4: many queries per pass over the database):
+ * group g's queries at g's rotations against entries first_entry_id ..
+ * first_entry_id + n - 1, written to g's outputs, all groups in ONE launch of
+ * the rotation-aware kernel (each group keeps its own row tiles; a tile never
+ * mixes groups).  With IMC_DOT_PERSISTENT set on the context the launch is a
+ * persistent grid (a multiple of 8 workgroups, at most one per CU) walking
+ * every group's tiles.  groups: HOST array of n_groups (<= IMC_MAX_DOT_GROUPS)
+ * descriptors, read during the call.  The same products as one
+ * imc_dot_shares call per group.  Errors: IMC_EINVAL (party, null or
+ * unaligned pointers, r outside 13..32, a rotation outside [-15, 15],
+ * first_entry_id % 64, mask_dot NULL in some groups only, n_groups >
+ * IMC_MAX_DOT_GROUPS), IMC_ESHAPE (ld < n, first+n > capacity, q*r >= 2^31). */
+imc_status imc_dot_shares_groups(imc_ctx* ctx, int party, const imc_dot_group* groups, size_t n_groups,
+                                 const void* db, size_t db_capacity, uint64_t first_entry_id, size_t n, size_t ld,
+                                 imc_stream stream);
 
 /* Select the dot-product configuration of an existing context (same values as
  * imc_params.flags bits 0-4).  Errors: IMC_EUNSUPPORTED. */
@@ -446,6 +477,11 @@ imc_status imc_galois_share_query(imc_ctx* ctx, const uint64_t* codes, const uin
 imc_status imc_galois_dot_shares(imc_ctx* ctx, int party, const void* qop, size_t q, const imc_ids* ids,
                                  const void* db, size_t db_capacity, size_t n, uint16_t* code_dot,
                                  uint16_t* mask_dot, size_t ld, imc_stream stream);
+
+/* imc_dot_shares_groups for Galois-form operands and regions. */
+imc_status imc_galois_dot_shares_groups(imc_ctx* ctx, int party, const imc_dot_group* groups, size_t n_groups,
+                                        const void* db, size_t db_capacity, uint64_t first_entry_id, size_t n,
+                                        size_t ld, imc_stream stream);
 
 /* imc_dot_shares_gather for Galois-form operands and regions. */
 imc_status imc_galois_dot_shares_gather(imc_ctx* ctx, int party, const void* qop, const uint32_t* qidx, size_t q,

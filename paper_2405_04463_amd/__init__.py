@@ -29,7 +29,8 @@ EXPORTS = [
     "imc_galois_append_db", "imc_mask_in_batch", "imc_or_bits", "imc_dot_shares_gather",
     "imc_galois_dot_shares_gather", "imc_compare_variant", "imc_rotate_masks", "imc_plain_ml", "imc_db32_bytes",
     "imc_query32_op_bytes", "imc_share32_db", "imc_share32_query", "imc_dot32_shares", "imc_reshare32",
-    "imc_dot_shares_rows_noalloc", "imc_compare_msg_bytes", "imc_or_pairs",
+    "imc_dot_shares_rows_noalloc", "imc_compare_msg_bytes", "imc_or_pairs", "imc_dot_shares_groups",
+    "imc_galois_dot_shares_groups",
 ]
 
 (DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW, DOT_TILES_ROTATION,
@@ -65,6 +66,20 @@ class imc_ids(ctypes.Structure):
         ("first_entry_id", ctypes.c_uint64),
         ("r", ctypes.c_int32),
         ("rot", ctypes.c_int8 * MAX_ROT),
+    ]
+
+
+MAX_DOT_GROUPS = 8
+
+
+class imc_dot_group(ctypes.Structure):
+    _fields_ = [
+        ("qop", ctypes.c_void_p),
+        ("q", ctypes.c_uint64),
+        ("r", ctypes.c_int32),
+        ("rot", ctypes.c_int8 * MAX_ROT),
+        ("code_dot", ctypes.c_void_p),
+        ("mask_dot", ctypes.c_void_p),
     ]
 
 
@@ -117,6 +132,9 @@ def lib():
         L.imc_dot_shares_gather.argtypes = [_VP, ctypes.c_int, _VP, _VP, sz, ctypes.POINTER(imc_ids), _VP, sz, sz, _VP,
                                             _VP, sz, _VP]
         L.imc_galois_dot_shares_gather.argtypes = L.imc_dot_shares_gather.argtypes
+        L.imc_dot_shares_groups.argtypes = [_VP, ctypes.c_int, ctypes.POINTER(imc_dot_group), sz, _VP, sz,
+                                            ctypes.c_uint64, sz, sz, _VP]
+        L.imc_galois_dot_shares_groups.argtypes = L.imc_dot_shares_groups.argtypes
         L.imc_or_bits.argtypes = [_VP, _P3, _P3, sz, ctypes.c_uint64, _P3, _VP]
         L.imc_compare_variant.argtypes = [_VP, ctypes.c_int, _P3, ctypes.c_int, _VP, _VP, sz, sz, sz,
                                           ctypes.POINTER(imc_ids), _VP, sz, _P3, sz, _VP]
@@ -285,6 +303,19 @@ class Context:
         f = "imc_galois_dot_shares_gather" if galois else "imc_dot_shares_gather"
         return _check(getattr(lib(), f)(self._h, party, addr(qop), addr(qidx), q, ctypes.byref(ids), addr(db),
                                         capacity, n, addr(code_dot), addr(mask_dot), ld, _stream(stream)), f)
+
+    # -- imc_dot_shares_groups / imc_galois_dot_shares_groups
+    #    (groups: list of (qop, q, rot, code_dot, mask_dot), one fused launch)
+    def dot_shares_groups(self, party, groups, db, capacity, first_entry_id, n, ld, stream=None, galois=False):
+        arr = (imc_dot_group * max(1, len(groups)))()
+        for g, (qop, q, rot, code_dot, mask_dot) in zip(arr, groups):
+            g.qop, g.q, g.r = addr(qop), q, len(rot)
+            for i, v in enumerate(rot):
+                g.rot[i] = int(v)
+            g.code_dot, g.mask_dot = addr(code_dot), addr(mask_dot)
+        f = "imc_galois_dot_shares_groups" if galois else "imc_dot_shares_groups"
+        return _check(getattr(lib(), f)(self._h, party, arr, len(groups), addr(db), capacity, first_entry_id, n, ld,
+                                        _stream(stream)), f)
 
     # -- imc_dot_shares_rows / imc_galois_dot_shares_rows
     #    (rows: device int32 tensor [nrows, 2] = (query_index, rot))

@@ -5,9 +5,12 @@ consecutive query ids.  A step over many batches computes every party's dot
 products for all their rows with one launch per database chunk per rotation
 list ("grouped": the batches of one list are contiguous, so the launch is a
 uniform `imc_dot_shares` and lists of 13 or more rotations get the
-rotation-aware kernel), or with ONE launch per chunk over a row table of all
-rows ("rows": `imc_dot_shares_rows`).  Either way the database streams from
-HBM once per chunk (per list) for all batches instead of once per batch.
+rotation-aware kernel), with ONE rotation-aware launch per chunk over every
+list of 13 or more rotations ("fused": `imc_dot_shares_groups`, optionally
+a persistent grid, plus one launch per shorter list), or with ONE launch per
+chunk over a row table of all rows ("rows": `imc_dot_shares_rows`).  Either
+way the database streams from HBM once per chunk (per launch) for all
+batches instead of once per batch.
 Resharing, comparison and the OR-tree are elementwise per comparison and run
 per batch on the batch's row range.
 
@@ -22,7 +25,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from . import Context, galois_query_op_bytes, make_ids, or_tree_ws_bytes, query_op_bytes
+from . import MAX_DOT_GROUPS, Context, galois_query_op_bytes, make_ids, or_tree_ws_bytes, query_op_bytes
 
 
 @dataclass
@@ -134,7 +137,10 @@ class BatchedStep:
         """Batched form.  mode "rows": one dot launch per party per chunk over
         the row table of all batches; mode "grouped": one launch per rotation
         list per party per chunk (uniform rotations, so the rotation-aware
-        kernel serves every list of 13 or more rotations)."""
+        kernel serves every list of 13 or more rotations); mode "fused": the
+        lists of 13 or more rotations in one rotation-aware launch per party
+        per chunk (a persistent grid when the context's tiles carry
+        DOT_PERSISTENT), each shorter list as in "grouped"."""
         ctx, bs, db = self.ctx, self.bs, self.db
         for c0, m in self._chunks():
             for p in self.parties:
@@ -143,7 +149,18 @@ class BatchedStep:
                                         self.first + c0, m, self.dot_code[p], self.dot_mask[p], self.ld, stream,
                                         galois=bs.galois)
                     continue
-                for rot, q0, qn, r0 in bs.groups:
+                rest = bs.groups
+                if self.mode == "fused":
+                    rest = [g for g in bs.groups if len(g[0]) < 13]
+                    big = [g for g in bs.groups if len(g[0]) >= 13]
+                    for i in range(0, len(big), MAX_DOT_GROUPS):
+                        desc = [(bs.op[p].data_ptr() + q0 * bs.row_bytes, qn, rot,
+                                 self.dot_code[p].data_ptr() + 2 * r0 * self.ld,
+                                 self.dot_mask[p].data_ptr() + 2 * r0 * self.ld)
+                                for rot, q0, qn, r0 in big[i:i + MAX_DOT_GROUPS]]
+                        ctx.dot_shares_groups(p, desc, db.regions[p], db.capacity, self.first + c0, m, self.ld,
+                                              stream, galois=bs.galois)
+                for rot, q0, qn, r0 in rest:
                     ids = make_ids(0, rot, self.first + c0)
                     ctx.dot_shares(p, bs.op[p].data_ptr() + q0 * bs.row_bytes, qn, ids, db.regions[p], db.capacity,
                                    m, self.dot_code[p].data_ptr() + 2 * r0 * self.ld,
@@ -154,11 +171,14 @@ class BatchedStep:
     def autotune(self, probe_n: int = 16384, reps: int = 2):
         """Time every (mode, tile configuration) on a probe slice of the
         database and keep the fastest; returns (mode, flags, {(mode, flags): ms})."""
-        from .tune import CANDIDATES_ROWS, CANDIDATES_UNIFORM
+        from .tune import CANDIDATES_FUSED, CANDIDATES_ROWS, CANDIDATES_UNIFORM
 
         probe = BatchedStep(self.ctx, self.bs, self.db, self.first, min(self.n, probe_n), parties=self.parties[:1])
         times = {}
-        for mode, cands in (("rows", CANDIDATES_ROWS), ("grouped", CANDIDATES_UNIFORM)):
+        modes = [("rows", CANDIDATES_ROWS), ("grouped", CANDIDATES_UNIFORM)]
+        if any(len(g[0]) >= 13 for g in self.bs.groups):
+            modes.append(("fused", CANDIDATES_FUSED))
+        for mode, cands in modes:
             probe.mode = mode
             for c in cands:
                 self.ctx.set_dot_tiles(c)

@@ -329,6 +329,53 @@ imc_status imc_galois_dot_shares(imc_ctx* c, int party, const void* qop, size_t 
                                  imc_stream stream) {
   return dot_shares_impl(c, party, qop, nullptr, q, ids, db, capacity, n, code_dot, mask_dot, ld, stream, true);
 }
+namespace {
+imc_status dot_groups_impl(imc_ctx* c, int party, const imc_dot_group* groups, size_t n_groups, const void* db,
+                           size_t capacity, uint64_t first_entry_id, size_t n, size_t ld, imc_stream stream,
+                           bool galois) {
+  if (!c || party < 0 || party > 2) return IMC_EINVAL;
+  if (n_groups > IMC_MAX_DOT_GROUPS || (n_groups && !groups)) return IMC_EINVAL;
+  if (first_entry_id % 64) return IMC_EINVAL;
+  imc::DotGroup g[IMC_MAX_DOT_GROUPS];
+  uint32_t used = 0;
+  int masks = -1;   // 0: no group has a mask output, 1: every group has one
+  for (size_t i = 0; i < n_groups; ++i) {
+    const imc_dot_group& x = groups[i];
+    if (x.q == 0) continue;
+    if (x.r < 13 || x.r > IMC_MAX_ROT) return IMC_EINVAL;
+    for (int j = 0; j < x.r; ++j)
+      if (x.rot[j] < -15 || x.rot[j] > 15) return IMC_EINVAL;
+    if (!x.qop || !x.code_dot || !aligned(x.qop, 16) || !aligned(x.code_dot, 2) || !aligned(x.mask_dot, 2))
+      return IMC_EINVAL;
+    const int m = x.mask_dot ? 1 : 0;
+    if (masks >= 0 && m != masks) return IMC_EINVAL;
+    masks = m;
+    if (x.q >= (1ull << 31) / uint64_t(x.r)) return IMC_ESHAPE;
+    g[used++] = imc::DotGroup{static_cast<const int8_t*>(x.qop), uint32_t(x.q), uint32_t(x.r), x.rot, x.code_dot,
+                              x.mask_dot};
+  }
+  if (used == 0 || n == 0) return IMC_OK;
+  if (!db || !aligned(db, 256)) return IMC_EINVAL;
+  if (ld < n) return IMC_ESHAPE;
+  if (first_entry_id > capacity || n > capacity - first_entry_id) return IMC_ESHAPE;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return IMC_EDEVICE;
+  const bool persistent = (c->dot_variant & IMC_DOT_PERSISTENT) != 0;
+  return dev_status(imc::launch_rot_dot_groups(g, used, static_cast<const int8_t*>(db), first_entry_id, n, ld,
+                                               persistent, hipStream_t(stream), galois));
+}
+}  // namespace
+
+imc_status imc_dot_shares_groups(imc_ctx* c, int party, const imc_dot_group* groups, size_t n_groups, const void* db,
+                                 size_t capacity, uint64_t first_entry_id, size_t n, size_t ld, imc_stream stream) {
+  return dot_groups_impl(c, party, groups, n_groups, db, capacity, first_entry_id, n, ld, stream, false);
+}
+imc_status imc_galois_dot_shares_groups(imc_ctx* c, int party, const imc_dot_group* groups, size_t n_groups,
+                                        const void* db, size_t capacity, uint64_t first_entry_id, size_t n, size_t ld,
+                                        imc_stream stream) {
+  return dot_groups_impl(c, party, groups, n_groups, db, capacity, first_entry_id, n, ld, stream, true);
+}
+
 imc_status imc_dot_shares_gather(imc_ctx* c, int party, const void* qop, const uint32_t* qidx, size_t q,
                                  const imc_ids* ids, const void* db, size_t capacity, size_t n, uint16_t* code_dot,
                                  uint16_t* mask_dot, size_t ld, imc_stream stream) {

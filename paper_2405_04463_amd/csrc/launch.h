@@ -36,6 +36,16 @@ hipError_t launch_rot_dot(const int8_t* qop, const uint32_t* qidx, uint32_t q, u
                           const int8_t* b,
                           uint64_t first_entry, uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld,
                           hipStream_t s, int kind, bool galois);
+// One query group of a fused rotation-aware launch (imc_dot_shares_groups).
+struct DotGroup {
+  const int8_t* qop;
+  uint32_t q, r;
+  const int8_t* rot;
+  uint16_t* code;
+  uint16_t* mask;
+};
+hipError_t launch_rot_dot_groups(const DotGroup* groups, uint32_t ngroups, const int8_t* b, uint64_t first_entry,
+                                 uint64_t n, uint64_t ld, bool persistent, hipStream_t s, bool galois);
 hipError_t launch_expand_rows(const int8_t* qop, uint32_t q, const imc_row* rows, uint32_t nrows, int8_t* a,
                               uint32_t rows_pad, hipStream_t s, bool galois);
 hipError_t launch_dot(const int8_t* a, uint32_t rows, uint32_t a_blocks, const int8_t* b, uint64_t first_entry,

@@ -4,6 +4,8 @@
 // accumulators); the query rotations (Sec. 3: circular shifts of the
 // angular axis, party-local because sharing is elementwise) are applied
 // while reading the query operand from LDS instead of being materialised.
+#include <algorithm>
+
 #include "device.h"
 #include "launch.h"
 
@@ -59,8 +61,24 @@ __device__ __forceinline__ void copy16(const int8_t* g, int8_t* l) {
                                    0);
 }
 
+// What one output tile of the rotation-aware kernel reads and writes: the
+// call's (or group's) unrotated query operand, its rotation list, the
+// database region and the output plane of vector `vec`.
+struct RotTile {
+  const int8_t* qop;
+  const uint32_t* qidx;
+  const int8_t* b;
+  uint16_t* out;
+  const int8_t* rot;
+  uint64_t ld, b_block0, b_blocks, n;
+  uint32_t rows, r, max_q;
+};
+
+// One 256 x 128 output tile (row tile u, column tile t) of vector `vec`,
+// the whole K loop and the epilogue.  LDS: 3 database stages, then the two
+// query segment buffers of max_q slots.
 template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int NSETS, int ACH>
-__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotArgs args) {
+__device__ __forceinline__ void rot_dot_tile(const RotTile& args, uint32_t u, uint32_t t, int vec, int8_t* lds) {
   using G = Geo<K>;
   constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N;
   constexpr int kThreads = 64 * WAVES_M * WAVES_N;
@@ -69,7 +87,6 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotA
   constexpr int kBPerThread = kBChunks / kThreads;
   constexpr int kBStage = kBChunks * 16;
   static_assert(kBChunks % kThreads == 0, "B chunks must divide evenly");
-  extern __shared__ __align__(16) int8_t lds[];
   int8_t* bst = lds;                                           // 3 B stages
   int8_t* ast = lds + 3 * kBStage;                             // 2 A segment buffers
   const uint32_t abuf = args.max_q * 2 * kSegBytes;            // bytes per A buffer
@@ -77,12 +94,6 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotA
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-  const int vec = blockIdx.z;
-  const uint32_t i = blockIdx.x;
-  const uint32_t xcd = i & 7, s8 = i >> 3;
-  const uint32_t u = s8 % args.mt, tg = s8 / args.mt;
-  const uint32_t t = tg * 8 + xcd;
-  if (t >= args.nt) return;
 
   const uint32_t m0 = u * kBM;
   const uint32_t q_lo = m0 / args.r;
@@ -239,7 +250,7 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotA
 #undef IMC_ALOAD
 #undef IMC_ASTORE
 
-  uint16_t* out = args.out[vec];
+  uint16_t* out = args.out;
 #pragma unroll
   for (int x = 0; x < WM; ++x)
 #pragma unroll
@@ -255,6 +266,72 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotA
         }
       }
     }
+}
+
+// One launch per call: workgroup i is output tile (u, t) in an XCD-aware
+// order (consecutive workgroups go to the 8 XCDs in turn; each XCD walks
+// every row tile of its column tiles, so a column tile's database bytes are
+// read into one XCD's L2).
+template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int NSETS, int ACH>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_kernel(RotDotArgs args) {
+  extern __shared__ __align__(16) int8_t lds[];
+  const int vec = blockIdx.z;
+  const uint32_t i = blockIdx.x;
+  const uint32_t xcd = i & 7, s8 = i >> 3;
+  const uint32_t u = s8 % args.mt, tg = s8 / args.mt;
+  const uint32_t t = tg * 8 + xcd;
+  if (t >= args.nt) return;
+  const RotTile tile{args.qop, args.qidx, args.b, args.out[vec], args.rot, args.ld, args.b_block0, args.b_blocks,
+                     args.n, args.rows, args.r, args.max_q};
+  rot_dot_tile<K, WM, WN, WAVES_M, WAVES_N, NSETS, ACH>(tile, u, t, vec, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Several query groups in one launch (uneven batches: each group is the
+// queries of one rotation list, e.g. the batches checked at 31 rotations and
+// those at 15).  Group g owns global tiles [tile0, tile0 + 8 * ntg * mt) and
+// maps them to its (row tile, column tile) pairs exactly as one launch of
+// rot_dot_kernel would, so every group keeps the XCD-aware order.  With a
+// persistent grid (a multiple of 8 workgroups, fewer than the tiles) each
+// workgroup walks tiles i, i + grid, ...: the same residue mod 8, so the
+// same XCD, as a one-tile-per-workgroup launch would give them.
+// ---------------------------------------------------------------------------
+constexpr int kMaxDotGroups = IMC_MAX_DOT_GROUPS;
+struct RotGroup {
+  const int8_t* qop;
+  uint16_t* out[2];
+  uint32_t rows, r, mt, tile0;
+  int8_t rot[IMC_MAX_ROT_DEV];
+};
+struct RotGroupsArgs {
+  const int8_t* b;
+  uint64_t ld, b_block0, b_blocks, n;
+  uint32_t nt, ntiles, ngroups, max_q;
+  RotGroup g[kMaxDotGroups];
+};
+
+template <int K, int WM, int WN, int WAVES_M, int WAVES_N, int NSETS, int ACH>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N) rot_dot_groups_kernel(RotGroupsArgs args) {
+  extern __shared__ __align__(16) int8_t lds[];
+  const int vec = blockIdx.z;
+  bool first = true;
+  for (uint32_t i = blockIdx.x; i < args.ntiles; i += gridDim.x) {
+    uint32_t gi = 0;
+    while (gi + 1 < args.ngroups && i >= args.g[gi + 1].tile0) ++gi;
+    const RotGroup& grp = args.g[gi];
+    const uint32_t li = i - grp.tile0;
+    const uint32_t xcd = li & 7, s8 = li >> 3;
+    const uint32_t u = s8 % grp.mt, tg = s8 / grp.mt;
+    const uint32_t t = tg * 8 + xcd;
+    if (t >= args.nt) continue;
+    // the previous tile's last fragment reads end before this tile's prologue
+    // overwrites the LDS stages
+    if (!first) __syncthreads();
+    first = false;
+    const RotTile tile{grp.qop, nullptr, args.b, grp.out[vec], grp.rot, args.ld, args.b_block0, args.b_blocks,
+                       args.n, grp.rows, grp.r, args.max_q};
+    rot_dot_tile<K, WM, WN, WAVES_M, WAVES_N, NSETS, ACH>(tile, u, t, vec, lds);
+  }
 }
 
 // The query slots of a 256-row tile (ceil(256 / r) + 1 of them) must fit the
@@ -751,6 +828,83 @@ static hipError_t launch_rot_gb(const int8_t* qop, const uint32_t* qidx, uint32_
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, d);
   return hipGetLastError();
+}
+
+template <int K, int ACH>
+static hipError_t launch_rot_groups_cfg(const DotGroup* groups, uint32_t ngroups, const int8_t* b,
+                                        uint64_t first_entry, uint64_t n, uint64_t ld, bool persistent,
+                                        hipStream_t s) {
+  constexpr int WM = 2, WN = 2, WAVES_M = 4, WAVES_N = 2, NSETS = 4;
+  constexpr int kBM = 32 * WM * WAVES_M, kBN = 32 * WN * WAVES_N, kThreads = 64 * WAVES_M * WAVES_N;
+  RotGroupsArgs d;
+  d.b = b;
+  d.ld = ld;
+  d.b_block0 = first_entry / 32;
+  d.b_blocks = (n + 31) / 32;
+  d.n = n;
+  d.nt = uint32_t((n + kBN - 1) / kBN);
+  const uint64_t ntg = (d.nt + 7) / 8;
+  uint64_t tiles = 0;
+  uint32_t max_q = 0, used = 0;
+  bool mask = false;
+  for (uint32_t gi = 0; gi < ngroups; ++gi) {
+    const DotGroup& g = groups[gi];
+    const uint32_t rows = g.q * g.r;
+    if (rows == 0) continue;
+    RotGroup& o = d.g[used++];
+    o.qop = g.qop;
+    o.out[0] = g.code;
+    o.out[1] = g.mask;
+    mask = g.mask != nullptr;
+    o.rows = rows;
+    o.r = g.r;
+    o.mt = (rows + kBM - 1) / kBM;
+    o.tile0 = uint32_t(tiles);
+    for (int j = 0; j < IMC_MAX_ROT_DEV; ++j) o.rot[j] = j < int(g.r) ? g.rot[j] : 0;
+    max_q = std::max(max_q, (kBM + g.r - 1) / g.r + 1);
+    tiles += ntg * 8 * o.mt;
+    if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  }
+  if (used == 0 || n == 0) return hipSuccess;
+  if (int(max_q) * 2 * kSegChunks > ACH * kThreads) return hipErrorInvalidValue;
+  d.ngroups = used;
+  d.ntiles = uint32_t(tiles);
+  d.max_q = max_q;
+  const size_t lds = 3 * size_t(kBN / 32) * 2 * 2 * 32 * 16 + 2 * size_t(max_q) * 2 * kSegBytes;
+  auto kern = rot_dot_groups_kernel<K, WM, WN, WAVES_M, WAVES_N, NSETS, ACH>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return e;
+  uint32_t grid = d.ntiles;
+  if (persistent) {
+    // one workgroup per CU (the LDS of a tile allows no second one), a
+    // multiple of the 8 XCDs
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      return hipErrorInvalidValue;
+    const uint32_t g8 = (uint32_t(cus) + 7) / 8 * 8;
+    grid = std::min<uint32_t>(grid, g8);
+  }
+  hipLaunchKernelGGL(kern, dim3(grid, 1, mask ? 2 : 1), dim3(kThreads), lds, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_rot_dot_groups(const DotGroup* groups, uint32_t ngroups, const int8_t* b, uint64_t first_entry,
+                                 uint64_t n, uint64_t ld, bool persistent, hipStream_t s, bool galois) {
+  if (ngroups > uint32_t(kMaxDotGroups)) return hipErrorInvalidValue;
+  uint32_t rmin = 32;
+  for (uint32_t gi = 0; gi < ngroups; ++gi) {
+    if (groups[gi].q == 0) continue;
+    if (groups[gi].r < 13) return hipErrorInvalidValue;
+    rmin = std::min(rmin, groups[gi].r);
+  }
+  // the staging of the fewest rotations (the most query slots) sizes the launch
+  if (galois)
+    return rmin >= 22 ? launch_rot_groups_cfg<kKGalois, 3>(groups, ngroups, b, first_entry, n, ld, persistent, s)
+                      : launch_rot_groups_cfg<kKGalois, 5>(groups, ngroups, b, first_entry, n, ld, persistent, s);
+  return rmin >= 22 ? launch_rot_groups_cfg<kK, 3>(groups, ngroups, b, first_entry, n, ld, persistent, s)
+                    : launch_rot_groups_cfg<kK, 5>(groups, ngroups, b, first_entry, n, ld, persistent, s);
 }
 
 hipError_t launch_rot_dot(const int8_t* qop, const uint32_t* qidx, uint32_t q, uint32_t r, const int8_t* rot,

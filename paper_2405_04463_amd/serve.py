@@ -16,16 +16,24 @@ Unique requests (dup = 0) are appended to the database.
 Because every random value is addressed by (query id, rotation, entry, gate)
 and the OR-tree runs over the request's complete buffer, a request's shares
 and result are the same alone and in any mix, whatever chunk it starts at.
+Each gate's correlated randomness is used once (App. C): the chunk passes
+compare whole 64-entry words below the request's snapshot only, and the
+word holding the snapshot -- whose lanes past the snapshot would otherwise
+run the gates first on padding and later on appended entries under the
+same randomness -- is compared exactly once, when the request is finalised,
+together with any entries appended since.
 Serial uniqueness (Sec. 6.4: a batch is also matched against itself): a
 request must also match the unique requests admitted before it that were
 still in flight at its admission.  With `serial=True` (the default) a request
 whose pass over its snapshot is complete is finalised only after every
 earlier-admitted request has been decided and, if unique, appended; it is
 then compared with the entries appended since its admission (a short tail
-pass over [64-aligned snapshot, current size) into the same match buffer,
-recomputing identical words below the snapshot) before its OR-tree runs over
-the whole buffer.  Its shares and result then equal a plain check against the
+pass over [64-aligned snapshot, current size) into the same match buffer)
+before its OR-tree runs over the whole buffer.  Its shares and result then equal a plain check against the
 database as it stands after every earlier request, i.e. the serial order.
+(The tail pass starts at the 64-aligned snapshot: entries below it in that
+word are reshared and compared there for the first time, so no gate runs
+twice.)
 
 Admission: a request needs a free slot (slots bound the rows of a tick) and
 its per-request buffers must fit in free HBM above a reserve.
@@ -243,32 +251,38 @@ class Server:
                                          self.db.capacity, first, n_max, self.dot_code[p], self.dot_mask[p], self.ld,
                                          galois=self.galois)
         # per request: reshare and compare its rows into its match buffer
+        finished = []
         for i, r in enumerate(reqs):
             n_j = min(self.chunk, r.snapshot - first)
+            r.remaining.discard(j)
+            if not r.remaining:
+                finished.append(r)
             if self.local:          # the party's share of the work ends with its dot products
                 if self.keep_shares:
                     for p in self.parties:
                         for v, src in enumerate((self.dot_code[p], self.dot_mask[p])):
                             r.dots[p][v][:, first:first + n_j].copy_(src[i * self.R:(i + 1) * self.R, :n_j])
-                r.remaining.discard(j)
                 self.cmps += self.R * n_j
-                if not r.remaining:
-                    self._finish(r)
+                continue
+            # whole words only: the word holding the snapshot waits for finalisation
+            n_w = min(self.chunk, (r.snapshot // 64) * 64 - first)
+            if n_w <= 0:
                 continue
             ids = make_ids(r.qid, self.rot, first)
             off = 2 * i * self.R * self.ld
             add_c = [self.dot_code[p].data_ptr() + off for p in range(3)]
             add_m = [self.dot_mask[p].data_ptr() + off for p in range(3)]
             s = r.slot
-            self.ctx.reshare(add_c, add_m, self.R, n_j, self.ld, ids, self.msg[s], self.rep_code[s],
+            self.ctx.reshare(add_c, add_m, self.R, n_w, self.ld, ids, self.msg[s], self.rep_code[s],
                              self.rep_mask[s])
             mw = [m.data_ptr() + 8 * (first // 64) for m in self.match[s]]
-            self.ctx.compare_threshold(self.rep_code[s], self.rep_mask[s], self.R, n_j, self.ld, ids, mw,
+            self.ctx.compare_threshold(self.rep_code[s], self.rep_mask[s], self.R, n_w, self.ld, ids, mw,
                                        self.nw_full)
-            r.remaining.discard(j)
-            self.cmps += self.R * n_j
-            if not r.remaining:
-                self._finish(r)
+            self.cmps += self.R * n_w
+        # after every request of the tick has consumed its rows of the shared
+        # dot buffers (a tail pass reuses them)
+        for r in finished:
+            self._finish(r)
         self.cursor = (j + 1) % max(1, self.n_chunks())
         self.ticks += 1
         ev = torch.cuda.Event()
@@ -289,6 +303,8 @@ class Server:
             self.pending.append(r)
             self._finalize_ready()
             return
+        if r.snapshot % 64:
+            self._tail_pass(r, r.snapshot)      # the word holding the snapshot, once
         self._finalize(r, r.snapshot)
 
     def _finalize_ready(self):
@@ -308,13 +324,14 @@ class Server:
                 continue
             self.pending.remove(r)
             n_now = self.db.n
-            if n_now > r.snapshot:
+            if n_now > (r.snapshot // 64) * 64:
                 self._tail_pass(r, n_now)
             self._finalize(r, n_now)
 
     def _tail_pass(self, r: Request, n_now: int):
-        """Compare r with the entries appended since its admission: entries
-        [64-aligned snapshot, n_now) into its match buffer."""
+        """Compare r with entries [64-aligned snapshot, n_now) into its match
+        buffer: the word holding the snapshot (not compared by the chunk
+        passes) and the entries appended since admission, each gate once."""
         first = (r.snapshot // 64) * 64
         s = r.slot
         b = self.ticks % self.ring

@@ -20,6 +20,10 @@ CANDIDATES_UNIFORM = [DOT_TILES_ROTATION, DOT_TILES_ROTATION_LDSCOPY, DOT_TILES_
                       DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW]
 CANDIDATES_ROWS = [DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_256x128 | DOT_PERSISTENT,
                    DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW]
+# the fused launch of every rotation-aware group (lists of fewer rotations
+# run as in the grouped mode, on the same tiles): one tile per workgroup, or
+# a persistent grid
+CANDIDATES_FUSED = [DOT_TILES_ROTATION, DOT_TILES_ROTATION | DOT_PERSISTENT]
 
 
 def _bucket(rows: int) -> int:

@@ -1,5 +1,9 @@
 """Batched uneven steps (one dot launch over the rows of many batches) against
-per-batch launches, the oracle, and HIP-graph replays; bit-exact."""
+per-batch launches, the oracle, and HIP-graph replays; bit-exact.  The fused
+launch of several rotation lists (imc_dot_shares_groups), one tile per
+workgroup and as a persistent grid walking several tiles per workgroup,
+against one imc_dot_shares launch per group and the oracle on sampled
+entries."""
 import numpy as np
 import pytest
 
@@ -41,14 +45,16 @@ def _u16(t):
     return t.cpu().numpy().view(np.uint16)
 
 
-@pytest.mark.parametrize("mode", ["grouped", "rows"])
-def test_batched_equals_plain_and_oracle(env, mode):
+@pytest.mark.parametrize("mode,tiles", [("grouped", 0), ("rows", 0), ("fused", 4), ("fused", 0x14)])
+def test_batched_equals_plain_and_oracle(env, mode, tiles):
     from paper_2405_04463_amd.batch import BatchedStep
 
     e = env
+    e["ctx"].set_dot_tiles(tiles)
     st = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], e["n"], parties=(0, 1, 2), compare=True, mode=mode)
     st.run()
     torch.cuda.synchronize()
+    e["ctx"].set_dot_tiles(0)
     got = {p: (_u16(st.dot_code[p]).copy(), _u16(st.dot_mask[p]).copy()) for p in range(3)}
     dup_b = [[pb["dup"][p].cpu().numpy().copy() for p in range(3)] for pb in st.per_batch]
     st.run_plain()
@@ -92,7 +98,7 @@ def test_chunked_db_walk_equals_one_pass(env):
     assert np.array_equal(np.concatenate(outs, axis=1), ref[:, :e["n"]])
 
 
-@pytest.mark.parametrize("mode,tiles", [("rows", 1), ("rows", 0x11), ("grouped", 0)])
+@pytest.mark.parametrize("mode,tiles", [("rows", 1), ("rows", 0x11), ("grouped", 0), ("fused", 0x14)])
 def test_graph_replay_matches_eager(env, mode, tiles):
     from paper_2405_04463_amd.batch import BatchedStep
 
@@ -122,7 +128,7 @@ def test_autotune_keeps_the_fastest_and_outputs_are_unchanged(env):
     probe slice and keeps the fastest; whichever it keeps, the outputs are the
     ones of the default configuration."""
     from paper_2405_04463_amd.batch import BatchedStep
-    from paper_2405_04463_amd.tune import CANDIDATES_ROWS, CANDIDATES_UNIFORM
+    from paper_2405_04463_amd.tune import CANDIDATES_FUSED, CANDIDATES_ROWS, CANDIDATES_UNIFORM
 
     e = env
     imc = e["imc"]
@@ -134,9 +140,81 @@ def test_autotune_keeps_the_fastest_and_outputs_are_unchanged(env):
     want = (_u16(ref.dot_code[0])[:, :n].copy(), _u16(ref.dot_mask[0])[:, :n].copy())
     st = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], n, parties=(0,))
     mode, flags, times = st.autotune(probe_n=128, reps=1)
-    assert set(times) == {("rows", c) for c in CANDIDATES_ROWS} | {("grouped", c) for c in CANDIDATES_UNIFORM}
+    assert set(times) == ({("rows", c) for c in CANDIDATES_ROWS} | {("grouped", c) for c in CANDIDATES_UNIFORM}
+                          | {("fused", c) for c in CANDIDATES_FUSED})
     assert times[(mode, flags)] == min(times.values()) and st.mode == mode
     st.run()
     torch.cuda.synchronize()
     assert np.array_equal(_u16(st.dot_code[0])[:, :n], want[0]) and np.array_equal(_u16(st.dot_mask[0])[:, :n], want[1])
     e["ctx"].set_dot_tiles(imc.DOT_TILES_AUTO)
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_dot_groups_equal_per_group_launches_and_oracle(env, persistent):
+    """Two rotation lists (31 and 15) over 16,480 entries in one launch: 640
+    tiles, so the persistent grid walks two or three tiles per workgroup; the
+    outputs equal one imc_dot_shares launch per group bit for bit, and the
+    oracle's local dot on the first 64 and the last 96 entries (a ragged
+    column tile)."""
+    from paper_2405_04463_amd.pipeline import SharedDB, SharedQueries
+
+    e = env
+    imc, ctx = e["imc"], e["ctx"]
+    n = 16384 + 96
+    d64 = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()  # noqa: E731
+    dc, dm = wl.gen_codes(62, 0, n)
+    db = SharedDB(ctx, n)
+    for s0 in range(0, n, 8192):
+        db.enroll(d64(dc[s0:s0 + 8192]), d64(dm[s0:s0 + 8192]), s0)
+    qc, qm = wl.gen_codes(62, 0, 50, query=True)
+    qc[3], qm[3] = wl.plant(62, 3, dc[n - 5], dm[n - 5], -7, h=0.2)
+    groups = [(SharedQueries(ctx, d64(qc[:20]), d64(qm[:20]), 700), wl.rotations(31)),
+              (SharedQueries(ctx, d64(qc[20:]), d64(qm[20:]), 720), wl.rotations(15))]
+    ld = n + 64
+    outs = [[torch.zeros(qs.q * len(rot), ld, dtype=torch.int16, device="cuda") for _ in range(4)]
+            for qs, rot in groups]
+    ctx.set_dot_tiles(imc.DOT_TILES_ROTATION | (imc.DOT_PERSISTENT if persistent else 0))
+    try:
+        for p in (0, 2):
+            desc = [(qs.op[p], qs.q, rot, o[0], o[1]) for (qs, rot), o in zip(groups, outs)]
+            desc.insert(1, (groups[0][0].op[p], 0, wl.rotations(31), outs[0][0], outs[0][1]))   # empty: skipped
+            ctx.dot_shares_groups(p, desc, db.regions[p], db.capacity, 0, n, ld)
+            for (qs, rot), o in zip(groups, outs):
+                ctx.dot_shares(p, qs.op[p], qs.q, imc.make_ids(0, rot, 0), db.regions[p], db.capacity, n, o[2], o[3],
+                               ld)
+            torch.cuda.synchronize()
+            for gi, o in enumerate(outs):
+                assert torch.equal(o[0][:, :n], o[2][:, :n]) and torch.equal(o[1][:, :n], o[3][:, :n]), (p, gi)
+                assert not o[0][:, n:].any(), (p, gi)          # nothing written past the last entry
+            # the oracle on sampled entries (party 0)
+            for a, b in ((0, 64), (n - 96, n)) if p == 0 else ():
+                dsh = orc.share(e["dealer"], orc.DOM_SHARE_DB, dc[a:b], dm[a:b], a)
+                for (qs, rot), o, (q0, q1) in zip(groups, outs, ((0, 20), (20, 50))):
+                    qsh = orc.share(e["dealer"], orc.DOM_SHARE_QUERY, qc[q0:q1], qm[q0:q1], qs.qid_base)
+                    rc, rm = orc.local_dot(p, qsh, rot, dsh)
+                    assert np.array_equal(_u16(o[0])[:, a:b], rc) and np.array_equal(_u16(o[1])[:, a:b], rm), (p, a)
+    finally:
+        ctx.set_dot_tiles(imc.DOT_TILES_AUTO)
+        del db
+        torch.cuda.empty_cache()
+
+
+def test_dot_groups_argument_errors(env):
+    e = env
+    imc, ctx, bs = e["imc"], e["ctx"], e["bs"]
+    out = torch.zeros(64 * 31, 256, dtype=torch.int16, device="cuda")
+    g31 = (bs.op[0], 1, wl.rotations(31), out, out)
+    cases = [([(bs.op[0], 1, [0], out, out)], 0),                    # fewer than 13 rotations
+             ([g31, (bs.op[0], 1, wl.rotations(15), out, None)], 0),  # mask output in one group only
+             ([g31] * 9, 0),                                          # more groups than the launch takes
+             ([g31], 32)]                                             # first entry not a multiple of 64
+    for desc, first in cases:
+        with pytest.raises(imc.IMCError) as err:
+            ctx.dot_shares_groups(0, desc, e["db"].regions[0], e["db"].capacity, first, 64, 256)
+        assert err.value.status == imc.IMC_EINVAL
+    with pytest.raises(imc.IMCError) as err:                                # ld < n
+        ctx.dot_shares_groups(0, [g31], e["db"].regions[0], e["db"].capacity, 0, 200, 128)
+    assert err.value.status == imc.IMC_ESHAPE
+    with pytest.raises(imc.IMCError) as err:                                # past the region's capacity
+        ctx.dot_shares_groups(0, [g31], e["db"].regions[0], e["db"].capacity, 64, e["db"].capacity, 1 << 20)
+    assert err.value.status == imc.IMC_ESHAPE

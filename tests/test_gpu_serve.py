@@ -1,6 +1,7 @@
 """Continuous-batching service: results are the same alone, in a mix (joining
 mid-cycle at another chunk) and on the plain per-query path; opened results
-agree with the oracle; unique requests are appended."""
+agree with the oracle; unique requests are appended; every (request,
+rotation, entry) is compared once, so each gate's randomness is used once."""
 import numpy as np
 import pytest
 
@@ -70,8 +71,11 @@ def test_same_alone_in_mix_and_plain(env, galois, gather):
     alone = _drive(Server(e["ctx"], db, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True, gather=gather),
                    {0: [_req(e, 0, 1000)]})[0]
     db2 = _db(e, galois=galois)
-    mixed = _drive(Server(e["ctx"], db2, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True, gather=gather),
-                   {0: [_req(e, i, 1000 + i) for i in (1, 2, 3)], 2: [_req(e, 0, 1000)], 3: [_req(e, 4, 1004)]})
+    srv = Server(e["ctx"], db2, ROT, chunk=CHUNK, slots=8, append=False, keep_shares=True, gather=gather)
+    mixed = _drive(srv, {0: [_req(e, i, 1000 + i) for i in (1, 2, 3)], 2: [_req(e, 0, 1000)], 3: [_req(e, 4, 1004)]})
+    # every (request, rotation, entry) compared exactly once: the chunk passes
+    # stop at the last whole word below the snapshot, finalisation does the rest
+    assert srv.cmps == len(ROT) * sum(r.checked for r in mixed.values()) == len(ROT) * N0 * 5
     x = mixed[0]
     assert alone.dup == x.dup == 1
     assert np.array_equal(alone.dup_shares, x.dup_shares)
@@ -188,6 +192,7 @@ def test_serial_uniqueness_of_requests_in_flight(env, galois):
     assert done[15].dup == 1 and done[15].entry == -1
     assert done[6].dup == 0 and done[6].checked == N0 + 1 and done[6].entry == N0 + 1
     assert db.n == N0 + 2
+    assert srv.cmps == len(ROT) * sum(r.checked for r in done.values())   # no entry compared twice
     # b against the database after a's append, checked plainly
     d64 = lambda x: torch.from_numpy(np.ascontiguousarray(x).view(np.int64).reshape(1, 200)).cuda()  # noqa: E731
     qs = SharedQueries(e["ctx"], d64(e["qc"][5]), d64(e["qm"][5]), 4015, galois=galois)
