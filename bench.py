@@ -579,7 +579,7 @@ def run_compare(args):
         "or_tree": lambda: ctx.or_tree(match, q, nw, nw, ids, ws, ws.numel(), dup, stream),
     }
     # the same settings with the parties apart and their messages through a device buffer
-    net = torch.empty(imc.compare_msg_bytes(0, rows, nw) // 8, dtype=torch.int64, device="cuda")
+    net = torch.empty(imc.compare_msg_bytes(0, rows, n) // 8, dtype=torch.int64, device="cuda")
     calls.update({
         "mpclift_buffers": lambda: ctx.compare_threshold(code, mask, rows, n, ld, ids, match, nw, stream, msg_ws=net),
         "lift18_buffers": lambda: ctx.compare_variant(imc.CMP_LIFT18, code, 16, mask, None, rows, n, ld, ids, match,

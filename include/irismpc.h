@@ -282,12 +282,16 @@ imc_status imc_reshare(imc_ctx* ctx, const uint16_t* const add_code[3], const ui
  * comparison and both BitInjects run, 64 comparisons bit-sliced per lane.
  * ids->first_entry_id must be a multiple of 64.
  * msg_ws: the network between the parties (Sec. 6.4 keeps it on the GPU):
- * device u64 [406][rows][mw_ld], msg_ws_bytes >= imc_compare_msg_bytes(0,
- * rows, mw_ld), alignment 8.  Then the three parties run as three waves of
- * a workgroup, each holding its own view only (components p and p-1, keys p
- * and p-1), and every message is stored by its sender into its plane and
- * loaded by its receiver after a workgroup barrier, one barrier per round
- * (50 rounds).  Plane order (the oracle's message log): AND gate g
+ * msg_ws_bytes >= imc_compare_msg_bytes(0, rows, n), alignment 8.  Then the
+ * three parties run as three waves of a workgroup, each holding its own
+ * view only (components p and p-1, keys p and p-1), and every message is
+ * stored by its sender into its plane and loaded by its receiver after a
+ * workgroup barrier, one barrier per round (50 rounds).  Layout: the match
+ * words are numbered t = row * nw + w (nw = ceil(n/64)) and taken 64 at a
+ * time; plane m of word t is the u64 at index
+ * (floor(t/64) * planes + m) * 64 + t % 64 (planes = 406 here), so the
+ * messages of one group of 64 words are contiguous.  Plane order (the
+ * oracle's message log): AND gate g
  * (numbered bit by bit, a bit's FA-layer gate before its ripple gate; gates
  * 0..32 the Lift, 33..93 the MSB) sent by party p at plane 3g + p; then
  * the BitInject of bit 17 (Z_2^15) at planes 282.. and of bit 16 (Z_2^16)
@@ -304,10 +308,12 @@ imc_status imc_compare_threshold(imc_ctx* ctx, const uint16_t* const rep_code[3]
                                  const imc_ids* ids, void* msg_ws, size_t msg_ws_bytes,
                                  uint64_t* const match[3], size_t mw_ld, imc_stream stream);
 
-/* Bytes of the message buffer of a comparison call: variant 0 = MPCLift
- * (imc_compare_threshold, 406 planes), IMC_CMP_PLAIN_MASK 87,
- * IMC_CMP_LIFT18 210, IMC_CMP_CONST32 183 planes of rows x mw_ld u64. */
-size_t imc_compare_msg_bytes(int variant, size_t rows, size_t mw_ld);
+/* Bytes of the message buffer of a comparison call over rows x n
+ * comparisons: planes x 64 x ceil(rows * ceil(n/64) / 64) u64, with
+ * variant 0 = MPCLift (imc_compare_threshold) 406 planes,
+ * IMC_CMP_PLAIN_MASK 87, IMC_CMP_LIFT18 210, IMC_CMP_CONST32 183; 0 for an
+ * unknown variant. */
+size_t imc_compare_msg_bytes(int variant, size_t rows, size_t n);
 
 /* Other settings of the threshold comparison (Sec. 4.3 Alg. 2 and Sec. 4.3.1;
  * Sec. 5.1-5.2; the settings compared in Sec. 6.2).  The threshold 1 - 2*3/8
@@ -331,7 +337,8 @@ size_t imc_compare_msg_bytes(int variant, size_t rows, size_t mw_ld);
  * layout and the first_entry_id alignment are as imc_compare_threshold.  Each
  * setting draws its randomness from its own PRF domain.
  * msg_ws, msg_ws_bytes: as imc_compare_threshold (NULL: messages held in
- * registers), imc_compare_msg_bytes(variant, rows, mw_ld) bytes: Plain AND
+ * registers), imc_compare_msg_bytes(variant, rows, n) bytes in the same
+ * layout with the setting's planes: Plain AND
  * gates 0..28 (87 planes); Lift18 gates 0..32 (Lift) and 33..65 (MSB), then
  * the BitInjects of bit 17 (Z_2^1) at planes 198.. and bit 16 (Z_2^2) at
  * 202.. (210 planes); Const32 gates 0..60 (183 planes).

@@ -234,9 +234,9 @@ def or_tree_ws_bytes(q: int, r: int, nw: int) -> int:
     return lib().imc_or_tree_ws_bytes(q, r, nw)
 
 
-def compare_msg_bytes(variant: int, rows: int, mw_ld: int) -> int:
+def compare_msg_bytes(variant: int, rows: int, n: int) -> int:
     """Bytes of a comparison call's message buffer (variant 0 = MPCLift)."""
-    return lib().imc_compare_msg_bytes(variant, rows, mw_ld)
+    return lib().imc_compare_msg_bytes(variant, rows, n)
 
 
 @dataclass
@@ -344,7 +344,7 @@ class Context:
                                         _p3(msg3), _p3(rep_code3), rm, _stream(stream)), "imc_reshare")
 
     # -- imc_compare_variant (variant CMP_*; rep_mask3 None for CMP_PLAIN_MASK; msg_ws: message buffer
-    #    of compare_msg_bytes(variant, rows, mw_ld) bytes, None: messages held in registers)
+    #    of compare_msg_bytes(variant, rows, n) bytes, None: messages held in registers)
     def compare_variant(self, variant, rep_code3, code_bits, rep_mask3, ml_pub, rows, n, ld, ids: imc_ids, match3,
                         mw_ld, stream=None, msg_ws=None):
         rm = ctypes.cast(_p3(rep_mask3), _VP) if rep_mask3 is not None else None
@@ -379,7 +379,7 @@ class Context:
         return _check(lib().imc_plain_ml(self._h, addr(row_masks), rows, addr(db_masks), n, addr(ml), ld,
                                          _stream(stream)), "imc_plain_ml")
 
-    # -- imc_compare_threshold (msg_ws: device tensor of compare_msg_bytes(0, rows, mw_ld) bytes, the
+    # -- imc_compare_threshold (msg_ws: device tensor of compare_msg_bytes(0, rows, n) bytes, the
     #    message buffer between the parties; None: messages held in registers)
     def compare_threshold(self, rep_code3, rep_mask3, rows, n, ld, ids: imc_ids, match3, mw_ld, stream=None,
                           msg_ws=None):

@@ -485,8 +485,9 @@ imc_status imc_reshare(imc_ctx* c, const uint16_t* const add_code[3], const uint
       imc::launch_reshare(c->party, add_code, add_mask, rows, n, ld, *ids, msg, rep_code, rep_mask, hipStream_t(stream)));
 }
 
-size_t imc_compare_msg_bytes(int variant, size_t rows, size_t mw_ld) {
-  return imc::compare_msg_planes(variant) * rows * mw_ld * sizeof(uint64_t);
+size_t imc_compare_msg_bytes(int variant, size_t rows, size_t n) {
+  const size_t groups = (rows * ((n + 63) / 64) + 63) / 64;   // workgroups of 64 match words
+  return imc::compare_msg_planes(variant) * groups * 64 * sizeof(uint64_t);
 }
 
 imc_status imc_compare_threshold(imc_ctx* c, const uint16_t* const rep_code[3], const uint16_t* const rep_mask[3],
@@ -506,7 +507,7 @@ imc_status imc_compare_threshold(imc_ctx* c, const uint16_t* const rep_code[3], 
   }
   if (msg_ws) {
     if (!aligned(msg_ws, 8)) return IMC_EINVAL;
-    if (msg_ws_bytes < imc_compare_msg_bytes(0, rows, mw_ld)) return IMC_ESHAPE;
+    if (msg_ws_bytes < imc_compare_msg_bytes(0, rows, n)) return IMC_ESHAPE;
   }
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;
@@ -542,7 +543,7 @@ imc_status imc_compare_variant(imc_ctx* c, int variant, const void* const rep_co
   if (variant == IMC_CMP_PLAIN_MASK && (!ml_pub || !aligned(ml_pub, 2))) return IMC_EINVAL;
   if (msg_ws) {
     if (!aligned(msg_ws, 8)) return IMC_EINVAL;
-    if (msg_ws_bytes < imc_compare_msg_bytes(variant, rows, mw_ld)) return IMC_ESHAPE;
+    if (msg_ws_bytes < imc_compare_msg_bytes(variant, rows, n)) return IMC_ESHAPE;
   }
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;

@@ -172,7 +172,7 @@ def alloc_check(q: int, r: int, n: int, device=0, compare: str = "mpclift", net:
         compare=compare,
         ml_pub=u16(rows, ld) if plain else None,
         row_masks=torch.empty(rows, 200, dtype=torch.int64, device=d) if plain else None,
-        net=(torch.empty(compare_msg_bytes(NET_VARIANT[compare], rows, nw) // 8, dtype=torch.int64, device=d)
+        net=(torch.empty(compare_msg_bytes(NET_VARIANT[compare], rows, n) // 8, dtype=torch.int64, device=d)
              if net == "buffers" else None),
     )
 

@@ -40,6 +40,12 @@ def test_host_side_helpers_without_gpu():
     assert L.imc_strerror(0) == b"ok" and L.imc_strerror(-5).startswith(b"components")
     assert imc.db_bytes(1) == 32 * 102400 and imc.db_bytes(33) == 2 * 32 * 102400
     assert imc.query_op_bytes(3) == 3 * 102400 and imc.query_raw_bytes(2) == 2 * 2 * 2 * 12800 * 2
+    # message buffers: planes x 64 words per group of 64 match words (31 rows x 5 words = 155 -> 3 groups)
+    assert imc.compare_msg_bytes(0, 31, 300) == 406 * 64 * 3 * 8
+    assert imc.compare_msg_bytes(imc.CMP_PLAIN_MASK, 31, 300) == 87 * 64 * 3 * 8
+    assert imc.compare_msg_bytes(imc.CMP_LIFT18, 1, 1) == 210 * 64 * 8
+    assert imc.compare_msg_bytes(imc.CMP_CONST32, 64, 64) == 183 * 64 * 8
+    assert imc.compare_msg_bytes(9, 64, 64) == 0
     # a null parameter block is rejected before any device call
     h = ctypes.c_void_p()
     assert L.imc_create(None, 0, ctypes.byref(h)) == imc.IMC_EINVAL

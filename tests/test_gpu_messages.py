@@ -61,9 +61,17 @@ def _check_components(match, want, nw):
         assert np.array_equal(got[1], want[(p + 2) % 3]), p
 
 
-def _check_log(msg, want_log, rows, n, mw_ld):
+def _planes(msg, nmsg, rows, nw):
+    """The buffer's per-workgroup blocks ([group][plane][64 words]) as
+    [plane][rows][nw]: word t = row * nw + w is lane t % 64 of group t // 64."""
+    groups = (rows * nw + 63) // 64
+    blocks = msg.cpu().numpy().view(np.uint64)[:groups * nmsg * 64].reshape(groups, nmsg, 64)
+    return blocks.transpose(1, 0, 2).reshape(nmsg, groups * 64)[:, :rows * nw].reshape(nmsg, rows, nw)
+
+
+def _check_log(msg, want_log, rows, n):
     nmsg, _, nw = want_log.shape
-    got = msg.cpu().numpy().view(np.uint64).reshape(nmsg, rows, mw_ld)[:, :, :nw].copy()
+    got = _planes(msg, nmsg, rows, nw).copy()
     if n % 64:
         got[:, :, nw - 1] &= np.uint64((1 << (n % 64)) - 1)     # columns past n are unspecified
     bad = np.argwhere(got != want_log)
@@ -91,14 +99,14 @@ def test_mpclift_messages_equal_the_oracle_log(ctx, imc, keys, rows_r, n, ld, fi
     mw_ld = nw + 1
     rep_code, rep_mask = _rep_dev(d, ld), _rep_dev(x, ld)
     ids = imc.make_ids(21, rot, first)
-    nbytes = imc.compare_msg_bytes(0, rows, mw_ld)
-    assert nbytes == 406 * rows * mw_ld * 8
+    nbytes = imc.compare_msg_bytes(0, rows, n)
+    assert nbytes == 406 * 64 * ((rows * nw + 63) // 64) * 8
     msg = torch.full((nbytes // 8,), -1, dtype=torch.int64, device="cuda")
     match = [torch.full((2, rows, mw_ld), -1, dtype=torch.int64, device="cuda") for _ in range(3)]
     ctx.compare_threshold(rep_code, rep_mask, rows, n, ld, ids, match, mw_ld, msg_ws=msg)
     torch.cuda.synchronize()
     _check_components(match, want, nw)
-    _check_log(msg, want_log, rows, n, mw_ld)
+    _check_log(msg, want_log, rows, n)
     # the register simulation gives the same components
     match2 = [torch.full((2, rows, mw_ld), -1, dtype=torch.int64, device="cuda") for _ in range(3)]
     ctx.compare_threshold(rep_code, rep_mask, rows, n, ld, ids, match2, mw_ld)
@@ -132,15 +140,15 @@ def test_variant_messages_equal_the_oracle_log(ctx, imc, keys, variant, rows_r, 
         h[:, :n] = ml
         ml_pub = torch.from_numpy(h.view(np.int16)).cuda()
     cv = {"plain": imc.CMP_PLAIN_MASK, "lift18": imc.CMP_LIFT18}.get(variant, imc.CMP_CONST32)
-    nbytes = imc.compare_msg_bytes(cv, rows, mw_ld)
-    assert nbytes == orc.msg_count(v) * rows * mw_ld * 8
+    nbytes = imc.compare_msg_bytes(cv, rows, n)
+    assert nbytes == orc.msg_count(v) * 64 * ((rows * nw + 63) // 64) * 8
     msg = torch.full((nbytes // 8,), -1, dtype=torch.int64, device="cuda")
     match = [torch.full((2, rows, mw_ld), -1, dtype=torch.int64, device="cuda") for _ in range(3)]
     ids = imc.make_ids(8, rot, first)
     ctx.compare_variant(cv, rep_code, code_bits, rep_mask, ml_pub, rows, n, ld, ids, match, mw_ld, msg_ws=msg)
     torch.cuda.synchronize()
     _check_components(match, want, nw)
-    _check_log(msg, want_log, rows, n, mw_ld)
+    _check_log(msg, want_log, rows, n)
 
 
 def test_message_buffer_argument_errors(ctx, imc):
@@ -148,11 +156,11 @@ def test_message_buffer_argument_errors(ctx, imc):
     rep = [torch.zeros(2, rows, ld, dtype=torch.int16, device="cuda") for _ in range(3)]
     match = [torch.zeros(2, rows, 1, dtype=torch.int64, device="cuda") for _ in range(3)]
     ids = imc.make_ids(0, rot, 0)
-    small = torch.zeros(imc.compare_msg_bytes(0, rows, 1) // 8 - 1, dtype=torch.int64, device="cuda")
+    small = torch.zeros(imc.compare_msg_bytes(0, rows, n) // 8 - 1, dtype=torch.int64, device="cuda")
     with pytest.raises(imc.IMCError) as e:
         ctx.compare_threshold(rep, rep, rows, n, ld, ids, match, 1, msg_ws=small)
     assert e.value.status == imc.IMC_ESHAPE
-    odd = torch.zeros(imc.compare_msg_bytes(0, rows, 1) + 8, dtype=torch.uint8, device="cuda")[1:]
+    odd = torch.zeros(imc.compare_msg_bytes(0, rows, n) + 8, dtype=torch.uint8, device="cuda")[1:]
     with pytest.raises(imc.IMCError) as e:
         ctx.compare_threshold(rep, rep, rows, n, ld, ids, match, 1, msg_ws=odd)
     assert e.value.status == imc.IMC_EINVAL
