@@ -787,7 +787,8 @@ def run_serve(args):
         reqs = [Request(rid=i, qid=qid + i, code=qc[i], mask=qm[i], arrival=float(arr[i])) for i in range(n_req)]
         qid += n_req
         decide = (lambda r: int(r.qid in planted_qids)) if local else None
-        srv = Server(ctx, db, rot, chunk=args.chunk, slots=args.slots, decide=decide, serial=not args.no_serial)
+        srv = Server(ctx, db, rot, chunk=args.chunk, slots=args.slots, decide=decide, serial=not args.no_serial,
+                     net=args.net)
         n0 = db.n
         log(f"serving lambda={lam}/s: {n_req} requests over {args.duration:.1f} s, DB {n0} entries")
         t0 = time.perf_counter()
@@ -831,7 +832,8 @@ def run_serve(args):
                                 f"(+ appends)") + f", 31 rotations, Poisson arrivals {args.rates}/s for "
                                                   f"{args.duration} s",
                    "chunk": args.chunk, "slots": args.slots, "sharing": args.scheme,
-                   "parties": len(parties), "serial_uniqueness": not (args.no_serial or local)},
+                   "parties": len(parties), "serial_uniqueness": not (args.no_serial or local),
+                   "compare_net": None if local else args.net},
         "latency_ms": {"p50": out["lambda"][top]["p50_ms"], "p99": out["lambda"][top]["p99_ms"], "at_lambda": top},
         "serve": out,
     }, (None, None, None)

@@ -54,7 +54,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import OPEN_U8_XOR, Context, make_ids, or_tree_ws_bytes
+from . import OPEN_U8_XOR, Context, compare_msg_bytes, make_ids, or_tree_ws_bytes
 
 ROW = 102400                 # query operand bytes per query (replicated form)
 RAW = 2 * 2 * 12800 * 2      # raw query share bytes per query (replicated form)
@@ -86,14 +86,17 @@ class Request:
 class Server:
     def __init__(self, ctx: Context, db, rot, chunk: int = 65536, slots: int = 64, max_entries: int | None = None,
                  hbm_reserve: float = 0.01, append: bool = True, keep_shares: bool = False, device=0,
-                 gather: bool = True, decide=None, serial: bool = True):
+                 gather: bool = True, decide=None, serial: bool = True, net: str = "buffers"):
         """hbm_reserve: fraction of the device's memory kept free by admission.
         gather: run each tick's dot products as one gathered uniform launch
         (`imc_dot_shares_gather`); otherwise through a row table
         (`imc_dot_shares_rows`).  decide: request -> 0/1, the uniqueness
         decision in party-local serving (required there, unused otherwise).
         serial: also match requests against earlier-admitted requests that were
-        in flight at their admission (see the module notes)."""
+        in flight at their admission (see the module notes).  net: "buffers"
+        runs each comparison with the parties apart and its messages through
+        a device buffer (one, shared by the comparisons, which run in stream
+        order); "registers" holds them in registers."""
         self.gather = gather
         self.parties = [p for p in range(3) if db.regions[p] is not None]
         self.local = len(self.parties) < 3
@@ -140,6 +143,9 @@ class Server:
         self.match = [None] * slots     # [3] x [2, R, nw_full] int64, allocated on admission
         self.dup = [[torch.empty(2, 1, dtype=torch.uint8, device=d) for _ in range(3)] for _ in range(slots)]
         self.ws = torch.empty(max(8, or_tree_ws_bytes(1, self.R, self.nw_full)), dtype=torch.uint8, device=d)
+        assert net in ("buffers", "registers")
+        self.net = (torch.empty(compare_msg_bytes(0, self.R, chunk) // 8, dtype=torch.int64, device=d)
+                    if net == "buffers" and not self.local else None)
         self.open_dev = torch.empty(slots, dtype=torch.uint8, device=d)
         self.open_host = torch.empty(slots, dtype=torch.uint8).pin_memory()
         self.free = list(range(slots))[::-1]
@@ -277,7 +283,7 @@ class Server:
                              self.rep_mask[s])
             mw = [m.data_ptr() + 8 * (first // 64) for m in self.match[s]]
             self.ctx.compare_threshold(self.rep_code[s], self.rep_mask[s], self.R, n_w, self.ld, ids, mw,
-                                       self.nw_full)
+                                       self.nw_full, msg_ws=self.net)
             self.cmps += self.R * n_w
         # after every request of the tick has consumed its rows of the shared
         # dot buffers (a tail pass reuses them)
@@ -353,7 +359,7 @@ class Server:
                              self.rep_mask[s])
             mw = [m.data_ptr() + 8 * (f // 64) for m in self.match[s]]
             self.ctx.compare_threshold(self.rep_code[s], self.rep_mask[s], self.R, n_j, self.ld, ids, mw,
-                                       self.nw_full)
+                                       self.nw_full, msg_ws=self.net)
             self.cmps += self.R * n_j
 
     def _finalize(self, r: Request, n_checked: int):
