@@ -78,16 +78,46 @@ struct Tape {
   }
 };
 
-// Bit planes of party p's two components of an arithmetic sharing, held in
-// registers (NB planes each, higher ones zero).
-template <int NB>
-struct Planes {
-  const uint64_t (&o)[NB];
-  const uint64_t (&v)[NB];
-  __device__ __forceinline__ void at(int i, uint64_t, uint64_t& bo, uint64_t& bv) const {
-    bo = i < NB ? o[i] : 0ull;
-    bv = i < NB ? v[i] : 0ull;
+// Bit planes of party p's two components of an arithmetic sharing, read one
+// bit at a time by the bit-serial circuits: planes 0..NREG-1 of each
+// component in registers, planes NREG..NB-1 in the wave's slice of LDS
+// (slots 0.. own component, then previous), planes >= NB zero.  The bit loop
+// indexes planes at run time; held in a register array they would go to
+// per-lane scratch, whose round trips through L2 cost a third of the kernel
+// (measured).  Up to kPlaneSlots LDS slots of 64 u64 per wave: 39 KB per
+// workgroup of three waves, so four workgroups (12 waves) share a CU, as many
+// as the registers allow.
+constexpr int kPlaneSlots = 26;
+__shared__ uint64_t lds_planes[3][kPlaneSlots][64];
+
+template <int NB, int NREG>
+struct SplitPlanes {
+  static constexpr int kLds = NB - NREG;
+  static_assert(NREG >= 1 && 2 * kLds <= kPlaneSlots, "planes exceed the LDS slots");
+  uint64_t ro[NREG], rv[NREG];
+  uint64_t* L;   // this lane's word of slot 0 of its wave
+  __device__ __forceinline__ SplitPlanes() : L(&lds_planes[threadIdx.x >> 6][0][threadIdx.x & 63]) {}
+  // component c (0: own, 1: previous)
+  __device__ __forceinline__ void put(int c, const uint64_t (&x)[NB]) {
+#pragma unroll
+    for (int j = 0; j < NREG; ++j) (c ? rv : ro)[j] = x[j];
+#pragma unroll
+    for (int j = NREG; j < NB; ++j) L[(c * kLds + j - NREG) * 64] = x[j];
   }
+  __device__ __forceinline__ void get(int k, uint64_t& bo, uint64_t& bv) const {
+    const int slot = k < NREG ? 0 : k < NB ? k - NREG : kLds - 1;
+    uint64_t a = L[slot * 64], b = L[(kLds + slot) * 64];
+    a = k < NB ? a : 0ull;
+    b = k < NB ? b : 0ull;
+#pragma unroll
+    for (int j = 0; j < NREG; ++j) {
+      a = k == j ? ro[j] : a;
+      b = k == j ? rv[j] : b;
+    }
+    bo = a;
+    bv = b;
+  }
+  __device__ __forceinline__ void at(int i, uint64_t, uint64_t& bo, uint64_t& bv) const { get(i, bo, bv); }
 };
 
 // BitExtract (App. D) of bits 0..M of y_0 + y_1 + y_2; y.at(i, dep, bo, bv)
@@ -121,7 +151,7 @@ __device__ __forceinline__ PV msg_bit_extract(int p, const Key& ko, const Key& k
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii) {
       const int i = 4 * blk + ii;
-      if (i > M) break;
+      if (i > M) continue;   // (no early exit: the four bits unroll)
       uint64_t bo, bv;
       y.at(i, carry.o ^ cprev.v, bo, bv);
       const PV a = inp(0, p, bo, bv), b = inp(1, p, bo, bv), c = inp(2, p, bo, bv);
@@ -287,44 +317,22 @@ __device__ __forceinline__ void mpclift_u(const uint64_t (&xm)[16], const uint64
   u[15] = u[15] ^ b1 ^ b2 ^ a0;
 }
 
-// Party p's planes of the MPCLift y, produced as the MSB circuit reaches
-// them: bits 14 and 15 from planes kept from the Lift's inputs, bits 16..31
-// computed (ml and dot reloaded and transposed) when bit 16 is reached, so
-// that only one set of planes is in registers at a time.
+// Party p's planes of the MPCLift y: bits 0..13 zero, bits 14 and 15 the ml
+// planes 0 and 1 kept from the Lift's inputs, bits 16..31 formed before the
+// MSB circuit starts (ml and the code dot reloaded and transposed, one
+// component at a time).
 struct MpcliftY {
-  const uint16_t* mrow;   // ml component p; component p-1 at + pe
-  const uint16_t* drow;   // code-dot component p; p-1 at + pe
-  uint64_t pe, col0;
-  int nval;
-  bool vec_ok;
-  uint64_t lo[2][2];      // [own / prev][ml planes 0, 1]
-  uint64_t a0[2], b0[2], b1[2];
-  uint64_t u[2][16];
-  __device__ __forceinline__ void at(int i, uint64_t dep, uint64_t& bo, uint64_t& bv) {
+  uint64_t lo[2][2];            // [own / prev][ml planes 0, 1]
+  SplitPlanes<16, 3> hi;        // bits 16..31
+  __device__ __forceinline__ void at(int i, uint64_t, uint64_t& bo, uint64_t& bv) const {
     if (i < 14) {
       bo = bv = 0;
-      return;
+    } else if (i < 16) {
+      bo = i == 14 ? lo[0][0] : lo[0][1];
+      bv = i == 14 ? lo[1][0] : lo[1][1];
+    } else {
+      hi.get(i - 16, bo, bv);
     }
-    if (i < 16) {
-      bo = lo[0][i - 14];
-      bv = lo[1][i - 14];
-      return;
-    }
-    if (i == 16) {
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        uint64_t xm[16], d[16];
-        uint32_t W[32];
-        load64(after_ptr(mrow + c * pe, dep), col0, nval, vec_ok, W);
-        to_planes(W, xm);
-        load64(after_ptr(drow + c * pe, xm[0]), col0, nval, vec_ok, W);
-        to_planes(W, d);
-        mpclift_u(xm, d, a0[c], b0[c], b1[c], u[c]);
-        dep ^= u[c][0];
-      }
-    }
-    bo = u[0][i - 16];
-    bv = u[1][i - 16];
   }
 };
 
@@ -378,20 +386,20 @@ __global__ void __launch_bounds__(192) compare_msg_kernel(CmpMsgArgs a) {
 
   // Lift: bits 16 and 17 of ml_0 + ml_1 + ml_2
   PV bit16{0, 0}, bit17{0, 0};
-  uint64_t ylo[2][2];   // ml planes 0, 1 of both components: bits 14, 15 of y
+  MpcliftY y;   // ml planes 0, 1 of both components: bits 14, 15 of y
   {
-    uint64_t xo[16], xv[16];
-    uint32_t W[32];
-    load64(mrow, l.col0, l.nval, vec_ok, W);
-    to_planes(W, xo);
-    load64(mrow + a.plane_elems, l.col0, l.nval, vec_ok, W);
-    to_planes(W, xv);
-    Planes<16> y{xo, xv};
-    bit17 = msg_bit_extract<17, 0, 0>(p, ko, kv, stream, base, y, net, &bit16);
-    ylo[0][0] = xo[0];
-    ylo[0][1] = xo[1];
-    ylo[1][0] = xv[0];
-    ylo[1][1] = xv[1];
+    SplitPlanes<16, 3> x;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint64_t xc[16];
+      uint32_t W[32];
+      load64(mrow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
+      to_planes(W, xc);
+      x.put(c, xc);
+      y.lo[c][0] = xc[0];
+      y.lo[c][1] = xc[1];
+    }
+    bit17 = msg_bit_extract<17, 0, 0>(p, ko, kv, stream, base, x, net, &bit16);
   }
 
   // BitInject bit 17 into Z_2^15 (A) and bit 16 into Z_2^16 (B): two rounds
@@ -406,10 +414,22 @@ __global__ void __launch_bounds__(192) compare_msg_kernel(CmpMsgArgs a) {
   inject_view<15, 1, 104, 104>(p, a.keys, stream, base, net, 282, c0A, c2A, c1A, Ao, Av);
   inject_view<16, 2, 120, 152>(p, a.keys, stream, base, net, 342, c0B, c2B, c1B, Bo, Bv);
 
-  // the MSB of y, whose planes are formed as the circuit reaches them
-  MpcliftY y{mrow, drow, a.plane_elems, l.col0, l.nval, vec_ok,
-             {{ylo[0][0], ylo[0][1]}, {ylo[1][0], ylo[1][1]}},
-             {Ao[0], Av[0]}, {Bo[0], Bv[0]}, {Bo[1], Bv[1]}, {}};
+  // bits 16..31 of y, one component at a time (the Lift's LDS planes are no
+  // longer read), then the MSB of y
+  {
+    const uint64_t a0[2] = {Ao[0], Av[0]}, b0[2] = {Bo[0], Bv[0]}, b1[2] = {Bo[1], Bv[1]};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint64_t xm[16], d[16], u[16];
+      uint32_t W[32];
+      load64(mrow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
+      to_planes(W, xm);
+      load64(drow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
+      to_planes(W, d);
+      mpclift_u(xm, d, a0[c], b0[c], b1[c], u);
+      y.hi.put(c, u);
+    }
+  }
   const PV r = msg_bit_extract<31, 40, 33>(p, ko, kv, stream, base, y, net, nullptr);
   store_match(a, p, l, r);
 }
@@ -447,9 +467,9 @@ __device__ __forceinline__ void lift18_y(const uint64_t (&x)[16], const uint64_t
 
 // Const32 / NoLift: y = 2^14 x - 2^16 d (mod 2^32) for one component, x over
 // Z_2^32 and d over Z_2^16 or Z_2^32: bits 0..13 zero, bits 14..31 =
-// t = (x - 4 d) mod 2^18.
+// t = (x - 4 d) mod 2^18, returned as the 18 planes of t.
 template <bool C32>
-__device__ __forceinline__ void const32_y(const uint32_t* xr, const void* drow, const Lane& l, uint64_t (&y)[32]) {
+__device__ __forceinline__ void const32_y(const uint32_t* xr, const void* drow, const Lane& l, uint64_t (&y)[18]) {
   uint32_t Wl[32];
   uint64_t h16 = 0, h17 = 0;
 #pragma unroll
@@ -474,8 +494,21 @@ __device__ __forceinline__ void const32_y(const uint32_t* xr, const void* drow, 
   uint64_t tp[16];
   to_planes(Wl, tp);
 #pragma unroll
-  for (int j = 0; j < 32; ++j) y[j] = j < 14 ? 0 : j < 30 ? tp[j - 14] : j == 30 ? h16 : h17;
+  for (int j = 0; j < 18; ++j) y[j] = j < 16 ? tp[j] : j == 16 ? h16 : h17;
 }
+
+// The Const32 y seen from the MSB circuit: bits 0..13 zero, bits 14..31 the
+// 18 planes of t.
+struct Const32Y {
+  SplitPlanes<18, 5> t;
+  __device__ __forceinline__ void at(int i, uint64_t, uint64_t& bo, uint64_t& bv) const {
+    if (i < 14) {
+      bo = bv = 0;
+    } else {
+      t.get(i - 14, bo, bv);
+    }
+  }
+};
 
 // The other comparison settings (Sec. 4.3 Alg. 2, Sec. 5.1-5.2), with the
 // tape words and AND-gate order of their register-mode kernels:
@@ -502,23 +535,30 @@ __global__ void __launch_bounds__(192) compare_msg_variant_kernel(CmpMsgArgs a) 
   PV r;
   if constexpr (V == 1) {
     const uint16_t* drow = static_cast<const uint16_t*>(a.code[p]) + l.row * a.ld;
-    uint64_t yo[16], yv[16];
-    plain_y(a, l, vec_ok, p, drow, yo);
-    plain_y(a, l, vec_ok, pm, drow + a.plane_elems, yv);
-    Planes<16> y{yo, yv};
+    SplitPlanes<16, 3> y;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint64_t yc[16];
+      plain_y(a, l, vec_ok, c ? pm : p, drow + c * a.plane_elems, yc);
+      y.put(c, yc);
+    }
     r = msg_bit_extract<15, 0, 0>(p, ko, kv, stream, base, y, net, nullptr);
   } else if constexpr (V == 2) {
     const uint16_t* mrow = static_cast<const uint16_t*>(a.mask[p]) + l.row * a.ld;
     const uint16_t* drow = static_cast<const uint16_t*>(a.code[p]) + l.row * a.ld;
-    uint64_t xo[16], xv[16];
-    uint32_t W[32];
-    load64(mrow, l.col0, l.nval, vec_ok, W);
-    to_planes(W, xo);
-    load64(mrow + a.plane_elems, l.col0, l.nval, vec_ok, W);
-    to_planes(W, xv);
-    PV bit16{0, 0};
-    Planes<16> xs{xo, xv};
-    const PV bit17 = msg_bit_extract<17, 0, 0>(p, ko, kv, stream, base, xs, net, &bit16);
+    PV bit16{0, 0}, bit17{0, 0};
+    {
+      SplitPlanes<16, 3> xs;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        uint64_t xc[16];
+        uint32_t W[32];
+        load64(mrow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
+        to_planes(W, xc);
+        xs.put(c, xc);
+      }
+      bit17 = msg_bit_extract<17, 0, 0>(p, ko, kv, stream, base, xs, net, &bit16);
+    }
     uint64_t c0A[1] = {0}, c2A[1] = {0}, c1A[1] = {0}, c0B[2] = {0, 0}, c2B[2] = {0, 0}, c1B[2] = {0, 0};
     inject_send<1, 1, 80, 80, 81, 82>(p, a.keys, stream, base, bit17, net, 198, c0A, c2A);
     inject_send<2, 2, 88, 88, 90, 92>(p, a.keys, stream, base, bit16, net, 202, c0B, c2B);
@@ -529,23 +569,33 @@ __global__ void __launch_bounds__(192) compare_msg_variant_kernel(CmpMsgArgs a) 
     uint64_t Ao[1], Av[1], Bo[2], Bv[2];
     inject_view<1, 1, 80, 80>(p, a.keys, stream, base, net, 198, c0A, c2A, c1A, Ao, Av);
     inject_view<2, 2, 88, 88>(p, a.keys, stream, base, net, 202, c0B, c2B, c1B, Bo, Bv);
-    uint64_t yo[18], yv[18], d[16];
-    load64(after_ptr(drow, Ao[0] ^ Bo[1]), l.col0, l.nval, vec_ok, W);
-    to_planes(W, d);
-    lift18_y(xo, d, Ao[0], Bo[0], Bo[1], yo);
-    load64(after_ptr(drow + a.plane_elems, yo[17]), l.col0, l.nval, vec_ok, W);
-    to_planes(W, d);
-    lift18_y(xv, d, Av[0], Bv[0], Bv[1], yv);
-    Planes<18> y{yo, yv};
+    // y over Z_2^18, one component at a time (ml reloaded: the Lift's LDS
+    // planes are overwritten)
+    SplitPlanes<18, 5> y;
+    const uint64_t a0[2] = {Ao[0], Av[0]}, b0[2] = {Bo[0], Bv[0]}, b1[2] = {Bo[1], Bv[1]};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint64_t x[16], d[16], yc[18];
+      uint32_t W[32];
+      load64(mrow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
+      to_planes(W, x);
+      load64(drow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
+      to_planes(W, d);
+      lift18_y(x, d, a0[c], b0[c], b1[c], yc);
+      y.put(c, yc);
+    }
     r = msg_bit_extract<17, 40, 33>(p, ko, kv, stream, base, y, net, nullptr);
   } else {
     const uint32_t* xr = static_cast<const uint32_t*>(a.mask[p]) + l.row * a.ld;
     const size_t dw = C32 ? 4 : 2;
     const uint8_t* dr = static_cast<const uint8_t*>(a.code[p]) + l.row * a.ld * dw;
-    uint64_t yo[32], yv[32];
-    const32_y<C32>(xr, dr, l, yo);
-    const32_y<C32>(xr + a.plane_elems, dr + a.plane_elems * dw, l, yv);
-    Planes<32> y{yo, yv};
+    Const32Y y;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint64_t tc[18];
+      const32_y<C32>(xr + c * a.plane_elems, dr + c * a.plane_elems * dw, l, tc);
+      y.t.put(c, tc);
+    }
     r = msg_bit_extract<31, 0, 0>(p, ko, kv, stream, base, y, net, nullptr);
   }
   store_match(a, p, l, r);
