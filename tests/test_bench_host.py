@@ -65,3 +65,31 @@ def test_in_batch_planting_targets_earlier_queries():
     dups = [int(orc.plain(qc[i:i + 1], qm[i:i + 1], w.rot, qc[:i], qm[:i])[3][0]) for i in (9, 11, 13, 15)]
     assert dups == [1, 1, 0, 0]                # HD 0.20 and 0.30 match; 0.42 and the exact threshold do not
     assert np.array_equal(wl.make_queries(w)[0][:9], qc[:9])
+
+
+def test_two_eye_recipe_plants_every_pattern():
+    """The two-eye workload: 32 persons of two queries, database plants by
+    the left eye, the right eye and both, and in-batch pairs whose plaintext
+    decisions (each eye against the eyes of earlier persons) are the ones the
+    recipe names: 22, 39 and 55 count, 31 (a right eye made from its own left
+    eye) and 46 (made from a later person's eye) and 62 (exactly at the
+    threshold) do not."""
+    import oracle as orc
+
+    w = wl.two_eyes(n_db=1024)
+    assert (w.n_q, w.group, len(w.rot)) == (64, 2, 31)
+    by_person = {}
+    for qi, _, _, hx in w.planted:
+        by_person.setdefault(qi // 2, set()).add(qi % 2)
+    assert by_person[0] >= {0} and by_person[1] >= {1} and by_person[2] == {0, 1}
+    assert 15 not in by_person and 23 not in by_person and 27 not in by_person
+    assert {(3, "eq"), (7, "lt")} <= {(qi // 2, hx) for qi, _, _, hx in w.planted if isinstance(hx, str)}
+    qc, qm = wl.make_queries(w)
+    wl.plant_in_batch(w, qc, qm, w.batch_pairs)
+    got = {}
+    for i in (22, 31, 39, 46, 55, 62):
+        k = 2 * (i // 2)
+        got[i] = int(orc.plain(qc[i:i + 1], qm[i:i + 1], w.rot, qc[:k], qm[:k])[3][0])
+    assert got == {22: 1, 31: 0, 39: 1, 46: 0, 55: 1, 62: 0}
+    # with groups of one, the right eye made from its own left eye would count
+    assert int(orc.plain(qc[31:32], qm[31:32], w.rot, qc[:31], qm[:31])[3][0]) == 1
