@@ -104,6 +104,10 @@ struct SplitPlanes {
 #pragma unroll
     for (int j = NREG; j < NB; ++j) L[(c * kLds + j - NREG) * 64] = x[j];
   }
+  // plane k (compile-time, < NB) of component c
+  __device__ __forceinline__ uint64_t plane(int c, int k) const {
+    return k < NREG ? (c ? rv : ro)[k < NREG ? k : 0] : L[(c * kLds + (k < NREG ? 0 : k - NREG)) * 64];
+  }
   __device__ __forceinline__ void get(int k, uint64_t& bo, uint64_t& bv) const {
     const int slot = k < NREG ? 0 : k < NB ? k - NREG : kLds - 1;
     uint64_t a = L[slot * 64], b = L[(kLds + slot) * 64];
@@ -318,12 +322,12 @@ __device__ __forceinline__ void mpclift_u(const uint64_t (&xm)[16], const uint64
 }
 
 // Party p's planes of the MPCLift y: bits 0..13 zero, bits 14 and 15 the ml
-// planes 0 and 1 kept from the Lift's inputs, bits 16..31 formed before the
-// MSB circuit starts (ml and the code dot reloaded and transposed, one
-// component at a time).
+// planes 0 and 1, bits 16..31 formed before the MSB circuit starts from the
+// ml planes the Lift read (in `hi` until then) and the transposed code dot,
+// one component at a time.
 struct MpcliftY {
   uint64_t lo[2][2];            // [own / prev][ml planes 0, 1]
-  SplitPlanes<16, 3> hi;        // bits 16..31
+  SplitPlanes<16, 3> hi;        // the Lift's ml planes, then bits 16..31
   __device__ __forceinline__ void at(int i, uint64_t, uint64_t& bo, uint64_t& bv) const {
     if (i < 14) {
       bo = bv = 0;
@@ -387,20 +391,17 @@ __global__ void __launch_bounds__(192) compare_msg_kernel(CmpMsgArgs a) {
   // Lift: bits 16 and 17 of ml_0 + ml_1 + ml_2
   PV bit16{0, 0}, bit17{0, 0};
   MpcliftY y;   // ml planes 0, 1 of both components: bits 14, 15 of y
-  {
-    SplitPlanes<16, 3> x;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      uint64_t xc[16];
-      uint32_t W[32];
-      load64(mrow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
-      to_planes(W, xc);
-      x.put(c, xc);
-      y.lo[c][0] = xc[0];
-      y.lo[c][1] = xc[1];
-    }
-    bit17 = msg_bit_extract<17, 0, 0>(p, ko, kv, stream, base, x, net, &bit16);
+  for (int c = 0; c < 2; ++c) {
+    uint64_t xc[16];
+    uint32_t W[32];
+    load64(mrow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
+    to_planes(W, xc);
+    y.hi.put(c, xc);
+    y.lo[c][0] = xc[0];
+    y.lo[c][1] = xc[1];
   }
+  bit17 = msg_bit_extract<17, 0, 0>(p, ko, kv, stream, base, y.hi, net, &bit16);
 
   // BitInject bit 17 into Z_2^15 (A) and bit 16 into Z_2^16 (B): two rounds
   uint64_t c0A[1] = {0}, c2A[1] = {0}, c1A[1] = {0}, c0B[2] = {0, 0}, c2B[2] = {0, 0}, c1B[2] = {0, 0};
@@ -414,16 +415,16 @@ __global__ void __launch_bounds__(192) compare_msg_kernel(CmpMsgArgs a) {
   inject_view<15, 1, 104, 104>(p, a.keys, stream, base, net, 282, c0A, c2A, c1A, Ao, Av);
   inject_view<16, 2, 120, 152>(p, a.keys, stream, base, net, 342, c0B, c2B, c1B, Bo, Bv);
 
-  // bits 16..31 of y, one component at a time (the Lift's LDS planes are no
-  // longer read), then the MSB of y
+  // bits 16..31 of y, one component at a time: component c's ml planes are
+  // read back before its y planes take their place; then the MSB of y
   {
     const uint64_t a0[2] = {Ao[0], Av[0]}, b0[2] = {Bo[0], Bv[0]}, b1[2] = {Bo[1], Bv[1]};
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       uint64_t xm[16], d[16], u[16];
       uint32_t W[32];
-      load64(mrow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
-      to_planes(W, xm);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) xm[j] = y.hi.plane(c, j);
       load64(drow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
       to_planes(W, d);
       mpclift_u(xm, d, a0[c], b0[c], b1[c], u);
@@ -469,27 +470,61 @@ __device__ __forceinline__ void lift18_y(const uint64_t (&x)[16], const uint64_t
 // Z_2^32 and d over Z_2^16 or Z_2^32: bits 0..13 zero, bits 14..31 =
 // t = (x - 4 d) mod 2^18, returned as the 18 planes of t.
 template <bool C32>
-__device__ __forceinline__ void const32_y(const uint32_t* xr, const void* drow, const Lane& l, uint64_t (&y)[18]) {
+__device__ __forceinline__ void const32_y(const uint32_t* xr, const void* drow, const Lane& l, bool vec_ok,
+                                          uint64_t (&y)[18]) {
   uint32_t Wl[32];
   uint64_t h16 = 0, h17 = 0;
+  const bool vec = vec_ok && l.nval == 64;
 #pragma unroll
-  for (int g = 0; g < 16; ++g) {
-    uint32_t tv[4];
+  for (int q = 0; q < 4; ++q) {   // 16 columns at a time (bounded live registers)
+    uint32_t xv[16], dv[16];
+    if (vec) {
+      const uint4* px = reinterpret_cast<const uint4*>(xr + l.col0 + 16 * q);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int c = 4 * g + k;
-      const uint32_t xv = c < l.nval ? xr[l.col0 + c] : 0u;
-      uint32_t dv = 0;
-      if (c < l.nval) {
-        if constexpr (C32) dv = static_cast<const uint32_t*>(drow)[l.col0 + c];
-        else dv = static_cast<const uint16_t*>(drow)[l.col0 + c];
+      for (int i = 0; i < 4; ++i) {
+        const uint4 v = px[i];
+        xv[4 * i] = v.x; xv[4 * i + 1] = v.y; xv[4 * i + 2] = v.z; xv[4 * i + 3] = v.w;
       }
-      tv[k] = xv - (dv << 2);
-      h16 |= uint64_t((tv[k] >> 16) & 1u) << c;
-      h17 |= uint64_t((tv[k] >> 17) & 1u) << c;
+      if constexpr (C32) {
+        const uint4* pd = reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(drow) + l.col0 + 16 * q);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint4 v = pd[i];
+          dv[4 * i] = v.x; dv[4 * i + 1] = v.y; dv[4 * i + 2] = v.z; dv[4 * i + 3] = v.w;
+        }
+      } else {
+        const uint4* pd = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(drow) + l.col0 + 16 * q);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const uint4 v = pd[i];
+          const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            dv[8 * i + 2 * j] = w[j] & 0xFFFFu;
+            dv[8 * i + 2 * j + 1] = w[j] >> 16;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int c = 16 * q + k;
+        xv[k] = c < l.nval ? xr[l.col0 + c] : 0u;
+        dv[k] = 0;
+        if (c < l.nval) {
+          if constexpr (C32) dv[k] = static_cast<const uint32_t*>(drow)[l.col0 + c];
+          else dv[k] = static_cast<const uint16_t*>(drow)[l.col0 + c];
+        }
+      }
     }
-    Wl[2 * g] = (tv[0] & 0xFFFFu) | (tv[1] << 16);
-    Wl[2 * g + 1] = (tv[2] & 0xFFFFu) | (tv[3] << 16);
+#pragma unroll
+    for (int k = 0; k < 16; k += 2) {
+      const int c = 16 * q + k;
+      const uint32_t t0 = xv[k] - (dv[k] << 2), t1 = xv[k + 1] - (dv[k + 1] << 2);
+      h16 |= (uint64_t((t0 >> 16) & 1u) << c) | (uint64_t((t1 >> 16) & 1u) << (c + 1));
+      h17 |= (uint64_t((t0 >> 17) & 1u) << c) | (uint64_t((t1 >> 17) & 1u) << (c + 1));
+      Wl[c >> 1] = (t0 & 0xFFFFu) | (t1 << 16);
+    }
   }
   uint64_t tp[16];
   to_planes(Wl, tp);
@@ -547,18 +582,16 @@ __global__ void __launch_bounds__(192) compare_msg_variant_kernel(CmpMsgArgs a) 
     const uint16_t* mrow = static_cast<const uint16_t*>(a.mask[p]) + l.row * a.ld;
     const uint16_t* drow = static_cast<const uint16_t*>(a.code[p]) + l.row * a.ld;
     PV bit16{0, 0}, bit17{0, 0};
-    {
-      SplitPlanes<16, 3> xs;
+    SplitPlanes<16, 3> xs;
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        uint64_t xc[16];
-        uint32_t W[32];
-        load64(mrow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
-        to_planes(W, xc);
-        xs.put(c, xc);
-      }
-      bit17 = msg_bit_extract<17, 0, 0>(p, ko, kv, stream, base, xs, net, &bit16);
+    for (int c = 0; c < 2; ++c) {
+      uint64_t xc[16];
+      uint32_t W[32];
+      load64(mrow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
+      to_planes(W, xc);
+      xs.put(c, xc);
     }
+    bit17 = msg_bit_extract<17, 0, 0>(p, ko, kv, stream, base, xs, net, &bit16);
     uint64_t c0A[1] = {0}, c2A[1] = {0}, c1A[1] = {0}, c0B[2] = {0, 0}, c2B[2] = {0, 0}, c1B[2] = {0, 0};
     inject_send<1, 1, 80, 80, 81, 82>(p, a.keys, stream, base, bit17, net, 198, c0A, c2A);
     inject_send<2, 2, 88, 88, 90, 92>(p, a.keys, stream, base, bit16, net, 202, c0B, c2B);
@@ -569,16 +602,16 @@ __global__ void __launch_bounds__(192) compare_msg_variant_kernel(CmpMsgArgs a) 
     uint64_t Ao[1], Av[1], Bo[2], Bv[2];
     inject_view<1, 1, 80, 80>(p, a.keys, stream, base, net, 198, c0A, c2A, c1A, Ao, Av);
     inject_view<2, 2, 88, 88>(p, a.keys, stream, base, net, 202, c0B, c2B, c1B, Bo, Bv);
-    // y over Z_2^18, one component at a time (ml reloaded: the Lift's LDS
-    // planes are overwritten)
+    // y over Z_2^18, one component at a time: component c's ml planes are
+    // read back before its y planes take their LDS slots
     SplitPlanes<18, 5> y;
     const uint64_t a0[2] = {Ao[0], Av[0]}, b0[2] = {Bo[0], Bv[0]}, b1[2] = {Bo[1], Bv[1]};
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       uint64_t x[16], d[16], yc[18];
       uint32_t W[32];
-      load64(mrow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
-      to_planes(W, x);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) x[j] = xs.plane(c, j);
       load64(drow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
       to_planes(W, d);
       lift18_y(x, d, a0[c], b0[c], b1[c], yc);
@@ -593,7 +626,7 @@ __global__ void __launch_bounds__(192) compare_msg_variant_kernel(CmpMsgArgs a) 
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       uint64_t tc[18];
-      const32_y<C32>(xr + c * a.plane_elems, dr + c * a.plane_elems * dw, l, tc);
+      const32_y<C32>(xr + c * a.plane_elems, dr + c * a.plane_elems * dw, l, vec_ok, tc);
       y.t.put(c, tc);
     }
     r = msg_bit_extract<31, 0, 0>(p, ko, kv, stream, base, y, net, nullptr);
