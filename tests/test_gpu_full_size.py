@@ -10,7 +10,9 @@ configuration the benchmark times, on outputs the oracle computes one by one.
   four 64-entry groups (the first, two random ones and the ragged last group
   of 32 entries) against the oracle's protocol run on those entries; the
   match-bit components of 32 more groups against the oracle's comparison of
-  the GPU's reshared components; the duplicate-bit components of every query
+  the GPU's reshared components, and for 8 of them every word of the message
+  buffer (406 planes, every row) against the oracle's message log; the
+  duplicate-bit components of every query
   against the oracle's OR-tree over the GPU's match-bit components of the
   whole database; every opened one re-decided by the plaintext check, the
   opened ones equal to the plaintext matches of the planted pairs and every
@@ -109,7 +111,8 @@ def test_party_dot_at_one_million_entries(imc, keys):
 def test_three_party_protocol_at_300k_entries(imc, keys, galois):
     """galois: the dot products on Galois-ring Shamir shares (the rest of the
     protocol unchanged).  Share-level parity on four groups from sharing on;
-    the comparison on the GPU's own reshared components of 32 more groups;
+    the comparison on the GPU's own reshared components of 32 more groups,
+    with every message word of 8 of them against the oracle's message log;
     every opened bit and duplicate against the plaintext decision; the
     duplicate-bit components against the oracle's OR-tree on the GPU's
     match-bit components of the whole database."""
@@ -148,6 +151,18 @@ def test_three_party_protocol_at_300k_entries(imc, keys, galois):
         dup_planes = [buf.dup[p].cpu().numpy() for p in range(3)]
         mo = mo.cpu().numpy().view(np.uint64)
         dup = do.cpu().numpy()
+        # the message words of 8 of those groups, every row and all 406 planes,
+        # gathered from the buffer's per-workgroup blocks (word t = row * nw + w
+        # is lane t % 64 of block t // 64)
+        nw = buf.nw
+        msg_groups = more[:8]
+        t = torch.arange(w.rows, dtype=torch.int64, device="cuda")[None, :] * nw
+        planes = torch.arange(406, dtype=torch.int64, device="cuda")[:, None]
+        msgs = {}
+        for g in msg_groups:
+            tg = t + g
+            idx = ((tg // 64) * 406 + planes) * 64 + tg % 64
+            msgs[g] = torch.take(buf.net, idx).cpu().numpy().view(np.uint64)     # [406][rows]
         del buf, db, qs
         free()
         for p in range(3):   # replicated: party p's second plane is component p-1
@@ -177,7 +192,11 @@ def test_three_party_protocol_at_300k_entries(imc, keys, galois):
             for p in range(3):
                 pm = (p + 2) % 3
                 assert np.array_equal(got[g][p][0][1], d[pm]) and np.array_equal(got[g][p][1][1], x[pm]), g
-            ref = orc.compare(party, d, x, w.n_q, w.rot, 0, a)
+            if g in msgs:      # and every message of the three parties, against the oracle's log
+                ref, log = orc.compare(party, d, x, w.n_q, w.rot, 0, a, want_msg=True)
+                assert np.array_equal(msgs[g], log[:, :, 0]), g
+            else:
+                ref = orc.compare(party, d, x, w.n_q, w.rot, 0, a)
             for p in range(3):
                 assert np.array_equal(match_own[p][:, g], ref[p][:, 0]), (g, p)
 
