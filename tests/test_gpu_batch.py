@@ -149,13 +149,14 @@ def test_autotune_keeps_the_fastest_and_outputs_are_unchanged(env):
     e["ctx"].set_dot_tiles(imc.DOT_TILES_AUTO)
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_dot_groups_equal_per_group_launches_and_oracle(env, persistent):
+@pytest.mark.parametrize("persistent,galois", [(False, False), (True, False), (True, True)])
+def test_dot_groups_equal_per_group_launches_and_oracle(env, persistent, galois):
     """Two rotation lists (31 and 15) over 16,480 entries in one launch: 640
     tiles, so the persistent grid walks two or three tiles per workgroup; the
     outputs equal one imc_dot_shares launch per group bit for bit, and the
     oracle's local dot on the first 64 and the last 96 entries (a ragged
-    column tile)."""
+    column tile).  galois: the same on Galois-ring Shamir operands (K =
+    12,800)."""
     from paper_2405_04463_amd.pipeline import SharedDB, SharedQueries
 
     e = env
@@ -163,13 +164,13 @@ def test_dot_groups_equal_per_group_launches_and_oracle(env, persistent):
     n = 16384 + 96
     d64 = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()  # noqa: E731
     dc, dm = wl.gen_codes(62, 0, n)
-    db = SharedDB(ctx, n)
+    db = SharedDB(ctx, n, galois=galois)
     for s0 in range(0, n, 8192):
         db.enroll(d64(dc[s0:s0 + 8192]), d64(dm[s0:s0 + 8192]), s0)
     qc, qm = wl.gen_codes(62, 0, 50, query=True)
     qc[3], qm[3] = wl.plant(62, 3, dc[n - 5], dm[n - 5], -7, h=0.2)
-    groups = [(SharedQueries(ctx, d64(qc[:20]), d64(qm[:20]), 700), wl.rotations(31)),
-              (SharedQueries(ctx, d64(qc[20:]), d64(qm[20:]), 720), wl.rotations(15))]
+    groups = [(SharedQueries(ctx, d64(qc[:20]), d64(qm[:20]), 700, galois=galois), wl.rotations(31)),
+              (SharedQueries(ctx, d64(qc[20:]), d64(qm[20:]), 720, galois=galois), wl.rotations(15))]
     ld = n + 64
     outs = [[torch.zeros(qs.q * len(rot), ld, dtype=torch.int16, device="cuda") for _ in range(4)]
             for qs, rot in groups]
@@ -178,20 +179,23 @@ def test_dot_groups_equal_per_group_launches_and_oracle(env, persistent):
         for p in (0, 2):
             desc = [(qs.op[p], qs.q, rot, o[0], o[1]) for (qs, rot), o in zip(groups, outs)]
             desc.insert(1, (groups[0][0].op[p], 0, wl.rotations(31), outs[0][0], outs[0][1]))   # empty: skipped
-            ctx.dot_shares_groups(p, desc, db.regions[p], db.capacity, 0, n, ld)
+            ctx.dot_shares_groups(p, desc, db.regions[p], db.capacity, 0, n, ld, galois=galois)
             for (qs, rot), o in zip(groups, outs):
                 ctx.dot_shares(p, qs.op[p], qs.q, imc.make_ids(0, rot, 0), db.regions[p], db.capacity, n, o[2], o[3],
-                               ld)
+                               ld, galois=galois)
             torch.cuda.synchronize()
             for gi, o in enumerate(outs):
                 assert torch.equal(o[0][:, :n], o[2][:, :n]) and torch.equal(o[1][:, :n], o[3][:, :n]), (p, gi)
                 assert not o[0][:, n:].any(), (p, gi)          # nothing written past the last entry
             # the oracle on sampled entries (party 0)
             for a, b in ((0, 64), (n - 96, n)) if p == 0 else ():
-                dsh = orc.share(e["dealer"], orc.DOM_SHARE_DB, dc[a:b], dm[a:b], a)
+                share, dot = ((orc.galois_share, orc.galois_local_dot) if galois else (orc.share, orc.local_dot))
+                dom_db, dom_q = ((orc.DOM_GALOIS_DB, orc.DOM_GALOIS_QUERY) if galois
+                                 else (orc.DOM_SHARE_DB, orc.DOM_SHARE_QUERY))
+                dsh = share(e["dealer"], dom_db, dc[a:b], dm[a:b], a)
                 for (qs, rot), o, (q0, q1) in zip(groups, outs, ((0, 20), (20, 50))):
-                    qsh = orc.share(e["dealer"], orc.DOM_SHARE_QUERY, qc[q0:q1], qm[q0:q1], qs.qid_base)
-                    rc, rm = orc.local_dot(p, qsh, rot, dsh)
+                    qsh = share(e["dealer"], dom_q, qc[q0:q1], qm[q0:q1], qs.qid_base)
+                    rc, rm = dot(p, qsh, rot, dsh)
                     assert np.array_equal(_u16(o[0])[:, a:b], rc) and np.array_equal(_u16(o[1])[:, a:b], rm), (p, a)
     finally:
         ctx.set_dot_tiles(imc.DOT_TILES_AUTO)
