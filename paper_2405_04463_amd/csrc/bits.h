@@ -16,17 +16,6 @@ __device__ __forceinline__ uint64_t after(uint64_t pos, uint64_t dep) {
   return (pos & 0xFFFFFFFF00000000ull) | lo;
 }
 
-// `ptr`, tied to `dep` for the compiler only (no instruction): loads through
-// it are not moved ahead of the computation of dep, which keeps their
-// results from being held in registers through the earlier rounds.
-template <typename T>
-__device__ __forceinline__ const T* after_ptr(const T* ptr, uint64_t dep) {
-  const uint64_t v = reinterpret_cast<uint64_t>(ptr);
-  uint32_t lo = uint32_t(v), d = uint32_t(dep);
-  asm volatile("" : "+v"(lo) : "v"(d));
-  return reinterpret_cast<const T*>((v & 0xFFFFFFFF00000000ull) | lo);
-}
-
 __device__ __forceinline__ uint64_t word64(const uint32_t* w, int u) {
   return uint64_t(w[2 * u]) | (uint64_t(w[2 * u + 1]) << 32);
 }

@@ -23,8 +23,6 @@ from . import (CMP_CONST32, CMP_LIFT18, CMP_PLAIN_MASK, OPEN_U8_XOR, OPEN_U16_AD
 COMPARE_SETTINGS = ("mpclift", "lift18", "plain", "constlift", "nolift")
 VECS32 = {"constlift": (1,), "nolift": (0, 1)}   # vectors whose dot products run over Z_2^32
 
-ROW_BYTES = 102400
-
 
 def _dev(device):
     if isinstance(device, torch.device):
