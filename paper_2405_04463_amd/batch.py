@@ -12,7 +12,8 @@ chunk over a row table of all rows ("rows": `imc_dot_shares_rows`).  Either
 way the database streams from HBM once per chunk (per launch) for all
 batches instead of once per batch.
 Resharing, comparison and the OR-tree are elementwise per comparison and run
-per batch on the batch's row range.
+per batch on the batch's row range; the comparisons pass their messages
+through one shared device buffer, as the single check does.
 
 `BatchedStep.capture()` records a whole step in a HIP graph (through torch's
 graph API); `replay()` re-runs it.  Per-batch plain launches (`run_plain`) are
@@ -25,7 +26,8 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from . import MAX_DOT_GROUPS, Context, galois_query_op_bytes, make_ids, or_tree_ws_bytes, query_op_bytes
+from . import (MAX_DOT_GROUPS, Context, compare_msg_bytes, galois_query_op_bytes, make_ids, or_tree_ws_bytes,
+               query_op_bytes)
 
 
 @dataclass
@@ -125,6 +127,10 @@ class BatchedStep:
                     dup=[torch.empty(2, b.q, dtype=torch.uint8, device=d) for _ in range(3)],
                     ws=torch.empty(max(8, or_tree_ws_bytes(b.q, len(b.rot), nw)), dtype=torch.uint8, device=d),
                 ))
+            # the comparisons' network: one message buffer for the largest batch,
+            # shared by the batches' comparisons (they run in stream order)
+            rmax = max(b.rows for b in bs.batches)
+            self.net = torch.empty(compare_msg_bytes(0, rmax, n) // 8, dtype=torch.int64, device=d)
         self.graph = None
 
     def _chunks(self):
@@ -223,7 +229,7 @@ class BatchedStep:
             add_m = [self.dot_mask[p].data_ptr() + 2 * r0 * self.ld for p in range(3)]
             ctx.reshare(add_c, add_m, b.rows, self.n, self.ld, ids, pb["msg"], pb["rep_code"], pb["rep_mask"], stream)
             ctx.compare_threshold(pb["rep_code"], pb["rep_mask"], b.rows, self.n, self.ld, ids, pb["match"], self.nw,
-                                  stream)
+                                  stream, msg_ws=self.net)
             ctx.or_tree(pb["match"], b.q, (self.n + 63) // 64, self.nw, ids, pb["ws"], pb["ws"].numel(), pb["dup"],
                         stream)
 
