@@ -51,7 +51,7 @@ typedef int imc_status;
 #define IMC_ENOMEM (-3)        /* the context could not allocate its own scratch */
 #define IMC_EDEVICE (-4)       /* a HIP call or launch failed */
 #define IMC_ECORRUPT (-5)      /* open with check: the two holders of a component disagree */
-#define IMC_EUNSUPPORTED (-6)  /* a parameter outside what this build implements */
+#define IMC_EUNSUPPORTED (-6)  /* a parameter outside what the library implements */
 
 #define IMC_CODE_BITS 12800
 #define IMC_CODE_WORDS 200
