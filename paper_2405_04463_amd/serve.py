@@ -144,8 +144,14 @@ class Server:
         self.dup = [[torch.empty(2, 1, dtype=torch.uint8, device=d) for _ in range(3)] for _ in range(slots)]
         self.ws = torch.empty(max(8, or_tree_ws_bytes(1, self.R, self.nw_full)), dtype=torch.uint8, device=d)
         assert net in ("buffers", "registers")
-        self.net = (torch.empty(compare_msg_bytes(0, self.R, chunk) // 8, dtype=torch.int64, device=d)
-                    if net == "buffers" and not self.local else None)
+        # the requests' reshare and compare calls of a tick go round-robin to a
+        # few streams (one message buffer each), so that the small per-request
+        # launches fill the GPU together; the main stream waits for all of them
+        # before the next tick's dot products reuse the dot buffers
+        self.side = [] if self.local else [torch.cuda.Stream(device=d) for _ in range(4)]
+        self.nets = [torch.empty(compare_msg_bytes(0, self.R, chunk) // 8, dtype=torch.int64, device=d)
+                     if net == "buffers" else None for _ in self.side]
+        self.net = self.nets[0] if self.nets else None   # the tail pass's (main stream)
         self.open_dev = torch.empty(slots, dtype=torch.uint8, device=d)
         self.open_host = torch.empty(slots, dtype=torch.uint8).pin_memory()
         self.free = list(range(slots))[::-1]
@@ -257,6 +263,12 @@ class Server:
                                          self.db.capacity, first, n_max, self.dot_code[p], self.dot_mask[p], self.ld,
                                          galois=self.galois)
         # per request: reshare and compare its rows into its match buffer
+        main = torch.cuda.current_stream()
+        if self.side:
+            dots_done = torch.cuda.Event()
+            dots_done.record(main)
+            for st in self.side:
+                st.wait_event(dots_done)
         finished = []
         for i, r in enumerate(reqs):
             n_j = min(self.chunk, r.snapshot - first)
@@ -279,12 +291,15 @@ class Server:
             add_c = [self.dot_code[p].data_ptr() + off for p in range(3)]
             add_m = [self.dot_mask[p].data_ptr() + off for p in range(3)]
             s = r.slot
+            k = i % len(self.side)
             self.ctx.reshare(add_c, add_m, self.R, n_w, self.ld, ids, self.msg[s], self.rep_code[s],
-                             self.rep_mask[s])
+                             self.rep_mask[s], self.side[k])
             mw = [m.data_ptr() + 8 * (first // 64) for m in self.match[s]]
             self.ctx.compare_threshold(self.rep_code[s], self.rep_mask[s], self.R, n_w, self.ld, ids, mw,
-                                       self.nw_full, msg_ws=self.net)
+                                       self.nw_full, self.side[k], msg_ws=self.nets[k])
             self.cmps += self.R * n_w
+        for st in self.side:
+            main.wait_stream(st)
         # after every request of the tick has consumed its rows of the shared
         # dot buffers (a tail pass reuses them)
         for r in finished:
