@@ -178,18 +178,24 @@ class Server:
         self.queue.append(req)
 
     def state(self) -> dict:
-        free_b, total_b = torch.cuda.mem_get_info(self.dev)
+        free_b, total_b = self.free_hbm(), torch.cuda.mem_get_info(self.dev)[1]
         return {"queued": len(self.queue), "active": len(self.active), "finishing": len(self.finishing),
                 "done": len(self.done), "free_slots": len(self.free), "cursor": self.cursor, "ticks": self.ticks,
                 "db_n": self.db.n, "hbm_free": free_b, "hbm_total": total_b, "reserve": self.hbm_reserve,
                 "next_arrival": self.queue[0].arrival if self.queue else None, "now": self.now()}
 
     # -------------------------------------------------------------- admission
+    def free_hbm(self) -> int:
+        """Device memory a new request can still get: what the driver has free
+        plus what torch's caching allocator holds unused (buffers of finished
+        requests stay there and are handed out again)."""
+        free_b, _ = torch.cuda.mem_get_info(self.dev)
+        return free_b + torch.cuda.memory_reserved(self.dev) - torch.cuda.memory_allocated(self.dev)
+
     def _admit(self):
         now = self.now()
         while self.queue and self.free and self.queue[0].arrival <= now:
-            free_b, _ = torch.cuda.mem_get_info(self.dev)
-            if free_b - self.request_bytes() < self.hbm_reserve:
+            if self.free_hbm() - self.request_bytes() < self.hbm_reserve:
                 break
             req = self.queue.popleft()
             slot = self.free.pop()
