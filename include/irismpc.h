@@ -270,7 +270,7 @@ imc_status imc_reshare(imc_ctx* ctx, const uint16_t* const add_code[3], const ui
                        size_t rows, size_t n, size_t ld, const imc_ids* ids, uint16_t* const msg[3],
                        uint16_t* const rep_code[3], uint16_t* const rep_mask[3], imc_stream stream);
 
-/* Threshold comparison, MPCLift variant (Alg. 3 lines lift/MSB; Sec. 5.1,
+/* Threshold comparison, MPCLift variant (Alg. 3, its lift and MSB steps; Sec. 5.1,
  * Sec. 5.2; App. D Lift, BitExtract, BitInject, 3OT, ConstLift):
  *   [ml'] = Lift([ml]_{2^16}) to Z_2^32, y = 2^14 [ml'] - ConstLift([dot], 2^16),
  *   [match] = MSB(y)   (match <=> hd/ml < 3/8 <=> 4 dot > ml).
@@ -307,6 +307,53 @@ imc_status imc_compare_threshold(imc_ctx* ctx, const uint16_t* const rep_code[3]
                                  const uint16_t* const rep_mask[3], size_t rows, size_t n, size_t ld,
                                  const imc_ids* ids, void* msg_ws, size_t msg_ws_bytes,
                                  uint64_t* const match[3], size_t mw_ld, imc_stream stream);
+
+/* One query of a reshare or comparison call whose queries are not
+ * consecutive: the requests of one serving tick (Sec. 1: sign-ups checked
+ * as they arrive against the database of the moment), each with its own id,
+ * its own database snapshot and its own match buffer.  A call reads a table
+ * of q of these from device memory; the caller owns it and keeps it
+ * unchanged until the call has completed on its stream. */
+typedef struct imc_query_entry {
+  uint64_t query_id;     /* keys the randomness of the query's rows, as ids->query_id_base + i
+                            does for query i of imc_reshare / imc_compare_threshold */
+  uint64_t n;            /* columns of its rows taken part: [0, min(n, call's n)) */
+  uint64_t* match[3];    /* imc_compare_threshold_queries: party p's match planes of this query,
+                            u64 [2][r][mw_ld] (plane 1 at + r * mw_ld), 8-byte aligned;
+                            ignored by imc_reshare_queries */
+} imc_query_entry;
+
+/* imc_reshare over the rows of q queries that each carry their own id and
+ * column count (table: device, q entries): rows i*r .. i*r + r - 1 of every
+ * plane belong to table[i], and the call writes exactly what imc_reshare
+ * writes for those rows with query_id_base = table[i].query_id and
+ * n = min(table[i].n, n) (columns past that are left untouched).  ids gives
+ * r, the rotations and first_entry_id; its query_id_base is ignored.
+ * Planes as in imc_reshare, with rows = q * r.  One launch for all q queries.
+ * Errors: as imc_reshare, plus IMC_EINVAL for a NULL or unaligned table. */
+imc_status imc_reshare_queries(imc_ctx* ctx, const uint16_t* const add_code[3], const uint16_t* const add_mask[3],
+                               size_t q, size_t n, size_t ld, const imc_ids* ids, const imc_query_entry* table,
+                               uint16_t* const msg[3], uint16_t* const rep_code[3], uint16_t* const rep_mask[3],
+                               imc_stream stream);
+
+/* imc_compare_threshold over the rows of q queries that each carry their own
+ * id, column count and match buffer (table: device, q entries): query i's
+ * rows i*r .. of rep_code / rep_mask are compared exactly as a call of
+ * imc_compare_threshold with query_id_base = table[i].query_id,
+ * n = min(table[i].n, n) and match = table[i].match would, and its match
+ * words are written there (words past ceil(n_i/64) are left untouched, the
+ * last one masked to n_i).  rep_code / rep_mask: [2][q*r][ld] as written by
+ * imc_reshare_queries.  msg_ws: NULL (register simulation) or a message
+ * buffer holding at least one query's messages,
+ * imc_compare_msg_bytes(0, r, n); the call then runs as few launches as the
+ * buffer allows, each over as many whole queries as fit in it (every launch
+ * reuses the buffer; on return it holds the last launch's messages).
+ * Errors: as imc_compare_threshold, plus IMC_EINVAL for a NULL or unaligned
+ * table and IMC_ESHAPE for a buffer smaller than one query's messages. */
+imc_status imc_compare_threshold_queries(imc_ctx* ctx, const uint16_t* const rep_code[3],
+                                         const uint16_t* const rep_mask[3], size_t q, size_t n, size_t ld,
+                                         const imc_ids* ids, const imc_query_entry* table, void* msg_ws,
+                                         size_t msg_ws_bytes, size_t mw_ld, imc_stream stream);
 
 /* Bytes of the message buffer of a comparison call over rows x n
  * comparisons: planes x 64 x ceil(rows * ceil(n/64) / 64) u64, with

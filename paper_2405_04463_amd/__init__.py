@@ -30,7 +30,7 @@ EXPORTS = [
     "imc_galois_dot_shares_gather", "imc_compare_variant", "imc_rotate_masks", "imc_plain_ml", "imc_db32_bytes",
     "imc_query32_op_bytes", "imc_share32_db", "imc_share32_query", "imc_dot32_shares", "imc_reshare32",
     "imc_dot_shares_rows_noalloc", "imc_compare_msg_bytes", "imc_or_pairs", "imc_dot_shares_groups",
-    "imc_galois_dot_shares_groups",
+    "imc_galois_dot_shares_groups", "imc_reshare_queries", "imc_compare_threshold_queries",
 ]
 
 (DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW, DOT_TILES_ROTATION,
@@ -113,6 +113,9 @@ def lib():
         L.imc_dot_shares.argtypes = [_VP, ctypes.c_int, _VP, sz, ctypes.POINTER(imc_ids), _VP, sz, sz, _VP, _VP, sz, _VP]
         L.imc_reshare.argtypes = [_VP, _P3, _VP, sz, sz, sz, ctypes.POINTER(imc_ids), _P3, _P3, _VP, _VP]
         L.imc_compare_threshold.argtypes = [_VP, _P3, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, sz, _P3, sz, _VP]
+        L.imc_reshare_queries.argtypes = [_VP, _P3, _VP, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, _P3, _P3, _VP, _VP]
+        L.imc_compare_threshold_queries.argtypes = [_VP, _P3, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, _VP, sz,
+                                                    sz, _VP]
         L.imc_compare_msg_bytes.argtypes = [ctypes.c_int, sz, sz]
         L.imc_compare_msg_bytes.restype = sz
         L.imc_or_tree.argtypes = [_VP, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, sz, _P3, _VP]
@@ -185,6 +188,25 @@ def _stream(stream) -> int | None:
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+QUERY_ENTRY_WORDS = 5   # imc_query_entry: query_id, n, match[3] (u64 each)
+
+
+def query_table(entries, out=None):
+    """Pack imc_query_entry rows: entries = [(query_id, n, (match0, match1, match2)), ...] with match
+    pointers as tensors, addresses or None.  Returns (or fills) an int64 tensor [q][5] on the host;
+    the caller copies it to the device."""
+    import torch
+
+    t = out if out is not None else torch.empty(len(entries), QUERY_ENTRY_WORDS, dtype=torch.int64)
+    vals = []
+    for qid, n, m3 in entries:
+        ptrs = [addr(m) or 0 for m in (m3 if m3 is not None else (None, None, None))]
+        vals.append([qid, n] + [x - (1 << 64) if x >= (1 << 63) else x for x in ptrs])
+    if vals:
+        t[:len(vals)] = torch.tensor(vals, dtype=torch.int64)
+    return t
 
 
 def make_ids(query_id_base: int, rot, first_entry_id: int = 0) -> imc_ids:
@@ -387,6 +409,24 @@ class Context:
         return _check(lib().imc_compare_threshold(self._h, _p3(rep_code3), _p3(rep_mask3), rows, n, ld,
                                                   ctypes.byref(ids), addr(msg_ws), mb, _p3(match3), mw_ld,
                                                   _stream(stream)), "imc_compare_threshold")
+
+    # -- imc_reshare_queries / imc_compare_threshold_queries: the rows of q queries that each carry
+    #    their own id, column count and match buffer (table: device tensor of q imc_query_entry rows,
+    #    see query_table)
+    def reshare_queries(self, add_code3, add_mask3, q, n, ld, ids: imc_ids, table, msg3, rep_code3, rep_mask3,
+                        stream=None):
+        am = ctypes.cast(_p3(add_mask3), _VP) if add_mask3 is not None else None
+        rm = ctypes.cast(_p3(rep_mask3), _VP) if rep_mask3 is not None else None
+        return _check(lib().imc_reshare_queries(self._h, _p3(add_code3), am, q, n, ld, ctypes.byref(ids), addr(table),
+                                                _p3(msg3), _p3(rep_code3), rm, _stream(stream)),
+                      "imc_reshare_queries")
+
+    def compare_threshold_queries(self, rep_code3, rep_mask3, q, n, ld, ids: imc_ids, table, mw_ld, stream=None,
+                                  msg_ws=None):
+        mb = msg_ws.numel() * msg_ws.element_size() if msg_ws is not None else 0
+        return _check(lib().imc_compare_threshold_queries(self._h, _p3(rep_code3), _p3(rep_mask3), q, n, ld,
+                                                          ctypes.byref(ids), addr(table), addr(msg_ws), mb, mw_ld,
+                                                          _stream(stream)), "imc_compare_threshold_queries")
 
     # -- imc_or_tree
     def or_tree(self, match3, q, nw, mw_ld, ids: imc_ids, ws, ws_bytes, dup3, stream=None):

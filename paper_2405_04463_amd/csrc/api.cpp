@@ -3,7 +3,9 @@
 // here, before anything is enqueued.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -519,6 +521,84 @@ imc_status imc_compare_threshold(imc_ctx* c, const uint16_t* const rep_code[3], 
   }
   return dev_status(imc::launch_compare(c->party, rep_code, rep_mask, rows, n, ld, *ids, match, mw_ld,
                                         hipStream_t(stream)));
+}
+
+static_assert(sizeof(imc_query_entry) == 40 && offsetof(imc_query_entry, match) == 16, "query entry layout");
+
+imc_status imc_reshare_queries(imc_ctx* c, const uint16_t* const add_code[3], const uint16_t* const add_mask[3],
+                               size_t q, size_t n, size_t ld, const imc_ids* ids, const imc_query_entry* table,
+                               uint16_t* const msg[3], uint16_t* const rep_code[3], uint16_t* const rep_mask[3],
+                               imc_stream stream) {
+  if (!c || !add_code || !msg || !rep_code) return IMC_EINVAL;
+  if (add_mask && !rep_mask) return IMC_EINVAL;
+  if (!table || !aligned(table, 8)) return IMC_EINVAL;
+  imc_status st = check_ids(ids);
+  if (st != IMC_OK) return st;
+  if (ld < n || q >= (size_t(1) << 31)) return IMC_ESHAPE;
+  const size_t rows = q * size_t(ids->r);
+  if (rows == 0 || n == 0) return IMC_OK;
+  const size_t va = ld % 8 == 0 ? 16 : 2;
+  for (int p = 0; p < 3; ++p) {
+    if (!add_code[p] || !msg[p] || !rep_code[p]) return IMC_EINVAL;
+    if (add_mask && (!add_mask[p] || !rep_mask[p])) return IMC_EINVAL;
+    if (!aligned(add_code[p], va) || !aligned(msg[p], va) || !aligned(rep_code[p], va)) return IMC_EINVAL;
+    if (add_mask && (!aligned(add_mask[p], va) || !aligned(rep_mask[p], va))) return IMC_EINVAL;
+  }
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  imc::QueryTab qt;
+  qt.tab = table;
+  return dev_status(imc::launch_reshare(c->party, add_code, add_mask, rows, n, ld, *ids, msg, rep_code, rep_mask,
+                                        hipStream_t(stream), qt));
+}
+
+imc_status imc_compare_threshold_queries(imc_ctx* c, const uint16_t* const rep_code[3],
+                                         const uint16_t* const rep_mask[3], size_t q, size_t n, size_t ld,
+                                         const imc_ids* ids, const imc_query_entry* table, void* msg_ws,
+                                         size_t msg_ws_bytes, size_t mw_ld, imc_stream stream) {
+  if (!c || !rep_code || !rep_mask) return IMC_EINVAL;
+  if (!table || !aligned(table, 8)) return IMC_EINVAL;
+  imc_status st = check_ids(ids);
+  if (st != IMC_OK) return st;
+  if (ld < n || mw_ld < (n + 63) / 64 || q >= (size_t(1) << 31)) return IMC_ESHAPE;
+  const size_t r = size_t(ids->r), rows = q * r;
+  if (rows == 0 || n == 0) return IMC_OK;
+  const size_t va = ld % 8 == 0 ? 16 : 2;
+  for (int p = 0; p < 3; ++p) {
+    if (!rep_code[p] || !rep_mask[p]) return IMC_EINVAL;
+    if (!aligned(rep_code[p], va) || !aligned(rep_mask[p], va)) return IMC_EINVAL;
+  }
+  if (msg_ws) {
+    if (!aligned(msg_ws, 8)) return IMC_EINVAL;
+    if (msg_ws_bytes < imc_compare_msg_bytes(0, r, n)) return IMC_ESHAPE;
+  }
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  uint64_t* const no_match[3] = {nullptr, nullptr, nullptr};   // each query's come from the table
+  imc::QueryTab qt;
+  qt.tab = table;
+  if (!msg_ws)
+    return dev_status(imc::launch_compare(c->party, rep_code, rep_mask, rows, n, ld, *ids, no_match, mw_ld,
+                                          hipStream_t(stream), qt));
+  // launches of as many whole queries as the buffer's workgroup blocks hold
+  const size_t nw = (n + 63) / 64;
+  const size_t blocks = msg_ws_bytes / (imc::compare_msg_planes(0) * 64 * sizeof(uint64_t));
+  const size_t per = std::min(q, blocks * 64 / nw / r);   // >= 1: the buffer holds one query
+  qt.plane_rows = rows;
+  for (size_t q0 = 0; q0 < q; q0 += per) {
+    const size_t k = std::min(per, q - q0);
+    const void* code[3], *mask[3];
+    for (int p = 0; p < 3; ++p) {
+      code[p] = rep_code[p] + q0 * r * ld;
+      mask[p] = rep_mask[p] + q0 * r * ld;
+    }
+    qt.tab = table + q0;
+    const imc_status e = dev_status(imc::launch_compare_msg(0, c->party, code, false, mask, nullptr, k * r, n, ld,
+                                                            *ids, no_match, mw_ld, static_cast<uint64_t*>(msg_ws),
+                                                            hipStream_t(stream), qt));
+    if (e != IMC_OK) return e;
+  }
+  return IMC_OK;
 }
 
 imc_status imc_compare_variant(imc_ctx* c, int variant, const void* const rep_code[3], int code_bits,

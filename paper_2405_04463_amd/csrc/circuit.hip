@@ -138,6 +138,7 @@ struct CmpArgs {
   const uint16_t* code[3];   // rep_code[p] plane 0 (party p's own component)
   const uint16_t* mask[3];
   uint64_t* match[3];        // [2][rows][mw_ld]
+  const imc_query_entry* tab;  // optional: per-query id, column count and match planes
   uint64_t ld, mw_ld, n, nw, rows, plane_elems, match_plane;
   uint64_t qid_base, first_entry;
   int32_t r;
@@ -149,9 +150,15 @@ __global__ void __launch_bounds__(256) compare_kernel(CmpArgs a) {
   if (t >= a.rows * a.nw) return;
   const uint64_t row = t / a.nw, w = t % a.nw;
   const uint64_t col0 = w * 64;
-  const int nval = int(min<uint64_t>(64, a.n - col0));
+  const uint64_t qi = row / uint64_t(a.r);
+  uint64_t qid = a.qid_base + qi, n = a.n;
+  if (a.tab) {
+    qid = a.tab[qi].query_id;
+    n = min<uint64_t>(n, a.tab[qi].n);
+    if (col0 >= n) return;
+  }
+  const int nval = int(min<uint64_t>(64, n - col0));
   const bool vec_ok = (a.ld % 8) == 0;
-  const uint64_t qid = a.qid_base + row / uint64_t(a.r);
   const int rot = a.rot[row % uint64_t(a.r)];
   const uint64_t stream = row_stream(kDomCmp, qid, rot);
   const uint64_t base = ((a.first_entry >> 6) + w) * kTapeBlocksPerGroup;
@@ -237,8 +244,10 @@ __global__ void __launch_bounds__(256) compare_kernel(CmpArgs a) {
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
     const int pm = (p + 2) % 3;
-    a.match[p][row * a.mw_ld + w] = r.c[p] & keep;
-    a.match[p][a.match_plane + row * a.mw_ld + w] = r.c[pm] & keep;
+    uint64_t* m = a.tab ? a.tab[qi].match[p] + (row % uint64_t(a.r)) * a.mw_ld : a.match[p] + row * a.mw_ld;
+    const uint64_t plane = a.tab ? uint64_t(a.r) * a.mw_ld : a.match_plane;
+    m[w] = r.c[p] & keep;
+    m[plane + w] = r.c[pm] & keep;
   }
 }
 
@@ -507,6 +516,7 @@ struct ReshareArgs {
   uint16_t* msg[3];          // [2][rows][ld]
   uint16_t* rep_code[3];     // [2][rows][ld]
   uint16_t* rep_mask[3];
+  const imc_query_entry* tab;  // optional: per-query id and column count
   uint64_t ld, n, rows, plane;
   uint64_t qid_base, first_entry;
   int32_t r;
@@ -544,12 +554,18 @@ __global__ void __launch_bounds__(256) reshare_kernel(ReshareArgs a) {
   const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= a.rows * nc) return;
   const uint64_t row = t / nc, c = t % nc;
-  const uint64_t qid = a.qid_base + row / uint64_t(a.r);
+  const uint64_t qi = row / uint64_t(a.r);
+  uint64_t qid = a.qid_base + qi, n = a.n;
+  const uint64_t col0 = 16 * c;
+  if (a.tab) {
+    qid = a.tab[qi].query_id;
+    n = min<uint64_t>(n, a.tab[qi].n);
+    if (col0 >= n) return;
+  }
   const int rot = a.rot[row % uint64_t(a.r)];
   const uint64_t stream = row_stream(kDomReshare, qid, rot);
   const uint64_t e0 = a.first_entry + 16 * c;
-  const uint64_t col0 = 16 * c;
-  const int nval = int(min<uint64_t>(16, a.n - col0));
+  const int nval = int(min<uint64_t>(16, n - col0));
   const uint64_t off = row * a.ld + col0;
   const bool vec = (a.ld % 8) == 0;
   const bool with_mask = a.add_mask[0] != nullptr;   // no mask dot when masks are public
@@ -767,9 +783,11 @@ static void fill_rot(int8_t* dst, const imc_ids_dev& ids) {
 
 hipError_t launch_reshare(const Keys3& keys, const uint16_t* const add_code[3], const uint16_t* const add_mask[3],
                           uint64_t rows, uint64_t n, uint64_t ld, const imc_ids_dev& ids, uint16_t* const msg[3],
-                          uint16_t* const rep_code[3], uint16_t* const rep_mask[3], hipStream_t s) {
+                          uint16_t* const rep_code[3], uint16_t* const rep_mask[3], hipStream_t s,
+                          const QueryTab& qt) {
   if (rows == 0 || n == 0) return hipSuccess;
   ReshareArgs a;
+  a.tab = qt.tab;
   a.keys = keys;
   for (int p = 0; p < 3; ++p) {
     a.add_code[p] = add_code[p];
@@ -781,7 +799,7 @@ hipError_t launch_reshare(const Keys3& keys, const uint16_t* const add_code[3], 
   a.ld = ld;
   a.n = n;
   a.rows = rows;
-  a.plane = rows * ld;
+  a.plane = (qt.plane_rows ? qt.plane_rows : rows) * ld;
   a.qid_base = ids.query_id_base;
   a.first_entry = ids.first_entry_id;
   a.r = ids.r;
@@ -794,9 +812,10 @@ hipError_t launch_reshare(const Keys3& keys, const uint16_t* const add_code[3], 
 
 hipError_t launch_compare(const Keys3& keys, const uint16_t* const rep_code[3], const uint16_t* const rep_mask[3],
                           uint64_t rows, uint64_t n, uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3],
-                          uint64_t mw_ld, hipStream_t s) {
+                          uint64_t mw_ld, hipStream_t s, const QueryTab& qt) {
   if (rows == 0 || n == 0) return hipSuccess;
   CmpArgs a;
+  a.tab = qt.tab;
   a.keys = keys;
   for (int p = 0; p < 3; ++p) {
     a.code[p] = rep_code[p];
@@ -808,7 +827,7 @@ hipError_t launch_compare(const Keys3& keys, const uint16_t* const rep_code[3], 
   a.n = n;
   a.nw = (n + 63) / 64;
   a.rows = rows;
-  a.plane_elems = rows * ld;
+  a.plane_elems = (qt.plane_rows ? qt.plane_rows : rows) * ld;
   a.match_plane = rows * mw_ld;
   a.qid_base = ids.query_id_base;
   a.first_entry = ids.first_entry_id;

@@ -293,6 +293,7 @@ struct CmpMsgArgs {
   const void* mask[3];       // rep_mask[p] likewise (MPCLift, Lift18, Const32)
   const uint16_t* ml_pub;    // [rows][ld] public ml (Plain)
   uint64_t* match[3];        // [2][rows][mw_ld]
+  const imc_query_entry* tab;  // optional: per-query id, column count and match planes
   uint64_t* msg;             // [workgroup][planes][64]
   uint64_t ld, mw_ld, n, nw, rows, plane_elems, match_plane;
   uint64_t qid_base, first_entry;
@@ -345,9 +346,12 @@ struct MpcliftY {
 __device__ __forceinline__ int party_of_wave() { return __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)); }
 
 // Lanes past the last word work on word 0 (in bounds) and store nothing.
+// A lane's match word: row, word, its query's id and columns.  With a query
+// table, a word at or past its query's column count is inactive (it still
+// reads in-range inputs and takes part in every barrier).
 struct Lane {
   bool active;
-  uint64_t row, w, col0;
+  uint64_t row, w, col0, qid;
   int nval;
 };
 __device__ __forceinline__ Lane lane_of(const CmpMsgArgs& a) {
@@ -358,15 +362,33 @@ __device__ __forceinline__ Lane lane_of(const CmpMsgArgs& a) {
   l.row = tt / a.nw;
   l.w = tt % a.nw;
   l.col0 = l.w * 64;
-  l.nval = int(min<uint64_t>(64, a.n - l.col0));
+  const uint64_t qi = l.row / uint64_t(a.r);
+  uint64_t n = a.n;
+  l.qid = a.qid_base + qi;
+  if (a.tab) {
+    l.qid = a.tab[qi].query_id;
+    const uint64_t nq = min<uint64_t>(n, a.tab[qi].n);
+    if (l.col0 < nq) n = nq;
+    else l.active = false;
+  }
+  l.nval = int(min<uint64_t>(64, n - l.col0));
   return l;
 }
 
 __device__ __forceinline__ void store_match(const CmpMsgArgs& a, int p, const Lane& l, PV r) {
   if (!l.active) return;
   const uint64_t keep = l.nval == 64 ? ~0ull : ((1ull << l.nval) - 1ull);
-  a.match[p][l.row * a.mw_ld + l.w] = r.o & keep;
-  a.match[p][a.match_plane + l.row * a.mw_ld + l.w] = r.v & keep;
+  uint64_t* m;
+  uint64_t plane;
+  if (a.tab) {
+    m = a.tab[l.row / uint64_t(a.r)].match[p] + (l.row % uint64_t(a.r)) * a.mw_ld;
+    plane = uint64_t(a.r) * a.mw_ld;
+  } else {
+    m = a.match[p] + l.row * a.mw_ld;
+    plane = a.match_plane;
+  }
+  m[l.w] = r.o & keep;
+  m[plane + l.w] = r.v & keep;
 }
 
 // MPCLift (Sec. 5.1-5.2): Lift ml to Z_2^32 (BitExtract m = 17 on words
@@ -379,8 +401,7 @@ __global__ void __launch_bounds__(192) compare_msg_kernel(CmpMsgArgs a) {
   const int p = party_of_wave(), pm = (p + 2) % 3;
   const Lane l = lane_of(a);
   const bool vec_ok = (a.ld % 8) == 0;
-  const uint64_t qid = a.qid_base + l.row / uint64_t(a.r);
-  const uint64_t stream = row_stream(kDomCmp, qid, a.rot[l.row % uint64_t(a.r)]);
+  const uint64_t stream = row_stream(kDomCmp, l.qid, a.rot[l.row % uint64_t(a.r)]);
   const uint64_t base = ((a.first_entry >> 6) + l.w) * kTapeBlocksPerGroup;
   const Key& ko = a.keys.k[p];
   const Key& kv = a.keys.k[pm];
@@ -560,9 +581,8 @@ __global__ void __launch_bounds__(192) compare_msg_variant_kernel(CmpMsgArgs a) 
   const int p = party_of_wave(), pm = (p + 2) % 3;
   const Lane l = lane_of(a);
   const bool vec_ok = a.vec != 0;
-  const uint64_t qid = a.qid_base + l.row / uint64_t(a.r);
   const uint32_t dom = V == 1 ? kDomCmpPlain : V == 2 ? kDomCmpLift18 : kDomCmpConst32;
-  const uint64_t stream = row_stream(dom, qid, a.rot[l.row % uint64_t(a.r)]);
+  const uint64_t stream = row_stream(dom, l.qid, a.rot[l.row % uint64_t(a.r)]);
   const uint64_t base = ((a.first_entry >> 6) + l.w) * kTapeBlocksPerGroup;
   const Key& ko = a.keys.k[p];
   const Key& kv = a.keys.k[pm];
@@ -647,9 +667,10 @@ size_t compare_msg_planes(int variant) {
 hipError_t launch_compare_msg(int variant, const Keys3& keys, const void* const rep_code[3], bool code32,
                               const void* const rep_mask[3], const uint16_t* ml_pub, uint64_t rows, uint64_t n,
                               uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3], uint64_t mw_ld,
-                              uint64_t* msg, hipStream_t s) {
+                              uint64_t* msg, hipStream_t s, const QueryTab& qt) {
   if (rows == 0 || n == 0) return hipSuccess;
   CmpMsgArgs a;
+  a.tab = qt.tab;
   a.keys = keys;
   for (int p = 0; p < 3; ++p) {
     a.code[p] = rep_code[p];
@@ -663,7 +684,7 @@ hipError_t launch_compare_msg(int variant, const Keys3& keys, const void* const 
   a.n = n;
   a.nw = (n + 63) / 64;
   a.rows = rows;
-  a.plane_elems = rows * ld;
+  a.plane_elems = (qt.plane_rows ? qt.plane_rows : rows) * ld;
   a.match_plane = rows * mw_ld;
   a.qid_base = ids.query_id_base;
   a.first_entry = ids.first_entry_id;

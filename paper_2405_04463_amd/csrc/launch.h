@@ -52,12 +52,21 @@ hipError_t launch_dot(const int8_t* a, uint32_t rows, uint32_t a_blocks, const i
                       uint64_t n, uint16_t* code, uint16_t* mask, uint64_t ld, hipStream_t s, int variant,
                       bool galois);
 
+// A call's optional table of per-query ids, column counts and match buffers
+// (imc_query_entry, one per query of the launch), and the row count of the
+// planes' allocation when a launch covers only some of its rows (plane 1
+// of an input at plane_rows * ld; 0: the launch's own rows).
+struct QueryTab {
+  const imc_query_entry* tab = nullptr;
+  uint64_t plane_rows = 0;
+};
 hipError_t launch_reshare(const Keys3& keys, const uint16_t* const add_code[3], const uint16_t* const add_mask[3],
                           uint64_t rows, uint64_t n, uint64_t ld, const imc_ids_dev& ids, uint16_t* const msg[3],
-                          uint16_t* const rep_code[3], uint16_t* const rep_mask[3], hipStream_t s);
+                          uint16_t* const rep_code[3], uint16_t* const rep_mask[3], hipStream_t s,
+                          const QueryTab& qt = QueryTab{});
 hipError_t launch_compare(const Keys3& keys, const uint16_t* const rep_code[3], const uint16_t* const rep_mask[3],
                           uint64_t rows, uint64_t n, uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3],
-                          uint64_t mw_ld, hipStream_t s);
+                          uint64_t mw_ld, hipStream_t s, const QueryTab& qt = QueryTab{});
 hipError_t launch_compare_variant(int variant, const Keys3& keys, const void* const rep_code[3], bool code32,
                                   const void* const rep_mask[3], const uint16_t* ml_pub, uint64_t rows, uint64_t n,
                                   uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3], uint64_t mw_ld,
@@ -66,7 +75,7 @@ size_t compare_msg_planes(int variant);
 hipError_t launch_compare_msg(int variant, const Keys3& keys, const void* const rep_code[3], bool code32,
                               const void* const rep_mask[3], const uint16_t* ml_pub, uint64_t rows, uint64_t n,
                               uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3], uint64_t mw_ld,
-                              uint64_t* msg, hipStream_t s);
+                              uint64_t* msg, hipStream_t s, const QueryTab& qt = QueryTab{});
 hipError_t launch_rotate_masks(const uint64_t* masks, uint64_t q, const imc_ids_dev& ids, uint64_t* out,
                                hipStream_t s);
 hipError_t launch_plain_ml(const uint64_t* row_masks, uint64_t rows, const uint64_t* db_masks, uint64_t n,

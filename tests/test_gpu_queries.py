@@ -1,0 +1,161 @@
+"""Reshare and comparison over the rows of queries that each carry their own
+id, column count and match buffer (one call for a serving tick's requests):
+every component equals the oracle's resharing and comparison of that query
+alone, and the one-query-per-call C functions; columns and match words past
+a query's count are left untouched; a message buffer that holds only some
+of the queries gives the same results in several launches."""
+import numpy as np
+import pytest
+
+import oracle as orc
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SENT16 = 0x5A5A
+SENT64 = 0x3C3C3C3C3C3C3C3C
+
+
+@pytest.fixture(scope="module")
+def imc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_04463_amd as imc_mod
+
+    imc_mod.lib()
+    return imc_mod
+
+
+def _setup(imc, keys, n=300, ld=304):
+    dealer, party = keys
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=64)
+    rot = [-1, 0, 2]
+    r = len(rot)
+    qids = [901, 17, 4242, 5, 77777]
+    ns = [300, 256, 64, 300, 128]            # the call's n (ragged), whole words, one word
+    q = len(qids)
+    rng = np.random.default_rng(77)
+    zc = rng.integers(0, 1 << 16, size=(3, q * r, ld), dtype=np.uint16)
+    zm = rng.integers(0, 1 << 16, size=(3, q * r, ld), dtype=np.uint16)
+    dev = lambda a: torch.from_numpy(a.view(np.int16).copy()).cuda()   # noqa: E731
+    add_c = [dev(zc[p]) for p in range(3)]
+    add_m = [dev(zm[p]) for p in range(3)]
+    return ctx, party, rot, r, qids, ns, q, zc, zm, add_c, add_m, n, ld
+
+
+def _planes(q, r, ld):
+    return [torch.full((2, q * r, ld), SENT16, dtype=torch.int16, device="cuda") for _ in range(3)]
+
+
+def _table(imc, qids, ns, match):
+    t = imc.query_table([(qid, nn, m3) for qid, nn, m3 in zip(qids, ns, match)])
+    return t.cuda()
+
+
+def test_queries_match_oracle_and_single_calls(imc, keys):
+    ctx, party, rot, r, qids, ns, q, zc, zm, add_c, add_m, n, ld = _setup(imc, keys)
+    first = 128
+    mw_ld = 6
+    ids = imc.make_ids(0, rot, first)
+    msg, rep_c, rep_m = _planes(q, r, ld), _planes(q, r, ld), _planes(q, r, ld)
+    match = [[torch.full((2, r, mw_ld), SENT64, dtype=torch.int64, device="cuda") for _ in range(3)]
+             for _ in range(q)]
+    table = _table(imc, qids, ns, match)
+    ctx.reshare_queries(add_c, add_m, q, n, ld, ids, table, msg, rep_c, rep_m)
+    net = torch.empty(imc.compare_msg_bytes(0, q * r, n) // 8, dtype=torch.int64, device="cuda")
+    ctx.compare_threshold_queries(rep_c, rep_m, q, n, ld, ids, table, mw_ld, msg_ws=net)
+    torch.cuda.synchronize()
+    host = lambda t: t.cpu().numpy().view(np.uint16)   # noqa: E731
+    for i, (qid, ni) in enumerate(zip(qids, ns)):
+        rows = slice(i * r, (i + 1) * r)
+        oc, om = orc.reshare(party, np.ascontiguousarray(zc[:, rows, :ni]), np.ascontiguousarray(zm[:, rows, :ni]),
+                             1, rot, qid, first)
+        for p in range(3):
+            pm = (p + 2) % 3
+            rc, rm, mg = host(rep_c[p]), host(rep_m[p]), host(msg[p])
+            assert np.array_equal(rc[0, rows, :ni], oc[p]) and np.array_equal(rc[1, rows, :ni], oc[pm]), (i, p)
+            assert np.array_equal(rm[0, rows, :ni], om[p]) and np.array_equal(rm[1, rows, :ni], om[pm]), (i, p)
+            assert np.array_equal(mg[0, rows, :ni], oc[p]) and np.array_equal(mg[1, rows, :ni], om[p]), (i, p)
+            for a in (rc, rm, mg):                  # columns past the query's count are untouched
+                assert (a[:, rows, ni:] == SENT16).all(), (i, p)
+        want = orc.compare(party, oc, om, 1, rot, qid, first)
+        nw = (ni + 63) // 64
+        for p in range(3):
+            pm = (p + 2) % 3
+            got = match[i][p].cpu().numpy().view(np.uint64)
+            assert np.array_equal(got[0, :, :nw], want[p]) and np.array_equal(got[1, :, :nw], want[pm]), (i, p)
+            assert (got[:, :, nw:] == np.uint64(SENT64)).all(), (i, p)
+
+    # the same rows through one call per query (rows, columns and ids of that query alone)
+    for i, (qid, ni) in enumerate(zip(qids, ns)):
+        idq = imc.make_ids(qid, rot, first)
+        off = i * r * ld * 2
+        m1, r1c, r1m = _planes(1, r, ld), _planes(1, r, ld), _planes(1, r, ld)
+        ctx.reshare([t.data_ptr() + off for t in add_c], [t.data_ptr() + off for t in add_m], r, ni, ld, idq, m1,
+                    r1c, r1m)
+        m3 = [torch.zeros(2, r, mw_ld, dtype=torch.int64, device="cuda") for _ in range(3)]
+        ctx.compare_threshold(r1c, r1m, r, ni, ld, idq, m3, mw_ld)
+        torch.cuda.synchronize()
+        nw = (ni + 63) // 64
+        for p in range(3):
+            assert torch.equal(r1c[p][:, :, :ni], rep_c[p][:, i * r:(i + 1) * r, :ni]), (i, p)
+            assert torch.equal(m3[p][:, :, :nw], match[i][p][:, :, :nw]), (i, p)
+    ctx.close()
+
+
+@pytest.mark.parametrize("fit", [1, 2, None])
+def test_queries_in_slices_of_the_message_buffer(imc, keys, fit):
+    """A buffer for `fit` queries (None: no buffer, messages in registers)
+    gives the same match words as one for all of them."""
+    ctx, party, rot, r, qids, ns, q, zc, zm, add_c, add_m, n, ld = _setup(imc, keys)
+    first = 0
+    mw_ld = 5
+    ids = imc.make_ids(0, rot, first)
+    msg, rep_c, rep_m = _planes(q, r, ld), _planes(q, r, ld), _planes(q, r, ld)
+    ref = [[torch.zeros(2, r, mw_ld, dtype=torch.int64, device="cuda") for _ in range(3)] for _ in range(q)]
+    got = [[torch.zeros(2, r, mw_ld, dtype=torch.int64, device="cuda") for _ in range(3)] for _ in range(q)]
+    t_ref, t_got = _table(imc, qids, ns, ref), _table(imc, qids, ns, got)
+    ctx.reshare_queries(add_c, add_m, q, n, ld, ids, t_ref, msg, rep_c, rep_m)
+    full = torch.empty(imc.compare_msg_bytes(0, q * r, n) // 8, dtype=torch.int64, device="cuda")
+    ctx.compare_threshold_queries(rep_c, rep_m, q, n, ld, ids, t_ref, mw_ld, msg_ws=full)
+    small = None
+    if fit is not None:
+        small = torch.empty(imc.compare_msg_bytes(0, fit * r, n) // 8, dtype=torch.int64, device="cuda")
+    ctx.compare_threshold_queries(rep_c, rep_m, q, n, ld, ids, t_got, mw_ld, msg_ws=small)
+    torch.cuda.synchronize()
+    for i in range(q):
+        for p in range(3):
+            assert torch.equal(ref[i][p], got[i][p]), (fit, i, p)
+    # the oracle's log of the last query's messages is what a one-query buffer holds at the end
+    if fit == 1:
+        oc, om = orc.reshare(party, np.ascontiguousarray(zc[:, -r:, :ns[-1]]),
+                             np.ascontiguousarray(zm[:, -r:, :ns[-1]]), 1, rot, qids[-1], first)
+        _, log = orc.compare(party, oc, om, 1, rot, qids[-1], first, want_msg=True)
+        nwq, nwc = (ns[-1] + 63) // 64, (n + 63) // 64   # the query's words; the call's words per row
+        planes = imc.compare_msg_bytes(0, 64, 64 * 64) // (64 * 64 * 8)   # 406
+        words = small.cpu().numpy().view(np.uint64)
+        for row in range(r):
+            for w in range(nwq):                    # word t of the last launch = row * nwc + w
+                t = row * nwc + w
+                blk = words[(t // 64) * planes * 64:(t // 64 + 1) * planes * 64].reshape(planes, 64)[:, t % 64]
+                assert np.array_equal(blk, log[:, row, w]), (row, w)
+    ctx.close()
+
+
+def test_queries_argument_errors(imc, keys):
+    ctx, party, rot, r, qids, ns, q, zc, zm, add_c, add_m, n, ld = _setup(imc, keys)
+    ids = imc.make_ids(0, rot, 0)
+    msg, rep_c, rep_m = _planes(q, r, ld), _planes(q, r, ld), _planes(q, r, ld)
+    with pytest.raises(imc.IMCError) as e:
+        ctx.reshare_queries(add_c, add_m, q, n, ld, ids, None, msg, rep_c, rep_m)
+    assert e.value.status == imc.IMC_EINVAL
+    match = [[torch.zeros(2, r, 5, dtype=torch.int64, device="cuda") for _ in range(3)] for _ in range(q)]
+    table = _table(imc, qids, ns, match)
+    tiny = torch.empty(imc.compare_msg_bytes(0, r, n) // 8 - 1, dtype=torch.int64, device="cuda")
+    with pytest.raises(imc.IMCError) as e:
+        ctx.compare_threshold_queries(rep_c, rep_m, q, n, ld, ids, table, 5, msg_ws=tiny)   # under one query
+    assert e.value.status == imc.IMC_ESHAPE
+    with pytest.raises(imc.IMCError) as e:
+        ctx.compare_threshold_queries(rep_c, rep_m, q, n, ld, ids, table, 4, msg_ws=None)   # mw_ld < ceil(n/64)
+    assert e.value.status == imc.IMC_ESHAPE
+    ctx.close()
