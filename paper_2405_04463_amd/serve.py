@@ -5,9 +5,12 @@ The database shares stay resident in HBM, split into fixed chunks of `chunk`
 entries (a multiple of 64).  A cursor walks the chunks cyclically; on each
 tick every admitted request that still needs the cursor's chunk contributes
 its R rows to ONE batched dot launch per party (`imc_dot_shares_gather` over
-the active slots, or `imc_dot_shares_rows` over a row table),
-then each request reshares and compares its rows, writing its match words
-into its own full-database match buffer at the chunk's word offset.  A
+the active slots, or `imc_dot_shares_rows` over a row table), then ONE
+resharing and ONE comparison call over all of those rows
+(`imc_reshare_queries`, `imc_compare_threshold_queries`: a device table
+gives each request's query id, its columns in this chunk and its own
+full-database match buffer, where its match words land at the chunk's word
+offset).  A
 request admitted while others are in flight joins at the current chunk (its
 work overlaps theirs on the device) and completes after one full cycle; its
 OR-tree then runs once over its whole match buffer and the result is opened.
@@ -54,7 +57,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import OPEN_U8_XOR, Context, compare_msg_bytes, make_ids, or_tree_ws_bytes
+from . import OPEN_U8_XOR, QUERY_ENTRY_WORDS, Context, compare_msg_bytes, make_ids, or_tree_ws_bytes, query_table
 
 ROW = 102400                 # query operand bytes per query (replicated form)
 RAW = 2 * 2 * 12800 * 2      # raw query share bytes per query (replicated form)
@@ -95,8 +98,9 @@ class Server:
         serial: also match requests against earlier-admitted requests that were
         in flight at their admission (see the module notes).  net: "buffers"
         runs each comparison with the parties apart and its messages through
-        a device buffer (one, shared by the comparisons, which run in stream
-        order); "registers" holds them in registers."""
+        a device buffer (one, sized for 16 requests' rows of a chunk; a tick
+        with more requests runs its comparison in launches of 16, which reuse
+        it in stream order); "registers" holds them in registers."""
         self.gather = gather
         self.parties = [p for p in range(3) if db.regions[p] is not None]
         self.local = len(self.parties) < 3
@@ -134,24 +138,30 @@ class Server:
         self.rows_host = [torch.empty(rows, 2, dtype=torch.int32).pin_memory() for _ in range(self.ring)]
         self.rows_dev = [torch.empty(rows, 2, dtype=torch.int32, device=d) for _ in range(self.ring)]
         self.rows_ev = [None] * self.ring
+        # the same ring for the tick's query tables (query id, columns, match buffers)
+        self.qtab_host = [torch.empty(slots, QUERY_ENTRY_WORDS, dtype=torch.int64).pin_memory()
+                          for _ in range(self.ring)]
+        self.qtab_dev = [torch.empty(slots, QUERY_ENTRY_WORDS, dtype=torch.int64, device=d) for _ in range(self.ring)]
+        self.qtab_ev = [None] * self.ring
         self.tick_ev = deque()          # the host runs at most two ticks ahead of the GPU
-        # per-slot buffers (the interactive steps; none in party-local serving)
-        nb = 0 if self.local else slots
-        self.msg = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(nb)]
-        self.rep_code = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(nb)]
-        self.rep_mask = [[i16(2, self.R, self.ld) for _ in range(3)] for _ in range(nb)]
+        # the interactive steps' buffers (none in party-local serving): a tick's
+        # resharing of all its rows, and one request's tail pass
+        tr = 0 if self.local else rows
+        self.t_msg = [i16(2, tr, self.ld) for _ in range(3)]
+        self.t_rep_code = [i16(2, tr, self.ld) for _ in range(3)]
+        self.t_rep_mask = [i16(2, tr, self.ld) for _ in range(3)]
+        tl = 0 if self.local else self.R
+        self.msg = [i16(2, tl, self.ld) for _ in range(3)]
+        self.rep_code = [i16(2, tl, self.ld) for _ in range(3)]
+        self.rep_mask = [i16(2, tl, self.ld) for _ in range(3)]
         self.match = [None] * slots     # [3] x [2, R, nw_full] int64, allocated on admission
         self.dup = [[torch.empty(2, 1, dtype=torch.uint8, device=d) for _ in range(3)] for _ in range(slots)]
         self.ws = torch.empty(max(8, or_tree_ws_bytes(1, self.R, self.nw_full)), dtype=torch.uint8, device=d)
         assert net in ("buffers", "registers")
-        # the requests' reshare and compare calls of a tick go round-robin to a
-        # few streams (one message buffer each), so that the small per-request
-        # launches fill the GPU together; the main stream waits for all of them
-        # before the next tick's dot products reuse the dot buffers
-        self.side = [] if self.local else [torch.cuda.Stream(device=d) for _ in range(4)]
-        self.nets = [torch.empty(compare_msg_bytes(0, self.R, chunk) // 8, dtype=torch.int64, device=d)
-                     if net == "buffers" else None for _ in self.side]
-        self.net = self.nets[0] if self.nets else None   # the tail pass's (main stream)
+        self.net = None
+        if net == "buffers" and not self.local:
+            self.net = torch.empty(compare_msg_bytes(0, min(slots, 16) * self.R, chunk) // 8, dtype=torch.int64,
+                                   device=d)
         self.open_dev = torch.empty(slots, dtype=torch.uint8, device=d)
         self.open_host = torch.empty(slots, dtype=torch.uint8).pin_memory()
         self.free = list(range(slots))[::-1]
@@ -268,14 +278,10 @@ class Server:
                 self.ctx.dot_shares_rows(p, self.op[p], self.slots, self.rows_dev[b], k, self.db.regions[p],
                                          self.db.capacity, first, n_max, self.dot_code[p], self.dot_mask[p], self.ld,
                                          galois=self.galois)
-        # per request: reshare and compare its rows into its match buffer
-        main = torch.cuda.current_stream()
-        if self.side:
-            dots_done = torch.cuda.Event()
-            dots_done.record(main)
-            for st in self.side:
-                st.wait_event(dots_done)
+        # every request's rows: reshared and compared in one call each, the
+        # match words going to the request's own buffer
         finished = []
+        entries = []
         for i, r in enumerate(reqs):
             n_j = min(self.chunk, r.snapshot - first)
             r.remaining.discard(j)
@@ -289,25 +295,24 @@ class Server:
                 self.cmps += self.R * n_j
                 continue
             # whole words only: the word holding the snapshot waits for finalisation
-            n_w = min(self.chunk, (r.snapshot // 64) * 64 - first)
-            if n_w <= 0:
-                continue
-            ids = make_ids(r.qid, self.rot, first)
-            off = 2 * i * self.R * self.ld
-            add_c = [self.dot_code[p].data_ptr() + off for p in range(3)]
-            add_m = [self.dot_mask[p].data_ptr() + off for p in range(3)]
-            s = r.slot
-            k = i % len(self.side)
-            self.ctx.reshare(add_c, add_m, self.R, n_w, self.ld, ids, self.msg[s], self.rep_code[s],
-                             self.rep_mask[s], self.side[k])
-            mw = [m.data_ptr() + 8 * (first // 64) for m in self.match[s]]
-            self.ctx.compare_threshold(self.rep_code[s], self.rep_mask[s], self.R, n_w, self.ld, ids, mw,
-                                       self.nw_full, self.side[k], msg_ws=self.nets[k])
+            n_w = max(0, min(self.chunk, (r.snapshot // 64) * 64 - first))
+            entries.append((r.qid, n_w, [m.data_ptr() + 8 * (first // 64) for m in self.match[r.slot]]))
             self.cmps += self.R * n_w
-        for st in self.side:
-            main.wait_stream(st)
-        # after every request of the tick has consumed its rows of the shared
-        # dot buffers (a tail pass reuses them)
+        n_t = max((e[1] for e in entries), default=0)
+        if n_t:
+            k = len(entries)
+            if self.qtab_ev[b] is not None:
+                self.qtab_ev[b].synchronize()
+            query_table(entries, out=self.qtab_host[b])
+            self.qtab_dev[b][:k].copy_(self.qtab_host[b][:k], non_blocking=True)
+            self.qtab_ev[b] = torch.cuda.Event()
+            self.qtab_ev[b].record()
+            self.ctx.reshare_queries(self.dot_code, self.dot_mask, k, n_t, self.ld, ids_t, self.qtab_dev[b],
+                                     self.t_msg, self.t_rep_code, self.t_rep_mask)
+            self.ctx.compare_threshold_queries(self.t_rep_code, self.t_rep_mask, k, n_t, self.ld, ids_t,
+                                               self.qtab_dev[b], self.nw_full, msg_ws=self.net)
+        # in stream order after every request of the tick has consumed its rows
+        # of the shared dot buffers (a tail pass reuses them)
         for r in finished:
             self._finish(r)
         self.cursor = (j + 1) % max(1, self.n_chunks())
@@ -376,10 +381,10 @@ class Server:
                 self.ctx.dot_shares_gather(p, self.op[p], self.rows_dev[b], 1, make_ids(0, self.rot, f),
                                            self.db.regions[p], self.db.capacity, n_j, self.dot_code[p],
                                            self.dot_mask[p], self.ld, galois=self.galois)
-            self.ctx.reshare(self.dot_code, self.dot_mask, self.R, n_j, self.ld, ids, self.msg[s], self.rep_code[s],
-                             self.rep_mask[s])
+            self.ctx.reshare(self.dot_code, self.dot_mask, self.R, n_j, self.ld, ids, self.msg, self.rep_code,
+                             self.rep_mask)
             mw = [m.data_ptr() + 8 * (f // 64) for m in self.match[s]]
-            self.ctx.compare_threshold(self.rep_code[s], self.rep_mask[s], self.R, n_j, self.ld, ids, mw,
+            self.ctx.compare_threshold(self.rep_code, self.rep_mask, self.R, n_j, self.ld, ids, mw,
                                        self.nw_full, msg_ws=self.net)
             self.cmps += self.R * n_j
 
