@@ -318,9 +318,11 @@ typedef struct imc_query_entry {
   uint64_t query_id;     /* keys the randomness of the query's rows, as ids->query_id_base + i
                             does for query i of imc_reshare / imc_compare_threshold */
   uint64_t n;            /* columns of its rows taken part: [0, min(n, call's n)) */
-  uint64_t* match[3];    /* imc_compare_threshold_queries: party p's match planes of this query,
-                            u64 [2][r][mw_ld] (plane 1 at + r * mw_ld), 8-byte aligned;
+  uint64_t* match[3];    /* imc_compare_threshold_queries: party p's match words of this query's
+                            first row in plane 0 (its r rows mw_ld u64 apart), 8-byte aligned;
                             ignored by imc_reshare_queries */
+  uint64_t match_plane;  /* u64 from a word of plane 0 to the same word of plane 1
+                            (r * mw_ld for a [2][r][mw_ld] buffer of the query alone) */
 } imc_query_entry;
 
 /* imc_reshare over the rows of q queries that each carry their own id and
@@ -341,8 +343,9 @@ imc_status imc_reshare_queries(imc_ctx* ctx, const uint16_t* const add_code[3], 
  * rows i*r .. of rep_code / rep_mask are compared exactly as a call of
  * imc_compare_threshold with query_id_base = table[i].query_id,
  * n = min(table[i].n, n) and match = table[i].match would, and its match
- * words are written there (words past ceil(n_i/64) are left untouched, the
- * last one masked to n_i).  rep_code / rep_mask: [2][q*r][ld] as written by
+ * words are written there, plane 1 at table[i].match_plane words from plane
+ * 0 (words past ceil(n_i/64) are left untouched, the last one masked to
+ * n_i).  rep_code / rep_mask: [2][q*r][ld] as written by
  * imc_reshare_queries.  msg_ws: NULL (register simulation) or a message
  * buffer holding at least one query's messages,
  * imc_compare_msg_bytes(0, r, n); the call then runs as few launches as the

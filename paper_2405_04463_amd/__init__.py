@@ -190,20 +190,20 @@ def _stream(stream) -> int | None:
     return stream.cuda_stream
 
 
-QUERY_ENTRY_WORDS = 5   # imc_query_entry: query_id, n, match[3] (u64 each)
+QUERY_ENTRY_WORDS = 6   # imc_query_entry: query_id, n, match[3], match_plane (u64 each)
 
 
 def query_table(entries, out=None):
-    """Pack imc_query_entry rows: entries = [(query_id, n, (match0, match1, match2)), ...] with match
-    pointers as tensors, addresses or None.  Returns (or fills) an int64 tensor [q][5] on the host;
-    the caller copies it to the device."""
+    """Pack imc_query_entry rows: entries = [(query_id, n, (match0, match1, match2), match_plane), ...]
+    with match pointers as tensors, addresses or None (match_plane in u64 words).  Returns (or fills)
+    an int64 tensor [q][6] on the host; the caller copies it to the device."""
     import torch
 
     t = out if out is not None else torch.empty(len(entries), QUERY_ENTRY_WORDS, dtype=torch.int64)
     vals = []
-    for qid, n, m3 in entries:
+    for qid, n, m3, plane in entries:
         ptrs = [addr(m) or 0 for m in (m3 if m3 is not None else (None, None, None))]
-        vals.append([qid, n] + [x - (1 << 64) if x >= (1 << 63) else x for x in ptrs])
+        vals.append([qid, n] + [x - (1 << 64) if x >= (1 << 63) else x for x in ptrs] + [plane])
     if vals:
         t[:len(vals)] = torch.tensor(vals, dtype=torch.int64)
     return t

@@ -11,9 +11,13 @@ a persistent grid, plus one launch per shorter list), or with ONE launch per
 chunk over a row table of all rows ("rows": `imc_dot_shares_rows`).  Either
 way the database streams from HBM once per chunk (per launch) for all
 batches instead of once per batch.
-Resharing, comparison and the OR-tree are elementwise per comparison and run
-per batch on the batch's row range; the comparisons pass their messages
-through one shared device buffer, as the single check does.
+Resharing and comparison are elementwise per comparison: the batched form
+runs them once per rotation list over the rows of all its batches
+(`imc_reshare_queries`, `imc_compare_threshold_queries`, with a device table
+giving every query its id and its place in its batch's match buffer); the
+OR-tree runs per batch.  The comparisons pass their messages through one
+shared device buffer, as the single check does.  The plain form reshares and
+compares batch by batch.
 
 `BatchedStep.capture()` records a whole step in a HIP graph (through torch's
 graph API); `replay()` re-runs it.  Per-batch plain launches (`run_plain`) are
@@ -27,7 +31,7 @@ import numpy as np
 import torch
 
 from . import (MAX_DOT_GROUPS, Context, compare_msg_bytes, galois_query_op_bytes, make_ids, or_tree_ws_bytes,
-               query_op_bytes)
+               query_op_bytes, query_table)
 
 
 @dataclass
@@ -120,15 +124,37 @@ class BatchedStep:
             for b in bs.batches:
                 rb, nw = b.rows, self.nw
                 self.per_batch.append(dict(
-                    msg=[i16(2, rb, self.ld) for _ in range(3)],
-                    rep_code=[i16(2, rb, self.ld) for _ in range(3)],
-                    rep_mask=[i16(2, rb, self.ld) for _ in range(3)],
                     match=[torch.empty(2, rb, nw, dtype=torch.int64, device=d) for _ in range(3)],
                     dup=[torch.empty(2, b.q, dtype=torch.uint8, device=d) for _ in range(3)],
                     ws=torch.empty(max(8, or_tree_ws_bytes(b.q, len(b.rot), nw)), dtype=torch.uint8, device=d),
                 ))
+            # resharing outputs of one rotation list's rows (the largest list);
+            # every list, and every batch of the plain form, reuses them in
+            # stream order
+            gmax = max(qn * len(rot) for rot, _, qn, _ in bs.groups)
+            self.msg = [i16(2, gmax, self.ld) for _ in range(3)]
+            self.rep_code = [i16(2, gmax, self.ld) for _ in range(3)]
+            self.rep_mask = [i16(2, gmax, self.ld) for _ in range(3)]
+            # per rotation list, its queries in layout order: id, columns and
+            # rows of its batch's match buffer (the table never changes, so a
+            # captured step reads it as it is)
+            self.tables = []
+            order = sorted(range(len(bs.batches)), key=lambda i: bs.rbase[i])
+            for rot, _, qn, r0 in bs.groups:
+                entries = []
+                for bi in order:
+                    b = bs.batches[bi]
+                    if not (r0 <= bs.rbase[bi] < r0 + qn * len(rot)):
+                        continue
+                    m = self.per_batch[bi]["match"]
+                    for i in range(b.q):
+                        entries.append((b.qid_base + i, n, [t.data_ptr() + 8 * i * len(rot) * nw for t in m],
+                                        b.rows * nw))
+                assert len(entries) == qn
+                self.tables.append(query_table(entries).to(d))
             # the comparisons' network: one message buffer for the largest batch,
-            # shared by the batches' comparisons (they run in stream order)
+            # shared by the comparisons (they run in stream order; a rotation
+            # list's call runs in launches of as many queries as it holds)
             rmax = max(b.rows for b in bs.batches)
             self.net = torch.empty(compare_msg_bytes(0, rmax, n) // 8, dtype=torch.int64, device=d)
         self.graph = None
@@ -172,7 +198,7 @@ class BatchedStep:
                                    m, self.dot_code[p].data_ptr() + 2 * r0 * self.ld,
                                    self.dot_mask[p].data_ptr() + 2 * r0 * self.ld, self.ld, stream, galois=bs.galois)
         if self.compare:
-            self._compare_all(stream)
+            self._compare_grouped(stream)
 
     def autotune(self, probe_n: int = 16384, reps: int = 2):
         """Time every (mode, tile configuration) on a probe slice of the
@@ -219,7 +245,29 @@ class BatchedStep:
         if self.compare:
             self._compare_all(stream)
 
+    def _or_trees(self, stream=None):
+        ctx, bs = self.ctx, self.bs
+        for bi, b in enumerate(bs.batches):
+            pb = self.per_batch[bi]
+            ids = make_ids(b.qid_base, b.rot, self.first)
+            ctx.or_tree(pb["match"], b.q, (self.n + 63) // 64, self.nw, ids, pb["ws"], pb["ws"].numel(), pb["dup"],
+                        stream)
+
+    def _compare_grouped(self, stream=None):
+        """One resharing and one comparison call per rotation list."""
+        ctx, bs = self.ctx, self.bs
+        for (rot, _, qn, r0), table in zip(bs.groups, self.tables):
+            ids = make_ids(0, rot, self.first)
+            add_c = [self.dot_code[p].data_ptr() + 2 * r0 * self.ld for p in range(3)]
+            add_m = [self.dot_mask[p].data_ptr() + 2 * r0 * self.ld for p in range(3)]
+            ctx.reshare_queries(add_c, add_m, qn, self.n, self.ld, ids, table, self.msg, self.rep_code,
+                                self.rep_mask, stream)
+            ctx.compare_threshold_queries(self.rep_code, self.rep_mask, qn, self.n, self.ld, ids, table, self.nw,
+                                          stream, msg_ws=self.net)
+        self._or_trees(stream)
+
     def _compare_all(self, stream=None):
+        """Batch by batch (the plain form)."""
         ctx, bs = self.ctx, self.bs
         for bi, b in enumerate(bs.batches):
             ids = make_ids(b.qid_base, b.rot, self.first)
@@ -227,11 +275,10 @@ class BatchedStep:
             pb = self.per_batch[bi]
             add_c = [self.dot_code[p].data_ptr() + 2 * r0 * self.ld for p in range(3)]
             add_m = [self.dot_mask[p].data_ptr() + 2 * r0 * self.ld for p in range(3)]
-            ctx.reshare(add_c, add_m, b.rows, self.n, self.ld, ids, pb["msg"], pb["rep_code"], pb["rep_mask"], stream)
-            ctx.compare_threshold(pb["rep_code"], pb["rep_mask"], b.rows, self.n, self.ld, ids, pb["match"], self.nw,
+            ctx.reshare(add_c, add_m, b.rows, self.n, self.ld, ids, self.msg, self.rep_code, self.rep_mask, stream)
+            ctx.compare_threshold(self.rep_code, self.rep_mask, b.rows, self.n, self.ld, ids, pb["match"], self.nw,
                                   stream, msg_ws=self.net)
-            ctx.or_tree(pb["match"], b.q, (self.n + 63) // 64, self.nw, ids, pb["ws"], pb["ws"].numel(), pb["dup"],
-                        stream)
+        self._or_trees(stream)
 
     def capture(self, plain: bool = False):
         """Record one step (batched or plain) in a HIP graph."""

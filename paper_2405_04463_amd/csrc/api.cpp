@@ -523,7 +523,9 @@ imc_status imc_compare_threshold(imc_ctx* c, const uint16_t* const rep_code[3], 
                                         hipStream_t(stream)));
 }
 
-static_assert(sizeof(imc_query_entry) == 40 && offsetof(imc_query_entry, match) == 16, "query entry layout");
+static_assert(sizeof(imc_query_entry) == 48 && offsetof(imc_query_entry, match) == 16 &&
+                  offsetof(imc_query_entry, match_plane) == 40,
+              "query entry layout");
 
 imc_status imc_reshare_queries(imc_ctx* c, const uint16_t* const add_code[3], const uint16_t* const add_mask[3],
                                size_t q, size_t n, size_t ld, const imc_ids* ids, const imc_query_entry* table,

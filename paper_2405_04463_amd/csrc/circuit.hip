@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(256) compare_kernel(CmpArgs a) {
   for (int p = 0; p < 3; ++p) {
     const int pm = (p + 2) % 3;
     uint64_t* m = a.tab ? a.tab[qi].match[p] + (row % uint64_t(a.r)) * a.mw_ld : a.match[p] + row * a.mw_ld;
-    const uint64_t plane = a.tab ? uint64_t(a.r) * a.mw_ld : a.match_plane;
+    const uint64_t plane = a.tab ? a.tab[qi].match_plane : a.match_plane;
     m[w] = r.c[p] & keep;
     m[plane + w] = r.c[pm] & keep;
   }

@@ -381,8 +381,9 @@ __device__ __forceinline__ void store_match(const CmpMsgArgs& a, int p, const La
   uint64_t* m;
   uint64_t plane;
   if (a.tab) {
-    m = a.tab[l.row / uint64_t(a.r)].match[p] + (l.row % uint64_t(a.r)) * a.mw_ld;
-    plane = uint64_t(a.r) * a.mw_ld;
+    const imc_query_entry& e = a.tab[l.row / uint64_t(a.r)];
+    m = e.match[p] + (l.row % uint64_t(a.r)) * a.mw_ld;
+    plane = e.match_plane;
   } else {
     m = a.match[p] + l.row * a.mw_ld;
     plane = a.match_plane;

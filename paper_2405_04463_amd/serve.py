@@ -296,7 +296,8 @@ class Server:
                 continue
             # whole words only: the word holding the snapshot waits for finalisation
             n_w = max(0, min(self.chunk, (r.snapshot // 64) * 64 - first))
-            entries.append((r.qid, n_w, [m.data_ptr() + 8 * (first // 64) for m in self.match[r.slot]]))
+            entries.append((r.qid, n_w, [m.data_ptr() + 8 * (first // 64) for m in self.match[r.slot]],
+                            self.R * self.nw_full))
             self.cmps += self.R * n_w
         n_t = max((e[1] for e in entries), default=0)
         if n_t:

@@ -57,10 +57,17 @@ def test_batched_equals_plain_and_oracle(env, mode, tiles):
     e["ctx"].set_dot_tiles(0)
     got = {p: (_u16(st.dot_code[p]).copy(), _u16(st.dot_mask[p]).copy()) for p in range(3)}
     dup_b = [[pb["dup"][p].cpu().numpy().copy() for p in range(3)] for pb in st.per_batch]
+    match_b = [[pb["match"][p].cpu().numpy().copy() for p in range(3)] for pb in st.per_batch]
     st.run_plain()
     torch.cuda.synchronize()
     for p in range(3):
         assert np.array_equal(_u16(st.dot_code[p]), got[p][0]) and np.array_equal(_u16(st.dot_mask[p]), got[p][1])
+    # the comparison of each rotation list in one call gives every component of
+    # the per-batch calls of the plain form
+    for bi, pb in enumerate(st.per_batch):
+        for p in range(3):
+            assert np.array_equal(pb["match"][p].cpu().numpy(), match_b[bi][p]), (bi, p)
+            assert np.array_equal(pb["dup"][p].cpu().numpy(), dup_b[bi][p]), (bi, p)
     # party 0 and 2 dot shares vs the oracle, batch by batch
     dsh = orc.share(e["dealer"], orc.DOM_SHARE_DB, e["dc"], e["dm"], e["first"])
     q0 = 0
@@ -121,6 +128,35 @@ def test_graph_replay_matches_eager(env, mode, tiles):
         st.run_plain()           # eager work between replays
         torch.cuda.synchronize()
     e["ctx"].set_dot_tiles(imc.DOT_TILES_AUTO)
+
+
+def test_graph_replay_of_the_three_party_step(env):
+    """A captured step with every party's dots, the resharing and comparison
+    of each rotation list in one call, and the per-batch OR-trees: every
+    replay gives the eager step's match and decision components."""
+    from paper_2405_04463_amd.batch import BatchedStep
+
+    e = env
+    st = BatchedStep(e["ctx"], e["bs"], e["db"], e["first"], e["n"], parties=(0, 1, 2), compare=True,
+                     mode="grouped")
+    st.run()
+    torch.cuda.synchronize()
+    ref = [[(pb["match"][p].cpu().numpy().copy(), pb["dup"][p].cpu().numpy().copy()) for p in range(3)]
+           for pb in st.per_batch]
+    st.capture()
+    for i in range(3):
+        for pb in st.per_batch:
+            for p in range(3):
+                pb["match"][p].zero_()
+                pb["dup"][p].zero_()
+        st.replay()
+        torch.cuda.synchronize()
+        for bi, pb in enumerate(st.per_batch):
+            for p in range(3):
+                assert np.array_equal(pb["match"][p].cpu().numpy(), ref[bi][p][0]), (i, bi, p)
+                assert np.array_equal(pb["dup"][p].cpu().numpy(), ref[bi][p][1]), (i, bi, p)
+        st.run_plain()           # eager work between replays
+        torch.cuda.synchronize()
 
 
 def test_autotune_keeps_the_fastest_and_outputs_are_unchanged(env):

@@ -48,7 +48,8 @@ def _planes(q, r, ld):
 
 
 def _table(imc, qids, ns, match):
-    t = imc.query_table([(qid, nn, m3) for qid, nn, m3 in zip(qids, ns, match)])
+    # each query's match buffer is its own [2][r][mw_ld] tensor: plane 1 at r * mw_ld words
+    t = imc.query_table([(qid, nn, m3, m3[0].shape[1] * m3[0].shape[2]) for qid, nn, m3 in zip(qids, ns, match)])
     return t.cuda()
 
 
