@@ -346,7 +346,9 @@ def run_full(args):
     nbytes += len(v32) * imc.db32_bytes(w.n_db)
     log(f"enrolling {w.n_db} entries x 3 parties ({3 * nbytes / 1e9:.1f} GB, {args.scheme} shares"
         + (f", Z_2^32 vectors {v32}" if v32 else "") + ")")
-    db = SharedDB(ctx, w.n_db if code16 else 32, galois=galois)
+    probe = serve_probe_applies(args)
+    # room for the served-latency probe's appended uniques
+    db = SharedDB(ctx, (w.n_db + (SERVE_PROBE_REQUESTS if probe else 0)) if code16 else 32, galois=galois)
     db32 = SharedDB32(ctx, w.n_db, vecs=v32) if v32 else None
     db_masks = enroll_db(ctx, db if code16 else None, w.seed, w.n_db, keep_masks=plain, db32=db32)
     qc, qm = wl.make_queries(w)
@@ -516,6 +518,18 @@ def run_full(args):
     elif in_batch:
         res["config"]["workload"] += (f", plus in-batch matching (each query against the batch's earlier "
                                       f"queries: {w.rows} x {w.n_q} more comparisons)")
+    if probe:
+        # per-query latency: the continuous-batching service on the same
+        # resident database (the step's buffers are released first)
+        del step, compare, buf, bb
+        torch.cuda.empty_cache()
+        db.n = w.n_db
+        served = serve_probe(ctx, db, w)
+        res["step_latency_ms"] = res["latency_ms"]
+        res["latency_ms"] = {"p50": served["p50_ms"], "p99": served["p99_ms"],
+                             "note": "per query, from arrival to opened decision, in the continuous-batching "
+                                     "service on the same database (see served)"}
+        res["served"] = served
     if in_batch:
         res["config"]["in_batch"] = True
         res["in_batch"] = {"ms_per_step": float(np.mean([ev[5][0].elapsed_time(ev[5][1]) for ev in evs])),
@@ -525,6 +539,87 @@ def run_full(args):
                                    + (", OR of each person's two eyes" if w.group == 2 else "")
                                    + "; inside the timed step"}
     return res, (w, qc, qm)
+
+
+SERVE_PROBE_RATE = 50.0        # requests per second
+SERVE_PROBE_REQUESTS = 100     # two seconds of arrivals
+
+
+def serve_probe_applies(args) -> bool:
+    return (args.workload == "full" and args.compare == "mpclift" and not args.in_batch and not args.two_eyes
+            and not args.no_serve_probe)
+
+
+def serve_probe(ctx, db, w):
+    """Poisson arrivals of single-iris requests (31 rotations) at 50/s into
+    the continuous-batching service over the step's resident database:
+    p50/p99 from arrival to opened decision, two requests planted as
+    near-duplicates of database entries (their decisions re-decided on the
+    plaintext pair), the rest random codes, which are appended as unique
+    entries in serial order; then the plain per-query path on the grown
+    database for comparison."""
+    import torch
+
+    import oracle as orc
+    import workload as wl
+    from paper_2405_04463_amd.serve import Request, Server, plain_check
+
+    rot = w.rot
+    n_req = SERVE_PROBE_REQUESTS
+    qid0 = 1 << 32                                    # ids apart from the step's queries
+    rng = np.random.default_rng(0x5E57E)
+    arr = np.cumsum(rng.exponential(1.0 / SERVE_PROBE_RATE, n_req))
+    qc, qm = wl.gen_codes(w.seed ^ 0x5E57E, qid0, n_req, query=True)
+    planted = {17: (int(w.n_db * 0.3), 5), 71: (w.n_db - 1, -9)}   # request -> (entry, rotation)
+    for i, (e, sft) in planted.items():
+        ec, em = wl.gen_codes(w.seed, e, 1)
+        qc[i], qm[i] = wl.plant(w.seed, qid0 + i, ec[0], em[0], sft, h=0.2)
+    reqs = [Request(rid=i, qid=qid0 + i, code=qc[i], mask=qm[i], arrival=float(arr[i])) for i in range(n_req)]
+    srv = Server(ctx, db, rot, chunk=65536, slots=64, serial=True, net="buffers")
+    n0 = db.n
+    log(f"served-latency probe: {n_req} requests at {SERVE_PROBE_RATE:.0f}/s, DB {n0} entries")
+    t0 = time.perf_counter()
+    done = srv.run(reqs, timeout=120)
+    wall = time.perf_counter() - t0
+    lat = np.array([r.done_at - r.arrival for r in done])
+    dups = sorted(r.rid for r in done if r.dup)
+    want = []
+    for i, (e, _) in planted.items():
+        ec, em = wl.gen_codes(w.seed, e, 1)
+        if orc.plain(qc[i:i + 1], qm[i:i + 1], rot, ec, em)[3][0]:
+            want.append(i)
+    ts, cache = [], {}
+    for i in range(4):
+        q = Request(rid=i, qid=qid0 + n_req + i, code=qc[i], mask=qm[i])
+        t1 = time.perf_counter()
+        plain_check(ctx, db, q, rot, cache)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    del srv, cache
+    torch.cuda.empty_cache()
+    t_plain = float(np.median(ts[1:]))
+    out = {"lambda_per_s": SERVE_PROBE_RATE, "requests": n_req, "wall_s": wall,
+           "comparisons_per_s": srv_cmps(done, rot, n0), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+           "p99_ms": float(np.percentile(lat, 99) * 1e3), "db_entries_at_start": n0,
+           "appended": db.n - n0, "duplicates": dups, "duplicates_expected": sorted(want),
+           "decisions_ok": dups == sorted(want) and db.n - n0 == n_req - len(want),
+           "plain_per_query_ms": t_plain * 1e3,
+           "workload": f"continuous-batching service, 3 parties on one GPU, Poisson arrivals at "
+                       f"{SERVE_PROBE_RATE:.0f}/s of one iris at {len(rot)} rotations, chunks of 65,536 entries, "
+                       f"64 slots, serial uniqueness, uniques appended, comparison messages through the device "
+                       f"buffer"}
+    log(f"served: p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms, plain per query {t_plain * 1e3:.1f} ms, "
+        f"decisions ok: {out['decisions_ok']}")
+    return out
+
+
+def srv_cmps(done, rot, n0):
+    """Comparisons per second the probe's requests received over its run
+    (each request against the database it was checked against)."""
+    if not done:
+        return 0.0
+    t = max(r.done_at for r in done) - min(r.arrival for r in done)
+    return sum(len(rot) * r.checked for r in done) / t if t > 0 else 0.0
 
 
 # AND gates and bits sent by party 0 per comparison, per setting (Sec. 6.2).
@@ -889,6 +984,8 @@ def main():
     ap.add_argument("--n-db", type=int, default=None)
     ap.add_argument("--n-q", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve-probe", action="store_true",
+                    help="full workload: skip the served-latency probe after the timed steps")
     ap.add_argument("--dot-tiles", type=int, default=0, help="dot kernel tile configuration (IMC_DOT_TILES_*)")
     ap.add_argument("--scheme", choices=["replicated", "galois"], default="replicated",
                     help="sharing of the dot-product operands (full, batched and serve workloads)")
