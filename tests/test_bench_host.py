@@ -93,3 +93,16 @@ def test_two_eye_recipe_plants_every_pattern():
     assert got == {22: 1, 31: 0, 39: 1, 46: 0, 55: 1, 62: 0}
     # with groups of one, the right eye made from its own left eye would count
     assert int(orc.plain(qc[31:32], qm[31:32], w.rot, qc[:31], qm[:31])[3][0]) == 1
+
+
+def test_served_latency_probe_runs_with_the_default_workload_only():
+    """The probe follows the default full workload (MPCLift, one decision per
+    query); the other settings and workloads report their own figures."""
+    from types import SimpleNamespace
+
+    base = dict(workload="full", compare="mpclift", in_batch=False, two_eyes=False, no_serve_probe=False)
+    assert bench.serve_probe_applies(SimpleNamespace(**base))
+    for change in (dict(workload="serve"), dict(compare="plain"), dict(in_batch=True), dict(two_eyes=True),
+                   dict(no_serve_probe=True)):
+        assert not bench.serve_probe_applies(SimpleNamespace(**{**base, **change})), change
+    assert bench.SERVE_PROBE_REQUESTS / bench.SERVE_PROBE_RATE == 2.0
