@@ -969,12 +969,46 @@ def run_copy_probe(args):
     print(json.dumps({"copy_probe_bytes": 1 << 30, "copies": 3}), flush=True)
 
 
+def run_gemm_probe(args):
+    """Reference point for the dot kernel's MFMA fraction: the vendor
+    library's plain int8 GEMM (torch._int_mm, i8 x i8 -> i32, which ROCm
+    serves with hipBLASLt) on one limb product of the dot's shape (M = 1,984
+    rows, K = 25,600, N = 300,000 entries, the database operand stored
+    entry-major as the library's column-major B) and on square shapes.  One
+    rot_dot_kernel launch does six such products (3 limb products x code and
+    mask) plus the mod 2^16 fold and the rotations.  Not part of the path."""
+    import torch
+
+    out = []
+    for m, k, n in ((8192, 8192, 8192), (4096, 16384, 16384), (1984, 25600, 300000)):
+        a = torch.randint(-128, 128, (m, k), dtype=torch.int8, device="cuda")
+        b = torch.randint(-128, 128, (n, k), dtype=torch.int8, device="cuda").t()
+        torch._int_mm(a, b)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            torch._int_mm(a, b)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        t = float(np.median(ts))
+        tops = 2 * m * n * k / t / 1e9
+        out.append({"m": m, "k": k, "n": n, "ms": t, "tops": tops, "frac": tops / MFMA_I8_PEAK_TOPS})
+        log(f"int8 GEMM {m} x {k} x {n}: {t:.2f} ms, {tops:.0f} TOP/s = {tops / MFMA_I8_PEAK_TOPS:.3f} of peak")
+        del a, b
+        torch.cuda.empty_cache()
+    print(json.dumps({"gemm_probe": out, "peak_tops": MFMA_I8_PEAK_TOPS}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["full", "party", "batched", "serve", "compare", "copy-probe"],
+    ap.add_argument("--workload", choices=["full", "party", "batched", "serve", "compare", "copy-probe",
+                                           "gemm-probe"],
                     default="full")
     ap.add_argument("--n-batches", type=int, default=200)
     ap.add_argument("--chunk", type=int, default=65536)
@@ -1008,6 +1042,9 @@ def main():
     args = ap.parse_args()
     if args.workload == "copy-probe":
         run_copy_probe(args)
+        return
+    if args.workload == "gemm-probe":
+        run_gemm_probe(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the protocol's three parties are simulated on it "
