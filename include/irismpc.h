@@ -316,7 +316,9 @@ imc_status imc_compare_threshold(imc_ctx* ctx, const uint16_t* const rep_code[3]
  * unchanged until the call has completed on its stream. */
 typedef struct imc_query_entry {
   uint64_t query_id;     /* keys the randomness of the query's rows, as ids->query_id_base + i
-                            does for query i of imc_reshare / imc_compare_threshold */
+                            does for query i of imc_reshare / imc_compare_threshold; must be
+                            < 2^48 like every query id (the kernels keep its low 48 bits, so a
+                            larger id would reuse another query's randomness) */
   uint64_t n;            /* columns of its rows taken part: [0, min(n, call's n)) */
   uint64_t* match[3];    /* imc_compare_threshold_queries: party p's match words of this query's
                             first row in plane 0 (its r rows mw_ld u64 apart), 8-byte aligned;
