@@ -160,3 +160,50 @@ def test_queries_argument_errors(imc, keys):
         ctx.compare_threshold_queries(rep_c, rep_m, q, n, ld, ids, table, 4, msg_ws=None)   # mw_ld < ceil(n/64)
     assert e.value.status == imc.IMC_ESHAPE
     ctx.close()
+
+
+def test_queries_at_a_serving_tick_shape(imc, keys):
+    """64 requests x 31 rotations over a 65,536-entry chunk (a full serving
+    tick), whole-word column counts drawn at random, one of them 0 and one
+    the whole chunk: every match word equals the one-query calls'."""
+    dealer, party = keys
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=64)
+    rot = list(range(-15, 16))
+    r, q, n = len(rot), 64, 65536
+    ld, mw_ld = n, n // 64 + 3
+    first = 64 * 4096
+    rng = np.random.default_rng(2024)
+    qids = [int(x) for x in rng.choice(1 << 40, size=q, replace=False)]
+    ns = [64 * int(x) for x in rng.integers(1, n // 64 + 1, size=q)]
+    ns[5], ns[9] = 0, n
+    add_c = [torch.randint(-32768, 32768, (q * r, ld), dtype=torch.int16, device="cuda") for _ in range(3)]
+    add_m = [torch.randint(-32768, 32768, (q * r, ld), dtype=torch.int16, device="cuda") for _ in range(3)]
+    ids = imc.make_ids(0, rot, first)
+    msg = [torch.empty(2, q * r, ld, dtype=torch.int16, device="cuda") for _ in range(3)]
+    rep_c = [torch.empty(2, q * r, ld, dtype=torch.int16, device="cuda") for _ in range(3)]
+    rep_m = [torch.empty(2, q * r, ld, dtype=torch.int16, device="cuda") for _ in range(3)]
+    match = [[torch.full((2, r, mw_ld), SENT64, dtype=torch.int64, device="cuda") for _ in range(3)]
+             for _ in range(q)]
+    table = _table(imc, qids, ns, match)
+    ctx.reshare_queries(add_c, add_m, q, n, ld, ids, table, msg, rep_c, rep_m)
+    net = torch.empty(imc.compare_msg_bytes(0, 16 * r, n) // 8, dtype=torch.int64, device="cuda")   # 4 launches
+    ctx.compare_threshold_queries(rep_c, rep_m, q, n, ld, ids, table, mw_ld, msg_ws=net)
+    m1 = [torch.empty(2, r, ld, dtype=torch.int16, device="cuda") for _ in range(3)]
+    r1c = [torch.empty(2, r, ld, dtype=torch.int16, device="cuda") for _ in range(3)]
+    r1m = [torch.empty(2, r, ld, dtype=torch.int16, device="cuda") for _ in range(3)]
+    one_net = torch.empty(imc.compare_msg_bytes(0, r, n) // 8, dtype=torch.int64, device="cuda")
+    for i in range(q):
+        nw = ns[i] // 64
+        if ns[i]:
+            off = i * r * ld * 2
+            idq = imc.make_ids(qids[i], rot, first)
+            ctx.reshare([t.data_ptr() + off for t in add_c], [t.data_ptr() + off for t in add_m], r, ns[i], ld,
+                        idq, m1, r1c, r1m)
+            ref = [torch.zeros(2, r, mw_ld, dtype=torch.int64, device="cuda") for _ in range(3)]
+            ctx.compare_threshold(r1c, r1m, r, ns[i], ld, idq, ref, mw_ld, msg_ws=one_net)
+            for p in range(3):
+                assert torch.equal(r1c[p][:, :, :ns[i]], rep_c[p][:, i * r:(i + 1) * r, :ns[i]]), (i, p)
+                assert torch.equal(ref[p][:, :, :nw], match[i][p][:, :, :nw]), (i, p)
+        for p in range(3):
+            assert bool((match[i][p][:, :, nw:] == SENT64).all()), (i, p)   # past its count: untouched
+    ctx.close()
