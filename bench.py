@@ -35,11 +35,11 @@ MFMA_I8_PEAK_TOPS = 5000.0      # MI355X dense int8, tera-ops/s (MAC = 2 ops)
 # WRITE_SIZE 1,048,580 KiB).  Valid only for the kernel sources it was taken on.
 DOT_TRAFFIC = {
     "sources": {"paper_2405_04463_amd/csrc/rot_dot.hip":
-                "b9ec8787f36d1e50c3af5c71ab5c889b9b44b2b5e9c4c77b200bab57e322f5ed",
+                "a9592bebea11d7be944f6ee6108420874e50f6ff51af5bcf44a651a8a84dd862",
                 "paper_2405_04463_amd/csrc/device.h":
                 "4c1a3b4ab4b31d959d8bad5a27477516a04872568ad8d0abc29b0de3c59b9f10"},
     "rows": 1984, "n_db": 300_000,
-    "fetch_kib": 16_895_078.0, "write_kib": 2_327_044.0,
+    "fetch_kib": 16_900_882.0, "write_kib": 2_329_442.0,
     "fetch_scale": 1_048_576 / 524_303.0, "write_scale": 1_048_576 / 1_048_580.0,
 }
 

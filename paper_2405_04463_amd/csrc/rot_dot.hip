@@ -209,39 +209,59 @@ __device__ __forceinline__ void rot_dot_tile(const RotTile& args, uint32_t u, ui
   for (int set = 0; set < NSETS; ++set) { IMC_BLOAD(rs[set], set + 2) }
   IMC_ALOAD(1)
   __syncthreads();
-  IMC_FRAGS(falo, fahi, fblo, fbhi, 0)
-
-  for (int k0 = 0; k0 < kSteps; k0 += NSETS) {
+  // a wave whose rows are all past the last row (the partial last row tile)
+  // only stages operands for the others: no fragment reads, no MFMAs
+  const bool live = m0 + uint32_t(wm * WM * 32) < args.rows;
+  if (!live) {
+    for (int k0 = 0; k0 < kSteps; k0 += NSETS) {
 #pragma unroll
-    for (int uu = 0; uu < NSETS; ++uu) {
-      const int k = k0 + uu;
-      const int seg = k / kSegSteps, ts = k - seg * kSegSteps;
-      // interleave the next step's fragment reads with this step's MFMAs
-      // (the compiler's single-wave small-GEMM schedule; ~1.5 % faster here)
-      __builtin_amdgcn_iglp_opt(1);
-      IMC_FRAGS(nalo, nahi, nblo, nbhi, min(k + 1, kSteps - 1))
-#pragma unroll
-      for (int x = 0; x < WM; ++x)
-#pragma unroll
-        for (int y = 0; y < WN; ++y) {
-          acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fblo[y], acc0[x][y], 0, 0, 0);
-          acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fbhi[y], acc1[x][y], 0, 0, 0);
-          acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fahi[x], fblo[y], acc1[x][y], 0, 0, 0);
+      for (int uu = 0; uu < NSETS; ++uu) {
+        const int k = k0 + uu;
+        const int seg = k / kSegSteps, ts = k - seg * kSegSteps;
+        IMC_BSTORE(rs[uu], (k + 2) % 3)
+        if (ts == kSegSteps / 2 && seg + 1 < kSteps / kSegSteps) {
+          IMC_ASTORE((seg + 1) & 1)
+          IMC_ALOAD(min(seg + 2, kSteps / kSegSteps - 1))
         }
-      IMC_BSTORE(rs[uu], (k + 2) % 3)             // step k + 2
-      // mid-segment: the next segment's query bytes go to the other A buffer
-      // (last read during the previous segment), then its loads are issued
-      // for the segment after it.
-      if (ts == kSegSteps / 2 && seg + 1 < kSteps / kSegSteps) {
-        IMC_ASTORE((seg + 1) & 1)
-        IMC_ALOAD(min(seg + 2, kSteps / kSegSteps - 1))
+        __syncthreads();
+        IMC_BLOAD(rs[uu], min(k + 2 + NSETS, kSteps - 1))
       }
-      __syncthreads();
-      IMC_BLOAD(rs[uu], min(k + 2 + NSETS, kSteps - 1))
+    }
+  } else {
+    IMC_FRAGS(falo, fahi, fblo, fbhi, 0)
+
+    for (int k0 = 0; k0 < kSteps; k0 += NSETS) {
 #pragma unroll
-      for (int x = 0; x < WM; ++x) { falo[x] = nalo[x]; fahi[x] = nahi[x]; }
+      for (int uu = 0; uu < NSETS; ++uu) {
+        const int k = k0 + uu;
+        const int seg = k / kSegSteps, ts = k - seg * kSegSteps;
+        // interleave the next step's fragment reads with this step's MFMAs
+        // (the compiler's single-wave small-GEMM schedule; ~1.5 % faster here)
+        __builtin_amdgcn_iglp_opt(1);
+        IMC_FRAGS(nalo, nahi, nblo, nbhi, min(k + 1, kSteps - 1))
 #pragma unroll
-      for (int y = 0; y < WN; ++y) { fblo[y] = nblo[y]; fbhi[y] = nbhi[y]; }
+        for (int x = 0; x < WM; ++x)
+#pragma unroll
+          for (int y = 0; y < WN; ++y) {
+            acc0[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fblo[y], acc0[x][y], 0, 0, 0);
+            acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(falo[x], fbhi[y], acc1[x][y], 0, 0, 0);
+            acc1[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fahi[x], fblo[y], acc1[x][y], 0, 0, 0);
+          }
+        IMC_BSTORE(rs[uu], (k + 2) % 3)             // step k + 2
+        // mid-segment: the next segment's query bytes go to the other A buffer
+        // (last read during the previous segment), then its loads are issued
+        // for the segment after it.
+        if (ts == kSegSteps / 2 && seg + 1 < kSteps / kSegSteps) {
+          IMC_ASTORE((seg + 1) & 1)
+          IMC_ALOAD(min(seg + 2, kSteps / kSegSteps - 1))
+        }
+        __syncthreads();
+        IMC_BLOAD(rs[uu], min(k + 2 + NSETS, kSteps - 1))
+#pragma unroll
+        for (int x = 0; x < WM; ++x) { falo[x] = nalo[x]; fahi[x] = nahi[x]; }
+#pragma unroll
+        for (int y = 0; y < WN; ++y) { fblo[y] = nblo[y]; fbhi[y] = nbhi[y]; }
+      }
     }
   }
 #undef IMC_FRAGS
