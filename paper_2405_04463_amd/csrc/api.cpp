@@ -533,11 +533,13 @@ imc_status imc_reshare_queries(imc_ctx* c, const uint16_t* const add_code[3], co
                                imc_stream stream) {
   if (!c || !add_code || !msg || !rep_code) return IMC_EINVAL;
   if (add_mask && !rep_mask) return IMC_EINVAL;
-  if (!table || !aligned(table, 8)) return IMC_EINVAL;
-  imc_status st = check_ids(ids);
+  if (!table || !aligned(table, 8) || !ids) return IMC_EINVAL;
+  imc_ids idt = *ids;
+  idt.query_id_base = 0;   // ignored: every query's id comes from the table
+  imc_status st = check_ids(&idt);
   if (st != IMC_OK) return st;
   if (ld < n || q >= (size_t(1) << 31)) return IMC_ESHAPE;
-  const size_t rows = q * size_t(ids->r);
+  const size_t rows = q * size_t(idt.r);
   if (rows == 0 || n == 0) return IMC_OK;
   const size_t va = ld % 8 == 0 ? 16 : 2;
   for (int p = 0; p < 3; ++p) {
@@ -550,7 +552,7 @@ imc_status imc_reshare_queries(imc_ctx* c, const uint16_t* const add_code[3], co
   if (!g.ok) return IMC_EDEVICE;
   imc::QueryTab qt;
   qt.tab = table;
-  return dev_status(imc::launch_reshare(c->party, add_code, add_mask, rows, n, ld, *ids, msg, rep_code, rep_mask,
+  return dev_status(imc::launch_reshare(c->party, add_code, add_mask, rows, n, ld, idt, msg, rep_code, rep_mask,
                                         hipStream_t(stream), qt));
 }
 
@@ -559,11 +561,13 @@ imc_status imc_compare_threshold_queries(imc_ctx* c, const uint16_t* const rep_c
                                          const imc_ids* ids, const imc_query_entry* table, void* msg_ws,
                                          size_t msg_ws_bytes, size_t mw_ld, imc_stream stream) {
   if (!c || !rep_code || !rep_mask) return IMC_EINVAL;
-  if (!table || !aligned(table, 8)) return IMC_EINVAL;
-  imc_status st = check_ids(ids);
+  if (!table || !aligned(table, 8) || !ids) return IMC_EINVAL;
+  imc_ids idt = *ids;
+  idt.query_id_base = 0;   // ignored: every query's id comes from the table
+  imc_status st = check_ids(&idt);
   if (st != IMC_OK) return st;
   if (ld < n || mw_ld < (n + 63) / 64 || q >= (size_t(1) << 31)) return IMC_ESHAPE;
-  const size_t r = size_t(ids->r), rows = q * r;
+  const size_t r = size_t(idt.r), rows = q * r;
   if (rows == 0 || n == 0) return IMC_OK;
   const size_t va = ld % 8 == 0 ? 16 : 2;
   for (int p = 0; p < 3; ++p) {
@@ -580,7 +584,7 @@ imc_status imc_compare_threshold_queries(imc_ctx* c, const uint16_t* const rep_c
   imc::QueryTab qt;
   qt.tab = table;
   if (!msg_ws)
-    return dev_status(imc::launch_compare(c->party, rep_code, rep_mask, rows, n, ld, *ids, no_match, mw_ld,
+    return dev_status(imc::launch_compare(c->party, rep_code, rep_mask, rows, n, ld, idt, no_match, mw_ld,
                                           hipStream_t(stream), qt));
   // launches of as many whole queries as the buffer's workgroup blocks hold
   const size_t nw = (n + 63) / 64;
@@ -596,7 +600,7 @@ imc_status imc_compare_threshold_queries(imc_ctx* c, const uint16_t* const rep_c
     }
     qt.tab = table + q0;
     const imc_status e = dev_status(imc::launch_compare_msg(0, c->party, code, false, mask, nullptr, k * r, n, ld,
-                                                            *ids, no_match, mw_ld, static_cast<uint64_t*>(msg_ws),
+                                                            idt, no_match, mw_ld, static_cast<uint64_t*>(msg_ws),
                                                             hipStream_t(stream), qt));
     if (e != IMC_OK) return e;
   }

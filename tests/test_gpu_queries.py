@@ -159,6 +159,11 @@ def test_queries_argument_errors(imc, keys):
     with pytest.raises(imc.IMCError) as e:
         ctx.compare_threshold_queries(rep_c, rep_m, q, n, ld, ids, table, 4, msg_ws=None)   # mw_ld < ceil(n/64)
     assert e.value.status == imc.IMC_ESHAPE
+    # the table gives every query's id: the call ignores ids.query_id_base, even one out of range
+    far = imc.make_ids(1 << 50, rot, 0)
+    ctx.reshare_queries(add_c, add_m, q, n, ld, far, table, msg, rep_c, rep_m)
+    ctx.compare_threshold_queries(rep_c, rep_m, q, n, ld, far, table, 5, msg_ws=None)
+    torch.cuda.synchronize()
     ctx.close()
 
 
