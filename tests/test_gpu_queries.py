@@ -212,3 +212,41 @@ def test_queries_at_a_serving_tick_shape(imc, keys):
         for p in range(3):
             assert bool((match[i][p][:, :, nw:] == SENT64).all()), (i, p)   # past its count: untouched
     ctx.close()
+
+
+@pytest.mark.parametrize("rot", [[0], list(range(-7, 8))])
+def test_queries_other_rotation_counts(imc, keys, rot):
+    """One rotation (the expanded path's shape) and 15: every component of
+    every query against the oracle's resharing and comparison of that query."""
+    dealer, party = keys
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=64)
+    r = len(rot)
+    qids, ns = [31, 7, 1 << 40], [130, 64, 128]
+    q, n, ld, first = len(qids), 130, 136, 64
+    rng = np.random.default_rng(r)
+    zc = rng.integers(0, 1 << 16, size=(3, q * r, ld), dtype=np.uint16)
+    zm = rng.integers(0, 1 << 16, size=(3, q * r, ld), dtype=np.uint16)
+    add_c = [torch.from_numpy(zc[p].view(np.int16).copy()).cuda() for p in range(3)]
+    add_m = [torch.from_numpy(zm[p].view(np.int16).copy()).cuda() for p in range(3)]
+    ids = imc.make_ids(0, rot, first)
+    msg, rep_c, rep_m = _planes(q, r, ld), _planes(q, r, ld), _planes(q, r, ld)
+    match = [[torch.full((2, r, 3), SENT64, dtype=torch.int64, device="cuda") for _ in range(3)] for _ in range(q)]
+    table = _table(imc, qids, ns, match)
+    ctx.reshare_queries(add_c, add_m, q, n, ld, ids, table, msg, rep_c, rep_m)
+    net = torch.empty(imc.compare_msg_bytes(0, q * r, n) // 8, dtype=torch.int64, device="cuda")
+    ctx.compare_threshold_queries(rep_c, rep_m, q, n, ld, ids, table, 3, msg_ws=net)
+    torch.cuda.synchronize()
+    for i, (qid, ni) in enumerate(zip(qids, ns)):
+        rows = slice(i * r, (i + 1) * r)
+        oc, om = orc.reshare(party, np.ascontiguousarray(zc[:, rows, :ni]), np.ascontiguousarray(zm[:, rows, :ni]),
+                             1, rot, qid, first)
+        want = orc.compare(party, oc, om, 1, rot, qid, first)
+        nw = (ni + 63) // 64
+        for p in range(3):
+            pm = (p + 2) % 3
+            rc = rep_c[p].cpu().numpy().view(np.uint16)
+            assert np.array_equal(rc[0, rows, :ni], oc[p]) and np.array_equal(rc[1, rows, :ni], oc[pm]), (i, p)
+            got = match[i][p].cpu().numpy().view(np.uint64)
+            assert np.array_equal(got[0, :, :nw], want[p]) and np.array_equal(got[1, :, :nw], want[pm]), (i, p)
+            assert (got[:, :, nw:] == np.uint64(SENT64)).all(), (i, p)
+    ctx.close()
