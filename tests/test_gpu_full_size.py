@@ -25,6 +25,7 @@ configuration the benchmark times, on outputs the oracle computes one by one.
   the plaintext OR over its two eyes.
 * The batched step of 200 uneven batches against 1,000,000 entries.
 * Party-local serving over 1,500,000 entries of a 2,000,000-entry region.
+* Three-party serving on Galois-ring shares of 1,500,000 entries.
 * The comparison settings (public masks, Lift to Z_2^18, ConstLift, NoLift)
   at 64 queries x 31 rotations against 300,000 entries, with the same
   OR-tree and opened-bit checks.
@@ -398,6 +399,69 @@ def test_party_local_serving_at_1_5M_entries(imc, keys):
             want_c, want_m = orc.local_dot(0, qsh[rid:rid + 1], rot, dsh)
             assert np.array_equal(gc, want_c), rid
             assert np.array_equal(gm, want_m), rid
+    finally:
+        ctx.close()
+        free()
+
+
+def test_three_party_galois_serving_at_1_5M_entries(imc, keys):
+    """The three-party service on Galois-ring shares of 1,500,000 entries
+    (230 GB), 31 rotations, 65,536-entry chunks (the last one ragged), one
+    resharing and one comparison call per tick: two requests planted as
+    near-duplicates of database entries are decided duplicates and two
+    random ones unique (and appended); a request's match components over
+    the database are the same alone and joining a mix mid-cycle; every
+    opened match bit of every request is re-decided by the plaintext check
+    on its pair and the planted pairs are among them."""
+    from paper_2405_04463_amd.pipeline import SharedDB
+    from paper_2405_04463_amd.serve import Request, Server
+
+    dealer, party = keys
+    seed, n0, chunk = 0x1A150005, 1_500_000, 65536
+    assert n0 % chunk != 0 and n0 % 64 != 0
+    rot = wl.ROT31
+    qc, qm = wl.gen_codes(seed ^ 0x3E, 0, 4, query=True)
+    planted = {0: (987_654, -4), 2: (n0 - 1, 11)}
+    for qi, (e, s) in planted.items():
+        ec, em = wl.gen_codes(seed, e, 1)
+        qc[qi], qm[qi] = wl.plant(seed, 9000 + qi, ec[0], em[0], s, h=0.2)
+    ctx = imc.Context(imc.Keys(dealer, party), max_rows=64 * len(rot))
+    try:
+        db = SharedDB(ctx, n0 + 64, galois=True)
+        enroll(db, seed, n0)
+        req = lambda i: Request(rid=i, qid=9000 + i, code=qc[i].copy(), mask=qm[i].copy())   # noqa: E731
+        alone = _drive(Server(ctx, db, rot, chunk=chunk, slots=64, append=False, keep_shares=True),
+                       {0: [req(0)]})[0]
+        free()
+        srv = Server(ctx, db, rot, chunk=chunk, slots=64, append=True, keep_shares=True)
+        done = _drive(srv, {0: [req(1), req(2)], 3: [req(0)], 7: [req(3)]})
+        assert {rid: r.dup for rid, r in done.items()} == {0: 1, 1: 0, 2: 1, 3: 0}
+        assert alone.dup == 1 and db.n == n0 + 2
+        # whole words below the snapshot, and the snapshot's word up to it (past it
+        # the mix also compared the entry appended meanwhile, serial order)
+        full, keep = n0 // 64, np.int64((1 << (n0 % 64)) - 1)
+        for p in range(3):
+            assert np.array_equal(alone.match[p][:, :, :full], done[0].match[p][:, :, :full]), p
+            assert np.array_equal(alone.match[p][:, :, full] & keep, done[0].match[p][:, :, full] & keep), p
+        del srv
+        free()
+        for rid, r in done.items():
+            assert r.snapshot == n0 and r.checked >= n0, rid
+            opened = r.match[0][0] ^ r.match[1][0] ^ r.match[2][0]      # [rows][words], plane 0 of each party
+            ones = [(row, 64 * w + b) for row, w in zip(*np.nonzero(opened))
+                    for b in range(64) if (int(opened[row, w]) >> b) & 1]
+            assert all(e < r.checked for _, e in ones), rid
+            for row, e in ones:
+                if e < n0:
+                    ec, em = wl.gen_codes(seed, e, 1)
+                else:                                   # an appended request's code
+                    j = e - n0
+                    ec, em = qc[[1, 3][j]:[1, 3][j] + 1], qm[[1, 3][j]:[1, 3][j] + 1]
+                assert orc.plain(qc[rid:rid + 1], qm[rid:rid + 1], rot, ec, em)[2][row, 0], (rid, row, e)
+            if rid in planted:
+                assert any(e == planted[rid][0] for _, e in ones), rid
+            else:
+                assert not ones, rid
     finally:
         ctx.close()
         free()
