@@ -288,25 +288,31 @@ MSG_BITS = {"mpclift": (156, 125, 125), "lift18": (72, 69, 69), "plain": (29, 29
             "nolift": (61, 61, 61)}
 
 
-def circuit_report(compare, ncmp, reshare_ms, compare_ms, plain, v32, net="registers", other_ms=None):
+def circuit_report(compare, ncmp, reshare_ms, compare_ms, plain, v32, net="registers", other_ms=None,
+                   msgs_only=False):
     """The interactive steps of one batch: resharing against the HBM roof
     (algorithmic bytes) and the comparison against the VALU roof (its PRF
     work alone, a lower bound on its ops).  net: how the step's comparison
     passed its messages ("buffers": parties apart, every message stored and
     loaded through device memory; "registers": the three parties of a
-    comparison in one lane); other_ms: the comparison in the other mode."""
+    comparison in one lane); other_ms: the comparison in the other mode;
+    msgs_only: the resharing wrote its messages only (the comparison reads
+    the replicated components in place from them)."""
     n16 = 0 if 0 in v32 else 1
     n16 += 0 if (plain or 1 in v32) else 1                 # Z_2^16 vectors reshared
     # per vector and comparison, 3 parties: read the additive share, write the
-    # message and both planes of the replicated share: 3 x (1 + 1 + 2) elements
-    per_vec16, per_vec32 = 3 * 4 * 2, 3 * 4 * 4
+    # message and both planes of the replicated share: 3 x (1 + 1 + 2) elements;
+    # messages only: 3 x (1 + 1)
+    per = 2 if msgs_only else 4
+    per_vec16, per_vec32 = 3 * per * 2, 3 * per * 4
     rb = ncmp * (n16 * per_vec16 + len(v32) * per_vec32)
     ops = ncmp * CMP_BLOCKS_PER_64[compare] * CHACHA12_OPS / 64
     bits = MSG_BITS[compare]
     # the buffered network runs each party's two keys: 2 of the 3 PRF blocks
     # per tape position per party, i.e. twice the register simulation's PRF work
     ops_net = ops * (2 if net == "buffers" else 1)
-    r = {"reshare_ms": reshare_ms, "reshare_bytes": rb, "reshare_gbs": rb / (reshare_ms / 1e3) / 1e9,
+    r = {"reshare_writes": "messages" if msgs_only else "messages and replicated planes",
+         "reshare_ms": reshare_ms, "reshare_bytes": rb, "reshare_gbs": rb / (reshare_ms / 1e3) / 1e9,
          "reshare_hbm_frac": rb / (reshare_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
          "compare_net": net, "compare_ms": compare_ms, "compare_prf_ops": ops_net,
          "compare_valu_tops": ops_net / (compare_ms / 1e3) / 1e12,
@@ -376,6 +382,9 @@ def run_full(args):
 
     stream = torch.cuda.current_stream()
     ids = imc.make_ids(0, w.rot, 0)
+    # MPCLift: the resharing writes its messages only and the comparison reads
+    # each party's components in place (own message, the one received)
+    msgs_only = args.compare == "mpclift"
 
     def compare(net):
         """The step's comparison; net: its message buffer (None: messages in registers)."""
@@ -390,8 +399,8 @@ def run_full(args):
             ctx.compare_variant(imc.CMP_CONST32, code, bits, buf.rep32[1], None, buf.rows, w.n_db, buf.ld, ids,
                                 buf.match, buf.nw, stream, msg_ws=net)
         else:
-            ctx.compare_threshold(buf.rep_code, buf.rep_mask, buf.rows, w.n_db, buf.ld, ids, buf.match, buf.nw,
-                                  stream, msg_ws=net)
+            # the replicated components read in place from the resharing's messages
+            ctx.compare_threshold_msgs(buf.msg, buf.rows, w.n_db, buf.ld, ids, buf.match, buf.nw, stream, msg_ws=net)
 
     def step(events=None):
         for p in range(3):
@@ -410,7 +419,9 @@ def run_full(args):
             ctx.plain_ml(buf.row_masks, buf.rows, db_masks, w.n_db, buf.ml_pub, buf.ld, stream)
         if events is not None:
             events[3][0].record(stream)
-        if code16:
+        if code16 and msgs_only:
+            ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, w.n_db, buf.ld, ids, buf.msg, None, None, stream)
+        elif code16:
             ctx.reshare(buf.dot_code, buf.dot_mask, buf.rows, w.n_db, buf.ld, ids, buf.msg, buf.rep_code,
                         buf.rep_mask, stream)
         for v in v32:
@@ -505,7 +516,7 @@ def run_full(args):
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "hbm_gbs": None if traffic is None else traffic / dot_avg_s / 1e9},
         "circuit": circuit_report(args.compare, w.rows * w.n_db, reshare_ms, compare_ms, plain, v32, args.net,
-                                  other_ms),
+                                  other_ms, msgs_only),
         "verification": ver,
     }
     if args.two_eyes:

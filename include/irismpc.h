@@ -265,7 +265,11 @@ imc_status imc_set_dot_tiles(imc_ctx* ctx, uint32_t flags);
  * received from party p-1.  rows must equal q * ids->r for some q.
  * add_mask may be NULL (masks in plain: no mask dot); then only the code
  * shares are reshared, rep_mask is ignored and the mask plane of msg[p] is
- * left untouched.  When ld % 8 == 0 every plane must be 16-byte aligned. */
+ * left untouched.  rep_code may be NULL: then only the messages are written
+ * (rep_mask is ignored), and party p's replicated components are msg[p]
+ * (its own) and msg[p-1] (the one it received), which
+ * imc_compare_threshold_msgs reads in place.  When ld % 8 == 0 every plane
+ * must be 16-byte aligned. */
 imc_status imc_reshare(imc_ctx* ctx, const uint16_t* const add_code[3], const uint16_t* const add_mask[3],
                        size_t rows, size_t n, size_t ld, const imc_ids* ids, uint16_t* const msg[3],
                        uint16_t* const rep_code[3], uint16_t* const rep_mask[3], imc_stream stream);
@@ -359,6 +363,17 @@ imc_status imc_compare_threshold_queries(imc_ctx* ctx, const uint16_t* const rep
                                          const uint16_t* const rep_mask[3], size_t q, size_t n, size_t ld,
                                          const imc_ids* ids, const imc_query_entry* table, void* msg_ws,
                                          size_t msg_ws_bytes, size_t mw_ld, imc_stream stream);
+
+/* imc_compare_threshold with the replicated components read in place from
+ * the resharing's messages (App. C: after the resharing party p holds its
+ * own re-randomised share and the one party p-1 sent it): party p's own
+ * code and mask dot components are planes 0 and 1 of msgs[p], its second
+ * ones planes 0 and 1 of msgs[p-1] (msgs[p]: u16 [2][rows][ld] as
+ * imc_reshare writes msg[p]; 16-byte aligned when ld % 8 == 0).  Outputs,
+ * msg_ws and errors as imc_compare_threshold; identical match components. */
+imc_status imc_compare_threshold_msgs(imc_ctx* ctx, const uint16_t* const msgs[3], size_t rows, size_t n, size_t ld,
+                                      const imc_ids* ids, void* msg_ws, size_t msg_ws_bytes,
+                                      uint64_t* const match[3], size_t mw_ld, imc_stream stream);
 
 /* Bytes of the message buffer of a comparison call over rows x n
  * comparisons: planes x 64 x ceil(rows * ceil(n/64) / 64) u64, with

@@ -31,6 +31,7 @@ EXPORTS = [
     "imc_query32_op_bytes", "imc_share32_db", "imc_share32_query", "imc_dot32_shares", "imc_reshare32",
     "imc_dot_shares_rows_noalloc", "imc_compare_msg_bytes", "imc_or_pairs", "imc_dot_shares_groups",
     "imc_galois_dot_shares_groups", "imc_reshare_queries", "imc_compare_threshold_queries",
+    "imc_compare_threshold_msgs",
 ]
 
 (DOT_TILES_AUTO, DOT_TILES_EXPANDED_256x128, DOT_TILES_EXPANDED_128x128, DOT_TILES_EXPANDED_SHALLOW, DOT_TILES_ROTATION,
@@ -111,7 +112,8 @@ def lib():
         L.imc_share_db.argtypes = [_VP, _VP, _VP, sz, ctypes.c_uint64, _P3, sz, _VP]
         L.imc_share_query.argtypes = [_VP, _VP, _VP, sz, ctypes.c_uint64, _P3, _VP, _VP]
         L.imc_dot_shares.argtypes = [_VP, ctypes.c_int, _VP, sz, ctypes.POINTER(imc_ids), _VP, sz, sz, _VP, _VP, sz, _VP]
-        L.imc_reshare.argtypes = [_VP, _P3, _VP, sz, sz, sz, ctypes.POINTER(imc_ids), _P3, _P3, _VP, _VP]
+        L.imc_reshare.argtypes = [_VP, _P3, _VP, sz, sz, sz, ctypes.POINTER(imc_ids), _P3, _VP, _VP, _VP]
+        L.imc_compare_threshold_msgs.argtypes = [_VP, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, sz, _P3, sz, _VP]
         L.imc_compare_threshold.argtypes = [_VP, _P3, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, sz, _P3, sz, _VP]
         L.imc_reshare_queries.argtypes = [_VP, _P3, _VP, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, _P3, _P3, _VP, _VP]
         L.imc_compare_threshold_queries.argtypes = [_VP, _P3, _P3, sz, sz, sz, ctypes.POINTER(imc_ids), _VP, _VP, sz,
@@ -358,12 +360,20 @@ class Context:
     def set_dot_tiles(self, flags: int):
         return _check(lib().imc_set_dot_tiles(self._h, flags), "imc_set_dot_tiles")
 
-    # -- imc_reshare (add_mask3 / rep_mask3 None: code shares only)
+    # -- imc_reshare (add_mask3 / rep_mask3 None: code shares only; rep_code3 None: the messages only)
     def reshare(self, add_code3, add_mask3, rows, n, ld, ids: imc_ids, msg3, rep_code3, rep_mask3, stream=None):
         am = ctypes.cast(_p3(add_mask3), _VP) if add_mask3 is not None else None
+        rc = ctypes.cast(_p3(rep_code3), _VP) if rep_code3 is not None else None
         rm = ctypes.cast(_p3(rep_mask3), _VP) if rep_mask3 is not None else None
         return _check(lib().imc_reshare(self._h, _p3(add_code3), am, rows, n, ld, ctypes.byref(ids),
-                                        _p3(msg3), _p3(rep_code3), rm, _stream(stream)), "imc_reshare")
+                                        _p3(msg3), rc, rm, _stream(stream)), "imc_reshare")
+
+    # -- imc_compare_threshold_msgs: the components read in place from the resharing's messages
+    def compare_threshold_msgs(self, msg3, rows, n, ld, ids: imc_ids, match3, mw_ld, stream=None, msg_ws=None):
+        mb = msg_ws.numel() * msg_ws.element_size() if msg_ws is not None else 0
+        return _check(lib().imc_compare_threshold_msgs(self._h, _p3(msg3), rows, n, ld, ctypes.byref(ids),
+                                                       addr(msg_ws), mb, _p3(match3), mw_ld, _stream(stream)),
+                      "imc_compare_threshold_msgs")
 
     # -- imc_compare_variant (variant CMP_*; rep_mask3 None for CMP_PLAIN_MASK; msg_ws: message buffer
     #    of compare_msg_bytes(variant, rows, n) bytes, None: messages held in registers)

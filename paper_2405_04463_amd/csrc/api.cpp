@@ -466,8 +466,8 @@ imc_status imc_set_dot_tiles(imc_ctx* c, uint32_t flags) {
 imc_status imc_reshare(imc_ctx* c, const uint16_t* const add_code[3], const uint16_t* const add_mask[3], size_t rows,
                        size_t n, size_t ld, const imc_ids* ids, uint16_t* const msg[3], uint16_t* const rep_code[3],
                        uint16_t* const rep_mask[3], imc_stream stream) {
-  if (!c || !add_code || !msg || !rep_code) return IMC_EINVAL;
-  if (add_mask && !rep_mask) return IMC_EINVAL;   // add_mask NULL: code shares only
+  if (!c || !add_code || !msg) return IMC_EINVAL;
+  if (add_mask && rep_code && !rep_mask) return IMC_EINVAL;   // add_mask NULL: code shares only
   imc_status st = check_ids(ids);
   if (st != IMC_OK) return st;
   if (rows % size_t(ids->r)) return IMC_ESHAPE;
@@ -476,10 +476,13 @@ imc_status imc_reshare(imc_ctx* c, const uint16_t* const add_code[3], const uint
   // 16-byte vector accesses are taken when ld % 8 == 0: every plane must then be 16-byte aligned
   const size_t va = ld % 8 == 0 ? 16 : 2;
   for (int p = 0; p < 3; ++p) {
-    if (!add_code[p] || !msg[p] || !rep_code[p]) return IMC_EINVAL;
-    if (add_mask && (!add_mask[p] || !rep_mask[p])) return IMC_EINVAL;
-    if (!aligned(add_code[p], va) || !aligned(msg[p], va) || !aligned(rep_code[p], va)) return IMC_EINVAL;
-    if (add_mask && (!aligned(add_mask[p], va) || !aligned(rep_mask[p], va))) return IMC_EINVAL;
+    if (!add_code[p] || !msg[p]) return IMC_EINVAL;
+    if (add_mask && !add_mask[p]) return IMC_EINVAL;
+    if (!aligned(add_code[p], va) || !aligned(msg[p], va)) return IMC_EINVAL;
+    if (add_mask && !aligned(add_mask[p], va)) return IMC_EINVAL;
+    if (!rep_code) continue;                      // the messages alone
+    if (!rep_code[p] || !aligned(rep_code[p], va)) return IMC_EINVAL;
+    if (add_mask && (!rep_mask[p] || !aligned(rep_mask[p], va))) return IMC_EINVAL;
   }
   DeviceGuard g(c->device);
   if (!g.ok) return IMC_EDEVICE;
@@ -521,6 +524,34 @@ imc_status imc_compare_threshold(imc_ctx* c, const uint16_t* const rep_code[3], 
   }
   return dev_status(imc::launch_compare(c->party, rep_code, rep_mask, rows, n, ld, *ids, match, mw_ld,
                                         hipStream_t(stream)));
+}
+
+imc_status imc_compare_threshold_msgs(imc_ctx* c, const uint16_t* const msgs[3], size_t rows, size_t n, size_t ld,
+                                      const imc_ids* ids, void* msg_ws, size_t msg_ws_bytes,
+                                      uint64_t* const match[3], size_t mw_ld, imc_stream stream) {
+  if (!c || !msgs || !match) return IMC_EINVAL;
+  imc_status st = check_ids(ids);
+  if (st != IMC_OK) return st;
+  if (rows % size_t(ids->r)) return IMC_ESHAPE;
+  if (ld < n || mw_ld < (n + 63) / 64) return IMC_ESHAPE;
+  if (rows == 0 || n == 0) return IMC_OK;
+  const size_t va = ld % 8 == 0 ? 16 : 2;
+  for (int p = 0; p < 3; ++p) {
+    if (!msgs[p] || !match[p]) return IMC_EINVAL;
+    if (!aligned(msgs[p], va) || !aligned(match[p], 8)) return IMC_EINVAL;
+  }
+  if (msg_ws) {
+    if (!aligned(msg_ws, 8)) return IMC_EINVAL;
+    if (msg_ws_bytes < imc_compare_msg_bytes(0, rows, n)) return IMC_ESHAPE;
+  }
+  DeviceGuard g(c->device);
+  if (!g.ok) return IMC_EDEVICE;
+  if (msg_ws)
+    return dev_status(imc::launch_compare_msgs(c->party, msgs, rows, n, ld, *ids, match, mw_ld,
+                                               static_cast<uint64_t*>(msg_ws), hipStream_t(stream)));
+  // the register simulation reads each party's own component only
+  const uint16_t* mask[3] = {msgs[0] + rows * ld, msgs[1] + rows * ld, msgs[2] + rows * ld};
+  return dev_status(imc::launch_compare(c->party, msgs, mask, rows, n, ld, *ids, match, mw_ld, hipStream_t(stream)));
 }
 
 static_assert(sizeof(imc_query_entry) == 48 && offsetof(imc_query_entry, match) == 16 &&

@@ -569,6 +569,7 @@ __global__ void __launch_bounds__(256) reshare_kernel(ReshareArgs a) {
   const uint64_t off = row * a.ld + col0;
   const bool vec = (a.ld % 8) == 0;
   const bool with_mask = a.add_mask[0] != nullptr;   // no mask dot when masks are public
+  const bool with_rep = a.rep_code[0] != nullptr;     // otherwise the messages alone
   uint16_t zc[3][16], zm[3][16];
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
@@ -595,12 +596,16 @@ __global__ void __launch_bounds__(256) reshare_kernel(ReshareArgs a) {
   for (int p = 0; p < 3; ++p) {
     const int pm = (p + 2) % 3;
     st16(a.msg[p] + off, nval, vec, oc[p]);              // party p -> party p+1
-    st16(a.rep_code[p] + off, nval, vec, oc[p]);
-    st16(a.rep_code[p] + a.plane + off, nval, vec, oc[pm]);   // received from party p-1
+    if (with_rep) {
+      st16(a.rep_code[p] + off, nval, vec, oc[p]);
+      st16(a.rep_code[p] + a.plane + off, nval, vec, oc[pm]);   // received from party p-1
+    }
     if (!with_mask) continue;
     st16(a.msg[p] + a.plane + off, nval, vec, om[p]);
-    st16(a.rep_mask[p] + off, nval, vec, om[p]);
-    st16(a.rep_mask[p] + a.plane + off, nval, vec, om[pm]);
+    if (with_rep) {
+      st16(a.rep_mask[p] + off, nval, vec, om[p]);
+      st16(a.rep_mask[p] + a.plane + off, nval, vec, om[pm]);
+    }
   }
 }
 
@@ -793,8 +798,8 @@ hipError_t launch_reshare(const Keys3& keys, const uint16_t* const add_code[3], 
     a.add_code[p] = add_code[p];
     a.add_mask[p] = add_mask ? add_mask[p] : nullptr;
     a.msg[p] = msg[p];
-    a.rep_code[p] = rep_code[p];
-    a.rep_mask[p] = add_mask ? rep_mask[p] : nullptr;
+    a.rep_code[p] = rep_code ? rep_code[p] : nullptr;
+    a.rep_mask[p] = (add_mask && rep_code) ? rep_mask[p] : nullptr;
   }
   a.ld = ld;
   a.n = n;

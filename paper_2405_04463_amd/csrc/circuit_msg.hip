@@ -290,6 +290,8 @@ __device__ __forceinline__ void inject_view(int p, const Keys3& keys, uint64_t s
 struct CmpMsgArgs {
   Keys3 keys;
   const void* code[3];       // rep_code[p] plane 0 (own component); plane 1 at + plane_elems
+  const uint16_t* prev_code[3];  // MPCLift: party p's second component (party p-1's share) of the
+  const uint16_t* prev_mask[3];  // code and mask dots: plane 1 of rep_*, or party p-1's message
   const void* mask[3];       // rep_mask[p] likewise (MPCLift, Lift18, Const32)
   const uint16_t* ml_pub;    // [rows][ld] public ml (Plain)
   uint64_t* match[3];        // [2][rows][mw_ld]
@@ -407,8 +409,10 @@ __global__ void __launch_bounds__(192) compare_msg_kernel(CmpMsgArgs a) {
   const Key& ko = a.keys.k[p];
   const Key& kv = a.keys.k[pm];
   const Net net = net_of(a.msg, kPlanes, l.active);
-  const uint16_t* mrow = static_cast<const uint16_t*>(a.mask[p]) + l.row * a.ld;
-  const uint16_t* drow = static_cast<const uint16_t*>(a.code[p]) + l.row * a.ld;
+  const uint16_t* const mrow[2] = {static_cast<const uint16_t*>(a.mask[p]) + l.row * a.ld,
+                                   a.prev_mask[p] + l.row * a.ld};
+  const uint16_t* const drow[2] = {static_cast<const uint16_t*>(a.code[p]) + l.row * a.ld,
+                                   a.prev_code[p] + l.row * a.ld};
 
   // Lift: bits 16 and 17 of ml_0 + ml_1 + ml_2
   PV bit16{0, 0}, bit17{0, 0};
@@ -417,7 +421,7 @@ __global__ void __launch_bounds__(192) compare_msg_kernel(CmpMsgArgs a) {
   for (int c = 0; c < 2; ++c) {
     uint64_t xc[16];
     uint32_t W[32];
-    load64(mrow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
+    load64(mrow[c], l.col0, l.nval, vec_ok, W);
     to_planes(W, xc);
     y.hi.put(c, xc);
     y.lo[c][0] = xc[0];
@@ -447,7 +451,7 @@ __global__ void __launch_bounds__(192) compare_msg_kernel(CmpMsgArgs a) {
       uint32_t W[32];
 #pragma unroll
       for (int j = 0; j < 16; ++j) xm[j] = y.hi.plane(c, j);
-      load64(drow + c * a.plane_elems, l.col0, l.nval, vec_ok, W);
+      load64(drow[c], l.col0, l.nval, vec_ok, W);
       to_planes(W, d);
       mpclift_u(xm, d, a0[c], b0[c], b1[c], u);
       y.hi.put(c, u);
@@ -665,6 +669,8 @@ size_t compare_msg_planes(int variant) {
   }
 }
 
+static hipError_t run_compare_msg(int variant, CmpMsgArgs& a, bool code32, hipStream_t s);
+
 hipError_t launch_compare_msg(int variant, const Keys3& keys, const void* const rep_code[3], bool code32,
                               const void* const rep_mask[3], const uint16_t* ml_pub, uint64_t rows, uint64_t n,
                               uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3], uint64_t mw_ld,
@@ -686,15 +692,57 @@ hipError_t launch_compare_msg(int variant, const Keys3& keys, const void* const 
   a.nw = (n + 63) / 64;
   a.rows = rows;
   a.plane_elems = (qt.plane_rows ? qt.plane_rows : rows) * ld;
+  for (int p = 0; p < 3; ++p) {
+    a.prev_code[p] = static_cast<const uint16_t*>(a.code[p]) + a.plane_elems;
+    a.prev_mask[p] = a.mask[p] ? static_cast<const uint16_t*>(a.mask[p]) + a.plane_elems : nullptr;
+  }
   a.match_plane = rows * mw_ld;
   a.qid_base = ids.query_id_base;
   a.first_entry = ids.first_entry_id;
   a.r = ids.r;
+  for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) a.rot[i] = i < ids.r ? ids.rot[i] : 0;
+  return run_compare_msg(variant, a, code32, s);
+}
+
+hipError_t launch_compare_msgs(const Keys3& keys, const uint16_t* const msgs[3], uint64_t rows, uint64_t n,
+                               uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3], uint64_t mw_ld,
+                               uint64_t* msg, hipStream_t s) {
+  if (rows == 0 || n == 0) return hipSuccess;
+  CmpMsgArgs a;
+  a.tab = nullptr;
+  a.keys = keys;
+  const uint64_t plane = rows * ld;       // msgs[p]: [code, mask][rows][ld]
+  for (int p = 0; p < 3; ++p) {
+    const int pm = (p + 2) % 3;
+    a.code[p] = msgs[p];
+    a.mask[p] = msgs[p] + plane;
+    a.prev_code[p] = msgs[pm];
+    a.prev_mask[p] = msgs[pm] + plane;
+    a.match[p] = match[p];
+  }
+  a.ml_pub = nullptr;
+  a.msg = msg;
+  a.ld = ld;
+  a.mw_ld = mw_ld;
+  a.n = n;
+  a.nw = (n + 63) / 64;
+  a.rows = rows;
+  a.plane_elems = plane;
+  a.match_plane = rows * mw_ld;
+  a.qid_base = ids.query_id_base;
+  a.first_entry = ids.first_entry_id;
+  a.r = ids.r;
+  for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) a.rot[i] = i < ids.r ? ids.rot[i] : 0;
+  return run_compare_msg(0, a, false, s);
+}
+
+static hipError_t run_compare_msg(int variant, CmpMsgArgs& a, bool code32, hipStream_t s) {
+  const uint64_t ld = a.ld, rows = a.rows;
+  const uint16_t* ml_pub = a.ml_pub;
   bool vec = (ld % 8) == 0 && (reinterpret_cast<uintptr_t>(ml_pub) % 16) == 0;
   for (int p = 0; p < 3; ++p)
     vec = vec && (reinterpret_cast<uintptr_t>(a.code[p]) % 16) == 0 && (reinterpret_cast<uintptr_t>(a.mask[p]) % 16) == 0;
   a.vec = vec ? 1 : 0;
-  for (int i = 0; i < IMC_MAX_ROT_DEV; ++i) a.rot[i] = i < ids.r ? ids.rot[i] : 0;
   const uint64_t groups = (rows * a.nw + 63) / 64;
   if (groups > 0x7FFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid{unsigned(groups), 1, 1}, block{192, 1, 1};

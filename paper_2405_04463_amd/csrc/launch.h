@@ -67,6 +67,11 @@ hipError_t launch_reshare(const Keys3& keys, const uint16_t* const add_code[3], 
 hipError_t launch_compare(const Keys3& keys, const uint16_t* const rep_code[3], const uint16_t* const rep_mask[3],
                           uint64_t rows, uint64_t n, uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3],
                           uint64_t mw_ld, hipStream_t s, const QueryTab& qt = QueryTab{});
+// MPCLift with the parties' replicated components read from the resharing's
+// messages: party p's own = msgs[p], its second = msgs[p-1] ([code, mask][rows][ld]).
+hipError_t launch_compare_msgs(const Keys3& keys, const uint16_t* const msgs[3], uint64_t rows, uint64_t n,
+                               uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3], uint64_t mw_ld,
+                               uint64_t* msg, hipStream_t s);
 hipError_t launch_compare_variant(int variant, const Keys3& keys, const void* const rep_code[3], bool code32,
                                   const void* const rep_mask[3], const uint16_t* ml_pub, uint64_t rows, uint64_t n,
                                   uint64_t ld, const imc_ids_dev& ids, uint64_t* const match[3], uint64_t mw_ld,

@@ -169,3 +169,47 @@ def test_message_buffer_argument_errors(ctx, imc):
     with pytest.raises(imc.IMCError) as e:
         ctx.compare_threshold(shifted, shifted, rows, n, ld, ids, match, 1)
     assert e.value.status == imc.IMC_EINVAL
+
+
+@pytest.mark.parametrize("rows,n,ld", [(62, 300, 304), (31, 129, 129)])
+def test_comparison_on_the_resharing_messages(imc, ctx, keys, rows, n, ld):
+    """The resharing writing its messages only (no replicated planes) and the
+    comparison reading each party's components in place from its own message
+    and the one it received give the match components and the message log of
+    the replicated-plane calls, which match the oracle's resharing and
+    comparison; with and without the 16-byte load path (ld % 8)."""
+    _, party = keys
+    rot = list(range(-15, 16))[:31] if rows % 31 == 0 else [0]
+    r = len(rot)
+    rng = np.random.default_rng(rows + n)
+    zc = rng.integers(0, 1 << 16, size=(3, rows, ld), dtype=np.uint16)
+    zm = rng.integers(0, 1 << 16, size=(3, rows, ld), dtype=np.uint16)
+    add_c = [torch.from_numpy(zc[p].view(np.int16).copy()).cuda() for p in range(3)]
+    add_m = [torch.from_numpy(zm[p].view(np.int16).copy()).cuda() for p in range(3)]
+    ids = imc.make_ids(40, rot, 64)
+    full = [torch.empty(2, rows, ld, dtype=torch.int16, device="cuda") for _ in range(9)]
+    msg_a, rep_c, rep_m = full[0:3], full[3:6], full[6:9]
+    ctx.reshare(add_c, add_m, rows, n, ld, ids, msg_a, rep_c, rep_m)
+    msg_b = [torch.zeros(2, rows, ld, dtype=torch.int16, device="cuda") for _ in range(3)]
+    ctx.reshare(add_c, add_m, rows, n, ld, ids, msg_b, None, None)        # the messages only
+    nw = (n + 63) // 64
+    net_a = torch.zeros(imc.compare_msg_bytes(0, rows, n) // 8, dtype=torch.int64, device="cuda")
+    net_b = torch.zeros_like(net_a)
+    ma = [torch.zeros(2, rows, nw, dtype=torch.int64, device="cuda") for _ in range(3)]
+    mb = [torch.zeros(2, rows, nw, dtype=torch.int64, device="cuda") for _ in range(3)]
+    mr = [torch.zeros(2, rows, nw, dtype=torch.int64, device="cuda") for _ in range(3)]
+    ctx.compare_threshold(rep_c, rep_m, rows, n, ld, ids, ma, nw, msg_ws=net_a)
+    ctx.compare_threshold_msgs(msg_b, rows, n, ld, ids, mb, nw, msg_ws=net_b)
+    ctx.compare_threshold_msgs(msg_b, rows, n, ld, ids, mr, nw)           # register simulation
+    torch.cuda.synchronize()
+    for p in range(3):
+        assert torch.equal(msg_a[p][:, :, :n], msg_b[p][:, :, :n]), p
+        assert torch.equal(ma[p], mb[p]) and torch.equal(ma[p], mr[p]), p
+    assert torch.equal(net_a, net_b)
+    oc, om = orc.reshare(party, np.ascontiguousarray(zc[:, :, :n]), np.ascontiguousarray(zm[:, :, :n]),
+                         rows // r, rot, 40, 64)
+    want = orc.compare(party, oc, om, rows // r, rot, 40, 64)
+    _check_components(mb, want, nw)
+    with pytest.raises(imc.IMCError) as e:
+        ctx.compare_threshold_msgs(msg_b, rows, n, ld, ids, mb, nw, msg_ws=net_b[:8])   # buffer too small
+    assert e.value.status == imc.IMC_ESHAPE
