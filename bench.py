@@ -373,6 +373,10 @@ def run_full(args):
     torch.cuda.synchronize()
     ver = verify(ctx, buf, w, qc, qm, party)
     log(f"verification: {ver}")
+    # the verified step's match and duplicate components, to check the timed
+    # steps (which may take another route, e.g. the messages-only resharing)
+    ref_match = [m.clone() for m in buf.match]
+    ref_dup = [d.clone() for d in buf.dup]
     bb = None
     if in_batch:
         bb = run_in_batch(ctx, qs, w.rot, buf, group=w.group)
@@ -463,6 +467,10 @@ def run_full(args):
         evs.append(ev)
         log(f"step {i + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms")
     total = time.perf_counter() - t0
+    ver["timed_steps_equal_verified_step"] = bool(
+        all(torch.equal(a, b) for a, b in zip(ref_match, buf.match)) and
+        all(torch.equal(a, b) for a, b in zip(ref_dup, buf.dup)))
+    del ref_match, ref_dup
     # the comparison in the other network mode, outside the timed steps (the
     # register simulation when the step passes messages through the buffer)
     other_ms = None
