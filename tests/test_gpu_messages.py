@@ -213,3 +213,28 @@ def test_comparison_on_the_resharing_messages(imc, ctx, keys, rows, n, ld):
     with pytest.raises(imc.IMCError) as e:
         ctx.compare_threshold_msgs(msg_b, rows, n, ld, ids, mb, nw, msg_ws=net_b[:8])   # buffer too small
     assert e.value.status == imc.IMC_ESHAPE
+
+
+def test_messages_only_resharing_edges(imc, ctx, keys):
+    """Code shares only and messages only together; misaligned message planes
+    for the 16-byte path are refused before anything runs."""
+    rows, n, ld = 31, 200, 208
+    rot = list(range(-15, 16))
+    ids = imc.make_ids(3, rot, 0)
+    rng = np.random.default_rng(5)
+    add_c = [torch.from_numpy(rng.integers(0, 1 << 16, size=(rows, ld), dtype=np.uint16).view(np.int16).copy()).cuda()
+             for _ in range(3)]
+    full = [torch.zeros(2, rows, ld, dtype=torch.int16, device="cuda") for _ in range(6)]
+    ctx.reshare(add_c, None, rows, n, ld, ids, full[:3], full[3:], None)         # code only, replicated planes
+    only = [torch.zeros(2, rows, ld, dtype=torch.int16, device="cuda") for _ in range(3)]
+    ctx.reshare(add_c, None, rows, n, ld, ids, only, None, None)                  # code only, messages only
+    torch.cuda.synchronize()
+    for p in range(3):
+        assert torch.equal(only[p][0, :, :n], full[p][0, :, :n]), p
+        assert torch.equal(only[p][1], torch.zeros_like(only[p][1])), p            # mask plane untouched
+    nw = (n + 63) // 64
+    match = [torch.zeros(2, rows, nw, dtype=torch.int64, device="cuda") for _ in range(3)]
+    off = [t.data_ptr() + 2 for t in only]                                        # 2-byte, not 16-byte aligned
+    with pytest.raises(imc.IMCError) as e:
+        ctx.compare_threshold_msgs(off, rows, n, ld, ids, match, nw)
+    assert e.value.status == imc.IMC_EINVAL
