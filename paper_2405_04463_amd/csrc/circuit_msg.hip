@@ -580,8 +580,13 @@ struct Const32Y {
 //            key_2 c2 88..89, w0 90..91, w1 92..93; planes 202..209), MSB
 //            m = 17 on words 40..73 (gates 33..65) (210 planes)
 //   Const32  MSB m = 31 on words 0..61, gates 0..60 (183 planes)
+// Held to 168 registers (three waves per SIMD) so that four workgroups share
+// a CU, as many as their LDS allows: the Const32 instances would otherwise
+// take about 184 and fit two; the few registers they then spill cost less
+// than the halved occupancy.
 template <int V, bool C32>
-__global__ void __launch_bounds__(192) compare_msg_variant_kernel(CmpMsgArgs a) {
+__global__ void __launch_bounds__(192) __attribute__((amdgpu_waves_per_eu(3)))
+compare_msg_variant_kernel(CmpMsgArgs a) {
   constexpr int kPlanes = V == 1 ? 87 : V == 2 ? 210 : 183;
   const int p = party_of_wave(), pm = (p + 2) % 3;
   const Lane l = lane_of(a);
