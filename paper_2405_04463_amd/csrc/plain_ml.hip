@@ -52,7 +52,9 @@ struct MlArgs {
 // Workgroup tile 64 rows x 128 entries; thread (tr, tc) owns rows 4tr..4tr+3
 // and entries tc + 16j.  Consecutive workgroups of one XCD walk the row tiles
 // of one entry tile, so the entry masks are read from HBM about once per XCD.
-__global__ void __launch_bounds__(256) plain_ml_kernel(MlArgs a) {
+// Held to 128 registers (it needs 125 then, no spills): four waves per SIMD
+// instead of the three that 129 allowed.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) plain_ml_kernel(MlArgs a) {
   __shared__ uint64_t sa[kMlKC][kMlTM + 1];
   __shared__ uint64_t sb[kMlKC][kMlTN + 1];
   const uint32_t i = blockIdx.x, xcd = i & 7, s8 = i >> 3;
